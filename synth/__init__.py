@@ -1,0 +1,191 @@
+"""Seeded synthetic int8 voltage streams shaped like the paper's workloads.
+
+Shared by the tests, the oracle's callers and the benchmark.  It holds no
+part of the correlator's arithmetic (no taps, no transforms, no products):
+only random draws, mixing and rounding to int8.
+
+Stream model, per antenna a and sample n (all float32 until the final
+round-half-even and clip to [-128, 127]):
+
+    x_a[n] = sigma * g_a[n]                       independent noise
+           + sqrt(corr) * sigma * c[n - d_a]       common sky component, lag d_a
+           + tone[n] + lines[n] + bursts[n]        common to all antennas
+
+Random numbers come from numpy's PCG64 seeded by SeedSequence((seed,
+stream id, chunk index)), so any chunk can be regenerated on its own.
+"""
+
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+CHUNK = 1 << 22
+
+
+def _rng(seed: int, stream: int, chunk: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, stream, chunk])))
+
+
+@dataclass
+class StreamSpec:
+    n_ant: int
+    n_samp: int
+    seed: int
+    sigma: float = 16.0
+    corr: float = 0.3
+    lags: tuple = ()
+    tone_amp: float = 0.0
+    tone_cycles_per_sample: float = 0.0
+    lines: list = field(default_factory=list)     # [(cycles_per_sample, amp, phase)]
+    bursts: list = field(default_factory=list)    # [(start_sample, length, rms)]
+
+
+def _common_component(spec: StreamSpec, lo: int, hi: int, max_lag: int) -> np.ndarray:
+    """c[n] for n in [lo - max_lag, hi), built chunk by chunk."""
+    out = np.empty(hi - lo + max_lag, np.float32)
+    start = lo - max_lag
+    pos = 0
+    n = start
+    while n < hi:
+        j = math.floor(n / CHUNK)
+        c0 = j * CHUNK
+        block = _rng(spec.seed, 1, j + 1_000_000).standard_normal(CHUNK, dtype=np.float32)
+        a = n - c0
+        b = min(CHUNK, hi - c0)
+        out[pos:pos + b - a] = block[a:b]
+        pos += b - a
+        n = c0 + b
+    return out
+
+
+def generate(spec: StreamSpec, out: np.ndarray | None = None) -> np.ndarray:
+    """int8 [n_ant, n_samp] stream for ``spec`` (deterministic in spec.seed)."""
+    n_ant, S = spec.n_ant, spec.n_samp
+    lags = tuple(spec.lags) if spec.lags else (0,) * n_ant
+    assert len(lags) == n_ant
+    max_lag = max(lags) if lags else 0
+    x = np.empty((n_ant, S), np.int8) if out is None else out
+    k_corr = np.float32(math.sqrt(spec.corr) * spec.sigma)
+    sig = np.float32(spec.sigma)
+    for lo in range(0, S, CHUNK):
+        hi = min(S, lo + CHUNK)
+        j = lo // CHUNK
+        L = hi - lo
+        common = np.zeros(L, np.float32)
+        n = np.arange(lo, hi, dtype=np.float64)
+        if spec.tone_amp:
+            ph = np.mod(n * spec.tone_cycles_per_sample, 1.0)
+            common += (spec.tone_amp * np.cos(2.0 * np.pi * ph)).astype(np.float32)
+        for (f, amp, phase) in spec.lines:
+            ph = np.mod(n * f, 1.0)
+            common += (amp * np.cos(2.0 * np.pi * ph + phase)).astype(np.float32)
+        for bi, (b0, blen, rms) in enumerate(spec.bursts):
+            a, b = max(lo, b0), min(hi, b0 + blen)
+            if a < b:
+                r = _rng(spec.seed, 3, bi).standard_normal(blen, dtype=np.float32)
+                common[a - lo:b - lo] += np.float32(rms) * r[a - b0:b - b0]
+        cpre = _common_component(spec, lo, hi, max_lag) if spec.corr else None
+        for a_ in range(n_ant):
+            v = sig * _rng(spec.seed, 100 + a_, j).standard_normal(L, dtype=np.float32)
+            if cpre is not None:
+                d = lags[a_]
+                v += k_corr * cpre[max_lag - d:max_lag - d + L]
+            v += common
+            np.rint(v, out=v)
+            np.clip(v, -128, 127, out=v)
+            x[a_, lo:hi] = v.astype(np.int8)
+    return x
+
+
+# ---- the workloads (seed = 1000 * config number + realisation) -------------
+
+@dataclass
+class Workload:
+    name: str
+    x: np.ndarray
+    n_fft: int
+    n_taps: int
+    spec_per_dump: int
+    params: dict
+
+
+def tone_stream(n_ant=4, n_samp=1 << 20, seed=1000, n_fft=1024, chan=137):
+    """4 antennas, sigma 16 noise, 30% correlated power at lags {0,3,5,7},
+    a tone of amplitude 16 centred on channel ``chan``, all seeded."""
+    lags = (0, 3, 5, 7)[:n_ant] if n_ant <= 4 else tuple(range(n_ant))
+    spec = StreamSpec(n_ant, n_samp, seed, corr=0.3, lags=lags,
+                      tone_amp=16.0, tone_cycles_per_sample=chan / n_fft)
+    return spec
+
+
+def plain_fx(n_samp=1 << 20, seed=1000) -> Workload:
+    """Plain FX correlator: 4 ant, 2^20 samples, N=1024, P=4, one dump."""
+    spec = tone_stream(4, n_samp, seed, 1024, 137)
+    x = generate(spec)
+    return Workload("plain_fx_4ant_n1024", x, 1024, 4, n_samp // 1024,
+                    {"lags": spec.lags, "tone_chan": 137})
+
+
+LINE_AMP = 1.4  # LSB: ~10x a channel's noise power at N=4096, sigma=16
+
+
+def realtime_spec(n_samp=1 << 28, seed=2000, n_fft=4096, spec_per_dump=4096,
+                  n_lines=20, burst_frac=0.05):
+    """Real-time-shaped stream: lags U{0..40}, 20 lines, 5% bursts."""
+    rng = _rng(seed, 7, 0)
+    n_ant = 4
+    lags = tuple(int(v) for v in rng.integers(0, 41, n_ant))
+    n_chan = n_fft // 2
+    chans = rng.choice(np.arange(8, n_chan - 8), n_lines, replace=False)
+    lines = [(float(k) / n_fft, LINE_AMP, float(rng.uniform(-np.pi, np.pi))) for k in sorted(chans)]
+    M = n_samp // n_fft
+    bursts = []
+    target = int(round(burst_frac * M))
+    covered = 0
+    while covered < target:
+        blen = int(rng.integers(1, 65))
+        start = int(rng.integers(0, max(1, M - blen)))
+        bursts.append((start * n_fft, blen * n_fft, math.sqrt(10.0) * 16.0))
+        covered += blen
+    tau_s = np.array(lags, np.float64) * 1e-9      # 1 GS/s: one sample = 1 ns
+    phi = rng.uniform(-np.pi, np.pi, n_ant)
+    spec = StreamSpec(n_ant, n_samp, seed, corr=0.3, lags=lags, lines=lines, bursts=bursts)
+    params = {"lags": lags, "line_chans": [int(k) for k in sorted(chans)],
+              "tau_s": tau_s, "phi_rad": phi, "fs_hz": 1e9,
+              "bursts": bursts}
+    return spec, params
+
+
+def realtime(n_samp=1 << 28, seed=2000) -> Workload:
+    spec, params = realtime_spec(n_samp, seed)
+    x = generate(spec)
+    return Workload("realtime_4ant_n4096", x, 4096, 4, 4096, params)
+
+
+def array_spec(n_ant=32, n_samp=1 << 24, seed=3000, corr=0.1, max_lag=40):
+    rng = _rng(seed, 7, 0)
+    lags = tuple(int(v) for v in rng.integers(0, max_lag + 1, n_ant))
+    return StreamSpec(n_ant, n_samp, seed, corr=corr, lags=lags)
+
+
+def precision(n_samp=1 << 24, seed=3000) -> Workload:
+    """32 antennas, sigma 16, 10% correlated, lags U{0..40}, N=4096."""
+    spec = array_spec(32, n_samp, seed)
+    x = generate(spec)
+    return Workload("precision_32ant_n4096", x, 4096, 4, n_samp // 4096, {"lags": spec.lags})
+
+
+BATCH_ARRAYS = ((4, 512), (8, 1024), (16, 2048), (24, 2048), (32, 4096))
+
+
+def batched(n_samp=1 << 22, seed=4000):
+    """Five arrays (n_ant, n_chan); 30% correlated, lags U{0..7}; N = 2 n_chan."""
+    out = []
+    for idx, (na, nch) in enumerate(BATCH_ARRAYS):
+        spec = array_spec(na, n_samp, seed + idx, corr=0.3, max_lag=7)
+        out.append(Workload(f"batch_{na}ant_{nch}ch", generate(spec), 2 * nch, 4,
+                            n_samp // (2 * nch), {"lags": spec.lags}))
+    return out
