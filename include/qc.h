@@ -1,0 +1,162 @@
+/*
+ * qc.h -- C ABI of libqc, an FX-correlator hot path for AMD gfx950 (MI355X).
+ *
+ * The method is that of arXiv 2604.20640 (QUEST Python/CuPy correlator):
+ *   F-engine  : polyphase-filter-bank weighting, then a real FFT of each
+ *               antenna's int8 voltage stream (Sec. 4.1 step 1; Sec. 4.2
+ *               "F-engine (PFB and FFT)"; Alg. 1 "Apply PFB weighting -> FFT").
+ *   X-engine  : V_ij(k) = sum_m X_i,m(k) conj(X_j,m(k)) for all baselines,
+ *               autos included, integrated over a dump (Sec. 4.1 eq. 1;
+ *               Sec. 4.2 "X-engine and integration"; Alg. 1).
+ *   MAD flags : T = median(A) + sigma * 1.4826 * MAD(A), flag A > T (Sec. 7 eq. 2).
+ *   Delay/phase application: V_ij *= exp(+i[2 pi f (tau_i - tau_j) + phi_i - phi_j])
+ *               (Sec. 4.1 step 2 and eq. 1; Sec. 7 delay and phase steps).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Pointers   : "device" pointers are HIP device memory owned by the caller; the
+ *              library never frees or retains them after the call returns.
+ *              "host" pointers are read (or written) before the call returns.
+ * Streams    : every call is asynchronous on `stream` (a hipStream_t passed as
+ *              void*; NULL = the default stream) unless its comment says it
+ *              synchronises.
+ * Errors     : arguments are validated on the host before anything is
+ *              launched; a bad argument returns QC_EINVAL (or QC_EUNSUPPORTED
+ *              for a valid but unimplemented combination) and launches nothing.
+ *              A HIP failure returns QC_EHIP.  qc_last_error() gives a
+ *              thread-local description of the last failure.
+ * Complex    : interleaved (re, im) float32 pairs ("cfloat" below).
+ * Antennas   : int8 input is antenna-major: x[a * ld_x + n], n = 0..n_samp-1.
+ * Baselines  : b(i, j) = i*n_ant - i*(i-1)/2 + (j - i) for 0 <= i <= j < n_ant
+ *              (upper triangle, row-major, autos included);
+ *              n_base = n_ant*(n_ant+1)/2.
+ * Channels   : n_chan = n_fft/2; channel k is DFT bin k of an n_fft-point real
+ *              transform with kernel exp(-2 pi i k n / n_fft), no normalisation;
+ *              the Nyquist bin is dropped.
+ * Spectra    : spectrum m uses stream blocks m-P+1 .. m (block = n_fft samples);
+ *              samples before the stream are `hist` if given, else zero, so a
+ *              stream of n_samp samples gives n_samp / n_fft spectra.
+ */
+#ifndef QC_H
+#define QC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t qc_status;
+enum {
+  QC_OK = 0,
+  QC_EINVAL = -1,       /* bad argument: nothing launched */
+  QC_EUNSUPPORTED = -2, /* valid but not implemented: nothing launched */
+  QC_EHIP = -3,         /* a HIP runtime call failed */
+  QC_ENOMEM = -4,       /* device or host allocation failed */
+  QC_ESTATE = -5        /* object used in the wrong state */
+};
+
+typedef enum { QC_F32 = 0, QC_F16 = 1, QC_BF16 = 2, QC_FP8_E4M3 = 3 } qc_prec;
+
+/* Polyphase filter bank parameters (Sec. 4.3: FFT length and number of PFB
+ * taps are runtime parameters).
+ *   n_fft : N, a power of two, 4 <= N <= 8192.
+ *   n_taps: P, 1 <= P <= 16.
+ *   taps  : device float[P*N] prototype h[q], or NULL for the built-in
+ *           Hann-windowed sinc h[q] = w[q] sinc((q-(L-1)/2)/N), L = P*N,
+ *           w[q] = 0.5 - 0.5 cos(2 pi q/(L-1)), unnormalised.  The filter
+ *           applied is y_m[n] = sum_p h[p*N+n] x[(m-P+1+p)*N + n].
+ *   keep_nyquist: must be 0 (reserved). */
+typedef struct {
+  int32_t n_fft;
+  int32_t n_taps;
+  const float* taps;
+  int32_t keep_nyquist;
+} qc_pfb_params;
+
+/* F-engine alone (Sec. 4.2 "F-engine", Alg. 1 F-Engine step).
+ *   x       : device int8, antenna stride ld_x bytes (ld_x >= n_samp, ld_x % 4 == 0,
+ *             x 4-byte aligned).
+ *   n_samp  : samples per antenna, a multiple of n_fft.
+ *   hist    : device int8 [n_ant][(P-1)*N] samples preceding x, or NULL (zeros).
+ *   hist_out: device int8 [n_ant][(P-1)*N] receives the last (P-1)*N samples of
+ *             (hist ++ x) for the next call, or NULL.  May not alias hist.
+ *   out_prec: QC_F32 -> out is cfloat [n_ant][n_spec][n_chan];
+ *             QC_F16 / QC_BF16 -> out is pairs of 16-bit (re, im) in the same
+ *             layout; QC_FP8_E4M3 -> pairs of E4M3 bytes.  For reduced
+ *             precision each antenna's values are multiplied by the power of
+ *             two scale_out[a] before rounding (round to nearest even,
+ *             saturating at the format's largest finite value).
+ *   scale_out: device float[n_ant], written when out_prec != QC_F32 (may be NULL
+ *             for QC_F32).  s_a = 2^round(log2(target/rms_a)), rms_a =
+ *             sqrt(mean(x_a^2) * sum h^2) over the first min(n_samp, 2^20)
+ *             samples; target 256 (F16), 1 (BF16), 32 (E4M3). */
+qc_status qc_pfb_channelize(const int8_t* x, int64_t ld_x, int32_t n_ant, int64_t n_samp,
+                            const qc_pfb_params* p, const int8_t* hist, int8_t* hist_out,
+                            qc_prec out_prec, void* out, float* scale_out, void* stream);
+
+/* Fused F+X from int8 (the hot path; Sec. 4.2, Alg. 1 F-Engine, X-Engine and
+ * Integration steps).
+ *   spec_per_dump: spectra integrated per dump (>= 1).
+ *   x_prec  : QC_F32 only for the fused path (reduced precision runs through
+ *             qc_pfb_channelize + qc_xcorrelate_chan).
+ *   vis     : device cfloat [n_dump][n_base][n_chan], n_dump = n_spec / spec_per_dump;
+ *             a trailing partial dump is not integrated.
+ *   accumulate: nonzero adds into vis, zero overwrites it.
+ *   n_dumps_out: host int64* (or NULL) receives n_dump.
+ * Deterministic: per-workgroup partial sums are reduced in a fixed order. */
+qc_status qc_xcorrelate(const int8_t* x, int64_t ld_x, int32_t n_ant, int64_t n_samp,
+                        const qc_pfb_params* p, const int8_t* hist, int8_t* hist_out,
+                        int64_t spec_per_dump, qc_prec x_prec, float* vis, int32_t accumulate,
+                        int64_t* n_dumps_out, void* stream);
+
+/* X-engine alone from channelised voltages as written by qc_pfb_channelize
+ * (Sec. 4.1 eq. 1; Sec. 4.2 X-engine and integration).
+ *   v      : device [n_ant][n_spec][n_chan] (re, im) pairs of type prec.
+ *   scale  : device float[n_ant] per-antenna scales for reduced precision
+ *            (visibilities are divided by scale_i*scale_j), NULL for QC_F32.
+ *   QC_F32 runs on the vector ALUs; QC_F16 / QC_BF16 / QC_FP8_E4M3 run on the
+ *   matrix cores with float32 accumulation.
+ *   vis    : device cfloat [n_spec/spec_per_dump][n_base][n_chan]. */
+qc_status qc_xcorrelate_chan(const void* v, qc_prec prec, const float* scale, int32_t n_ant,
+                             int64_t n_spec, int32_t n_chan, int64_t spec_per_dump,
+                             float* vis, int32_t accumulate, void* stream);
+
+/* MAD flagging (Sec. 7 eq. 2).
+ *   vis        : device cfloat [n_time][n_base][n_chan].
+ *   sigma      : threshold in units of 1.4826*MAD (the paper uses 5).
+ *   population : 0 = per baseline over its (time x channel) plane;
+ *                1 = per (baseline, channel) over time;
+ *                2 = per (baseline, time) over channel.
+ *   mask       : device uint8, same shape as vis; 1 = flagged (A > T).
+ *   thresh_out : device double [n_base] (population 0), [n_base][n_chan] (1) or
+ *                [n_time][n_base] (2), or NULL.
+ * Amplitudes are |V| formed in float64 and rounded once to float32; medians,
+ * the MAD and T = med + (sigma*1.4826)*MAD are float64, the even-count median
+ * is the mean of the two middle values, and MAD = 0 gives T = median. */
+qc_status qc_mad_flag(const float* vis, int64_t n_time, int64_t n_base, int32_t n_chan,
+                      float sigma, int32_t population, uint8_t* mask, double* thresh_out,
+                      void* stream);
+
+/* In-place per-antenna delay and phase correction (Sec. 4.1 step 2, eq. 1;
+ * Sec. 7 delay/phase correction).  For b = (i, j) and channel k:
+ *   V[t][b][k] *= exp(+i [2 pi f_k (tau_i - tau_j) + (phi_i - phi_j)]),
+ *   f_k = f0_hz + k * df_hz.
+ *   tau_s, phi_rad: HOST double[n_ant], copied before the call returns.
+ * The phase is formed in float64 (cycles reduced modulo 1 before sin/cos). */
+qc_status qc_apply_delay_phase(float* vis, int64_t n_time, int32_t n_ant, int32_t n_chan,
+                               double f0_hz, double df_hz, const double* tau_s,
+                               const double* phi_rad, void* stream);
+
+/* Human-readable name of a status code (static storage). */
+const char* qc_status_string(qc_status s);
+/* Thread-local detail of the last failure in this thread ("" if none). */
+const char* qc_last_error(void);
+/* Library version string (static storage). */
+const char* qc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QC_H */

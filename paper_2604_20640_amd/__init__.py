@@ -1,0 +1,182 @@
+"""qc: an FX-correlator hot path for AMD MI355X (gfx950), after arXiv 2604.20640.
+
+A thin ctypes binding over ``libqc.so`` (C ABI in ``include/qc.h``).  The
+functions here only marshal arguments: every step runs in the library's HIP
+kernels.  PyTorch provides device memory and the current stream.  If the
+library is missing this module raises on first use; there is no fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+__all__ = [
+    "QCError", "lib", "pfb_channelize", "xcorrelate", "xcorrelate_chan", "mad_flag",
+    "apply_delay_phase", "n_base", "PREC",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqc.so")
+
+PREC = {"f32": 0, "f16": 1, "bf16": 2, "fp8": 3}
+_PAIR_BYTES = {0: 8, 1: 4, 2: 4, 3: 2}
+
+
+class QCError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where} failed: status {status} ({detail})")
+        self.status = status
+
+
+class PfbParams(ctypes.Structure):
+    _fields_ = [("n_fft", ctypes.c_int32), ("n_taps", ctypes.c_int32),
+                ("taps", ctypes.c_void_p), ("keep_nyquist", ctypes.c_int32)]
+
+
+_lib = None
+
+_P = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
+_SIGS = {
+    "qc_pfb_channelize": [_P, _I64, _I32, _I64, ctypes.POINTER(PfbParams), _P, _P, _I32, _P, _P, _P],
+    "qc_xcorrelate": [_P, _I64, _I32, _I64, ctypes.POINTER(PfbParams), _P, _P, _I64, _I32, _P, _I32,
+                      ctypes.POINTER(_I64), _P],
+    "qc_xcorrelate_chan": [_P, _I32, _P, _I32, _I64, _I32, _I64, _P, _I32, _P],
+    "qc_mad_flag": [_P, _I64, _I64, _I32, ctypes.c_float, _I32, _P, _P, _P],
+    "qc_apply_delay_phase": [_P, _I64, _I32, _I32, ctypes.c_double, ctypes.c_double,
+                             ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), _P],
+}
+
+
+def lib() -> ctypes.CDLL:
+    """Load libqc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2604_20640_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, args in _SIGS.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_int32
+        L.qc_status_string.restype = ctypes.c_char_p
+        L.qc_status_string.argtypes = [ctypes.c_int32]
+        L.qc_last_error.restype = ctypes.c_char_p
+        L.qc_version.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(st: int, where: str):
+    if st != 0:
+        L = lib()
+        raise QCError(st, where, f"{L.qc_status_string(st).decode()}: {L.qc_last_error().decode()}")
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def n_base(n_ant: int) -> int:
+    return n_ant * (n_ant + 1) // 2
+
+
+def _pfb(n_fft, n_taps, taps):
+    if taps is not None:
+        assert taps.dtype == torch.float32 and taps.is_cuda and taps.numel() == n_fft * n_taps
+    return PfbParams(n_fft, n_taps, None if taps is None else taps.data_ptr(), 0)
+
+
+def _check_x(x):
+    assert x.dtype == torch.int8 and x.is_cuda and x.dim() == 2 and x.stride(1) == 1, \
+        "x must be a CUDA int8 [n_ant, n_samp] tensor with unit sample stride"
+
+
+def pfb_channelize(x, n_fft, n_taps, taps=None, hist=None, hist_out=None, out_prec="f32",
+                   out=None, scale_out=None):
+    """F-engine: returns (out, scale).  out is complex64 [n_ant, n_spec, n_chan]
+    for f32, else a uint8 tensor holding (re, im) pairs of the format."""
+    _check_x(x)
+    n_ant, n_samp = x.shape
+    prec = PREC[out_prec]
+    n_spec, n_chan = n_samp // n_fft, n_fft // 2
+    if out is None:
+        if prec == 0:
+            out = torch.empty((n_ant, n_spec, n_chan), dtype=torch.complex64, device=x.device)
+        else:
+            out = torch.empty((n_ant, n_spec, n_chan * _PAIR_BYTES[prec]), dtype=torch.uint8,
+                              device=x.device)
+    if prec != 0 and scale_out is None:
+        scale_out = torch.empty(n_ant, dtype=torch.float32, device=x.device)
+    p = _pfb(n_fft, n_taps, taps)
+    st = lib().qc_pfb_channelize(_ptr(x), x.stride(0), n_ant, n_samp, ctypes.byref(p), _ptr(hist),
+                                 _ptr(hist_out), prec, _ptr(out), _ptr(scale_out), _stream())
+    _check(st, "qc_pfb_channelize")
+    return out, scale_out
+
+
+def xcorrelate(x, n_fft, n_taps, spec_per_dump, taps=None, hist=None, hist_out=None, vis=None,
+               accumulate=False, x_prec="f32"):
+    """Fused F+X: complex64 visibilities [n_dump, n_base, n_chan]."""
+    _check_x(x)
+    n_ant, n_samp = x.shape
+    n_dump = (n_samp // n_fft) // spec_per_dump
+    if vis is None:
+        vis = torch.empty((n_dump, n_base(n_ant), n_fft // 2), dtype=torch.complex64, device=x.device)
+    p = _pfb(n_fft, n_taps, taps)
+    nd = _I64(0)
+    st = lib().qc_xcorrelate(_ptr(x), x.stride(0), n_ant, n_samp, ctypes.byref(p), _ptr(hist),
+                             _ptr(hist_out), spec_per_dump, PREC[x_prec], _ptr(vis),
+                             1 if accumulate else 0, ctypes.byref(nd), _stream())
+    _check(st, "qc_xcorrelate")
+    assert nd.value == n_dump
+    return vis
+
+
+def xcorrelate_chan(v, prec, scale, n_ant, n_spec, n_chan, spec_per_dump, vis=None,
+                    accumulate=False):
+    """X-engine alone over channelised voltages laid out [n_ant][n_spec][n_chan]."""
+    n_dump = n_spec // spec_per_dump
+    if vis is None:
+        vis = torch.empty((n_dump, n_base(n_ant), n_chan), dtype=torch.complex64, device=v.device)
+    st = lib().qc_xcorrelate_chan(_ptr(v), PREC[prec], _ptr(scale), n_ant, n_spec, n_chan,
+                                  spec_per_dump, _ptr(vis), 1 if accumulate else 0, _stream())
+    _check(st, "qc_xcorrelate_chan")
+    return vis
+
+
+def mad_flag(vis, sigma=5.0, population=0, mask=None, thresh=None):
+    """MAD flags for complex64 vis [n_time, n_base, n_chan]: (mask uint8, thresholds float64)."""
+    assert vis.dtype == torch.complex64 and vis.is_cuda and vis.is_contiguous()
+    n_time, nb, n_chan = vis.shape
+    if mask is None:
+        mask = torch.empty(vis.shape, dtype=torch.uint8, device=vis.device)
+    tshape = {0: (nb,), 1: (nb, n_chan), 2: (n_time, nb)}[population]
+    if thresh is None:
+        thresh = torch.empty(tshape, dtype=torch.float64, device=vis.device)
+    st = lib().qc_mad_flag(_ptr(vis), n_time, nb, n_chan, float(sigma), population, _ptr(mask),
+                           _ptr(thresh), _stream())
+    _check(st, "qc_mad_flag")
+    return mask, thresh
+
+
+def apply_delay_phase(vis, n_ant, f0_hz, df_hz, tau_s, phi_rad):
+    """In-place delay/phase correction of complex64 vis [n_time, n_base, n_chan]."""
+    assert vis.dtype == torch.complex64 and vis.is_cuda and vis.is_contiguous()
+    n_time, nb, n_chan = vis.shape
+    assert nb == n_base(n_ant)
+    tau = (ctypes.c_double * n_ant)(*[float(v) for v in tau_s])
+    phi = (ctypes.c_double * n_ant)(*[float(v) for v in phi_rad])
+    st = lib().qc_apply_delay_phase(_ptr(vis), n_time, n_ant, n_chan, float(f0_hz), float(df_hz),
+                                    tau, phi, _stream())
+    _check(st, "qc_apply_delay_phase")
+    return vis

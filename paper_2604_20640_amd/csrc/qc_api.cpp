@@ -1,0 +1,405 @@
+// C-ABI entry points of libqc: host-side argument validation, per-device
+// caches of filter taps and FFT twiddles, workspace management and kernel
+// selection.  See include/qc.h for the contract of each call.
+#include "qc.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "qc_kernels.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+qc_status fail(qc_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+qc_status hip_fail(hipError_t e, const char* what) {
+  return fail(QC_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define QC_HIP(call, what)                        \
+  do {                                            \
+    hipError_t e_ = (call);                       \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// ---- built-in prototype filter and twiddles (float64 on the host) ----------
+
+// Hann-windowed sinc, L = P*N taps, centre (L-1)/2, sinc zeros every N.
+std::vector<double> hann_sinc(int N, int P) {
+  const int L = N * P;
+  std::vector<double> h(L);
+  const double pi = 3.14159265358979323846;
+  for (int q = 0; q < L; ++q) {
+    const double w = L > 1 ? 0.5 - 0.5 * std::cos(2.0 * pi * q / (L - 1)) : 1.0;
+    const double u = (q - (L - 1) / 2.0) / N;
+    const double s = (u == 0.0) ? 1.0 : std::sin(pi * u) / (pi * u);
+    h[q] = w * s;
+  }
+  return h;
+}
+
+struct TapsEntry {
+  float* dev = nullptr;
+  double sum_h2 = 0.0;
+};
+
+std::mutex g_mu;
+std::map<std::tuple<int, int, int>, TapsEntry> g_taps;  // (device, N, P)
+std::map<std::pair<int, int>, float2*> g_tw;            // (device, N)
+
+qc_status get_taps(int N, int P, TapsEntry* out) {
+  int dev = 0;
+  QC_HIP(hipGetDevice(&dev), "hipGetDevice");
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto key = std::make_tuple(dev, N, P);
+  auto it = g_taps.find(key);
+  if (it != g_taps.end()) {
+    *out = it->second;
+    return QC_OK;
+  }
+  std::vector<double> h = hann_sinc(N, P);
+  std::vector<float> hf(h.size());
+  double s2 = 0.0;
+  for (size_t i = 0; i < h.size(); ++i) {
+    hf[i] = (float)h[i];
+    s2 += h[i] * h[i];
+  }
+  TapsEntry e;
+  QC_HIP(hipMalloc(&e.dev, hf.size() * sizeof(float)), "hipMalloc(taps)");
+  QC_HIP(hipMemcpy(e.dev, hf.data(), hf.size() * sizeof(float), hipMemcpyHostToDevice),
+         "hipMemcpy(taps)");
+  e.sum_h2 = s2;
+  g_taps[key] = e;
+  *out = e;
+  return QC_OK;
+}
+
+qc_status get_twiddles(int N, float2** out) {
+  int dev = 0;
+  QC_HIP(hipGetDevice(&dev), "hipGetDevice");
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto key = std::make_pair(dev, N);
+  auto it = g_tw.find(key);
+  if (it != g_tw.end()) {
+    *out = it->second;
+    return QC_OK;
+  }
+  // exp(-2 pi i e / N): angle from the exact integer e, evaluated in float64,
+  // rounded once to float32.
+  std::vector<float2> tw(N);
+  const double pi = 3.14159265358979323846;
+  for (int e = 0; e < N; ++e) {
+    const double a = -2.0 * pi * (double)e / (double)N;
+    tw[e] = make_float2((float)std::cos(a), (float)std::sin(a));
+  }
+  float2* d = nullptr;
+  QC_HIP(hipMalloc(&d, N * sizeof(float2)), "hipMalloc(twiddles)");
+  QC_HIP(hipMemcpy(d, tw.data(), N * sizeof(float2), hipMemcpyHostToDevice), "hipMemcpy(twiddles)");
+  g_tw[key] = d;
+  *out = d;
+  return QC_OK;
+}
+
+qc_status check_pfb(const qc_pfb_params* p) {
+  if (!p) return fail(QC_EINVAL, "pfb params is NULL");
+  if (!is_pow2(p->n_fft) || p->n_fft < 4 || p->n_fft > 8192)
+    return fail(QC_EINVAL, "n_fft must be a power of two in [4, 8192] (got %d)", p->n_fft);
+  if (p->n_taps < 1 || p->n_taps > 16)
+    return fail(QC_EINVAL, "n_taps must be in [1, 16] (got %d)", p->n_taps);
+  if (p->keep_nyquist != 0) return fail(QC_EUNSUPPORTED, "keep_nyquist must be 0");
+  if (p->taps && (reinterpret_cast<uintptr_t>(p->taps) & 15u))
+    return fail(QC_EINVAL, "taps must be 16-byte aligned");
+  return QC_OK;
+}
+
+qc_status check_stream_args(const int8_t* x, int64_t ld_x, int32_t n_ant, int64_t n_samp,
+                            const qc_pfb_params* p, const int8_t* hist, const int8_t* hist_out) {
+  qc_status st = check_pfb(p);
+  if (st != QC_OK) return st;
+  if (n_ant < 1 || n_ant > 4096) return fail(QC_EINVAL, "n_ant must be in [1, 4096] (got %d)", n_ant);
+  if (n_samp < 0 || n_samp % p->n_fft)
+    return fail(QC_EINVAL, "n_samp (%lld) must be a non-negative multiple of n_fft (%d)",
+                (long long)n_samp, p->n_fft);
+  if (n_samp > 0 && !x) return fail(QC_EINVAL, "x is NULL");
+  if (ld_x < n_samp || (ld_x & 3)) return fail(QC_EINVAL, "ld_x must be >= n_samp and a multiple of 4");
+  if (reinterpret_cast<uintptr_t>(x) & 3u) return fail(QC_EINVAL, "x must be 4-byte aligned");
+  if (hist && (reinterpret_cast<uintptr_t>(hist) & 3u)) return fail(QC_EINVAL, "hist must be 4-byte aligned");
+  if (hist && hist == hist_out) return fail(QC_EINVAL, "hist_out may not alias hist");
+  return QC_OK;
+}
+
+struct Resolved {
+  qc::FxArgs args;
+  double sum_h2;
+};
+
+qc_status resolve(const int8_t* x, int64_t ld_x, int32_t n_ant, int64_t n_samp,
+                  const qc_pfb_params* p, const int8_t* hist, Resolved* r) {
+  float2* tw = nullptr;
+  qc_status st = get_twiddles(p->n_fft, &tw);
+  if (st != QC_OK) return st;
+  const float* taps = p->taps;
+  double s2 = 0.0;
+  if (!taps) {
+    TapsEntry e;
+    st = get_taps(p->n_fft, p->n_taps, &e);
+    if (st != QC_OK) return st;
+    taps = e.dev;
+    s2 = e.sum_h2;
+  }
+  r->args = qc::FxArgs{x, ld_x, n_ant, n_samp, p->n_fft, p->n_taps, taps, tw, hist};
+  r->sum_h2 = s2;
+  return QC_OK;
+}
+
+// sum of squares of user taps (float64), read back from the device
+qc_status user_sum_h2(const float* taps, int L, double* out) {
+  std::vector<float> h(L);
+  QC_HIP(hipMemcpy(h.data(), taps, L * sizeof(float), hipMemcpyDeviceToHost), "hipMemcpy(user taps)");
+  double s = 0.0;
+  for (float v : h) s += (double)v * (double)v;
+  *out = s;
+  return QC_OK;
+}
+
+double prec_target(int prec) {
+  return prec == QC_F16 ? 256.0 : prec == QC_BF16 ? 1.0 : 32.0;
+}
+
+size_t prec_pair_bytes(int prec) {
+  return prec == QC_F32 ? 8 : prec == QC_FP8_E4M3 ? 2 : 4;
+}
+
+// Stream-ordered scratch allocation released at scope end (also stream-ordered).
+struct AsyncBuf {
+  void* p = nullptr;
+  hipStream_t s = nullptr;
+  ~AsyncBuf() {
+    if (p) (void)hipFreeAsync(p, s);
+  }
+};
+
+qc_status alloc_async(AsyncBuf& b, size_t bytes, hipStream_t s) {
+  b.s = s;
+  if (bytes == 0) bytes = 16;
+  hipError_t e = hipMallocAsync(&b.p, bytes, s);
+  if (e != hipSuccess) return fail(QC_ENOMEM, "hipMallocAsync(%zu): %s", bytes, hipGetErrorString(e));
+  return QC_OK;
+}
+
+qc_status channelize_impl(const Resolved& r, qc_prec out_prec, void* out, float* scale_out,
+                          hipStream_t s) {
+  const qc::FxArgs& a = r.args;
+  if (out_prec != QC_F32) {
+    double s2 = r.sum_h2;
+    if (a.taps != nullptr && s2 == 0.0) {
+      qc_status st = user_sum_h2(a.taps, a.n_fft * a.n_taps, &s2);
+      if (st != QC_OK) return st;
+    }
+    const int64_t n_use = a.n_samp < (1 << 20) ? a.n_samp : (1 << 20);
+    if (n_use > 0)
+      QC_HIP(qc::launch_scales(a.x, a.ld_x, a.n_ant, n_use, s2, prec_target(out_prec), scale_out, s),
+             "scales kernel");
+  }
+  if (a.n_samp > 0) QC_HIP(qc::launch_channelize(a, (int)out_prec, out, scale_out, s), "channelize kernel");
+  return QC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* qc_status_string(qc_status s) {
+  switch (s) {
+    case QC_OK: return "QC_OK";
+    case QC_EINVAL: return "QC_EINVAL";
+    case QC_EUNSUPPORTED: return "QC_EUNSUPPORTED";
+    case QC_EHIP: return "QC_EHIP";
+    case QC_ENOMEM: return "QC_ENOMEM";
+    case QC_ESTATE: return "QC_ESTATE";
+  }
+  return "QC_UNKNOWN";
+}
+
+const char* qc_last_error(void) { return g_err.c_str(); }
+
+const char* qc_version(void) { return "qc 0.1.0 (gfx950)"; }
+
+qc_status qc_pfb_channelize(const int8_t* x, int64_t ld_x, int32_t n_ant, int64_t n_samp,
+                            const qc_pfb_params* p, const int8_t* hist, int8_t* hist_out,
+                            qc_prec out_prec, void* out, float* scale_out, void* stream) {
+  g_err.clear();
+  qc_status st = check_stream_args(x, ld_x, n_ant, n_samp, p, hist, hist_out);
+  if (st != QC_OK) return st;
+  if (out_prec < QC_F32 || out_prec > QC_FP8_E4M3) return fail(QC_EINVAL, "bad out_prec %d", (int)out_prec);
+  if (n_samp > 0 && !out) return fail(QC_EINVAL, "out is NULL");
+  if (out_prec != QC_F32 && !scale_out) return fail(QC_EINVAL, "scale_out is NULL for reduced precision");
+  if (reinterpret_cast<uintptr_t>(out) % prec_pair_bytes(out_prec))
+    return fail(QC_EINVAL, "out is misaligned for its precision");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  Resolved r;
+  st = resolve(x, ld_x, n_ant, n_samp, p, hist, &r);
+  if (st != QC_OK) return st;
+  st = channelize_impl(r, out_prec, out, scale_out, s);
+  if (st != QC_OK) return st;
+  if (hist_out && p->n_taps > 1)
+    QC_HIP(qc::launch_hist_copy(x, ld_x, n_ant, n_samp, hist, (int64_t)(p->n_taps - 1) * p->n_fft,
+                                hist_out, s),
+           "history copy");
+  return QC_OK;
+}
+
+qc_status qc_xcorrelate(const int8_t* x, int64_t ld_x, int32_t n_ant, int64_t n_samp,
+                        const qc_pfb_params* p, const int8_t* hist, int8_t* hist_out,
+                        int64_t spec_per_dump, qc_prec x_prec, float* vis, int32_t accumulate,
+                        int64_t* n_dumps_out, void* stream) {
+  g_err.clear();
+  qc_status st = check_stream_args(x, ld_x, n_ant, n_samp, p, hist, hist_out);
+  if (st != QC_OK) return st;
+  if (spec_per_dump < 1) return fail(QC_EINVAL, "spec_per_dump must be >= 1");
+  if (x_prec < QC_F32 || x_prec > QC_FP8_E4M3) return fail(QC_EINVAL, "bad x_prec %d", (int)x_prec);
+  const int N = p->n_fft;
+  const int64_t n_spec = n_samp / N;
+  const int64_t n_dump = n_spec / spec_per_dump;
+  if (n_dump > 0 && !vis) return fail(QC_EINVAL, "vis is NULL");
+  if (reinterpret_cast<uintptr_t>(vis) & 7u) return fail(QC_EINVAL, "vis must be 8-byte aligned");
+  if (n_dumps_out) *n_dumps_out = n_dump;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int nch = N / 2;
+  const int64_t nb = (int64_t)n_ant * (n_ant + 1) / 2;
+  if (n_dump > 0) {
+    Resolved r;
+    st = resolve(x, ld_x, n_ant, n_samp, p, hist, &r);
+    if (st != QC_OK) return st;
+    // only the spectra of full dumps are transformed
+    r.args.n_samp = n_dump * spec_per_dump * N;
+    if (x_prec == QC_F32 && qc::fused_supported(N, n_ant)) {
+      const int64_t cpd = qc::fused_chunks_per_dump(N, n_ant, n_dump, spec_per_dump);
+      AsyncBuf part;
+      st = alloc_async(part, (size_t)(n_dump * cpd) * nb * nch * sizeof(float2), s);
+      if (st != QC_OK) return st;
+      QC_HIP(qc::launch_fused(r.args, n_dump, spec_per_dump, cpd, (float2*)part.p, s), "fused F+X kernel");
+      QC_HIP(qc::launch_reduce((const float2*)part.p, n_dump, cpd, nb * nch, 0.25f, accumulate,
+                               reinterpret_cast<float2*>(vis), s),
+             "reduce kernel");
+    } else {
+      // two passes: F-engine to HBM, then the X-engine
+      const int64_t ns = n_dump * spec_per_dump;
+      AsyncBuf v, scale;
+      st = alloc_async(v, (size_t)n_ant * ns * nch * prec_pair_bytes(x_prec), s);
+      if (st != QC_OK) return st;
+      st = alloc_async(scale, (size_t)n_ant * sizeof(float), s);
+      if (st != QC_OK) return st;
+      st = channelize_impl(r, x_prec, v.p, (float*)scale.p, s);
+      if (st != QC_OK) return st;
+      st = qc_xcorrelate_chan(v.p, x_prec, (const float*)scale.p, n_ant, ns, nch, spec_per_dump,
+                              vis, accumulate, stream);
+      if (st != QC_OK) return st;
+    }
+  }
+  if (hist_out && p->n_taps > 1)
+    QC_HIP(qc::launch_hist_copy(x, ld_x, n_ant, n_samp, hist, (int64_t)(p->n_taps - 1) * N, hist_out, s),
+           "history copy");
+  return QC_OK;
+}
+
+qc_status qc_xcorrelate_chan(const void* v, qc_prec prec, const float* scale, int32_t n_ant,
+                             int64_t n_spec, int32_t n_chan, int64_t spec_per_dump, float* vis,
+                             int32_t accumulate, void* stream) {
+  g_err.clear();
+  if (prec < QC_F32 || prec > QC_FP8_E4M3) return fail(QC_EINVAL, "bad prec %d", (int)prec);
+  if (n_ant < 1 || n_ant > 4096) return fail(QC_EINVAL, "n_ant must be in [1, 4096]");
+  if (n_chan < 1 || n_spec < 0 || spec_per_dump < 1) return fail(QC_EINVAL, "bad sizes");
+  const int64_t n_dump = n_spec / spec_per_dump;
+  if (n_dump == 0) return QC_OK;
+  if (!v || !vis) return fail(QC_EINVAL, "v or vis is NULL");
+  if (prec != QC_F32 && !scale) return fail(QC_EINVAL, "scale is NULL for reduced precision");
+  if (reinterpret_cast<uintptr_t>(v) % prec_pair_bytes(prec)) return fail(QC_EINVAL, "v misaligned");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int64_t nb = (int64_t)n_ant * (n_ant + 1) / 2;
+  if (prec == QC_F32) {
+    const int64_t ks = qc::xeng_f32_ksplit(n_ant, spec_per_dump, n_chan, n_dump);
+    AsyncBuf part;
+    qc_status st = alloc_async(part, (size_t)(n_dump * ks) * nb * n_chan * sizeof(float2), s);
+    if (st != QC_OK) return st;
+    QC_HIP(qc::launch_xeng_f32((const float2*)v, n_ant, n_spec, n_chan, spec_per_dump, n_dump, ks,
+                               (float2*)part.p, s),
+           "X-engine f32 kernel");
+    QC_HIP(qc::launch_reduce((const float2*)part.p, n_dump, ks, nb * n_chan, 1.0f, accumulate,
+                             reinterpret_cast<float2*>(vis), s),
+           "reduce kernel");
+    return QC_OK;
+  }
+  const int64_t ks = qc::xeng_mfma_ksplit(n_ant, spec_per_dump, n_chan, n_dump);
+  if (ks <= 0)
+    return fail(QC_EUNSUPPORTED, "matrix-core X-engine needs n_ant <= 32 and n_chan %% 32 == 0");
+  if (reinterpret_cast<uintptr_t>(v) & 15u) return fail(QC_EINVAL, "v must be 16-byte aligned");
+  AsyncBuf part;
+  qc_status st = alloc_async(part, (size_t)(n_dump * ks) * nb * n_chan * sizeof(float2), s);
+  if (st != QC_OK) return st;
+  QC_HIP(qc::launch_xeng_mfma(v, (int)prec, scale, n_ant, n_spec, n_chan, spec_per_dump, n_dump, ks,
+                              (float2*)part.p, s),
+         "X-engine matrix-core kernel");
+  QC_HIP(qc::launch_reduce((const float2*)part.p, n_dump, ks, nb * n_chan, 1.0f, accumulate,
+                           reinterpret_cast<float2*>(vis), s),
+         "reduce kernel");
+  return QC_OK;
+}
+
+qc_status qc_mad_flag(const float* vis, int64_t n_time, int64_t n_base, int32_t n_chan, float sigma,
+                      int32_t population, uint8_t* mask, double* thresh_out, void* stream) {
+  g_err.clear();
+  if (population < 0 || population > 2) return fail(QC_EINVAL, "population must be 0, 1 or 2");
+  if (n_time < 1 || n_base < 1 || n_chan < 1) return fail(QC_EINVAL, "sizes must be >= 1");
+  if (!(sigma >= 0.0f) || !std::isfinite(sigma)) return fail(QC_EINVAL, "sigma must be finite and >= 0");
+  if (!vis || !mask) return fail(QC_EINVAL, "vis or mask is NULL");
+  if (reinterpret_cast<uintptr_t>(vis) & 7u) return fail(QC_EINVAL, "vis must be 8-byte aligned");
+  const int64_t npop = population == 0 ? n_base : population == 1 ? n_base * n_chan : n_time * n_base;
+  if (npop > 0x7fffffffLL) return fail(QC_EINVAL, "too many populations");
+  QC_HIP(qc::launch_mad(reinterpret_cast<const float2*>(vis), n_time, n_base, n_chan, sigma, population,
+                        mask, thresh_out, reinterpret_cast<hipStream_t>(stream)),
+         "MAD kernel");
+  return QC_OK;
+}
+
+qc_status qc_apply_delay_phase(float* vis, int64_t n_time, int32_t n_ant, int32_t n_chan, double f0_hz,
+                               double df_hz, const double* tau_s, const double* phi_rad, void* stream) {
+  g_err.clear();
+  if (n_ant < 1 || n_ant > 64) return fail(QC_EINVAL, "n_ant must be in [1, 64]");
+  if (n_time < 0 || n_time > 65535 || n_chan < 1) return fail(QC_EINVAL, "bad n_time/n_chan");
+  if (!tau_s || !phi_rad) return fail(QC_EINVAL, "tau_s or phi_rad is NULL");
+  if (!std::isfinite(f0_hz) || !std::isfinite(df_hz)) return fail(QC_EINVAL, "f0/df must be finite");
+  for (int a = 0; a < n_ant; ++a)
+    if (!std::isfinite(tau_s[a]) || !std::isfinite(phi_rad[a]))
+      return fail(QC_EINVAL, "tau/phi must be finite");
+  if (n_time == 0) return QC_OK;
+  if (!vis) return fail(QC_EINVAL, "vis is NULL");
+  if (reinterpret_cast<uintptr_t>(vis) & 7u) return fail(QC_EINVAL, "vis must be 8-byte aligned");
+  QC_HIP(qc::launch_apply(reinterpret_cast<float2*>(vis), n_time, n_ant, n_chan, f0_hz, df_hz, tau_s,
+                          phi_rad, reinterpret_cast<hipStream_t>(stream)),
+         "apply kernel");
+  return QC_OK;
+}
+
+}  // extern "C"

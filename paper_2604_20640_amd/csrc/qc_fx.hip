@@ -1,0 +1,583 @@
+// F-engine and X-engine kernels for gfx950.
+//
+// Method (arXiv 2604.20640): Sec. 4.1 steps 1 and 3 with eq. (1); Sec. 4.2
+// "F-engine (PFB and FFT)" and "X-engine and integration"; Alg. 1 F-Engine,
+// X-Engine and Integration steps.
+//
+// F-engine: y_m[n] = sum_p h[pN+n] x[(m-P+1+p)N + n] (polyphase FIR), then an
+// N-point real DFT.  Two antennas a, b share one complex transform:
+// z = y_a + i y_b, Z = FFT(z), and
+//   Y_a[k] = (Z[k] + conj Z[N-k]) / 2,  Y_b[k] = (Z[k] - conj Z[N-k]) / (2i).
+// The factor 1/2 is applied as an exact power-of-two scale at the end.
+//
+// X-engine: V_ij[k] += Y_i[k] conj(Y_j[k]) for i <= j; autos keep an exactly
+// zero imaginary part.  Integration is a plain sum over a dump's spectra.
+// Each workgroup accumulates a contiguous run of spectra in registers and
+// writes one partial; partials are summed in a fixed order (deterministic,
+// no floating-point atomics).
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+#include "qc_fft.h"
+#include "qc_kernels.h"
+
+namespace qc {
+
+// ---------------------------------------------------------------------------
+// int8 block loads (4 consecutive samples as one dword)
+// ---------------------------------------------------------------------------
+// Stream block `blk` of antenna `a`, samples n0..n0+3.  Blocks before the
+// stream come from `hist` ((P-1) blocks per antenna) or are zero.
+__device__ __forceinline__ uint32_t load_x4(const int8_t* __restrict__ x, int64_t ld_x,
+                                            const int8_t* __restrict__ hist, int a, int64_t blk,
+                                            int n0, int N, int P) {
+  if (blk >= 0) {
+    return *reinterpret_cast<const uint32_t*>(x + (int64_t)a * ld_x + blk * N + n0);
+  }
+  if (hist == nullptr) return 0u;
+  const int64_t hb = blk + (P - 1);  // 0 .. P-2
+  return *reinterpret_cast<const uint32_t*>(hist + ((int64_t)a * (P - 1) + hb) * N + n0);
+}
+
+__device__ __forceinline__ float sbyte(uint32_t w, int i) {
+  return (float)(int8_t)((w >> (8 * i)) & 0xffu);
+}
+
+// FIR for 4 consecutive samples n0..n0+3 of spectrum m, antennas a0 (real
+// part) and a1 (imaginary part; a1 < 0 means none).
+__device__ __forceinline__ void fir4(const int8_t* __restrict__ x, int64_t ld_x,
+                                     const int8_t* __restrict__ hist,
+                                     const float* __restrict__ taps, int a0, int a1, int64_t m,
+                                     int n0, int N, int P, float2 out[4]) {
+  float y0[4] = {0.f, 0.f, 0.f, 0.f}, y1[4] = {0.f, 0.f, 0.f, 0.f};
+  for (int q = 0; q < P; ++q) {
+    const int64_t blk = m - P + 1 + q;
+    const float4 h = *reinterpret_cast<const float4*>(taps + (int64_t)q * N + n0);
+    const uint32_t w0 = load_x4(x, ld_x, hist, a0, blk, n0, N, P);
+    y0[0] += h.x * sbyte(w0, 0);
+    y0[1] += h.y * sbyte(w0, 1);
+    y0[2] += h.z * sbyte(w0, 2);
+    y0[3] += h.w * sbyte(w0, 3);
+    if (a1 >= 0) {
+      const uint32_t w1 = load_x4(x, ld_x, hist, a1, blk, n0, N, P);
+      y1[0] += h.x * sbyte(w1, 0);
+      y1[1] += h.y * sbyte(w1, 1);
+      y1[2] += h.z * sbyte(w1, 2);
+      y1[3] += h.w * sbyte(w1, 3);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) out[i] = make_float2(y0[i], y1[i]);
+}
+
+// Separate one packed transform into its two real-input spectra (times 2).
+__device__ __forceinline__ void separate(float2 zk, float2 zn, float2& ya, float2& yb) {
+  ya = make_float2(zk.x + zn.x, zk.y - zn.y);
+  yb = make_float2(zk.y + zn.y, zn.x - zk.x);
+}
+
+// ---------------------------------------------------------------------------
+// Fused F+X: NA antennas (NP = ceil(NA/2) packed transforms), S spectra in
+// flight, NT = NP*S*N/16 threads.  Grid: n_dump * chunks_per_dump blocks.
+// ---------------------------------------------------------------------------
+template <int N, int NA, int S>
+struct FusedCfg {
+  static constexpr int NP = (NA + 1) / 2;
+  static constexpr int NFFT = NP * S;
+  static constexpr int NT = NFFT * N / 16;
+  static constexpr int NCH = N / 2;
+  static constexpr int NB = NA * (NA + 1) / 2;
+  static constexpr int CPT = (NCH + NT - 1) / NT;
+  static constexpr int LDS = lds_padded_size(NFFT * N);
+};
+
+template <int N, int NA, int S>
+__global__ void __launch_bounds__((FusedCfg<N, NA, S>::NT))
+fx_fused_kernel(const int8_t* __restrict__ x, int64_t ld_x, const int8_t* __restrict__ hist,
+                const float* __restrict__ taps, int P, const float2* __restrict__ tw,
+                int64_t spec_per_dump, int64_t cpd, float2* __restrict__ part) {
+  using C = FusedCfg<N, NA, S>;
+  extern __shared__ float2 buf[];
+  const int tid = threadIdx.x;
+  const int64_t w = blockIdx.x;
+  const int64_t d = w / cpd, c = w % cpd;
+  const int64_t m_lo = d * spec_per_dump + (c * spec_per_dump) / cpd;
+  const int64_t m_hi = d * spec_per_dump + ((c + 1) * spec_per_dump) / cpd;
+
+  float2 acc[C::CPT][C::NB];
+#pragma unroll
+  for (int cc = 0; cc < C::CPT; ++cc)
+#pragma unroll
+    for (int b = 0; b < C::NB; ++b) acc[cc][b] = make_float2(0.f, 0.f);
+
+  for (int64_t m0 = m_lo; m0 < m_hi; m0 += S) {
+    // polyphase FIR into the packed transform inputs
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const int c4 = tid + g * C::NT;
+      const int f = c4 / (N / 4);
+      const int n0 = 4 * (c4 % (N / 4));
+      const int s = f / C::NP, p = f % C::NP;
+      const int64_t m = m0 + s;
+      float2 y[4];
+      if (m < m_hi) {
+        fir4(x, ld_x, hist, taps, 2 * p, (2 * p + 1 < NA) ? 2 * p + 1 : -1, m, n0, N, P, y);
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) y[i] = make_float2(0.f, 0.f);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) buf[lds_pad(f * N + n0 + i)] = y[i];
+    }
+    __syncthreads();
+    fft_lds<N, C::NT>(buf, tw, tid);
+    // separate and cross-multiply
+#pragma unroll
+    for (int cc = 0; cc < C::CPT; ++cc) {
+      const int k = tid + cc * C::NT;
+      if (C::NCH % C::NT == 0 || k < C::NCH) {
+        const int kn = (N - k) & (N - 1);
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+          if (m0 + s < m_hi) {
+            float2 X[2 * C::NP];
+#pragma unroll
+            for (int p = 0; p < C::NP; ++p) {
+              const float2 zk = buf[lds_pad((s * C::NP + p) * N + k)];
+              const float2 zn = buf[lds_pad((s * C::NP + p) * N + kn)];
+              separate(zk, zn, X[2 * p], X[2 * p + 1]);
+            }
+            int b = 0;
+#pragma unroll
+            for (int i = 0; i < NA; ++i) {
+              acc[cc][b].x += X[i].x * X[i].x + X[i].y * X[i].y;
+              ++b;
+#pragma unroll
+              for (int j = i + 1; j < NA; ++j) {
+                acc[cc][b].x += X[i].x * X[j].x + X[i].y * X[j].y;
+                acc[cc][b].y += X[i].y * X[j].x - X[i].x * X[j].y;
+                ++b;
+              }
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  float2* out = part + w * (int64_t)C::NB * C::NCH;
+#pragma unroll
+  for (int cc = 0; cc < C::CPT; ++cc) {
+    const int k = tid + cc * C::NT;
+    if (C::NCH % C::NT == 0 || k < C::NCH) {
+#pragma unroll
+      for (int b = 0; b < C::NB; ++b) out[(int64_t)b * C::NCH + k] = acc[cc][b];
+    }
+  }
+}
+
+template <int N, int NA, int S>
+static hipError_t launch_fused_t(const FxArgs& a, int64_t n_dump, int64_t spd, int64_t cpd,
+                                 float2* part, hipStream_t s) {
+  using C = FusedCfg<N, NA, S>;
+  const size_t lds = sizeof(float2) * C::LDS;
+  auto kern = fx_fused_kernel<N, NA, S>;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3((unsigned)(n_dump * cpd)), dim3(C::NT), lds, s, a.x, a.ld_x,
+                     a.hist, a.taps, a.n_taps, a.tw, spd, cpd, part);
+  return hipGetLastError();
+}
+
+bool fused_supported(int n_fft, int n_ant) {
+  if (n_ant == 4) return n_fft == 1024 || n_fft == 4096 || n_fft == 2048 || n_fft == 512;
+  if (n_ant == 8) return n_fft == 2048 || n_fft == 1024;
+  if (n_ant == 2) return n_fft == 4096 || n_fft == 1024;
+  return false;
+}
+
+int64_t fused_chunks_per_dump(int n_fft, int n_ant, int64_t n_dump, int64_t spd) {
+  // aim for ~2 waves of workgroups over 256 CUs, at least 8 spectra each
+  int64_t want = (512 + n_dump - 1) / n_dump;
+  int64_t maxc = spd / 8 > 0 ? spd / 8 : 1;
+  int64_t c = want < maxc ? want : maxc;
+  return c < 1 ? 1 : c;
+}
+
+hipError_t launch_fused(const FxArgs& a, int64_t n_dump, int64_t spd, int64_t cpd, float2* part,
+                        hipStream_t s) {
+  if (a.n_ant == 4) {
+    switch (a.n_fft) {
+      case 512: return launch_fused_t<512, 4, 4>(a, n_dump, spd, cpd, part, s);
+      case 1024: return launch_fused_t<1024, 4, 2>(a, n_dump, spd, cpd, part, s);
+      case 2048: return launch_fused_t<2048, 4, 1>(a, n_dump, spd, cpd, part, s);
+      case 4096: return launch_fused_t<4096, 4, 1>(a, n_dump, spd, cpd, part, s);
+    }
+  } else if (a.n_ant == 8) {
+    switch (a.n_fft) {
+      case 1024: return launch_fused_t<1024, 8, 1>(a, n_dump, spd, cpd, part, s);
+      case 2048: return launch_fused_t<2048, 8, 1>(a, n_dump, spd, cpd, part, s);
+    }
+  } else if (a.n_ant == 2) {
+    switch (a.n_fft) {
+      case 1024: return launch_fused_t<1024, 2, 4>(a, n_dump, spd, cpd, part, s);
+      case 4096: return launch_fused_t<4096, 2, 1>(a, n_dump, spd, cpd, part, s);
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// Fixed-order reduction of partials.
+// ---------------------------------------------------------------------------
+__global__ void reduce_partials_kernel(const float2* __restrict__ part, int64_t cpd, int64_t elems,
+                                       int64_t bx_per_dump, float scale, int accumulate,
+                                       float2* __restrict__ vis) {
+  const int64_t d = blockIdx.x / bx_per_dump;
+  const int64_t bx = blockIdx.x % bx_per_dump;
+  for (int64_t e = bx * blockDim.x + threadIdx.x; e < elems; e += bx_per_dump * blockDim.x) {
+    float2 sacc = make_float2(0.f, 0.f);
+    const float2* p = part + d * cpd * elems + e;
+    for (int64_t c = 0; c < cpd; ++c) {
+      const float2 v = p[c * elems];
+      sacc.x += v.x;
+      sacc.y += v.y;
+    }
+    sacc.x *= scale;
+    sacc.y *= scale;
+    float2* o = vis + d * elems + e;
+    if (accumulate) {
+      const float2 old = *o;
+      sacc.x += old.x;
+      sacc.y += old.y;
+    }
+    *o = sacc;
+  }
+}
+
+hipError_t launch_reduce(const float2* part, int64_t n_dump, int64_t cpd, int64_t elems,
+                         float scale, int accumulate, float2* vis, hipStream_t s) {
+  if (n_dump <= 0 || elems <= 0) return hipSuccess;
+  int64_t bx = (elems + 255) / 256;
+  if (bx > 4096) bx = 4096;
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)(bx * n_dump)), dim3(256), 0, s, part, cpd,
+                     elems, bx, scale, accumulate, vis);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Requantisation helpers (round to nearest even, saturating).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint16_t enc_f16(float v) {
+  v = fminf(fmaxf(v, -65504.f), 65504.f);
+  return __half_as_ushort(__float2half_rn(v));
+}
+
+__device__ __forceinline__ uint16_t enc_bf16(float v) {
+  uint32_t u = __float_as_uint(v);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// OCP E4M3 ("fn"): bias 7, 3 mantissa bits, max 448, subnormal step 2^-9.
+__device__ __forceinline__ uint8_t enc_e4m3(float v) {
+  const uint32_t sign = (__float_as_uint(v) >> 24) & 0x80u;
+  float a = fminf(fabsf(v), 448.f);
+  uint32_t code;
+  if (a < 0.015625f) {                       // below 2^-6: subnormal grid of 2^-9
+    code = (uint32_t)__builtin_rintf(a * 512.f);  // 0..8 (8 = min normal)
+  } else {
+    uint32_t u = __float_as_uint(a);
+    u += 0x7ffffu + ((u >> 20) & 1u);
+    const int e = (int)(u >> 23) - 127;      // -6 .. 8
+    code = ((uint32_t)(e + 7) << 3) | ((u >> 20) & 7u);
+  }
+  return (uint8_t)(code | sign);
+}
+
+// ---------------------------------------------------------------------------
+// Standalone F-engine: one antenna pair per block, S spectra in flight.
+// ---------------------------------------------------------------------------
+template <int N>
+struct ChanCfg {
+  static constexpr int S = N >= 4096 ? 1 : 4096 / N;
+  static constexpr int NT = S * N / 16;
+  static constexpr int NCH = N / 2;
+  static constexpr int LDS = lds_padded_size(S * N);
+};
+
+template <int N, int PREC>
+__global__ void __launch_bounds__(ChanCfg<N>::NT)
+channelize_kernel(const int8_t* __restrict__ x, int64_t ld_x, int n_ant, int64_t n_spec,
+                  const int8_t* __restrict__ hist, const float* __restrict__ taps, int P,
+                  const float2* __restrict__ tw, int64_t spec_per_blk, const float* __restrict__ scale,
+                  void* __restrict__ out) {
+  using C = ChanCfg<N>;
+  extern __shared__ float2 buf[];
+  const int tid = threadIdx.x;
+  const int p = blockIdx.y;
+  const int a0 = 2 * p, a1 = (2 * p + 1 < n_ant) ? 2 * p + 1 : -1;
+  const int64_t m_lo = (int64_t)blockIdx.x * spec_per_blk;
+  int64_t m_hi = m_lo + spec_per_blk;
+  if (m_hi > n_spec) m_hi = n_spec;
+  float sa = 1.f, sb = 1.f;
+  if (PREC != 0) {
+    sa = scale[a0];
+    sb = a1 >= 0 ? scale[a1] : 1.f;
+  }
+  for (int64_t m0 = m_lo; m0 < m_hi; m0 += C::S) {
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const int c4 = tid + g * C::NT;
+      const int s = c4 / (N / 4);
+      const int n0 = 4 * (c4 % (N / 4));
+      float2 y[4];
+      if (m0 + s < m_hi) {
+        fir4(x, ld_x, hist, taps, a0, a1, m0 + s, n0, N, P, y);
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) y[i] = make_float2(0.f, 0.f);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) buf[lds_pad(s * N + n0 + i)] = y[i];
+    }
+    __syncthreads();
+    fft_lds<N, C::NT>(buf, tw, tid);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int e = tid + i * C::NT;  // over S * NCH
+      const int s = e / C::NCH, k = e % C::NCH;
+      const int64_t m = m0 + s;
+      if (m < m_hi) {
+        const float2 zk = buf[lds_pad(s * N + k)];
+        const float2 zn = buf[lds_pad(s * N + ((N - k) & (N - 1)))];
+        float2 ya, yb;
+        separate(zk, zn, ya, yb);
+        const float ha = 0.5f * sa, hb = 0.5f * sb;
+        const int64_t ia = ((int64_t)a0 * n_spec + m) * C::NCH + k;
+        const int64_t ib = ((int64_t)a1 * n_spec + m) * C::NCH + k;
+        if constexpr (PREC == 0) {
+          float2* o = reinterpret_cast<float2*>(out);
+          o[ia] = make_float2(ya.x * 0.5f, ya.y * 0.5f);
+          if (a1 >= 0) o[ib] = make_float2(yb.x * 0.5f, yb.y * 0.5f);
+        } else if constexpr (PREC == 1 || PREC == 2) {
+          uint32_t* o = reinterpret_cast<uint32_t*>(out);
+          auto enc = [](float v) -> uint32_t {
+            if constexpr (PREC == 1) return enc_f16(v);
+            else return enc_bf16(v);
+          };
+          o[ia] = enc(ya.x * ha) | (enc(ya.y * ha) << 16);
+          if (a1 >= 0) o[ib] = enc(yb.x * hb) | (enc(yb.y * hb) << 16);
+        } else {
+          uint16_t* o = reinterpret_cast<uint16_t*>(out);
+          o[ia] = (uint16_t)(enc_e4m3(ya.x * ha) | ((uint16_t)enc_e4m3(ya.y * ha) << 8));
+          if (a1 >= 0) o[ib] = (uint16_t)(enc_e4m3(yb.x * hb) | ((uint16_t)enc_e4m3(yb.y * hb) << 8));
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <int N>
+static hipError_t launch_chan_t(const FxArgs& a, int prec, void* out, const float* scale,
+                                hipStream_t s) {
+  using C = ChanCfg<N>;
+  const int64_t n_spec = a.n_samp / N;
+  const int n_pair = (a.n_ant + 1) / 2;
+  // spectra per block: a multiple of S giving ~2048 blocks in total
+  int64_t per = (n_spec * n_pair + 2047) / 2048;
+  per = ((per + C::S - 1) / C::S) * C::S;
+  if (per < C::S) per = C::S;
+  const int64_t nbx = (n_spec + per - 1) / per;
+  const size_t lds = sizeof(float2) * C::LDS;
+  const void* k = nullptr;
+  switch (prec) {
+    case 0: k = reinterpret_cast<const void*>(channelize_kernel<N, 0>); break;
+    case 1: k = reinterpret_cast<const void*>(channelize_kernel<N, 1>); break;
+    case 2: k = reinterpret_cast<const void*>(channelize_kernel<N, 2>); break;
+    default: k = reinterpret_cast<const void*>(channelize_kernel<N, 3>); break;
+  }
+  hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  dim3 grid((unsigned)nbx, (unsigned)n_pair);
+#define QC_CHAN_LAUNCH(PR)                                                                       \
+  hipLaunchKernelGGL((channelize_kernel<N, PR>), grid, dim3(C::NT), lds, s, a.x, a.ld_x,         \
+                     a.n_ant, n_spec, a.hist, a.taps, a.n_taps, a.tw, per, scale, out)
+  switch (prec) {
+    case 0: QC_CHAN_LAUNCH(0); break;
+    case 1: QC_CHAN_LAUNCH(1); break;
+    case 2: QC_CHAN_LAUNCH(2); break;
+    default: QC_CHAN_LAUNCH(3); break;
+  }
+#undef QC_CHAN_LAUNCH
+  return hipGetLastError();
+}
+
+hipError_t launch_channelize(const FxArgs& a, int prec, void* out, const float* scale,
+                             hipStream_t s) {
+  switch (a.n_fft) {
+    case 4: return launch_chan_t<4>(a, prec, out, scale, s);
+    case 8: return launch_chan_t<8>(a, prec, out, scale, s);
+    case 16: return launch_chan_t<16>(a, prec, out, scale, s);
+    case 32: return launch_chan_t<32>(a, prec, out, scale, s);
+    case 64: return launch_chan_t<64>(a, prec, out, scale, s);
+    case 128: return launch_chan_t<128>(a, prec, out, scale, s);
+    case 256: return launch_chan_t<256>(a, prec, out, scale, s);
+    case 512: return launch_chan_t<512>(a, prec, out, scale, s);
+    case 1024: return launch_chan_t<1024>(a, prec, out, scale, s);
+    case 2048: return launch_chan_t<2048>(a, prec, out, scale, s);
+    case 4096: return launch_chan_t<4096>(a, prec, out, scale, s);
+    case 8192: return launch_chan_t<8192>(a, prec, out, scale, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// Per-antenna power-of-two scale from the input power.
+// ---------------------------------------------------------------------------
+__global__ void scales_kernel(const int8_t* __restrict__ x, int64_t ld_x, int64_t n_use,
+                              double sum_h2, double target, float* __restrict__ scale_out) {
+  __shared__ unsigned long long red[256];
+  const int a = blockIdx.x;
+  const int8_t* xa = x + (int64_t)a * ld_x;
+  unsigned long long acc = 0;
+  for (int64_t n = threadIdx.x; n < n_use; n += blockDim.x) {
+    const int v = xa[n];
+    acc += (unsigned long long)(v * v);
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double pw = (double)red[0] / (double)n_use;
+    const double rms = sqrt(pw * sum_h2);
+    float sc = 1.f;
+    if (rms > 0.0) {
+      const double e = rint(log2(target / rms));
+      sc = (float)ldexp(1.0, (int)e);
+    }
+    scale_out[a] = sc;
+  }
+}
+
+hipError_t launch_scales(const int8_t* x, int64_t ld_x, int n_ant, int64_t n_use, double sum_h2,
+                         double target, float* scale_out, hipStream_t s) {
+  hipLaunchKernelGGL(scales_kernel, dim3(n_ant), dim3(256), 0, s, x, ld_x, n_use, sum_h2, target,
+                     scale_out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// History for the next chunk: last `keep` samples of (hist ++ x).
+// ---------------------------------------------------------------------------
+__global__ void hist_copy_kernel(const int8_t* __restrict__ x, int64_t ld_x, int64_t n_samp,
+                                 const int8_t* __restrict__ hist, int64_t keep,
+                                 int8_t* __restrict__ hist_out) {
+  const int a = blockIdx.y;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < keep;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    // position in (hist ++ x) coordinates: n = n_samp - keep + i (may be < 0)
+    const int64_t n = n_samp - keep + i;
+    int8_t v;
+    if (n >= 0) v = x[(int64_t)a * ld_x + n];
+    else v = hist ? hist[(int64_t)a * keep + (keep + n)] : (int8_t)0;
+    hist_out[(int64_t)a * keep + i] = v;
+  }
+}
+
+hipError_t launch_hist_copy(const int8_t* x, int64_t ld_x, int n_ant, int64_t n_samp,
+                            const int8_t* hist, int64_t keep, int8_t* hist_out, hipStream_t s) {
+  if (keep <= 0) return hipSuccess;
+  int64_t bx = (keep + 255) / 256;
+  if (bx > 1024) bx = 1024;
+  hipLaunchKernelGGL(hist_copy_kernel, dim3((unsigned)bx, n_ant), dim3(256), 0, s, x, ld_x, n_samp,
+                     hist, keep, hist_out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// X-engine on the vector ALUs (float32), any n_ant.  Thread = one channel and
+// one 4x4 antenna block pair (I <= J); spectra split into `ksplit` runs.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+xeng_f32_kernel(const float2* __restrict__ v, int n_ant, int64_t n_spec, int n_chan,
+                int64_t spec_per_dump, int64_t ksplit, int n_cgrp, float2* __restrict__ part) {
+  const int nblk = (n_ant + 3) / 4;
+  // block pair index -> (I, J), I <= J
+  int bp = blockIdx.y, I = 0;
+  while (bp >= nblk - I) { bp -= nblk - I; ++I; }
+  const int J = I + bp;
+  const int k = (int)(blockIdx.x % n_cgrp) * blockDim.x + threadIdx.x;
+  const int64_t dz = blockIdx.x / n_cgrp;
+  const int64_t d = dz / ksplit, ks = dz % ksplit;
+  const int64_t m_lo = d * spec_per_dump + (ks * spec_per_dump) / ksplit;
+  const int64_t m_hi = d * spec_per_dump + ((ks + 1) * spec_per_dump) / ksplit;
+  if (k >= n_chan) return;
+  float2 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = make_float2(0.f, 0.f);
+  int ai[4], aj[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    ai[i] = 4 * I + i < n_ant ? 4 * I + i : n_ant - 1;
+    aj[i] = 4 * J + i < n_ant ? 4 * J + i : n_ant - 1;
+  }
+  for (int64_t m = m_lo; m < m_hi; ++m) {
+    float2 xi[4], xj[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      xi[i] = v[((int64_t)ai[i] * n_spec + m) * n_chan + k];
+      xj[i] = v[((int64_t)aj[i] * n_spec + m) * n_chan + k];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        acc[i][j].x += xi[i].x * xj[j].x + xi[i].y * xj[j].y;
+        acc[i][j].y += xi[i].y * xj[j].x - xi[i].x * xj[j].y;
+      }
+  }
+  const int nb = n_ant * (n_ant + 1) / 2;
+  float2* out = part + dz * (int64_t)nb * n_chan;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int gi = 4 * I + i, gj = 4 * J + j;
+      if (gi < n_ant && gj < n_ant && gi <= gj) {
+        const int b = gi * n_ant - gi * (gi - 1) / 2 + (gj - gi);
+        float2 r = acc[i][j];
+        if (gi == gj) r.y = 0.f;
+        out[(int64_t)b * n_chan + k] = r;
+      }
+    }
+}
+
+int64_t xeng_f32_ksplit(int n_ant, int64_t spd, int n_chan, int64_t n_dump) {
+  const int nblk = (n_ant + 3) / 4;
+  const int64_t waves = (int64_t)nblk * (nblk + 1) / 2 * ((n_chan + 63) / 64) * n_dump;
+  int64_t ks = (8192 + waves - 1) / waves;
+  const int64_t maxk = spd / 64 > 0 ? spd / 64 : 1;
+  if (ks > maxk) ks = maxk;
+  return ks < 1 ? 1 : ks;
+}
+
+hipError_t launch_xeng_f32(const float2* v, int n_ant, int64_t n_spec, int n_chan, int64_t spd,
+                           int64_t n_dump, int64_t ksplit, float2* part, hipStream_t s) {
+  const int nblk = (n_ant + 3) / 4;
+  const int n_cgrp = (n_chan + 255) / 256;
+  dim3 grid((unsigned)(n_cgrp * n_dump * ksplit), (unsigned)(nblk * (nblk + 1) / 2));
+  hipLaunchKernelGGL(xeng_f32_kernel, grid, dim3(256), 0, s, v, n_ant, n_spec, n_chan, spd,
+                     ksplit, n_cgrp, part);
+  return hipGetLastError();
+}
+
+}  // namespace qc

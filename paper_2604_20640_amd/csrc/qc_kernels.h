@@ -1,0 +1,64 @@
+// Launchers shared between the C-ABI layer and the kernel translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qc {
+
+struct FxArgs {
+  const int8_t* x;
+  int64_t ld_x;
+  int32_t n_ant;
+  int64_t n_samp;
+  int32_t n_fft;
+  int32_t n_taps;
+  const float* taps;   // device [P*N]
+  const float2* tw;    // device [N], exp(-2 pi i e/N)
+  const int8_t* hist;  // device [n_ant][(P-1)N] or null
+};
+
+// Fused F+X for small arrays.  Returns false if no fused kernel exists for
+// (n_fft, n_ant); part must hold fused_part_elems() float2.
+bool fused_supported(int n_fft, int n_ant);
+int64_t fused_chunks_per_dump(int n_fft, int n_ant, int64_t n_dump, int64_t spec_per_dump);
+hipError_t launch_fused(const FxArgs& a, int64_t n_dump, int64_t spec_per_dump,
+                        int64_t chunks_per_dump, float2* part, hipStream_t s);
+
+// Deterministic reduction of per-chunk partials:
+// vis[d][e] = (accumulate ? vis[d][e] : 0) + scale * sum_c part[d*cpd + c][e].
+hipError_t launch_reduce(const float2* part, int64_t n_dump, int64_t cpd, int64_t elems,
+                         float scale, int accumulate, float2* vis, hipStream_t s);
+
+// Standalone F-engine.  out layout [n_ant][n_spec][n_chan]; prec 0..3 as qc_prec.
+hipError_t launch_channelize(const FxArgs& a, int prec, void* out, const float* scale,
+                             hipStream_t s);
+
+// Per-antenna power-of-two scales for requantised output.
+hipError_t launch_scales(const int8_t* x, int64_t ld_x, int n_ant, int64_t n_use, double sum_h2,
+                         double target, float* scale_out, hipStream_t s);
+
+// Copy the last (P-1)N samples of (hist ++ x) to hist_out.
+hipError_t launch_hist_copy(const int8_t* x, int64_t ld_x, int n_ant, int64_t n_samp,
+                            const int8_t* hist, int64_t keep, int8_t* hist_out, hipStream_t s);
+
+// X-engine (vector ALU, float32) over v[n_ant][n_spec][n_chan] cfloat.
+int64_t xeng_f32_ksplit(int n_ant, int64_t spec_per_dump, int n_chan, int64_t n_dump);
+hipError_t launch_xeng_f32(const float2* v, int n_ant, int64_t n_spec, int n_chan,
+                           int64_t spec_per_dump, int64_t n_dump, int64_t ksplit, float2* part,
+                           hipStream_t s);
+
+// X-engine on matrix cores over requantised v (prec 1..3).
+hipError_t launch_xeng_mfma(const void* v, int prec, const float* scale, int n_ant,
+                            int64_t n_spec, int n_chan, int64_t spec_per_dump, int64_t n_dump,
+                            int64_t ksplit, float2* part, hipStream_t s);
+int64_t xeng_mfma_ksplit(int n_ant, int64_t spec_per_dump, int n_chan, int64_t n_dump);
+
+// MAD flagging.
+hipError_t launch_mad(const float2* vis, int64_t n_time, int64_t n_base, int n_chan, float sigma,
+                      int population, uint8_t* mask, double* thresh, hipStream_t s);
+
+// Delay/phase application; tau/phi host arrays of n_ant doubles (n_ant <= 64).
+hipError_t launch_apply(float2* vis, int64_t n_time, int n_ant, int n_chan, double f0, double df,
+                        const double* tau, const double* phi, hipStream_t s);
+
+}  // namespace qc

@@ -1,0 +1,151 @@
+"""GPU parity: F-engine, fused F+X and the two-pass F -> X path against the
+FP64 oracle.  Bar for the FP32 path: max |V - V_ref| / sqrt(V_ii V_jj) <= 1e-5."""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import pfb, xengine
+from tests.util import vis_err
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def _stream(n_ant, n_samp, seed, corr=0.3):
+    spec = synth.array_spec(n_ant, n_samp, seed, corr=corr, max_lag=9)
+    return synth.generate(spec)
+
+
+def _chans(N, n=48, seed=0):
+    nch = N // 2
+    if nch <= 96:
+        return np.arange(nch)
+    rng = np.random.default_rng(seed)
+    pick = set(rng.choice(nch, n, replace=False).tolist()) | {0, 1, nch // 2, nch - 2, nch - 1}
+    return np.array(sorted(pick))
+
+
+def _oracle_vis(x, N, P, spd, hist=None, chans=None):
+    X = pfb.channelize(x, N, P, hist=hist, chans=chans)
+    return xengine.correlate_fast(X, spd)
+
+
+def _gpu_vis(qc, x, N, P, spd, **kw):
+    import torch
+    xd = torch.from_numpy(x).cuda()
+    V = qc.xcorrelate(xd, N, P, spd, **kw)
+    torch.cuda.synchronize()
+    return V.cpu().numpy()
+
+
+# (n_fft, n_ant, n_spec, spec_per_dump): fused shapes (4 and 8 antennas, pairs),
+# and two-pass shapes (odd antenna counts, small and large N); ragged dumps
+# (trailing spectra not a multiple of spec_per_dump) included.
+CASES = [
+    (1024, 4, 37, 12),
+    (1024, 4, 1024, 1024),     # plain-FX shape, full length
+    (4096, 4, 41, 16),
+    (4096, 4, 70, 35),
+    (2048, 4, 30, 10),
+    (512, 4, 66, 33),
+    (1024, 8, 20, 10),
+    (2048, 8, 21, 7),
+    (1024, 2, 23, 23),
+    (4096, 2, 17, 8),
+    (16, 3, 50, 7),
+    (4, 5, 40, 9),
+    (64, 1, 33, 11),
+    (256, 6, 24, 24),
+    (8192, 4, 10, 5),
+    (128, 32, 20, 10),
+]
+
+
+@pytest.mark.parametrize("N,n_ant,n_spec,spd", CASES)
+def test_xcorrelate_matches_oracle(qc, N, n_ant, n_spec, spd):
+    P = 4
+    x = _stream(n_ant, N * n_spec, seed=11 + N + n_ant)
+    chans = _chans(N)
+    V_ref = _oracle_vis(x, N, P, spd, chans=chans)
+    V = _gpu_vis(qc, x, N, P, spd)
+    assert V.shape == (n_spec // spd, n_ant * (n_ant + 1) // 2, N // 2)
+    V = V[:, :, chans]
+    err = vis_err(V, V_ref, n_ant)
+    assert err <= TOL, err
+    # autos: exactly real, non-negative
+    for a in range(n_ant):
+        b = a * n_ant - a * (a - 1) // 2
+        assert np.all(V[:, b].imag == 0) and np.all(V[:, b].real >= 0)
+
+
+@pytest.mark.parametrize("N,n_ant,P", [(1024, 4, 4), (64, 3, 2), (4096, 2, 8), (16, 4, 1)])
+def test_channelize_f32_matches_oracle(qc, N, n_ant, P):
+    import torch
+    n_spec = 19
+    x = _stream(n_ant, N * n_spec, seed=5 + N)
+    chans = _chans(N)
+    X_ref = pfb.channelize(x, N, P, chans=chans)
+    out, _ = qc.pfb_channelize(torch.from_numpy(x).cuda(), N, P)
+    X = out.cpu().numpy()[:, :, chans]
+    rms = np.sqrt(np.mean(np.abs(X_ref) ** 2))
+    assert np.max(np.abs(X - X_ref)) / rms <= TOL
+
+
+def test_user_taps(qc):
+    import torch
+    N, P, n_ant = 256, 3, 4
+    x = _stream(n_ant, N * 20, seed=3)
+    taps = np.random.default_rng(1).normal(size=N * P).astype(np.float32)
+    V_ref = xengine.correlate_fast(pfb.channelize(x, N, P, taps=taps.astype(np.float64)), 20)
+    V = _gpu_vis(qc, x, N, P, 20, taps=torch.from_numpy(taps).cuda())
+    assert vis_err(V, V_ref, n_ant) <= TOL
+
+
+@pytest.mark.parametrize("N,n_ant", [(1024, 4), (4096, 4), (64, 3)])
+def test_history_carry_equals_one_shot(qc, N, n_ant):
+    import torch
+    P, spd = 4, 8
+    x = _stream(n_ant, N * 48, seed=21)
+    cut = N * 24
+    xd = torch.from_numpy(x).cuda()
+    hist = torch.zeros((n_ant, (P - 1) * N), dtype=torch.int8, device="cuda")
+    v1 = qc.xcorrelate(xd[:, :cut].contiguous(), N, P, spd, hist_out=hist)
+    v2 = qc.xcorrelate(xd[:, cut:].contiguous(), N, P, spd, hist=hist)
+    one = qc.xcorrelate(xd, N, P, spd)
+    both = torch.cat([v1, v2]).cpu().numpy()
+    # identical arithmetic: same spectra, same partial grouping per dump
+    assert vis_err(both, one.cpu().numpy(), n_ant) <= 1e-6
+    V_ref = _oracle_vis(x, N, P, spd, chans=_chans(N))
+    assert vis_err(both[:, :, _chans(N)], V_ref, n_ant) <= TOL
+    # the history output is exactly the last (P-1)N input samples
+    assert np.array_equal(hist.cpu().numpy(), x[:, cut - (P - 1) * N:cut])
+
+
+def test_accumulate_and_determinism(qc):
+    import torch
+    N, n_ant = 1024, 4
+    x = torch.from_numpy(_stream(n_ant, N * 64, seed=7)).cuda()
+    a = qc.xcorrelate(x, N, 4, 32)
+    b = qc.xcorrelate(x, N, 4, 32)
+    assert torch.equal(a, b)                           # bitwise deterministic
+    c = qc.xcorrelate(x, N, 4, 32, vis=b.clone(), accumulate=True)
+    assert torch.allclose(c, 2 * a, rtol=1e-6, atol=0)
+
+
+def test_zero_input_gives_zero(qc):
+    import torch
+    x = torch.zeros((4, 4096 * 8), dtype=torch.int8, device="cuda")
+    V = qc.xcorrelate(x, 4096, 4, 8)
+    assert torch.count_nonzero(V) == 0
+
+
+def test_extreme_values(qc):
+    """Full-scale +-128/127 input: no overflow, still within tolerance."""
+    N, n_ant = 1024, 4
+    rng = np.random.default_rng(9)
+    x = rng.choice(np.array([-128, 127], np.int8), size=(n_ant, N * 16))
+    V_ref = _oracle_vis(x, N, 4, 16)
+    V = _gpu_vis(qc, x, N, 4, 16)
+    assert vis_err(V, V_ref, n_ant) <= TOL
