@@ -1,0 +1,264 @@
+#!/usr/bin/env python3
+"""Benchmark of the FX-correlator hot path on one MI355X.
+
+Workload (real-time-shaped stream): 4 antennas x 2^28 int8 samples (1 GiB,
+resident in HBM before timing), 4-tap x 4096-point PFB (2048 channels),
+4096 spectra per dump (16 dumps), 20 narrowband lines and 5% broadband
+bursts.  One step = fused F+X (+ fixed-order partial reduction) -> MAD
+flagging (5 sigma, per baseline) -> per-antenna delay/phase application.
+
+Prints one JSON line: input GB/s (10^9 B/s) with a roofline record of the
+dominant kernel (fused F+X, timed by HIP events around its own launches on
+its own stream), the 32-antenna X-engine comparison (FP32 vector ALUs vs
+FP16/BF16/E4M3 matrix cores, with visibility errors against the FP64
+oracle), and the FP64 oracle timed on the host cores on a bounded sample.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+
+PEAK_HBM_GBS = 8000.0          # MI355X HBM3E, GB/s
+PEAK_FP32_TFLOPS = 157.3       # MI355X FP32 vector (published)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-precision", action="store_true", help="skip the 32-antenna section")
+    ap.add_argument("--traffic", type=str, default=None,
+                    help="JSON file with measured HBM bytes per fused launch")
+    return ap.parse_args()
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def fx_flops(n_ant, n_samp, n_fft, n_taps, n_spec_used):
+    """Algorithmic flops: FIR 2P and real FFT 2.5 log2 N per sample, X 8 per
+    baseline (autos included) per channel per spectrum."""
+    nb = n_ant * (n_ant + 1) // 2
+    f = n_ant * n_spec_used * n_fft * (2 * n_taps + 2.5 * math.log2(n_fft))
+    x = 8.0 * nb * (n_fft // 2) * n_spec_used
+    return f + x
+
+
+def timed(torch, fn, reps):
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    s.record()
+    for _ in range(reps):
+        fn()
+    e.record()
+    torch.cuda.synchronize()
+    return s.elapsed_time(e) / reps
+
+
+def oracle_vis_subset(x, N, P, spd, chans, dumps, block=256):
+    """FP64 oracle visibilities for the given dumps and channels, evaluated
+    in blocks of spectra (history taken from the stream itself)."""
+    from oracle import pfb, xengine
+    n_ant = x.shape[0]
+    out = []
+    for d in dumps:
+        acc = None
+        for m0 in range(d * spd, (d + 1) * spd, block):
+            m1 = min(m0 + block, (d + 1) * spd)
+            lo = m0 * N
+            hist = None
+            if m0 > 0:
+                hist = np.zeros((n_ant, (P - 1) * N), np.int64)
+                h0 = max(0, lo - (P - 1) * N)
+                hist[:, (P - 1) * N - (lo - h0):] = x[:, h0:lo]
+            X = pfb.channelize(x[:, lo:m1 * N], N, P, hist=hist, chans=chans)
+            V = xengine.correlate_fast(X, m1 - m0)[0]
+            acc = V if acc is None else acc + V
+        out.append(acc)
+    return np.stack(out)
+
+
+def precision_section(torch, qc, steps):
+    """32 antennas x 2^24 samples, N=4096: FP32 two-pass vs matrix cores."""
+    from tests.util import vis_err as vis_err_local
+    n_ant, N, P = 32, 4096, 4
+    S = 1 << 24
+    spd = S // N
+    t0 = time.time()
+    x = synth.generate(synth.array_spec(n_ant, S, 3000))
+    log(f"[bench] 32-antenna stream generated in {time.time() - t0:.1f}s")
+    xd = torch.from_numpy(x).cuda()
+    res = {"workload": "precision_32ant_n4096", "n_ant": n_ant, "n_samp": S, "n_fft": N,
+           "spec_per_dump": spd}
+    rng = np.random.default_rng(3)
+    chans = np.sort(rng.choice(N // 2, 8, replace=False))
+    t0 = time.time()
+    V_ref = oracle_vis_subset(x, N, P, spd, chans, [0], block=128)
+    log(f"[bench] 32-antenna oracle subset in {time.time() - t0:.1f}s")
+    reps = max(3, steps // 10)
+    for prec in ["f32", "f16", "bf16", "fp8"]:
+        vis = torch.empty((1, n_ant * (n_ant + 1) // 2, N // 2), dtype=torch.complex64, device="cuda")
+        fn = lambda: qc.xcorrelate(xd, N, P, spd, vis=vis, x_prec=prec)  # noqa: E731
+        fn()
+        qc.timing_enable(True)
+        ms = timed(torch, fn, reps)
+        qc.timing_enable(False)
+        k_ch, n_ch = qc.timing_read("channelize")
+        kname = "xeng_f32" if prec == "f32" else "xeng_mfma"
+        k_x, n_x = qc.timing_read(kname)
+        V = vis.cpu().numpy()[:, :, chans]
+        err = vis_err_local(V, V_ref, n_ant)
+        res[prec] = {"ms": round(ms, 4), "input_GBps": round(x.nbytes / ms / 1e6, 2),
+                     "f_engine_ms": round(k_ch / max(n_ch, 1), 4),
+                     "x_engine_ms": round(k_x / max(n_x, 1), 4),
+                     "vis_err_vs_fp64": float(f"{err:.3e}")}
+        log(f"[bench] 32-ant {prec}: {ms:.3f} ms, err {err:.2e}")
+    del xd
+    return res
+
+
+def cpu_baseline(x, N, P, spd, sigma, tau, phi, df, gpu_vis, n_dumps=8):
+    """The FP64 oracle on the host cores over a bounded sample: the first
+    n_dumps dumps (64 MiB of input each) on a 64-channel subset, F+X then MAD
+    then apply."""
+    from oracle import calib, mad
+    from tests.util import vis_err as vis_err_local
+    cores = len(os.sched_getaffinity(0))
+    rng = np.random.default_rng(0)
+    chans = np.sort(rng.choice(N // 2, 64, replace=False))
+    xs = x[:, :n_dumps * spd * N]
+    t0 = time.perf_counter()
+    V = oracle_vis_subset(xs, N, P, spd, chans, list(range(n_dumps)), block=512)
+    mk, _ = mad.mad_flag(V.astype(np.complex64), sigma, 0)
+    n_ant = x.shape[0]
+    full = np.zeros((V.shape[0], V.shape[1], N // 2), np.complex128)
+    full[:, :, chans] = V
+    W = calib.apply_delay_phase(full, n_ant, 0.0, df, tau, phi)[:, :, chans]
+    dt = time.perf_counter() - t0
+    err = vis_err_local(gpu_vis[:n_dumps][:, :, chans], V, n_ant)
+    return {"value": round(xs.nbytes / dt / 1e9, 5), "unit": "GB/s", "cores": cores, "kind": "oracle",
+            "sample": f"first {n_dumps} dumps (4 ant x {n_dumps * spd * N} samples = {xs.nbytes >> 20} MiB), "
+                      f"{len(chans)} of {N // 2} channels, F+X + MAD + apply, float64",
+            "seconds": round(dt, 2), "gpu_vs_oracle_err_on_sample": float(f"{err:.3e}")}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+    import paper_2604_20640_amd as qc
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    qc.lib()
+
+    N, P, spd, sigma = 4096, 4, 4096, 5.0
+    S = 1 << 28
+    t0 = time.time()
+    spec, params = synth.realtime_spec(S, 2000)
+    x = synth.generate(spec)
+    log(f"[bench] real-time stream generated in {time.time() - t0:.1f}s ({x.nbytes >> 20} MiB)")
+    n_ant = x.shape[0]
+    nb = n_ant * (n_ant + 1) // 2
+    xd = torch.from_numpy(x).cuda()
+    n_spec = S // N
+    n_dump = n_spec // spd
+    vis = torch.empty((n_dump, nb, N // 2), dtype=torch.complex64, device="cuda")
+    mask = torch.empty(vis.shape, dtype=torch.uint8, device="cuda")
+    thr = torch.empty(nb, dtype=torch.float64, device="cuda")
+    fs = params["fs_hz"]
+    df = fs / N
+    tau, phi = params["tau_s"], params["phi_rad"]
+
+    def step():
+        qc.xcorrelate(xd, N, P, spd, vis=vis)
+        qc.mad_flag(vis, sigma, 0, mask=mask, thresh=thr)
+        qc.apply_delay_phase(vis, n_ant, 0.0, df, tau, phi)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    qc.timing_enable(True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter()
+    ev0.record()
+    for _ in range(args.steps):
+        step()
+    ev1.record()
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall
+    qc.timing_enable(False)
+    total_ms = ev0.elapsed_time(ev1)
+    ms_step = total_ms / args.steps
+    value = x.nbytes / (ms_step * 1e-3) / 1e9
+    kt = {k: qc.timing_read(k) for k in ("fx_fused", "reduce", "mad", "apply")}
+    fx_ms = kt["fx_fused"][0] / max(kt["fx_fused"][1], 1)
+    flops = fx_flops(n_ant, S, N, P, n_dump * spd)
+    achieved = flops / (fx_ms * 1e-3) / 1e12
+    traffic = None
+    if args.traffic and os.path.exists(args.traffic):
+        traffic = json.load(open(args.traffic)).get("hbm_bytes_per_launch")
+    log(f"[bench] step {ms_step:.3f} ms, {value:.1f} GB/s; fused F+X {fx_ms:.3f} ms")
+
+    # parity of this very run on a sample (oracle: first dump, 64 channels)
+    vis_check = torch.empty_like(vis)
+    qc.xcorrelate(xd, N, P, spd, vis=vis_check)
+    gpu_vis = vis_check.cpu().numpy()
+
+    out = {
+        "metric": "F+X input GB/s @4 and 32 antennas; MFMA vs FP32 X-engine at stated vis error",
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "realtime_4ant_n4096", "n_ant": n_ant, "n_samp_per_ant": S,
+                   "input_bytes": x.nbytes, "n_fft": N, "n_taps": P, "n_chan": N // 2,
+                   "spec_per_dump": spd, "n_dump": n_dump, "mad_sigma": sigma,
+                   "mad_population": "per baseline", "rfi_lines": len(params["line_chans"]),
+                   "burst_fraction": 0.05, "parallelism": "single GPU"},
+        "roofline": {"kernel": "fx_fused", "bound": "alu", "achieved": round(achieved, 2),
+                     "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                     "traffic": traffic,
+                     "launch_ms": round(fx_ms, 4),
+                     "algorithmic_flop_per_launch": flops,
+                     "hbm_frac_of_input_read": round(x.nbytes / (fx_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)},
+        "stages_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in kt.items()},
+        "wall_s_timed_region": round(t_wall, 4),
+    }
+    if not args.no_precision:
+        del vis_check
+        out["precision_32ant"] = precision_section(torch, qc, args.steps)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(x, N, P, spd, sigma, tau, phi, df, gpu_vis)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -148,6 +148,26 @@ qc_status qc_apply_delay_phase(float* vis, int64_t n_time, int32_t n_ant, int32_
                                double f0_hz, double df_hz, const double* tau_s,
                                const double* phi_rad, void* stream);
 
+/* Kernel timing for measurement harnesses.  While enabled, every launch of
+ * the kernels below is bracketed by HIP events recorded on the stream the
+ * kernel is launched on (so the figure is the kernel's own duration, on its
+ * own stream).  qc_timing_enable(1) starts a fresh record and qc_timing_enable(0)
+ * stops recording; qc_timing_read synchronises on the recorded events and
+ * returns the summed duration in milliseconds and the launch count.
+ * Not thread-safe with respect to concurrent enable/read. */
+enum {
+  QC_KERNEL_FX_FUSED = 0,   /* fused F+X (int8 -> per-chunk partial visibilities) */
+  QC_KERNEL_CHANNELIZE = 1, /* standalone F-engine */
+  QC_KERNEL_XENG_F32 = 2,   /* X-engine, vector ALUs */
+  QC_KERNEL_XENG_MFMA = 3,  /* X-engine, matrix cores */
+  QC_KERNEL_REDUCE = 4,     /* fixed-order partial reduction */
+  QC_KERNEL_MAD = 5,        /* MAD flagging */
+  QC_KERNEL_APPLY = 6,      /* delay/phase application */
+  QC_KERNEL_COUNT = 7
+};
+qc_status qc_timing_enable(int32_t on);
+qc_status qc_timing_read(int32_t kernel, double* total_ms, int64_t* launches);
+
 /* Human-readable name of a status code (static storage). */
 const char* qc_status_string(qc_status s);
 /* Thread-local detail of the last failure in this thread ("" if none). */

@@ -15,7 +15,7 @@ import torch
 
 __all__ = [
     "QCError", "lib", "pfb_channelize", "xcorrelate", "xcorrelate_chan", "mad_flag",
-    "apply_delay_phase", "n_base", "PREC",
+    "apply_delay_phase", "n_base", "PREC", "timing_enable", "timing_read", "KERNELS",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -68,6 +68,11 @@ def lib() -> ctypes.CDLL:
         L.qc_status_string.argtypes = [ctypes.c_int32]
         L.qc_last_error.restype = ctypes.c_char_p
         L.qc_version.restype = ctypes.c_char_p
+        L.qc_timing_enable.argtypes = [ctypes.c_int32]
+        L.qc_timing_enable.restype = ctypes.c_int32
+        L.qc_timing_read.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_int64)]
+        L.qc_timing_read.restype = ctypes.c_int32
         _lib = L
     return _lib
 
@@ -84,6 +89,22 @@ def _stream():
 
 def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+KERNELS = {"fx_fused": 0, "channelize": 1, "xeng_f32": 2, "xeng_mfma": 3, "reduce": 4,
+           "mad": 5, "apply": 6}
+
+
+def timing_enable(on: bool = True):
+    """Start (clearing) or stop per-kernel event timing inside the library."""
+    _check(lib().qc_timing_enable(1 if on else 0), "qc_timing_enable")
+
+
+def timing_read(kernel: str):
+    """(total milliseconds, launch count) recorded for a kernel; synchronises."""
+    ms, n = ctypes.c_double(0.0), ctypes.c_int64(0)
+    _check(lib().qc_timing_read(KERNELS[kernel], ctypes.byref(ms), ctypes.byref(n)), "qc_timing_read")
+    return ms.value, n.value
 
 
 def n_base(n_ant: int) -> int:

@@ -95,10 +95,27 @@ qc_status get_taps(int N, int P, TapsEntry* out) {
   return QC_OK;
 }
 
+// Once per device: keep freed stream-ordered allocations in the device's
+// default pool instead of returning them at every synchronisation, so the
+// per-call scratch buffers are reused rather than re-mapped.
+std::map<int, bool> g_pool_ready;
+
+qc_status device_init_locked(int dev) {
+  if (g_pool_ready.count(dev)) return QC_OK;
+  hipMemPool_t pool = nullptr;
+  QC_HIP(hipDeviceGetDefaultMemPool(&pool, dev), "hipDeviceGetDefaultMemPool");
+  uint64_t thr = UINT64_MAX;
+  QC_HIP(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr), "hipMemPoolSetAttribute");
+  g_pool_ready[dev] = true;
+  return QC_OK;
+}
+
 qc_status get_twiddles(int N, float2** out) {
   int dev = 0;
   QC_HIP(hipGetDevice(&dev), "hipGetDevice");
   std::lock_guard<std::mutex> lk(g_mu);
+  qc_status st = device_init_locked(dev);
+  if (st != QC_OK) return st;
   auto key = std::make_pair(dev, N);
   auto it = g_tw.find(key);
   if (it != g_tw.end()) {
@@ -208,6 +225,43 @@ qc_status alloc_async(AsyncBuf& b, size_t bytes, hipStream_t s) {
   return QC_OK;
 }
 
+// ---- kernel timing ----------------------------------------------------------
+struct TimingRec {
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[QC_KERNEL_COUNT];
+};
+std::mutex g_tmu;
+bool g_timing = false;
+TimingRec g_trec;
+
+void timing_clear_locked() {
+  for (auto& v : g_trec.ev) {
+    for (auto& p : v) {
+      (void)hipEventDestroy(p.first);
+      (void)hipEventDestroy(p.second);
+    }
+    v.clear();
+  }
+}
+
+// Brackets one launch with events on its stream when timing is enabled.
+struct KTimer {
+  int k;
+  hipStream_t s;
+  hipEvent_t a = nullptr, b = nullptr;
+  KTimer(int kernel, hipStream_t st) : k(kernel), s(st) {
+    std::lock_guard<std::mutex> lk(g_tmu);
+    if (!g_timing) return;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) { a = b = nullptr; return; }
+    (void)hipEventRecord(a, s);
+  }
+  ~KTimer() {
+    if (!a) return;
+    (void)hipEventRecord(b, s);
+    std::lock_guard<std::mutex> lk(g_tmu);
+    g_trec.ev[k].emplace_back(a, b);
+  }
+};
+
 qc_status channelize_impl(const Resolved& r, qc_prec out_prec, void* out, float* scale_out,
                           hipStream_t s) {
   const qc::FxArgs& a = r.args;
@@ -222,7 +276,10 @@ qc_status channelize_impl(const Resolved& r, qc_prec out_prec, void* out, float*
       QC_HIP(qc::launch_scales(a.x, a.ld_x, a.n_ant, n_use, s2, prec_target(out_prec), scale_out, s),
              "scales kernel");
   }
-  if (a.n_samp > 0) QC_HIP(qc::launch_channelize(a, (int)out_prec, out, scale_out, s), "channelize kernel");
+  if (a.n_samp > 0) {
+    KTimer t(QC_KERNEL_CHANNELIZE, s);
+    QC_HIP(qc::launch_channelize(a, (int)out_prec, out, scale_out, s), "channelize kernel");
+  }
   return QC_OK;
 }
 
@@ -299,7 +356,11 @@ qc_status qc_xcorrelate(const int8_t* x, int64_t ld_x, int32_t n_ant, int64_t n_
       AsyncBuf part;
       st = alloc_async(part, (size_t)(n_dump * cpd) * nb * nch * sizeof(float2), s);
       if (st != QC_OK) return st;
-      QC_HIP(qc::launch_fused(r.args, n_dump, spec_per_dump, cpd, (float2*)part.p, s), "fused F+X kernel");
+      {
+        KTimer t(QC_KERNEL_FX_FUSED, s);
+        QC_HIP(qc::launch_fused(r.args, n_dump, spec_per_dump, cpd, (float2*)part.p, s), "fused F+X kernel");
+      }
+      KTimer t(QC_KERNEL_REDUCE, s);
       QC_HIP(qc::launch_reduce((const float2*)part.p, n_dump, cpd, nb * nch, 0.25f, accumulate,
                                reinterpret_cast<float2*>(vis), s),
              "reduce kernel");
@@ -343,9 +404,13 @@ qc_status qc_xcorrelate_chan(const void* v, qc_prec prec, const float* scale, in
     AsyncBuf part;
     qc_status st = alloc_async(part, (size_t)(n_dump * ks) * nb * n_chan * sizeof(float2), s);
     if (st != QC_OK) return st;
-    QC_HIP(qc::launch_xeng_f32((const float2*)v, n_ant, n_spec, n_chan, spec_per_dump, n_dump, ks,
-                               (float2*)part.p, s),
-           "X-engine f32 kernel");
+    {
+      KTimer t(QC_KERNEL_XENG_F32, s);
+      QC_HIP(qc::launch_xeng_f32((const float2*)v, n_ant, n_spec, n_chan, spec_per_dump, n_dump, ks,
+                                 (float2*)part.p, s),
+             "X-engine f32 kernel");
+    }
+    KTimer t(QC_KERNEL_REDUCE, s);
     QC_HIP(qc::launch_reduce((const float2*)part.p, n_dump, ks, nb * n_chan, 1.0f, accumulate,
                              reinterpret_cast<float2*>(vis), s),
            "reduce kernel");
@@ -358,9 +423,13 @@ qc_status qc_xcorrelate_chan(const void* v, qc_prec prec, const float* scale, in
   AsyncBuf part;
   qc_status st = alloc_async(part, (size_t)(n_dump * ks) * nb * n_chan * sizeof(float2), s);
   if (st != QC_OK) return st;
-  QC_HIP(qc::launch_xeng_mfma(v, (int)prec, scale, n_ant, n_spec, n_chan, spec_per_dump, n_dump, ks,
-                              (float2*)part.p, s),
-         "X-engine matrix-core kernel");
+  {
+    KTimer t(QC_KERNEL_XENG_MFMA, s);
+    QC_HIP(qc::launch_xeng_mfma(v, (int)prec, scale, n_ant, n_spec, n_chan, spec_per_dump, n_dump, ks,
+                                (float2*)part.p, s),
+           "X-engine matrix-core kernel");
+  }
+  KTimer t(QC_KERNEL_REDUCE, s);
   QC_HIP(qc::launch_reduce((const float2*)part.p, n_dump, ks, nb * n_chan, 1.0f, accumulate,
                            reinterpret_cast<float2*>(vis), s),
          "reduce kernel");
@@ -377,6 +446,7 @@ qc_status qc_mad_flag(const float* vis, int64_t n_time, int64_t n_base, int32_t 
   if (reinterpret_cast<uintptr_t>(vis) & 7u) return fail(QC_EINVAL, "vis must be 8-byte aligned");
   const int64_t npop = population == 0 ? n_base : population == 1 ? n_base * n_chan : n_time * n_base;
   if (npop > 0x7fffffffLL) return fail(QC_EINVAL, "too many populations");
+  KTimer t(QC_KERNEL_MAD, reinterpret_cast<hipStream_t>(stream));
   QC_HIP(qc::launch_mad(reinterpret_cast<const float2*>(vis), n_time, n_base, n_chan, sigma, population,
                         mask, thresh_out, reinterpret_cast<hipStream_t>(stream)),
          "MAD kernel");
@@ -396,9 +466,35 @@ qc_status qc_apply_delay_phase(float* vis, int64_t n_time, int32_t n_ant, int32_
   if (n_time == 0) return QC_OK;
   if (!vis) return fail(QC_EINVAL, "vis is NULL");
   if (reinterpret_cast<uintptr_t>(vis) & 7u) return fail(QC_EINVAL, "vis must be 8-byte aligned");
+  KTimer t(QC_KERNEL_APPLY, reinterpret_cast<hipStream_t>(stream));
   QC_HIP(qc::launch_apply(reinterpret_cast<float2*>(vis), n_time, n_ant, n_chan, f0_hz, df_hz, tau_s,
                           phi_rad, reinterpret_cast<hipStream_t>(stream)),
          "apply kernel");
+  return QC_OK;
+}
+
+qc_status qc_timing_enable(int32_t on) {
+  g_err.clear();
+  std::lock_guard<std::mutex> lk(g_tmu);
+  if (on) timing_clear_locked();
+  g_timing = on != 0;
+  return QC_OK;
+}
+
+qc_status qc_timing_read(int32_t kernel, double* total_ms, int64_t* launches) {
+  g_err.clear();
+  if (kernel < 0 || kernel >= QC_KERNEL_COUNT) return fail(QC_EINVAL, "bad kernel id %d", kernel);
+  if (!total_ms || !launches) return fail(QC_EINVAL, "NULL output");
+  std::lock_guard<std::mutex> lk(g_tmu);
+  double tot = 0.0;
+  for (auto& p : g_trec.ev[kernel]) {
+    QC_HIP(hipEventSynchronize(p.second), "hipEventSynchronize");
+    float ms = 0.f;
+    QC_HIP(hipEventElapsedTime(&ms, p.first, p.second), "hipEventElapsedTime");
+    tot += ms;
+  }
+  *total_ms = tot;
+  *launches = (int64_t)g_trec.ev[kernel].size();
   return QC_OK;
 }
 

@@ -2,11 +2,13 @@
 //
 // MAD (arXiv 2604.20640 Sec. 7, eq. 2): T = median(A) + sigma*1.4826*MAD(A)
 // on the visibility amplitude A; flag A > T.  Medians are exact order
-// statistics found by radix selection (8-bit digits, most significant
-// first) over the bit patterns of non-negative floats, whose unsigned order
-// equals their numeric order: float32 amplitudes (4 passes), float64
-// deviations |A - median| (8 passes).  Even counts average the two middle
-// order statistics.  One workgroup handles one population.
+// statistics found by radix selection (most significant digit first) over
+// the bit patterns of non-negative floats, whose unsigned order equals their
+// numeric order: float32 amplitudes and float64 deviations |A - median|.
+// Even counts average the two middle order statistics.  One workgroup
+// handles one population; its amplitudes are cached in LDS when they fit
+// (1024 threads and 11-bit digits for large populations, one wave and 8-bit
+// digits for small ones).
 //
 // Delay/phase application (Sec. 4.1 step 2 and eq. 1; Sec. 7 delay and phase
 // corrections): V_ij[k] *= exp(+i [2 pi f_k (tau_i - tau_j) + phi_i - phi_j]).
@@ -21,7 +23,10 @@ namespace qc {
 
 namespace {
 
-constexpr int MAD_NT = 256;
+// Every float64 step of the threshold is a separately rounded IEEE operation
+// (no contraction into fused multiply-adds), so the decisions match a plain
+// float64 evaluation of the same expressions bit for bit.
+#pragma clang fp contract(off)
 
 struct Pop {
   int64_t base, count, inner_n, s_inner, s_outer;
@@ -35,65 +40,86 @@ __device__ __forceinline__ float amp_f32(float2 v) {
   return (float)sqrt(re * re + im * im);
 }
 
-// k-th smallest (0-based) amplitude bit pattern in the population.
-__device__ uint32_t select_amp(const float2* __restrict__ vis, const Pop& pop, int64_t k,
-                               unsigned* hist, unsigned long long* sh) {
-  uint32_t prefix = 0, mask = 0;
-  int64_t kk = k;
-  for (int shift = 24; shift >= 0; shift -= 8) {
-    for (int i = threadIdx.x; i < 256; i += MAD_NT) hist[i] = 0;
+// Amplitudes of a population: from an LDS cache when it fits, else from vis.
+struct AmpSrc {
+  const float2* vis;
+  Pop pop;
+  const float* cache;  // null when not cached
+  __device__ __forceinline__ float operator()(int64_t i) const {
+    return cache ? cache[i] : amp_f32(vis[pop.off(i)]);
+  }
+};
+
+// Block-wide search of the digit that holds rank kk in hist[0..NBINS):
+// returns (digit, rank within the digit) through sh[].
+template <int NT, int NBINS>
+__device__ __forceinline__ void find_digit(const unsigned* hist, int64_t kk, unsigned* wsum,
+                                           unsigned long long* sh) {
+  constexpr int PER = NBINS / NT;  // bins per thread (>= 1)
+  constexpr int NW = NT / 64;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  unsigned loc = 0;
+#pragma unroll
+  for (int i = 0; i < PER; ++i) loc += hist[t * PER + i];
+  unsigned v = loc;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const unsigned n = __shfl_up(v, d);
+    if (lane >= d) v += n;
+  }
+  if (NW > 1) {
+    if (lane == 63) wsum[wave] = v;
     __syncthreads();
-    for (int64_t i = threadIdx.x; i < pop.count; i += MAD_NT) {
-      const uint32_t key = __float_as_uint(amp_f32(vis[pop.off(i)]));
-      if ((key & mask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      int64_t cum = 0;
-      int dsel = 255;
-      for (int dgt = 0; dgt < 256; ++dgt) {
-        if (cum + hist[dgt] > kk) { dsel = dgt; break; }
-        cum += hist[dgt];
+    if (t == 0) {
+      unsigned acc = 0;
+      for (int w = 0; w < NW; ++w) {
+        acc += wsum[w];
+        wsum[w] = acc;
       }
-      sh[0] = (unsigned long long)dsel;
-      sh[1] = (unsigned long long)(kk - cum);
     }
-    __syncthreads();
-    prefix |= (uint32_t)sh[0] << shift;
-    mask |= 255u << shift;
-    kk = (int64_t)sh[1];
     __syncthreads();
   }
-  return prefix;
+  const int64_t incl = (int64_t)v + ((NW > 1 && wave > 0) ? wsum[wave - 1] : 0u);
+  const int64_t excl = incl - loc;
+  if (excl <= kk && kk < incl) {
+    int64_t c = excl;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const unsigned h = hist[t * PER + i];
+      if (kk < c + (int64_t)h) {
+        sh[0] = (unsigned long long)(t * PER + i);
+        sh[1] = (unsigned long long)(kk - c);
+        break;
+      }
+      c += h;
+    }
+  }
+  __syncthreads();
 }
 
-// k-th smallest deviation |A - med| (float64 bit pattern).
-__device__ uint64_t select_dev(const float2* __restrict__ vis, const Pop& pop, int64_t k, double med,
-                               unsigned* hist, unsigned long long* sh) {
-  uint64_t prefix = 0, mask = 0;
+// k-th smallest (0-based) key of the population, most significant digit
+// first.  KEY(i) returns the unsigned key of element i; W is the key width.
+template <int NT, int DB, typename K, typename KeyFn>
+__device__ K radix_select(int64_t count, int64_t k, KeyFn key, unsigned* hist, unsigned* wsum,
+                          unsigned long long* sh) {
+  constexpr int W = (int)sizeof(K) * 8;
+  constexpr int NBINS = 1 << DB;
+  K prefix = 0, mask = 0;
   int64_t kk = k;
-  for (int shift = 56; shift >= 0; shift -= 8) {
-    for (int i = threadIdx.x; i < 256; i += MAD_NT) hist[i] = 0;
+  for (int hi = W; hi > 0; hi -= DB) {
+    const int width = hi >= DB ? DB : hi;
+    const int shift = hi - width;
+    const K dmask = (K)((1u << width) - 1u);
+    for (int i = threadIdx.x; i < NBINS; i += NT) hist[i] = 0;
     __syncthreads();
-    for (int64_t i = threadIdx.x; i < pop.count; i += MAD_NT) {
-      const double dev = fabs((double)amp_f32(vis[pop.off(i)]) - med);
-      const uint64_t key = (uint64_t)__double_as_longlong(dev);
-      if ((key & mask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
+    for (int64_t i = threadIdx.x; i < count; i += NT) {
+      const K kv = key(i);
+      if ((kv & mask) == prefix) atomicAdd(&hist[(unsigned)((kv >> shift) & dmask)], 1u);
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-      int64_t cum = 0;
-      int dsel = 255;
-      for (int dgt = 0; dgt < 256; ++dgt) {
-        if (cum + hist[dgt] > kk) { dsel = dgt; break; }
-        cum += hist[dgt];
-      }
-      sh[0] = (unsigned long long)dsel;
-      sh[1] = (unsigned long long)(kk - cum);
-    }
-    __syncthreads();
-    prefix |= (uint64_t)sh[0] << shift;
-    mask |= (uint64_t)255u << shift;
+    find_digit<NT, NBINS>(hist, kk, wsum, sh);
+    prefix |= (K)sh[0] << shift;
+    mask |= dmask << shift;
     kk = (int64_t)sh[1];
     __syncthreads();
   }
@@ -102,11 +128,16 @@ __device__ uint64_t select_dev(const float2* __restrict__ vis, const Pop& pop, i
 
 }  // namespace
 
-__global__ void __launch_bounds__(MAD_NT)
+// One block per population.  Amplitudes are cached in dynamic LDS when the
+// population has at most `cap` members.
+template <int NT, int DB>
+__global__ void __launch_bounds__(NT)
 mad_kernel(const float2* __restrict__ vis, int64_t n_time, int64_t n_base, int n_chan, float sigma,
-           int population, uint8_t* __restrict__ mask, double* __restrict__ thresh) {
-  __shared__ unsigned hist[256];
+           int population, int64_t cap, uint8_t* __restrict__ mask, double* __restrict__ thresh) {
+  __shared__ unsigned hist[1 << DB];
+  __shared__ unsigned wsum[NT / 64];
   __shared__ unsigned long long sh[2];
+  extern __shared__ float acache[];
   const int64_t id = blockIdx.x;
   Pop pop;
   const int64_t plane = n_base * (int64_t)n_chan;
@@ -120,27 +151,53 @@ mad_kernel(const float2* __restrict__ vis, int64_t n_time, int64_t n_base, int n
     pop = Pop{t * plane + b * n_chan, n_chan, n_chan, 1, 0};
   }
   const int64_t n = pop.count;
-  const int64_t k1 = (n - 1) / 2, k2 = n / 2;
-  const uint32_t a1 = select_amp(vis, pop, k1, hist, sh);
-  const uint32_t a2 = (k2 == k1) ? a1 : select_amp(vis, pop, k2, hist, sh);
-  const double med = ((double)__uint_as_float(a1) + (double)__uint_as_float(a2)) / 2.0;
-  const uint64_t d1 = select_dev(vis, pop, k1, med, hist, sh);
-  const uint64_t d2 = (k2 == k1) ? d1 : select_dev(vis, pop, k2, med, hist, sh);
-  const double madv = (__longlong_as_double((long long)d1) + __longlong_as_double((long long)d2)) / 2.0;
-  const double T = med + ((double)sigma * 1.4826) * madv;
-  for (int64_t i = threadIdx.x; i < n; i += MAD_NT) {
-    const int64_t o = pop.off(i);
-    mask[o] = (double)amp_f32(vis[o]) > T ? 1 : 0;
+  const bool cached = n <= cap;
+  if (cached) {
+    for (int64_t i = threadIdx.x; i < n; i += NT) acache[i] = amp_f32(vis[pop.off(i)]);
+    __syncthreads();
   }
+  const AmpSrc amp{vis, pop, cached ? acache : nullptr};
+  const int64_t k1 = (n - 1) / 2, k2 = n / 2;
+  auto akey = [&](int64_t i) -> uint32_t { return __float_as_uint(amp(i)); };
+  const uint32_t a1 = radix_select<NT, DB, uint32_t>(n, k1, akey, hist, wsum, sh);
+  const uint32_t a2 = (k2 == k1) ? a1 : radix_select<NT, DB, uint32_t>(n, k2, akey, hist, wsum, sh);
+  const double med = ((double)__uint_as_float(a1) + (double)__uint_as_float(a2)) / 2.0;
+  auto dkey = [&](int64_t i) -> uint64_t {
+    return (uint64_t)__double_as_longlong(fabs((double)amp(i) - med));
+  };
+  const uint64_t d1 = radix_select<NT, DB, uint64_t>(n, k1, dkey, hist, wsum, sh);
+  const uint64_t d2 = (k2 == k1) ? d1 : radix_select<NT, DB, uint64_t>(n, k2, dkey, hist, wsum, sh);
+  const double madv =
+      (__longlong_as_double((long long)d1) + __longlong_as_double((long long)d2)) / 2.0;
+  const double c = (double)sigma * 1.4826;
+  const double T = med + c * madv;
+  for (int64_t i = threadIdx.x; i < n; i += NT) mask[pop.off(i)] = (double)amp(i) > T ? 1 : 0;
   if (thresh && threadIdx.x == 0) thresh[id] = T;
 }
 
+#pragma clang fp contract(on)
+
+constexpr int64_t MAD_CAP_BIG = 36864;   // floats cached in LDS (144 KiB)
+constexpr int64_t MAD_CAP_SMALL = 2048;
+
 hipError_t launch_mad(const float2* vis, int64_t n_time, int64_t n_base, int n_chan, float sigma,
                       int population, uint8_t* mask, double* thresh, hipStream_t s) {
-  int64_t npop = population == 0 ? n_base : population == 1 ? n_base * n_chan : n_time * n_base;
+  const int64_t npop = population == 0 ? n_base : population == 1 ? n_base * n_chan : n_time * n_base;
+  const int64_t count = population == 0 ? n_time * n_chan : population == 1 ? n_time : n_chan;
   if (npop <= 0) return hipSuccess;
-  hipLaunchKernelGGL(mad_kernel, dim3((unsigned)npop), dim3(MAD_NT), 0, s, vis, n_time, n_base,
-                     n_chan, sigma, population, mask, thresh);
+  if (count <= MAD_CAP_SMALL) {
+    const size_t lds = (size_t)count * sizeof(float);
+    hipLaunchKernelGGL((mad_kernel<64, 8>), dim3((unsigned)npop), dim3(64), lds, s, vis, n_time,
+                       n_base, n_chan, sigma, population, MAD_CAP_SMALL, mask, thresh);
+  } else {
+    const int64_t cap = count <= MAD_CAP_BIG ? count : 0;
+    const size_t lds = (size_t)cap * sizeof(float);
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(mad_kernel<1024, 11>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((mad_kernel<1024, 11>), dim3((unsigned)npop), dim3(1024), lds, s, vis, n_time,
+                       n_base, n_chan, sigma, population, cap, mask, thresh);
+  }
   return hipGetLastError();
 }
 

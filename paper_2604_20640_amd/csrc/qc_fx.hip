@@ -438,19 +438,24 @@ hipError_t launch_channelize(const FxArgs& a, int prec, void* out, const float* 
 // ---------------------------------------------------------------------------
 // Per-antenna power-of-two scale from the input power.
 // ---------------------------------------------------------------------------
-__global__ void scales_kernel(const int8_t* __restrict__ x, int64_t ld_x, int64_t n_use,
-                              double sum_h2, double target, float* __restrict__ scale_out) {
-  __shared__ unsigned long long red[256];
+__global__ void __launch_bounds__(1024)
+scales_kernel(const int8_t* __restrict__ x, int64_t ld_x, int64_t n_use, double sum_h2,
+              double target, float* __restrict__ scale_out) {
+  __shared__ unsigned long long red[1024];
   const int a = blockIdx.x;
-  const int8_t* xa = x + (int64_t)a * ld_x;
+  const uint32_t* xa = reinterpret_cast<const uint32_t*>(x + (int64_t)a * ld_x);
   unsigned long long acc = 0;
-  for (int64_t n = threadIdx.x; n < n_use; n += blockDim.x) {
-    const int v = xa[n];
-    acc += (unsigned long long)(v * v);
+  for (int64_t n = threadIdx.x; n < n_use / 4; n += blockDim.x) {
+    const uint32_t w = xa[n];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int v = (int)(int8_t)((w >> (8 * i)) & 0xffu);
+      acc += (unsigned long long)(v * v);
+    }
   }
   red[threadIdx.x] = acc;
   __syncthreads();
-  for (int st = 128; st > 0; st >>= 1) {
+  for (int st = 512; st > 0; st >>= 1) {
     if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
     __syncthreads();
   }
@@ -468,7 +473,7 @@ __global__ void scales_kernel(const int8_t* __restrict__ x, int64_t ld_x, int64_
 
 hipError_t launch_scales(const int8_t* x, int64_t ld_x, int n_ant, int64_t n_use, double sum_h2,
                          double target, float* scale_out, hipStream_t s) {
-  hipLaunchKernelGGL(scales_kernel, dim3(n_ant), dim3(256), 0, s, x, ld_x, n_use, sum_h2, target,
+  hipLaunchKernelGGL(scales_kernel, dim3(n_ant), dim3(1024), 0, s, x, ld_x, n_use, sum_h2, target,
                      scale_out);
   return hipGetLastError();
 }

@@ -12,17 +12,22 @@ round-half-even and clip to [-128, 127]):
            + tone[n] + lines[n] + bursts[n]        common to all antennas
 
 Random numbers come from numpy's PCG64 seeded by SeedSequence((seed,
-stream id, chunk index)), so any chunk can be regenerated on its own.
+stream id, block index)), so any chunk can be regenerated on its own and
+chunks are filled in parallel.  Tones and lines sit at frequencies k/period
+and are evaluated over one period, then indexed.
 """
 
 from __future__ import annotations
 
+import concurrent.futures as cf
 import math
+import os
 from dataclasses import dataclass, field
 
 import numpy as np
 
 CHUNK = 1 << 22
+C_BLOCK = 1 << 16      # granularity of the common (lagged) component
 
 
 def _rng(seed: int, stream: int, chunk: int) -> np.random.Generator:
@@ -41,62 +46,87 @@ class StreamSpec:
     tone_cycles_per_sample: float = 0.0
     lines: list = field(default_factory=list)     # [(cycles_per_sample, amp, phase)]
     bursts: list = field(default_factory=list)    # [(start_sample, length, rms)]
+    period: int = 0   # tone and line frequencies are multiples of 1/period
 
 
 def _common_component(spec: StreamSpec, lo: int, hi: int, max_lag: int) -> np.ndarray:
-    """c[n] for n in [lo - max_lag, hi), built chunk by chunk."""
+    """c[n] for n in [lo - max_lag, hi), assembled from seeded blocks."""
     out = np.empty(hi - lo + max_lag, np.float32)
-    start = lo - max_lag
+    n = lo - max_lag
     pos = 0
-    n = start
     while n < hi:
-        j = math.floor(n / CHUNK)
-        c0 = j * CHUNK
-        block = _rng(spec.seed, 1, j + 1_000_000).standard_normal(CHUNK, dtype=np.float32)
+        j = math.floor(n / C_BLOCK)
+        c0 = j * C_BLOCK
+        block = _rng(spec.seed, 1, j + 1_000_000).standard_normal(C_BLOCK, dtype=np.float32)
         a = n - c0
-        b = min(CHUNK, hi - c0)
+        b = min(C_BLOCK, hi - c0)
         out[pos:pos + b - a] = block[a:b]
         pos += b - a
         n = c0 + b
     return out
 
 
-def generate(spec: StreamSpec, out: np.ndarray | None = None) -> np.ndarray:
+def _periodic_component(spec: StreamSpec) -> np.ndarray | None:
+    """One period of the tone plus lines (float32), or None."""
+    if not spec.tone_amp and not spec.lines:
+        return None
+    per = spec.period
+    assert per > 0, "tones and lines need a period"
+    n = np.arange(per, dtype=np.float64)
+    acc = np.zeros(per, np.float64)
+    if spec.tone_amp:
+        acc += spec.tone_amp * np.cos(2.0 * np.pi * np.mod(n * spec.tone_cycles_per_sample, 1.0))
+    for (f, amp, phase) in spec.lines:
+        acc += amp * np.cos(2.0 * np.pi * np.mod(n * f, 1.0) + phase)
+    return acc.astype(np.float32)
+
+
+def _fill_chunk(spec: StreamSpec, x: np.ndarray, lo: int, lags, max_lag, periodic):
+    n_ant, S = spec.n_ant, spec.n_samp
+    hi = min(S, lo + CHUNK)
+    j = lo // CHUNK
+    L = hi - lo
+    common = np.zeros(L, np.float32)
+    if periodic is not None:
+        per = periodic.size
+        common += periodic[np.arange(lo, hi, dtype=np.int64) % per]
+    for bi, (b0, blen, rms) in enumerate(spec.bursts):
+        a, b = max(lo, b0), min(hi, b0 + blen)
+        if a < b:
+            r = _rng(spec.seed, 3, bi).standard_normal(blen, dtype=np.float32)
+            common[a - lo:b - lo] += np.float32(rms) * r[a - b0:b - b0]
+    cpre = _common_component(spec, lo, hi, max_lag) if spec.corr else None
+    k_corr = np.float32(math.sqrt(spec.corr) * spec.sigma)
+    sig = np.float32(spec.sigma)
+    for a_ in range(n_ant):
+        v = _rng(spec.seed, 100 + a_, j).standard_normal(L, dtype=np.float32)
+        v *= sig
+        if cpre is not None:
+            d = lags[a_]
+            v += k_corr * cpre[max_lag - d:max_lag - d + L]
+        v += common
+        np.rint(v, out=v)
+        np.clip(v, -128, 127, out=v)
+        x[a_, lo:hi] = v.astype(np.int8)
+
+
+def generate(spec: StreamSpec, out: np.ndarray | None = None, threads: int | None = None) -> np.ndarray:
     """int8 [n_ant, n_samp] stream for ``spec`` (deterministic in spec.seed)."""
     n_ant, S = spec.n_ant, spec.n_samp
     lags = tuple(spec.lags) if spec.lags else (0,) * n_ant
     assert len(lags) == n_ant
     max_lag = max(lags) if lags else 0
     x = np.empty((n_ant, S), np.int8) if out is None else out
-    k_corr = np.float32(math.sqrt(spec.corr) * spec.sigma)
-    sig = np.float32(spec.sigma)
-    for lo in range(0, S, CHUNK):
-        hi = min(S, lo + CHUNK)
-        j = lo // CHUNK
-        L = hi - lo
-        common = np.zeros(L, np.float32)
-        n = np.arange(lo, hi, dtype=np.float64)
-        if spec.tone_amp:
-            ph = np.mod(n * spec.tone_cycles_per_sample, 1.0)
-            common += (spec.tone_amp * np.cos(2.0 * np.pi * ph)).astype(np.float32)
-        for (f, amp, phase) in spec.lines:
-            ph = np.mod(n * f, 1.0)
-            common += (amp * np.cos(2.0 * np.pi * ph + phase)).astype(np.float32)
-        for bi, (b0, blen, rms) in enumerate(spec.bursts):
-            a, b = max(lo, b0), min(hi, b0 + blen)
-            if a < b:
-                r = _rng(spec.seed, 3, bi).standard_normal(blen, dtype=np.float32)
-                common[a - lo:b - lo] += np.float32(rms) * r[a - b0:b - b0]
-        cpre = _common_component(spec, lo, hi, max_lag) if spec.corr else None
-        for a_ in range(n_ant):
-            v = sig * _rng(spec.seed, 100 + a_, j).standard_normal(L, dtype=np.float32)
-            if cpre is not None:
-                d = lags[a_]
-                v += k_corr * cpre[max_lag - d:max_lag - d + L]
-            v += common
-            np.rint(v, out=v)
-            np.clip(v, -128, 127, out=v)
-            x[a_, lo:hi] = v.astype(np.int8)
+    periodic = _periodic_component(spec)
+    starts = list(range(0, S, CHUNK))
+    if threads is None:
+        threads = min(16, len(os.sched_getaffinity(0)))
+    if threads <= 1 or len(starts) == 1:
+        for lo in starts:
+            _fill_chunk(spec, x, lo, lags, max_lag, periodic)
+    else:
+        with cf.ThreadPoolExecutor(threads) as ex:
+            list(ex.map(lambda lo: _fill_chunk(spec, x, lo, lags, max_lag, periodic), starts))
     return x
 
 
@@ -117,7 +147,7 @@ def tone_stream(n_ant=4, n_samp=1 << 20, seed=1000, n_fft=1024, chan=137):
     a tone of amplitude 16 centred on channel ``chan``, all seeded."""
     lags = (0, 3, 5, 7)[:n_ant] if n_ant <= 4 else tuple(range(n_ant))
     spec = StreamSpec(n_ant, n_samp, seed, corr=0.3, lags=lags,
-                      tone_amp=16.0, tone_cycles_per_sample=chan / n_fft)
+                      tone_amp=16.0, tone_cycles_per_sample=chan / n_fft, period=n_fft)
     return spec
 
 
@@ -152,7 +182,8 @@ def realtime_spec(n_samp=1 << 28, seed=2000, n_fft=4096, spec_per_dump=4096,
         covered += blen
     tau_s = np.array(lags, np.float64) * 1e-9      # 1 GS/s: one sample = 1 ns
     phi = rng.uniform(-np.pi, np.pi, n_ant)
-    spec = StreamSpec(n_ant, n_samp, seed, corr=0.3, lags=lags, lines=lines, bursts=bursts)
+    spec = StreamSpec(n_ant, n_samp, seed, corr=0.3, lags=lags, lines=lines, bursts=bursts,
+                      period=n_fft)
     params = {"lags": lags, "line_chans": [int(k) for k in sorted(chans)],
               "tau_s": tau_s, "phi_rad": phi, "fs_hz": 1e9,
               "bursts": bursts}

