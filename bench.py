@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--no-precision", action="store_true", help="skip the 32-antenna section")
     ap.add_argument("--traffic", type=str, default=None,
                     help="JSON file with measured HBM bytes per fused launch")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run a plain 256 MiB device copy kernel (counter calibration)")
     return ap.parse_args()
 
 
@@ -193,6 +195,16 @@ def main():
         qc.mad_flag(vis, sigma, 0, mask=mask, thresh=thr)
         qc.apply_delay_phase(vis, n_ant, 0.0, df, tau, phi)
 
+    if args.copy_calib:
+        # a plain elementwise copy of known size: 256 MiB read + 256 MiB written
+        a = torch.ones(1 << 26, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.mul(a, 1.0, out=b)
+        torch.cuda.synchronize()
+        del a, b
+    # the autotuner picks the fused kernel's tile shape on this very input
+    best_tile, tile_ms = qc.fx_autotune(xd, N, P, spd, reps=3)
+    log(f"[bench] autotune: tile {best_tile}; ms per tile {[round(v, 3) for v in tile_ms]}")
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -250,6 +262,7 @@ def main():
                      "algorithmic_flop_per_launch": flops,
                      "hbm_frac_of_input_read": round(x.nbytes / (fx_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)},
         "stages_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in kt.items()},
+        "fused_tile": {"chosen": best_tile, "ms_per_tile": [round(v, 4) for v in tile_ms]},
         "wall_s_timed_region": round(t_wall, 4),
     }
     if not args.no_precision:

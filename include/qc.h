@@ -148,6 +148,53 @@ qc_status qc_apply_delay_phase(float* vis, int64_t n_time, int32_t n_ant, int32_
                                double f0_hz, double df_hz, const double* tau_s,
                                const double* phi_rad, void* stream);
 
+/* Streaming ingest (Alg. 1: pinned host buffers, asynchronous host-to-device
+ * copies on a stream, then F-engine, X-engine and integration; Sec. 4.2
+ * "Asynchronous I/O").  The library owns a ring of `depth` device slots, a
+ * copy stream and a compute stream, and carries the PFB history between
+ * chunks, so a chunked stream gives the spectra of one long stream.
+ *   qc_stream_create: chunk_samp samples per antenna per chunk (a multiple of
+ *     n_fft holding a whole number of dumps).  Synchronises once.
+ *   qc_stream_push: host_chunk is int8 [n_ant][chunk_samp] in page-locked host
+ *     memory; it must stay unchanged until qc_stream_wait_copied(st, seq) or
+ *     qc_stream_sync returns.  seq must increase; a gap (seq != previous + 1)
+ *     marks dropped chunks and restarts the filter history from zeros.
+ *     vis_out: device cfloat [chunk dumps][n_base][n_chan], written on the
+ *     compute stream.  n_dumps_out: host, or NULL.  Asynchronous.
+ *   qc_stream_wait_copied: blocks until chunk seq has reached the device.
+ *   qc_stream_sync: blocks until all pushed work is done.
+ *   qc_stream_compute_stream: the hipStream_t (as void*) results are written on.
+ *   qc_stream_last_error: thread-local detail of the last streaming failure. */
+typedef struct qc_stream qc_stream;
+qc_status qc_stream_create(int32_t n_ant, int64_t chunk_samp, const qc_pfb_params* p,
+                           int64_t spec_per_dump, int32_t depth, qc_stream** out);
+qc_status qc_stream_push(qc_stream* st, const int8_t* host_chunk, int64_t seq, float* vis_out,
+                         int64_t* n_dumps_out);
+qc_status qc_stream_wait_copied(qc_stream* st, int64_t seq);
+qc_status qc_stream_sync(qc_stream* st);
+void* qc_stream_compute_stream(qc_stream* st);
+void qc_stream_destroy(qc_stream* st);
+const char* qc_stream_last_error(void);
+
+/* Tile shape of the fused F+X kernel for one (n_fft, n_ant): an index into a
+ * fixed list of shapes (spectra in flight, values per thread per FFT pass,
+ * ping-pong LDS buffers).  Every shape computes the same sums; shapes differ
+ * in speed only.  Index 0 is the default.  qc_fx_tile_count returns 0 when
+ * no fused kernel exists for the pair.  The choice is process-wide and is
+ * what the autotuner sets. */
+int32_t qc_fx_tile_count(int32_t n_fft, int32_t n_ant);
+qc_status qc_fx_set_tile(int32_t n_fft, int32_t n_ant, int32_t tile);
+int32_t qc_fx_get_tile(int32_t n_fft, int32_t n_ant);
+/* Autotuner for the fused kernel: times every tile shape of (n_fft, n_ant) on
+ * the caller's input (reps calls of qc_xcorrelate each, after one untimed
+ * call) with HIP events on `stream`, keeps the fastest via qc_fx_set_tile and
+ * returns its index in *best_out (host).  vis: device scratch sized for the
+ * output of qc_xcorrelate on this input.  ms_per_tile: host double[cap] for
+ * the per-tile average times, or NULL.  Synchronises. */
+qc_status qc_fx_autotune(const int8_t* x, int64_t ld_x, int32_t n_ant, int64_t n_samp,
+                         const qc_pfb_params* p, int64_t spec_per_dump, int32_t reps, float* vis,
+                         double* ms_per_tile, int32_t cap, int32_t* best_out, void* stream);
+
 /* Kernel timing for measurement harnesses.  While enabled, every launch of
  * the kernels below is bracketed by HIP events recorded on the stream the
  * kernel is launched on (so the figure is the kernel's own duration, on its

@@ -15,7 +15,7 @@ import torch
 
 __all__ = [
     "QCError", "lib", "pfb_channelize", "xcorrelate", "xcorrelate_chan", "mad_flag",
-    "apply_delay_phase", "n_base", "PREC", "timing_enable", "timing_read", "KERNELS",
+    "apply_delay_phase", "n_base", "PREC", "timing_enable", "timing_read", "KERNELS", "Stream",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -68,6 +68,29 @@ def lib() -> ctypes.CDLL:
         L.qc_status_string.argtypes = [ctypes.c_int32]
         L.qc_last_error.restype = ctypes.c_char_p
         L.qc_version.restype = ctypes.c_char_p
+        L.qc_stream_create.argtypes = [_I32, _I64, ctypes.POINTER(PfbParams), _I64, _I32,
+                                       ctypes.POINTER(ctypes.c_void_p)]
+        L.qc_stream_create.restype = ctypes.c_int32
+        L.qc_stream_push.argtypes = [_P, _P, _I64, _P, ctypes.POINTER(_I64)]
+        L.qc_stream_push.restype = ctypes.c_int32
+        L.qc_stream_wait_copied.argtypes = [_P, _I64]
+        L.qc_stream_wait_copied.restype = ctypes.c_int32
+        L.qc_stream_sync.argtypes = [_P]
+        L.qc_stream_sync.restype = ctypes.c_int32
+        L.qc_stream_compute_stream.argtypes = [_P]
+        L.qc_stream_compute_stream.restype = ctypes.c_void_p
+        L.qc_stream_destroy.argtypes = [_P]
+        L.qc_stream_destroy.restype = None
+        L.qc_stream_last_error.restype = ctypes.c_char_p
+        L.qc_fx_tile_count.argtypes = [_I32, _I32]
+        L.qc_fx_tile_count.restype = ctypes.c_int32
+        L.qc_fx_set_tile.argtypes = [_I32, _I32, _I32]
+        L.qc_fx_set_tile.restype = ctypes.c_int32
+        L.qc_fx_get_tile.argtypes = [_I32, _I32]
+        L.qc_fx_get_tile.restype = ctypes.c_int32
+        L.qc_fx_autotune.argtypes = [_P, _I64, _I32, _I64, ctypes.POINTER(PfbParams), _I64, _I32, _P,
+                                     ctypes.POINTER(ctypes.c_double), _I32, ctypes.POINTER(_I32), _P]
+        L.qc_fx_autotune.restype = ctypes.c_int32
         L.qc_timing_enable.argtypes = [ctypes.c_int32]
         L.qc_timing_enable.restype = ctypes.c_int32
         L.qc_timing_read.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
@@ -91,6 +114,58 @@ def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
+class Stream:
+    """Streaming ingest: pinned host chunks -> device ring -> fused F+X with
+    the filter history carried between chunks."""
+
+    def __init__(self, n_ant, chunk_samp, n_fft, n_taps, spec_per_dump, depth=4):
+        self.n_ant, self.chunk_samp, self.n_fft = n_ant, chunk_samp, n_fft
+        self.spec_per_dump = spec_per_dump
+        self._p = PfbParams(n_fft, n_taps, None, 0)
+        h = ctypes.c_void_p()
+        st = lib().qc_stream_create(n_ant, chunk_samp, ctypes.byref(self._p), spec_per_dump, depth,
+                                    ctypes.byref(h))
+        if st != 0:
+            raise QCError(st, "qc_stream_create", lib().qc_stream_last_error().decode())
+        self._h = h
+
+    @property
+    def n_dump_per_chunk(self):
+        return (self.chunk_samp // self.n_fft) // self.spec_per_dump
+
+    def push(self, host_chunk, seq, vis_out):
+        """host_chunk: pinned int8 CPU tensor [n_ant, chunk_samp]; vis_out: device complex64."""
+        assert host_chunk.dtype == torch.int8 and not host_chunk.is_cuda and host_chunk.is_contiguous()
+        assert vis_out.is_cuda and vis_out.dtype == torch.complex64
+        nd = _I64(0)
+        st = lib().qc_stream_push(self._h, ctypes.c_void_p(host_chunk.data_ptr()), seq,
+                                  ctypes.c_void_p(vis_out.data_ptr()), ctypes.byref(nd))
+        if st != 0:
+            raise QCError(st, "qc_stream_push", lib().qc_stream_last_error().decode())
+        return nd.value
+
+    def wait_copied(self, seq):
+        st = lib().qc_stream_wait_copied(self._h, seq)
+        if st != 0:
+            raise QCError(st, "qc_stream_wait_copied", lib().qc_stream_last_error().decode())
+
+    def sync(self):
+        st = lib().qc_stream_sync(self._h)
+        if st != 0:
+            raise QCError(st, "qc_stream_sync", lib().qc_stream_last_error().decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().qc_stream_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 KERNELS = {"fx_fused": 0, "channelize": 1, "xeng_f32": 2, "xeng_mfma": 3, "reduce": 4,
            "mad": 5, "apply": 6}
 
@@ -105,6 +180,33 @@ def timing_read(kernel: str):
     ms, n = ctypes.c_double(0.0), ctypes.c_int64(0)
     _check(lib().qc_timing_read(KERNELS[kernel], ctypes.byref(ms), ctypes.byref(n)), "qc_timing_read")
     return ms.value, n.value
+
+
+def fx_tile_count(n_fft: int, n_ant: int) -> int:
+    return lib().qc_fx_tile_count(n_fft, n_ant)
+
+
+def fx_set_tile(n_fft: int, n_ant: int, tile: int):
+    _check(lib().qc_fx_set_tile(n_fft, n_ant, tile), "qc_fx_set_tile")
+
+
+def fx_get_tile(n_fft: int, n_ant: int) -> int:
+    return lib().qc_fx_get_tile(n_fft, n_ant)
+
+
+def fx_autotune(x, n_fft, n_taps, spec_per_dump, reps=5):
+    """Time every fused tile shape on x, keep the fastest; returns (best, [ms per tile])."""
+    _check_x(x)
+    n_ant, n_samp = x.shape
+    n = fx_tile_count(n_fft, n_ant)
+    n_dump = (n_samp // n_fft) // spec_per_dump
+    vis = torch.empty((n_dump, n_base(n_ant), n_fft // 2), dtype=torch.complex64, device=x.device)
+    ms = (ctypes.c_double * max(n, 1))()
+    best = _I32(-1)
+    p = PfbParams(n_fft, n_taps, None, 0)
+    _check(lib().qc_fx_autotune(_ptr(x), x.stride(0), n_ant, n_samp, ctypes.byref(p), spec_per_dump,
+                                reps, _ptr(vis), ms, n, ctypes.byref(best), _stream()), "qc_fx_autotune")
+    return best.value, list(ms)[:n]
 
 
 def n_base(n_ant: int) -> int:

@@ -116,21 +116,34 @@ constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
 __device__ __forceinline__ int lds_pad(int i) { return i + (i >> 4); }
 __host__ __device__ constexpr int lds_padded_size(int n) { return n + (n >> 4) + 1; }
 
-// One Stockham pass of radix R over NFFT transforms of length N stored
-// back to back (padded) in `buf`.  NT = NFFT*N/16 threads, 16 values each.
-template <int N, int R, int NS, int NT>
-__device__ __forceinline__ void stockham_pass(float2* buf, const float2* __restrict__ tw, int tid) {
-  constexpr int Q = 16 / R;  // butterflies per thread
+// One Stockham pass of radix R over NFFT transforms of length N stored back
+// to back (padded).  NT threads each hold V complex values (V/R butterflies).
+// With INPLACE the pass reads and writes the same buffer, so a barrier
+// separates all loads from all stores; otherwise src and dst differ.
+template <int N, int R, int NS, int NT, int V, bool INPLACE, bool LN>
+__device__ __forceinline__ void stockham_pass(const float2* src, float2* dst,
+                                              const float2* __restrict__ tw, int tid) {
+  // Twiddles and LDS addresses depend only on the thread index, so the
+  // compiler would hoist every pass's twiddle loads and address arithmetic
+  // out of the caller's spectrum loop and keep them live in registers.
+  // Hiding the values here (LN) keeps that work inside the pass, for blocks
+  // whose register budget cannot afford to keep them.
+  if constexpr (LN) {
+    asm volatile("" : "+s"(tw));
+    asm volatile("" : "+v"(tid));
+  }
+  constexpr int Q = V / R;   // butterflies per thread
   constexpr int NB = N / R;  // butterflies per transform
+  static_assert(Q >= 1, "radix larger than the values a thread holds");
   float2 v[Q][R];
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const int q = tid + i * NT;
     const int f = q / NB, j = q % NB;
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[i][r] = buf[lds_pad(f * N + j + r * NB)];
+    for (int r = 0; r < R; ++r) v[i][r] = src[lds_pad(f * N + j + r * NB)];
   }
-  __syncthreads();
+  if constexpr (INPLACE) __syncthreads();
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const int q = tid + i * NT;
@@ -144,28 +157,58 @@ __device__ __forceinline__ void stockham_pass(float2* buf, const float2* __restr
     dft_r<R>(v[i]);
     const int k = (j / NS) * NS * R + jm;
 #pragma unroll
-    for (int r = 0; r < R; ++r) buf[lds_pad(f * N + k + r * NS)] = v[i][r];
+    for (int r = 0; r < R; ++r) dst[lds_pad(f * N + k + r * NS)] = v[i][r];
   }
   __syncthreads();
 }
 
-template <int N, int NS, int NT>
-__device__ __forceinline__ void fft_passes(float2* buf, const float2* __restrict__ tw, int tid) {
+constexpr int fft_radix(int rem, int V) { return rem >= V ? V : rem; }
+
+constexpr int fft_pass_count(int N, int V) {
+  int c = 0;
+  for (int ns = 1; N / ns > 1; ns *= fft_radix(N / ns, V)) ++c;
+  return c;
+}
+
+// Passes NS.. of a Stockham FFT.  PP selects ping-pong buffers: pass p reads
+// buffer p%2 and writes buffer (p+1)%2 (one barrier per pass); without PP
+// every pass works in place in buffer 0 (two barriers per pass).
+template <int N, int NS, int NT, int V, bool PP, bool LN, int PASS>
+__device__ __forceinline__ void fft_passes(float2* b0, float2* b1, const float2* __restrict__ tw,
+                                           int tid) {
   constexpr int REM = N / NS;
   if constexpr (REM > 1) {
-    constexpr int R = REM >= 16 ? 16 : REM;
-    stockham_pass<N, R, NS, NT>(buf, tw, tid);
-    fft_passes<N, NS * R, NT>(buf, tw, tid);
+    constexpr int R = fft_radix(REM, V);
+    if constexpr (PP) {
+      float2* src = (PASS % 2 == 0) ? b0 : b1;
+      float2* dst = (PASS % 2 == 0) ? b1 : b0;
+      stockham_pass<N, R, NS, NT, V, false, LN>(src, dst, tw, tid);
+    } else {
+      stockham_pass<N, R, NS, NT, V, true, LN>(b0, b0, tw, tid);
+    }
+    fft_passes<N, NS * R, NT, V, PP, LN, PASS + 1>(b0, b1, tw, tid);
   }
 }
 
-// NFFT forward transforms of length N, in place in `buf` (padded layout),
-// natural order in and out.  tw[e] = exp(-2 pi i e / N), e = 0..N-1.
-// Must be called by all NT = NFFT*N/16 threads of the block; begins and
-// ends with the block synchronised.
+// NFFT forward transforms of length N, natural order in and out, each
+// thread holding V values per pass (NT = NFFT*N/V threads).  The input is
+// read from b0; the output is in b0, or in b(fft_pass_count % 2) with
+// ping-pong.  Must be called by all NT threads of the block; begins with
+// the block synchronised and ends with a barrier.
+template <int N, int NT, int V, bool PP, bool LN = false>
+struct Fft {
+  static constexpr int PASSES = fft_pass_count(N, V);
+  static constexpr int OUT = PP ? (PASSES % 2) : 0;
+  static __device__ __forceinline__ void run(float2* b0, float2* b1, const float2* __restrict__ tw,
+                                             int tid) {
+    fft_passes<N, 1, NT, V, PP, LN, 0>(b0, b1, tw, tid);
+  }
+};
+
+// In-place, 16 values per thread (NT = NFFT*N/16).
 template <int N, int NT>
 __device__ __forceinline__ void fft_lds(float2* buf, const float2* __restrict__ tw, int tid) {
-  fft_passes<N, 1, NT>(buf, tw, tid);
+  Fft<N, NT, 16, false, (NT >= 1024)>::run(buf, buf, tw, tid);
 }
 
 }  // namespace qc

@@ -79,27 +79,77 @@ __device__ __forceinline__ void separate(float2 zk, float2 zn, float2& ya, float
 
 // ---------------------------------------------------------------------------
 // Fused F+X: NA antennas (NP = ceil(NA/2) packed transforms), S spectra in
-// flight, NT = NP*S*N/16 threads.  Grid: n_dump * chunks_per_dump blocks.
+// flight, V complex values per thread per FFT pass (NT = NP*S*N/V threads),
+// optional ping-pong LDS buffers (PP) and a compile-time tap count (P > 0;
+// P = 0 reads it at run time).  Grid: n_dump * chunks_per_dump blocks.
 // ---------------------------------------------------------------------------
-template <int N, int NA, int S>
+template <int N, int NA, int S, int V, bool PP, int OCC = 0>
 struct FusedCfg {
   static constexpr int NP = (NA + 1) / 2;
   static constexpr int NFFT = NP * S;
-  static constexpr int NT = NFFT * N / 16;
+  static constexpr int NT = NFFT * N / V;
   static constexpr int NCH = N / 2;
   static constexpr int NB = NA * (NA + 1) / 2;
   static constexpr int CPT = (NCH + NT - 1) / NT;
-  static constexpr int LDS = lds_padded_size(NFFT * N);
+  static constexpr int BUF = lds_padded_size(NFFT * N);
+  static constexpr int LDS = (PP ? 2 : 1) * BUF;
+  static constexpr int CHUNKS = V / 4;  // FIR chunks of 4 samples per thread
+  // hide loop-invariant address/twiddle work from hoisting when the
+  // register budget is 128 per lane or less
+  static constexpr bool LN = NT >= 1024 || OCC >= 4;
 };
 
-template <int N, int NA, int S>
-__global__ void __launch_bounds__((FusedCfg<N, NA, S>::NT))
+// FIR for 4 consecutive samples of antennas a0 (real part) and a1 (imaginary
+// part; none when a1 < 0), stream block blk0 = m - P + 1 of spectrum m.
+template <int PT>
+__device__ __forceinline__ void fir4_t(const int8_t* __restrict__ xa0, const int8_t* __restrict__ xa1,
+                                       const int8_t* __restrict__ ha0, const int8_t* __restrict__ ha1,
+                                       const float* __restrict__ taps, int P_rt, int64_t blk0, int n0,
+                                       int N, float2 out[4]) {
+  const int P = PT > 0 ? PT : P_rt;
+  float y0[4] = {0.f, 0.f, 0.f, 0.f}, y1[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int q = 0; q < (PT > 0 ? PT : 16); ++q) {
+    if (PT == 0 && q >= P) break;
+    const int64_t blk = blk0 + q;
+    const float4 h = *reinterpret_cast<const float4*>(taps + q * N + n0);
+    uint32_t w0, w1 = 0u;
+    if (blk >= 0) {
+      const int off = (int)blk * N + n0;
+      w0 = *reinterpret_cast<const uint32_t*>(xa0 + off);
+      if (xa1) w1 = *reinterpret_cast<const uint32_t*>(xa1 + off);
+    } else if (ha0) {
+      const int off = (int)(blk + (P - 1)) * N + n0;
+      w0 = *reinterpret_cast<const uint32_t*>(ha0 + off);
+      if (ha1) w1 = *reinterpret_cast<const uint32_t*>(ha1 + off);
+    } else {
+      w0 = 0u;
+    }
+    y0[0] += h.x * sbyte(w0, 0);
+    y0[1] += h.y * sbyte(w0, 1);
+    y0[2] += h.z * sbyte(w0, 2);
+    y0[3] += h.w * sbyte(w0, 3);
+    y1[0] += h.x * sbyte(w1, 0);
+    y1[1] += h.y * sbyte(w1, 1);
+    y1[2] += h.z * sbyte(w1, 2);
+    y1[3] += h.w * sbyte(w1, 3);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) out[i] = make_float2(y0[i], y1[i]);
+}
+
+template <int N, int NA, int S, int V, bool PP, int OCC, int PT>
+__global__ void __launch_bounds__((FusedCfg<N, NA, S, V, PP, OCC>::NT), (OCC > 0 ? OCC : 1))
 fx_fused_kernel(const int8_t* __restrict__ x, int64_t ld_x, const int8_t* __restrict__ hist,
-                const float* __restrict__ taps, int P, const float2* __restrict__ tw,
+                const float* __restrict__ taps, int P_rt, const float2* __restrict__ tw,
                 int64_t spec_per_dump, int64_t cpd, float2* __restrict__ part) {
-  using C = FusedCfg<N, NA, S>;
+  using C = FusedCfg<N, NA, S, V, PP, OCC>;
+  using F = Fft<N, C::NT, V, PP, C::LN>;
   extern __shared__ float2 buf[];
-  const int tid = threadIdx.x;
+  float2* b0 = buf;
+  float2* b1 = buf + (PP ? C::BUF : 0);
+  const float2* bout = F::OUT ? b1 : b0;
+  const int P = PT > 0 ? PT : P_rt;
   const int64_t w = blockIdx.x;
   const int64_t d = w / cpd, c = w % cpd;
   const int64_t m_lo = d * spec_per_dump + (c * spec_per_dump) / cpd;
@@ -112,26 +162,34 @@ fx_fused_kernel(const int8_t* __restrict__ x, int64_t ld_x, const int8_t* __rest
     for (int b = 0; b < C::NB; ++b) acc[cc][b] = make_float2(0.f, 0.f);
 
   for (int64_t m0 = m_lo; m0 < m_hi; m0 += S) {
-    // polyphase FIR into the packed transform inputs
-#pragma unroll
-    for (int g = 0; g < 4; ++g) {
+    int tid = threadIdx.x;  // per iteration: see the note in stockham_pass
+    if constexpr (C::LN) asm volatile("" : "+v"(tid));
+    // polyphase FIR into the packed transform inputs (buffer 0); one chunk
+    // at a time keeps the tap and sample registers of only one chunk live
+#pragma unroll 1
+    for (int g = 0; g < C::CHUNKS; ++g) {
       const int c4 = tid + g * C::NT;
       const int f = c4 / (N / 4);
       const int n0 = 4 * (c4 % (N / 4));
       const int s = f / C::NP, p = f % C::NP;
       const int64_t m = m0 + s;
+      const int a0 = 2 * p, a1 = (2 * p + 1 < NA) ? 2 * p + 1 : -1;
       float2 y[4];
       if (m < m_hi) {
-        fir4(x, ld_x, hist, taps, 2 * p, (2 * p + 1 < NA) ? 2 * p + 1 : -1, m, n0, N, P, y);
+        const int8_t* xa0 = x + (int64_t)a0 * ld_x;
+        const int8_t* xa1 = a1 >= 0 ? x + (int64_t)a1 * ld_x : nullptr;
+        const int8_t* ha0 = hist ? hist + (int64_t)a0 * (P - 1) * N : nullptr;
+        const int8_t* ha1 = (hist && a1 >= 0) ? hist + (int64_t)a1 * (P - 1) * N : nullptr;
+        fir4_t<PT>(xa0, xa1, ha0, ha1, taps, P, m - P + 1, n0, N, y);
       } else {
 #pragma unroll
         for (int i = 0; i < 4; ++i) y[i] = make_float2(0.f, 0.f);
       }
 #pragma unroll
-      for (int i = 0; i < 4; ++i) buf[lds_pad(f * N + n0 + i)] = y[i];
+      for (int i = 0; i < 4; ++i) b0[lds_pad(f * N + n0 + i)] = y[i];
     }
     __syncthreads();
-    fft_lds<N, C::NT>(buf, tw, tid);
+    F::run(b0, b1, tw, tid);
     // separate and cross-multiply
 #pragma unroll
     for (int cc = 0; cc < C::CPT; ++cc) {
@@ -144,8 +202,8 @@ fx_fused_kernel(const int8_t* __restrict__ x, int64_t ld_x, const int8_t* __rest
             float2 X[2 * C::NP];
 #pragma unroll
             for (int p = 0; p < C::NP; ++p) {
-              const float2 zk = buf[lds_pad((s * C::NP + p) * N + k)];
-              const float2 zn = buf[lds_pad((s * C::NP + p) * N + kn)];
+              const float2 zk = bout[lds_pad((s * C::NP + p) * N + k)];
+              const float2 zn = bout[lds_pad((s * C::NP + p) * N + kn)];
               separate(zk, zn, X[2 * p], X[2 * p + 1]);
             }
             int b = 0;
@@ -164,12 +222,15 @@ fx_fused_kernel(const int8_t* __restrict__ x, int64_t ld_x, const int8_t* __rest
         }
       }
     }
-    __syncthreads();
+    // with an in-place transform (or an output in buffer 0) the next FIR
+    // overwrites what was just read; with the output in buffer 1 the next
+    // FIR writes buffer 0, last read before the final pass's barrier
+    if constexpr (F::OUT == 0) __syncthreads();
   }
   float2* out = part + w * (int64_t)C::NB * C::NCH;
 #pragma unroll
   for (int cc = 0; cc < C::CPT; ++cc) {
-    const int k = tid + cc * C::NT;
+    const int k = (int)threadIdx.x + cc * C::NT;
     if (C::NCH % C::NT == 0 || k < C::NCH) {
 #pragma unroll
       for (int b = 0; b < C::NB; ++b) out[(int64_t)b * C::NCH + k] = acc[cc][b];
@@ -177,12 +238,12 @@ fx_fused_kernel(const int8_t* __restrict__ x, int64_t ld_x, const int8_t* __rest
   }
 }
 
-template <int N, int NA, int S>
+template <int N, int NA, int S, int V, bool PP, int OCC, int PT>
 static hipError_t launch_fused_t(const FxArgs& a, int64_t n_dump, int64_t spd, int64_t cpd,
                                  float2* part, hipStream_t s) {
-  using C = FusedCfg<N, NA, S>;
+  using C = FusedCfg<N, NA, S, V, PP, OCC>;
   const size_t lds = sizeof(float2) * C::LDS;
-  auto kern = fx_fused_kernel<N, NA, S>;
+  auto kern = fx_fused_kernel<N, NA, S, V, PP, OCC, PT>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
@@ -191,12 +252,77 @@ static hipError_t launch_fused_t(const FxArgs& a, int64_t n_dump, int64_t spd, i
   return hipGetLastError();
 }
 
-bool fused_supported(int n_fft, int n_ant) {
-  if (n_ant == 4) return n_fft == 1024 || n_fft == 4096 || n_fft == 2048 || n_fft == 512;
-  if (n_ant == 8) return n_fft == 2048 || n_fft == 1024;
-  if (n_ant == 2) return n_fft == 4096 || n_fft == 1024;
-  return false;
+template <int N, int NA, int S, int V, bool PP, int OCC>
+static hipError_t launch_fused_p(const FxArgs& a, int64_t n_dump, int64_t spd, int64_t cpd,
+                                 float2* part, hipStream_t s) {
+  using C = FusedCfg<N, NA, S, V, PP, OCC>;
+  static_assert(C::NT >= 64 && C::NT <= 1024, "fused tile: threads per block");
+  static_assert(C::LDS * sizeof(float2) <= 160 * 1024, "fused tile: LDS");
+  if (a.n_taps == 4) return launch_fused_t<N, NA, S, V, PP, OCC, 4>(a, n_dump, spd, cpd, part, s);
+  return launch_fused_t<N, NA, S, V, PP, OCC, 0>(a, n_dump, spd, cpd, part, s);
 }
+
+// Tile shapes of the fused kernel per (n_fft, n_ant): spectra in flight S,
+// values per thread per FFT pass V, ping-pong LDS buffers PP.  Entry 0 is
+// the default; the others are the candidates an autotuner may time.
+struct FusedTile {
+  int S, V;
+  bool PP;
+  int OCC;  // minimum waves per SIMD requested from the compiler (0: none)
+};
+
+template <int N, int NA>
+struct TileList {
+  static constexpr int count = 0;
+  static constexpr FusedTile tiles[1] = {{1, 16, false, 0}};
+};
+#define QC_TILES(NN, NAA, ...)                                                  \
+  template <>                                                                   \
+  struct TileList<NN, NAA> {                                                    \
+    static constexpr FusedTile tiles[] = {__VA_ARGS__};                         \
+    static constexpr int count = (int)(sizeof(tiles) / sizeof(tiles[0]));       \
+  };
+QC_TILES(4096, 4, {1, 16, true, 0}, {1, 16, false, 0}, {2, 16, false, 0}, {1, 8, true, 0},
+         {1, 16, false, 4})
+QC_TILES(1024, 4, {2, 16, true, 0}, {2, 16, false, 0}, {4, 16, false, 0}, {2, 8, true, 0},
+         {1, 16, true, 4}, {2, 16, false, 4})
+QC_TILES(2048, 4, {1, 16, true, 0}, {1, 16, false, 0}, {1, 16, false, 4}, {1, 8, true, 0})
+QC_TILES(512, 4, {4, 16, true, 0}, {4, 16, false, 0}, {2, 16, true, 4})
+QC_TILES(1024, 8, {1, 16, true, 0}, {1, 8, true, 0})
+QC_TILES(2048, 8, {1, 8, true, 0}, {1, 8, false, 0})
+QC_TILES(1024, 2, {4, 16, true, 0}, {4, 16, false, 0}, {2, 16, true, 4})
+QC_TILES(4096, 2, {1, 16, true, 0}, {1, 16, false, 0}, {1, 16, false, 4})
+#undef QC_TILES
+
+template <int N, int NA, int I>
+static hipError_t dispatch_tile(int tile, const FxArgs& a, int64_t n_dump, int64_t spd, int64_t cpd,
+                                float2* part, hipStream_t s) {
+  if constexpr (I >= TileList<N, NA>::count) {
+    return hipErrorInvalidValue;
+  } else {
+    if (tile == I) {
+      constexpr FusedTile t = TileList<N, NA>::tiles[I];
+      return launch_fused_p<N, NA, t.S, t.V, t.PP, t.OCC>(a, n_dump, spd, cpd, part, s);
+    }
+    return dispatch_tile<N, NA, I + 1>(tile, a, n_dump, spd, cpd, part, s);
+  }
+}
+
+template <int N, int NA>
+static int tile_count() {
+  return TileList<N, NA>::count;
+}
+
+int fused_tile_count(int n_fft, int n_ant) {
+#define QC_CASE(NN, NAA) \
+  if (n_fft == NN && n_ant == NAA) return tile_count<NN, NAA>();
+  QC_CASE(4096, 4) QC_CASE(1024, 4) QC_CASE(2048, 4) QC_CASE(512, 4)
+  QC_CASE(1024, 8) QC_CASE(2048, 8) QC_CASE(1024, 2) QC_CASE(4096, 2)
+#undef QC_CASE
+  return 0;
+}
+
+bool fused_supported(int n_fft, int n_ant) { return fused_tile_count(n_fft, n_ant) > 0; }
 
 int64_t fused_chunks_per_dump(int n_fft, int n_ant, int64_t n_dump, int64_t spd) {
   // aim for ~2 waves of workgroups over 256 CUs, at least 8 spectra each
@@ -207,25 +333,13 @@ int64_t fused_chunks_per_dump(int n_fft, int n_ant, int64_t n_dump, int64_t spd)
 }
 
 hipError_t launch_fused(const FxArgs& a, int64_t n_dump, int64_t spd, int64_t cpd, float2* part,
-                        hipStream_t s) {
-  if (a.n_ant == 4) {
-    switch (a.n_fft) {
-      case 512: return launch_fused_t<512, 4, 4>(a, n_dump, spd, cpd, part, s);
-      case 1024: return launch_fused_t<1024, 4, 2>(a, n_dump, spd, cpd, part, s);
-      case 2048: return launch_fused_t<2048, 4, 1>(a, n_dump, spd, cpd, part, s);
-      case 4096: return launch_fused_t<4096, 4, 1>(a, n_dump, spd, cpd, part, s);
-    }
-  } else if (a.n_ant == 8) {
-    switch (a.n_fft) {
-      case 1024: return launch_fused_t<1024, 8, 1>(a, n_dump, spd, cpd, part, s);
-      case 2048: return launch_fused_t<2048, 8, 1>(a, n_dump, spd, cpd, part, s);
-    }
-  } else if (a.n_ant == 2) {
-    switch (a.n_fft) {
-      case 1024: return launch_fused_t<1024, 2, 4>(a, n_dump, spd, cpd, part, s);
-      case 4096: return launch_fused_t<4096, 2, 1>(a, n_dump, spd, cpd, part, s);
-    }
-  }
+                        hipStream_t s, int tile) {
+#define QC_CASE(NN, NAA)                 \
+  if (a.n_fft == NN && a.n_ant == NAA) \
+    return dispatch_tile<NN, NAA, 0>(tile, a, n_dump, spd, cpd, part, s);
+  QC_CASE(4096, 4) QC_CASE(1024, 4) QC_CASE(2048, 4) QC_CASE(512, 4)
+  QC_CASE(1024, 8) QC_CASE(2048, 8) QC_CASE(1024, 2) QC_CASE(4096, 2)
+#undef QC_CASE
   return hipErrorInvalidValue;
 }
 

@@ -20,9 +20,11 @@ struct FxArgs {
 // Fused F+X for small arrays.  Returns false if no fused kernel exists for
 // (n_fft, n_ant); part must hold fused_part_elems() float2.
 bool fused_supported(int n_fft, int n_ant);
+int fused_tile_count(int n_fft, int n_ant);
 int64_t fused_chunks_per_dump(int n_fft, int n_ant, int64_t n_dump, int64_t spec_per_dump);
+// tile: index into the (n_fft, n_ant) tile list; 0 is the default shape.
 hipError_t launch_fused(const FxArgs& a, int64_t n_dump, int64_t spec_per_dump,
-                        int64_t chunks_per_dump, float2* part, hipStream_t s);
+                        int64_t chunks_per_dump, float2* part, hipStream_t s, int tile);
 
 // Deterministic reduction of per-chunk partials:
 // vis[d][e] = (accumulate ? vis[d][e] : 0) + scale * sum_c part[d*cpd + c][e].

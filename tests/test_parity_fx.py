@@ -149,3 +149,42 @@ def test_extreme_values(qc):
     V_ref = _oracle_vis(x, N, 4, 16)
     V = _gpu_vis(qc, x, N, 4, 16)
     assert vis_err(V, V_ref, n_ant) <= TOL
+
+
+FUSED_PAIRS = [(4096, 4), (1024, 4), (2048, 4), (512, 4), (1024, 8), (2048, 8), (1024, 2), (4096, 2)]
+
+
+@pytest.mark.parametrize("N,n_ant", FUSED_PAIRS)
+def test_every_fused_tile_matches_oracle(qc, N, n_ant):
+    """Every tile shape of the fused kernel computes the same sums."""
+    import torch
+    P, spd, n_spec = 4, 9, 21
+    x = _stream(n_ant, N * n_spec, seed=40 + N + n_ant)
+    chans = _chans(N, n=24)
+    V_ref = _oracle_vis(x, N, P, spd, chans=chans)
+    xd = torch.from_numpy(x).cuda()
+    n = qc.fx_tile_count(N, n_ant)
+    assert n >= 1
+    try:
+        for t in range(n):
+            qc.fx_set_tile(N, n_ant, t)
+            V = qc.xcorrelate(xd, N, P, spd).cpu().numpy()[:, :, chans]
+            assert vis_err(V, V_ref, n_ant) <= TOL, (t, vis_err(V, V_ref, n_ant))
+            # and with a run-time tap count
+            if t == 0:
+                V3 = qc.xcorrelate(xd, N, 3, spd).cpu().numpy()[:, :, chans]
+                R3 = _oracle_vis(x, N, 3, spd, chans=chans)
+                assert vis_err(V3, R3, n_ant) <= TOL
+    finally:
+        qc.fx_set_tile(N, n_ant, 0)
+
+
+def test_autotune_picks_a_tile(qc):
+    import torch
+    x = torch.from_numpy(_stream(4, 1024 * 64, seed=3)).cuda()
+    best, ms = qc.fx_autotune(x, 1024, 4, 32, reps=2)
+    assert 0 <= best < qc.fx_tile_count(1024, 4) and len(ms) == qc.fx_tile_count(1024, 4)
+    assert qc.fx_get_tile(1024, 4) == best and min(ms) == ms[best] and all(m > 0 for m in ms)
+    qc.fx_set_tile(1024, 4, 0)
+    with pytest.raises(qc.QCError):
+        qc.fx_set_tile(1024, 4, 99)
