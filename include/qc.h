@@ -77,7 +77,7 @@ typedef struct {
 /* F-engine alone (Sec. 4.2 "F-engine", Alg. 1 F-Engine step).
  *   x       : device int8, antenna stride ld_x bytes (ld_x >= n_samp, ld_x % 4 == 0,
  *             x 4-byte aligned).
- *   n_samp  : samples per antenna, a multiple of n_fft.
+ *   n_samp  : samples per antenna, a multiple of n_fft, below 2^31.
  *   hist    : device int8 [n_ant][(P-1)*N] samples preceding x, or NULL (zeros).
  *   hist_out: device int8 [n_ant][(P-1)*N] receives the last (P-1)*N samples of
  *             (hist ++ x) for the next call, or NULL.  May not alias hist.
@@ -147,6 +147,27 @@ qc_status qc_mad_flag(const float* vis, int64_t n_time, int64_t n_base, int32_t 
 qc_status qc_apply_delay_phase(float* vis, int64_t n_time, int32_t n_ant, int32_t n_chan,
                                double f0_hz, double df_hz, const double* tau_s,
                                const double* phi_rad, void* stream);
+
+/* Delay and phase calibration solve (Sec. 7, the three serial steps: coarse
+ * group delay from the delay-spectrum peak, fine delay from a weighted fit
+ * of unwrapped phase against frequency in a clean band (eq. 3), residual
+ * phase from the band's mean complex vector).  Per baseline the visibilities
+ * are summed over time with flagged cells (mask != 0) left out; the delay
+ * spectrum has n_lag lags, the smallest power of two >= lag_pad*n_chan, at
+ * most 8192 (and at least n_chan).  Phases and the delay spectrum are
+ * float32; the least-squares sums and solves are float64.  The per-antenna
+ * solution is the float64 least-squares fit of tau_i - tau_j over the cross
+ * baselines with tau_ref = phi_ref = 0, in the sign convention of
+ * qc_apply_delay_phase (applying the result flattens the phases).
+ *   vis   : device cfloat [n_time][n_ant(n_ant+1)/2][n_chan]; mask: device
+ *           uint8 of the same shape, or NULL.
+ *   band  : channels [chan_lo, chan_hi), at least two.
+ *   tau_s, phi_rad: HOST double[n_ant] outputs.  Synchronises `stream`.
+ *   2 <= n_ant <= 64, 4 <= n_chan <= 4096. */
+qc_status qc_solve_delay_phase(const float* vis, const uint8_t* mask, int64_t n_time, int32_t n_ant,
+                               int32_t n_chan, double f0_hz, double df_hz, int32_t ref_ant,
+                               int32_t chan_lo, int32_t chan_hi, int32_t lag_pad, double* tau_s,
+                               double* phi_rad, void* stream);
 
 /* Streaming ingest (Alg. 1: pinned host buffers, asynchronous host-to-device
  * copies on a stream, then F-engine, X-engine and integration; Sec. 4.2

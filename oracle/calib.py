@@ -24,8 +24,11 @@ baselines with a reference antenna held at zero.
 
 Readings (not fixed by the paper): visibilities are integrated over time
 with flagged cells zeroed before the solve; the delay spectrum is a direct
-transform on a grid of n_lag = lag_pad * n_chan lags; fit weights are the
-amplitudes of the time-integrated, flag-zeroed visibilities.
+transform on a grid of n_lag lags, n_lag the smallest power of two at least
+lag_pad * n_chan, at most 8192 (and at least n_chan); fit weights are the
+amplitudes of the time-integrated, flag-zeroed visibilities; the phase is
+unwrapped as numpy.unwrap does (a step of magnitude above pi gets a 2 pi
+correction of the opposite sign).
 Status: pinned on noiseless synthetic phases (tests/test_oracle.py).
 """
 
@@ -63,6 +66,17 @@ def delay_spectrum(Vb, n_lag: int) -> np.ndarray:
     return np.exp(2j * np.pi * ph) @ Vb
 
 
+def lag_grid(n_chan: int, lag_pad: int = 4) -> int:
+    """Number of lags of the delay spectrum (see the module's readings)."""
+    n = 1
+    while n < lag_pad * n_chan:
+        n *= 2
+    n = min(n, 8192)
+    while n < n_chan:
+        n *= 2
+    return n
+
+
 def solve_baseline(Vb, f0, df, chan_lo, chan_hi, lag_pad: int = 4):
     """(tau, phi) for one baseline's time-integrated spectrum Vb[k].
 
@@ -70,7 +84,7 @@ def solve_baseline(Vb, f0, df, chan_lo, chan_hi, lag_pad: int = 4):
     """
     Vb = np.asarray(Vb, np.complex128)
     n_chan = Vb.size
-    n_lag = lag_pad * n_chan
+    n_lag = lag_grid(n_chan, lag_pad)
     f = f0 + np.arange(n_chan, dtype=np.float64) * df
     # step 1: coarse delay from the delay-spectrum peak
     D = np.abs(delay_spectrum(Vb, n_lag))

@@ -15,7 +15,7 @@ import torch
 
 __all__ = [
     "QCError", "lib", "pfb_channelize", "xcorrelate", "xcorrelate_chan", "mad_flag",
-    "apply_delay_phase", "n_base", "PREC", "timing_enable", "timing_read", "KERNELS", "Stream",
+    "apply_delay_phase", "n_base", "PREC", "timing_enable", "timing_read", "KERNELS", "Stream", "solve_delay_phase",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -91,6 +91,10 @@ def lib() -> ctypes.CDLL:
         L.qc_fx_autotune.argtypes = [_P, _I64, _I32, _I64, ctypes.POINTER(PfbParams), _I64, _I32, _P,
                                      ctypes.POINTER(ctypes.c_double), _I32, ctypes.POINTER(_I32), _P]
         L.qc_fx_autotune.restype = ctypes.c_int32
+        L.qc_solve_delay_phase.argtypes = [_P, _P, _I64, _I32, _I32, ctypes.c_double, ctypes.c_double,
+                                           _I32, _I32, _I32, _I32, ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(ctypes.c_double), _P]
+        L.qc_solve_delay_phase.restype = ctypes.c_int32
         L.qc_timing_enable.argtypes = [ctypes.c_int32]
         L.qc_timing_enable.restype = ctypes.c_int32
         L.qc_timing_read.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
@@ -180,6 +184,22 @@ def timing_read(kernel: str):
     ms, n = ctypes.c_double(0.0), ctypes.c_int64(0)
     _check(lib().qc_timing_read(KERNELS[kernel], ctypes.byref(ms), ctypes.byref(n)), "qc_timing_read")
     return ms.value, n.value
+
+
+def solve_delay_phase(vis, n_ant, f0_hz, df_hz, ref_ant, chan_lo, chan_hi, mask=None, lag_pad=4):
+    """Per-antenna (tau_s, phi_rad) numpy arrays from complex64 vis [n_time, n_base, n_chan]."""
+    import numpy as np
+    assert vis.dtype == torch.complex64 and vis.is_cuda and vis.is_contiguous()
+    n_time, nb, n_chan = vis.shape
+    assert nb == n_base(n_ant)
+    if mask is not None:
+        assert mask.dtype == torch.uint8 and mask.shape == vis.shape and mask.is_contiguous()
+    tau = (ctypes.c_double * n_ant)()
+    phi = (ctypes.c_double * n_ant)()
+    _check(lib().qc_solve_delay_phase(_ptr(vis), _ptr(mask), n_time, n_ant, n_chan, float(f0_hz),
+                                      float(df_hz), ref_ant, chan_lo, chan_hi, lag_pad, tau, phi,
+                                      _stream()), "qc_solve_delay_phase")
+    return np.array(list(tau)), np.array(list(phi))
 
 
 def fx_tile_count(n_fft: int, n_ant: int) -> int:

@@ -158,6 +158,7 @@ qc_status check_stream_args(const int8_t* x, int64_t ld_x, int32_t n_ant, int64_
   if (n_samp < 0 || n_samp % p->n_fft)
     return fail(QC_EINVAL, "n_samp (%lld) must be a non-negative multiple of n_fft (%d)",
                 (long long)n_samp, p->n_fft);
+  if (n_samp > 0x7fffffffLL) return fail(QC_EINVAL, "n_samp must be below 2^31 per antenna");
   if (n_samp > 0 && !x) return fail(QC_EINVAL, "x is NULL");
   if (ld_x < n_samp || (ld_x & 3)) return fail(QC_EINVAL, "ld_x must be >= n_samp and a multiple of 4");
   if (reinterpret_cast<uintptr_t>(x) & 3u) return fail(QC_EINVAL, "x must be 4-byte aligned");
@@ -185,7 +186,7 @@ qc_status resolve(const int8_t* x, int64_t ld_x, int32_t n_ant, int64_t n_samp,
     taps = e.dev;
     s2 = e.sum_h2;
   }
-  r->args = qc::FxArgs{x, ld_x, n_ant, n_samp, p->n_fft, p->n_taps, taps, tw, hist};
+  r->args = qc::FxArgs{x, ld_x, n_ant, n_samp, p->n_fft, p->n_taps, taps, tw, hist, p->taps == nullptr};
   r->sum_h2 = s2;
   return QC_OK;
 }
@@ -482,6 +483,49 @@ qc_status qc_apply_delay_phase(float* vis, int64_t n_time, int32_t n_ant, int32_
   QC_HIP(qc::launch_apply(reinterpret_cast<float2*>(vis), n_time, n_ant, n_chan, f0_hz, df_hz, tau_s,
                           phi_rad, reinterpret_cast<hipStream_t>(stream)),
          "apply kernel");
+  return QC_OK;
+}
+
+qc_status qc_solve_delay_phase(const float* vis, const uint8_t* mask, int64_t n_time, int32_t n_ant,
+                               int32_t n_chan, double f0_hz, double df_hz, int32_t ref_ant,
+                               int32_t chan_lo, int32_t chan_hi, int32_t lag_pad, double* tau_s,
+                               double* phi_rad, void* stream) {
+  g_err.clear();
+  if (n_ant < 2 || n_ant > 64) return fail(QC_EINVAL, "n_ant must be in [2, 64]");
+  if (n_chan < 4 || n_chan > 4096) return fail(QC_EINVAL, "n_chan must be in [4, 4096]");
+  if (n_time < 1) return fail(QC_EINVAL, "n_time must be >= 1");
+  if (chan_lo < 0 || chan_hi > n_chan || chan_hi - chan_lo < 2)
+    return fail(QC_EINVAL, "need 0 <= chan_lo, chan_hi <= n_chan and at least two band channels");
+  if (ref_ant < 0 || ref_ant >= n_ant) return fail(QC_EINVAL, "ref_ant out of range");
+  if (lag_pad < 1 || lag_pad > 64) return fail(QC_EINVAL, "lag_pad must be in [1, 64]");
+  if (!std::isfinite(f0_hz) || !std::isfinite(df_hz) || !(df_hz > 0.0))
+    return fail(QC_EINVAL, "f0 must be finite and df positive");
+  if (!vis || !tau_s || !phi_rad) return fail(QC_EINVAL, "NULL argument");
+  if (reinterpret_cast<uintptr_t>(vis) & 7u) return fail(QC_EINVAL, "vis must be 8-byte aligned");
+  // lag grid: smallest power of two >= lag_pad * n_chan, at most 8192, at least n_chan
+  int n_lag = 1;
+  while (n_lag < lag_pad * n_chan) n_lag *= 2;
+  if (n_lag > 8192) n_lag = 8192;
+  while (n_lag < n_chan) n_lag *= 2;
+  if (n_lag < 16) n_lag = 16;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  float2* tw = nullptr;
+  qc_status st = get_twiddles(n_lag, &tw);
+  if (st != QC_OK) return st;
+  const int n_cross = n_ant * (n_ant - 1) / 2;
+  AsyncBuf scratch;
+  st = alloc_async(scratch, sizeof(double) * (2 * n_cross + 2 * n_ant), s);
+  if (st != QC_OK) return st;
+  double* tb = (double*)scratch.p;
+  double* pb = tb + n_cross;
+  double* ta = pb + n_cross;
+  double* pa = ta + n_ant;
+  QC_HIP(qc::launch_solve(reinterpret_cast<const float2*>(vis), mask, n_time, n_ant, n_chan, f0_hz, df_hz,
+                          ref_ant, chan_lo, chan_hi, n_lag, tw, tb, pb, ta, pa, s),
+         "solve kernels");
+  QC_HIP(hipMemcpyAsync(tau_s, ta, sizeof(double) * n_ant, hipMemcpyDeviceToHost, s), "copy tau");
+  QC_HIP(hipMemcpyAsync(phi_rad, pa, sizeof(double) * n_ant, hipMemcpyDeviceToHost, s), "copy phi");
+  QC_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
   return QC_OK;
 }
 

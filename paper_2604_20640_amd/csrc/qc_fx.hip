@@ -238,6 +238,184 @@ fx_fused_kernel(const int8_t* __restrict__ x, int64_t ld_x, const int8_t* __rest
   }
 }
 
+// Ring variant of the fused kernel (one spectrum in flight, compile-time P):
+// each thread keeps its samples of the last P blocks in a register ring and
+// prefetches the next block at the start of every spectrum, so the newest
+// block's memory latency is hidden behind the FFT and X steps; the taps are
+// read from LDS (loaded once per workgroup).  Sums are the same as the plain
+// variant's.
+template <int N, int NA, int V, int P>
+struct RingCfg {
+  using C = FusedCfg<N, NA, 1, V, false, 0>;
+  static constexpr int TAPS = P * N / 2;  // floats: half of a symmetric prototype
+  static constexpr size_t LDS_BYTES =
+      sizeof(float2) * (C::LDS + N) + sizeof(float) * TAPS;  // FFT, twiddles, taps
+};
+
+template <int N, int NA, int V, int P>
+__global__ void __launch_bounds__((FusedCfg<N, NA, 1, V, false, 0>::NT))
+fx_fused_ring_kernel(const int8_t* __restrict__ x, int64_t ld_x, const int8_t* __restrict__ hist,
+                     const float* __restrict__ taps, const float2* __restrict__ tw,
+                     int64_t spec_per_dump, int64_t cpd, float2* __restrict__ part) {
+  using C = FusedCfg<N, NA, 1, V, false, 0>;
+  using F = Fft<N, C::NT, V, false, false>;
+  constexpr int G = C::CHUNKS;
+  constexpr int L = P * N;
+  extern __shared__ float2 buf[];
+  float2* b0 = buf;
+  float2* twl = buf + C::LDS;                             // twiddles, N
+  float4* tl = reinterpret_cast<float4*>(twl + N);        // taps h[0 .. L/2)
+  const int tid = threadIdx.x;
+  const int64_t w = blockIdx.x;
+  const int64_t d = w / cpd, c = w % cpd;
+  const int64_t m_lo = d * spec_per_dump + (c * spec_per_dump) / cpd;
+  const int64_t m_hi = d * spec_per_dump + ((c + 1) * spec_per_dump) / cpd;
+
+  // the prototype is symmetric, h[q] = h[L-1-q]: keep its first half
+  for (int i = tid; i < L / 8; i += C::NT) tl[i] = reinterpret_cast<const float4*>(taps)[i];
+  for (int i = tid; i < N; i += C::NT) twl[i] = tw[i];
+
+  // this thread's FIR chunks: chunk g belongs to packed pair g / GP (a
+  // compile-time constant), so the antenna rows are wave-uniform and only
+  // the sample offset n0 varies per lane
+  constexpr int GP = G / C::NP;
+  static_assert(GP * C::NP == G && GP * C::NT * 4 == N, "ring chunk mapping");
+  int cn0[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) cn0[g] = 4 * (tid + (g % GP) * C::NT);
+  auto row = [&](int a) -> const int8_t* { return x + (int64_t)a * ld_x; };
+  auto hrow = [&](int a) -> const int8_t* {
+    return hist ? hist + (int64_t)a * (P - 1) * N : nullptr;
+  };
+  auto load_blk = [&](int g, int which, int64_t blk) -> uint32_t {
+    const int a = 2 * (g / GP) + which;
+    if (a >= NA) return 0u;
+    if (blk >= 0) return *reinterpret_cast<const uint32_t*>(row(a) + (int)blk * N + cn0[g]);
+    const int8_t* h = hrow(a);
+    if (!h) return 0u;
+    return *reinterpret_cast<const uint32_t*>(h + (int)(blk + P - 1) * N + cn0[g]);
+  };
+  uint32_t ring[P][G][2];
+#pragma unroll
+  for (int q = 0; q < P; ++q)
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int64_t blk = m_lo - P + 1 + q;
+      ring[q][g][0] = load_blk(g, 0, blk);
+      ring[q][g][1] = load_blk(g, 1, blk);
+    }
+
+  float2 acc[C::CPT][C::NB];
+#pragma unroll
+  for (int cc = 0; cc < C::CPT; ++cc)
+#pragma unroll
+    for (int b = 0; b < C::NB; ++b) acc[cc][b] = make_float2(0.f, 0.f);
+  __syncthreads();  // taps in LDS
+
+  for (int64_t m = m_lo; m < m_hi; ++m) {
+    // prefetch block m+1 (consumed at the end of this iteration)
+    uint32_t nxt[G][2];
+    const bool more = m + 1 < m_hi;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      nxt[g][0] = more ? load_blk(g, 0, m + 1) : 0u;
+      nxt[g][1] = more ? load_blk(g, 1, m + 1) : 0u;
+    }
+    // polyphase FIR from the ring
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      float y0[4] = {0.f, 0.f, 0.f, 0.f}, y1[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int q = 0; q < P; ++q) {
+        float4 h;
+        if (2 * q < P) {
+          h = tl[(q * N + cn0[g]) / 4];
+        } else {
+          // h[qN+n+i] = h[L-1-qN-n-i]: the mirrored float4, reversed
+          const float4 r = tl[(L - q * N - cn0[g] - 4) / 4];
+          h = make_float4(r.w, r.z, r.y, r.x);
+        }
+        const uint32_t w0 = ring[q][g][0], w1 = ring[q][g][1];
+        y0[0] += h.x * sbyte(w0, 0);
+        y0[1] += h.y * sbyte(w0, 1);
+        y0[2] += h.z * sbyte(w0, 2);
+        y0[3] += h.w * sbyte(w0, 3);
+        y1[0] += h.x * sbyte(w1, 0);
+        y1[1] += h.y * sbyte(w1, 1);
+        y1[2] += h.z * sbyte(w1, 2);
+        y1[3] += h.w * sbyte(w1, 3);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) b0[lds_pad((g / GP) * N + cn0[g] + i)] = make_float2(y0[i], y1[i]);
+    }
+    __syncthreads();
+    F::run(b0, b0, twl, tid);
+#pragma unroll
+    for (int cc = 0; cc < C::CPT; ++cc) {
+      const int k = tid + cc * C::NT;
+      if (C::NCH % C::NT == 0 || k < C::NCH) {
+        const int kn = (N - k) & (N - 1);
+        float2 X[2 * C::NP];
+#pragma unroll
+        for (int p = 0; p < C::NP; ++p) {
+          const float2 zk = b0[lds_pad(p * N + k)];
+          const float2 zn = b0[lds_pad(p * N + kn)];
+          separate(zk, zn, X[2 * p], X[2 * p + 1]);
+        }
+        int b = 0;
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+          acc[cc][b].x += X[i].x * X[i].x + X[i].y * X[i].y;
+          ++b;
+#pragma unroll
+          for (int j = i + 1; j < NA; ++j) {
+            acc[cc][b].x += X[i].x * X[j].x + X[i].y * X[j].y;
+            acc[cc][b].y += X[i].y * X[j].x - X[i].x * X[j].y;
+            ++b;
+          }
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q + 1 < P; ++q)
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        ring[q][g][0] = ring[q + 1][g][0];
+        ring[q][g][1] = ring[q + 1][g][1];
+      }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      ring[P - 1][g][0] = nxt[g][0];
+      ring[P - 1][g][1] = nxt[g][1];
+    }
+  }
+  float2* out = part + w * (int64_t)C::NB * C::NCH;
+#pragma unroll
+  for (int cc = 0; cc < C::CPT; ++cc) {
+    const int k = tid + cc * C::NT;
+    if (C::NCH % C::NT == 0 || k < C::NCH) {
+#pragma unroll
+      for (int b = 0; b < C::NB; ++b) out[(int64_t)b * C::NCH + k] = acc[cc][b];
+    }
+  }
+}
+
+template <int N, int NA, int V>
+static hipError_t launch_fused_ring(const FxArgs& a, int64_t n_dump, int64_t spd, int64_t cpd,
+                                    float2* part, hipStream_t s) {
+  using RC = RingCfg<N, NA, V, 4>;
+  static_assert(RC::LDS_BYTES <= 160 * 1024, "ring tile: LDS");
+  if (a.n_taps != 4) return hipErrorInvalidValue;
+  auto kern = fx_fused_ring_kernel<N, NA, V, 4>;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)RC::LDS_BYTES);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3((unsigned)(n_dump * cpd)), dim3(RC::C::NT), RC::LDS_BYTES, s, a.x,
+                     a.ld_x, a.hist, a.taps, a.tw, spd, cpd, part);
+  return hipGetLastError();
+}
+
 template <int N, int NA, int S, int V, bool PP, int OCC, int PT>
 static hipError_t launch_fused_t(const FxArgs& a, int64_t n_dump, int64_t spd, int64_t cpd,
                                  float2* part, hipStream_t s) {
@@ -266,7 +444,7 @@ static hipError_t launch_fused_p(const FxArgs& a, int64_t n_dump, int64_t spd, i
 // values per thread per FFT pass V, ping-pong LDS buffers PP.  Entry 0 is
 // the default; the others are the candidates an autotuner may time.
 struct FusedTile {
-  int S, V;
+  int S, V;  // S = 0: ring variant (one spectrum in flight, register ring)
   bool PP;
   int OCC;  // minimum waves per SIMD requested from the compiler (0: none)
 };
@@ -282,16 +460,17 @@ struct TileList {
     static constexpr FusedTile tiles[] = {__VA_ARGS__};                         \
     static constexpr int count = (int)(sizeof(tiles) / sizeof(tiles[0]));       \
   };
-QC_TILES(4096, 4, {1, 16, true, 0}, {1, 16, false, 0}, {2, 16, false, 0}, {1, 8, true, 0},
-         {1, 16, false, 4})
+QC_TILES(4096, 4, {0, 16, false, 0}, {1, 16, false, 0}, {1, 16, true, 0}, {2, 16, false, 0},
+         {1, 8, true, 0}, {1, 16, false, 4})
 QC_TILES(1024, 4, {2, 16, true, 0}, {2, 16, false, 0}, {4, 16, false, 0}, {2, 8, true, 0},
-         {1, 16, true, 4}, {2, 16, false, 4})
-QC_TILES(2048, 4, {1, 16, true, 0}, {1, 16, false, 0}, {1, 16, false, 4}, {1, 8, true, 0})
+         {1, 16, true, 4}, {2, 16, false, 4}, {0, 16, false, 0})
+QC_TILES(2048, 4, {0, 16, false, 0}, {1, 16, true, 0}, {1, 16, false, 0}, {1, 16, false, 4},
+         {1, 8, true, 0})
 QC_TILES(512, 4, {4, 16, true, 0}, {4, 16, false, 0}, {2, 16, true, 4})
 QC_TILES(1024, 8, {1, 16, true, 0}, {1, 8, true, 0})
 QC_TILES(2048, 8, {1, 8, true, 0}, {1, 8, false, 0})
 QC_TILES(1024, 2, {4, 16, true, 0}, {4, 16, false, 0}, {2, 16, true, 4})
-QC_TILES(4096, 2, {1, 16, true, 0}, {1, 16, false, 0}, {1, 16, false, 4})
+QC_TILES(4096, 2, {0, 16, false, 0}, {1, 16, true, 0}, {1, 16, false, 0}, {1, 16, false, 4})
 #undef QC_TILES
 
 template <int N, int NA, int I>
@@ -302,7 +481,15 @@ static hipError_t dispatch_tile(int tile, const FxArgs& a, int64_t n_dump, int64
   } else {
     if (tile == I) {
       constexpr FusedTile t = TileList<N, NA>::tiles[I];
-      return launch_fused_p<N, NA, t.S, t.V, t.PP, t.OCC>(a, n_dump, spd, cpd, part, s);
+      if constexpr (t.S == 0) {
+        // ring variant (one spectrum in flight): needs P = 4 and the built-in
+        // (symmetric) prototype
+        if (a.n_taps == 4 && a.taps_symmetric)
+          return launch_fused_ring<N, NA, t.V>(a, n_dump, spd, cpd, part, s);
+        return launch_fused_p<N, NA, 1, t.V, false, 0>(a, n_dump, spd, cpd, part, s);
+      } else {
+        return launch_fused_p<N, NA, t.S, t.V, t.PP, t.OCC>(a, n_dump, spd, cpd, part, s);
+      }
     }
     return dispatch_tile<N, NA, I + 1>(tile, a, n_dump, spd, cpd, part, s);
   }

@@ -15,6 +15,7 @@ struct FxArgs {
   const float* taps;   // device [P*N]
   const float2* tw;    // device [N], exp(-2 pi i e/N)
   const int8_t* hist;  // device [n_ant][(P-1)N] or null
+  bool taps_symmetric; // h[q] == h[P*N-1-q] (the built-in prototype)
 };
 
 // Fused F+X for small arrays.  Returns false if no fused kernel exists for
@@ -62,5 +63,11 @@ hipError_t launch_mad(const float2* vis, int64_t n_time, int64_t n_base, int n_c
 // Delay/phase application; tau/phi host arrays of n_ant doubles (n_ant <= 64).
 hipError_t launch_apply(float2* vis, int64_t n_time, int n_ant, int n_chan, double f0, double df,
                         const double* tau, const double* phi, hipStream_t s);
+
+// Delay/phase solve: per-cross-baseline fits, then the per-antenna solution.
+// tau_b, phi_b: device scratch double[n_ant(n_ant-1)/2]; tau, phi: device double[n_ant].
+hipError_t launch_solve(const float2* vis, const uint8_t* mask, int64_t n_time, int n_ant, int n_chan,
+                        double f0, double df, int ref, int lo, int hi, int n_lag, const float2* tw,
+                        double* tau_b, double* phi_b, double* tau, double* phi, hipStream_t s);
 
 }  // namespace qc
