@@ -120,7 +120,33 @@ __host__ __device__ constexpr int lds_padded_size(int n) { return n + (n >> 4) +
 // to back (padded).  NT threads each hold V complex values (V/R butterflies).
 // With INPLACE the pass reads and writes the same buffer, so a barrier
 // separates all loads from all stores; otherwise src and dst differ.
-template <int N, int R, int NS, int NT, int V, bool INPLACE, bool LN>
+// Twiddle layouts.  TWL = false: tw[e] = W_N^e, e = 0..N-1 (read at
+// e = jm*r*N/(NS*R)).  TWL = true: per-pass tables, the pass with stride NS
+// holding T[(NS-1) + (r-1)*NS + jm] = W_{NS R}^{jm r}; for a fixed r the
+// lanes of a wave then read consecutive entries (no LDS bank conflicts).
+// Over all passes the per-pass tables take exactly N-1 entries.
+template <int N, int V>
+__device__ __forceinline__ void build_pass_twiddles(float2* dst, const float2* __restrict__ tw, int tid,
+                                                    int nt) {
+  for (int i = tid; i < N - 1; i += nt) {
+    // find the pass: offsets NS-1 for NS = 1, R1, R1*R2, ...
+    int ns = 1, off = 0;
+    while (true) {
+      const int R = (N / ns) >= V ? V : (N / ns);
+      const int size = (R - 1) * ns;
+      if (i < off + size || ns * R >= N) {
+        const int q = i - off;
+        const int r = 1 + q / ns, jm = q % ns;
+        dst[i] = tw[jm * r * (N / (ns * R))];
+        break;
+      }
+      off += size;
+      ns *= R;
+    }
+  }
+}
+
+template <int N, int R, int NS, int NT, int V, bool INPLACE, bool LN, bool TWL = false>
 __device__ __forceinline__ void stockham_pass(const float2* src, float2* dst,
                                               const float2* __restrict__ tw, int tid) {
   // Twiddles and LDS addresses depend only on the thread index, so the
@@ -152,7 +178,8 @@ __device__ __forceinline__ void stockham_pass(const float2* src, float2* dst,
     if constexpr (NS > 1) {
       constexpr int STEP = N / (NS * R);
 #pragma unroll
-      for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], tw[jm * r * STEP]);
+      for (int r = 1; r < R; ++r)
+        v[i][r] = cmul(v[i][r], TWL ? tw[(NS - 1) + (r - 1) * NS + jm] : tw[jm * r * STEP]);
     }
     dft_r<R>(v[i]);
     const int k = (j / NS) * NS * R + jm;
@@ -173,7 +200,7 @@ constexpr int fft_pass_count(int N, int V) {
 // Passes NS.. of a Stockham FFT.  PP selects ping-pong buffers: pass p reads
 // buffer p%2 and writes buffer (p+1)%2 (one barrier per pass); without PP
 // every pass works in place in buffer 0 (two barriers per pass).
-template <int N, int NS, int NT, int V, bool PP, bool LN, int PASS>
+template <int N, int NS, int NT, int V, bool PP, bool LN, int PASS, bool TWL = false>
 __device__ __forceinline__ void fft_passes(float2* b0, float2* b1, const float2* __restrict__ tw,
                                            int tid) {
   constexpr int REM = N / NS;
@@ -182,11 +209,11 @@ __device__ __forceinline__ void fft_passes(float2* b0, float2* b1, const float2*
     if constexpr (PP) {
       float2* src = (PASS % 2 == 0) ? b0 : b1;
       float2* dst = (PASS % 2 == 0) ? b1 : b0;
-      stockham_pass<N, R, NS, NT, V, false, LN>(src, dst, tw, tid);
+      stockham_pass<N, R, NS, NT, V, false, LN, TWL>(src, dst, tw, tid);
     } else {
-      stockham_pass<N, R, NS, NT, V, true, LN>(b0, b0, tw, tid);
+      stockham_pass<N, R, NS, NT, V, true, LN, TWL>(b0, b0, tw, tid);
     }
-    fft_passes<N, NS * R, NT, V, PP, LN, PASS + 1>(b0, b1, tw, tid);
+    fft_passes<N, NS * R, NT, V, PP, LN, PASS + 1, TWL>(b0, b1, tw, tid);
   }
 }
 
@@ -195,13 +222,13 @@ __device__ __forceinline__ void fft_passes(float2* b0, float2* b1, const float2*
 // read from b0; the output is in b0, or in b(fft_pass_count % 2) with
 // ping-pong.  Must be called by all NT threads of the block; begins with
 // the block synchronised and ends with a barrier.
-template <int N, int NT, int V, bool PP, bool LN = false>
+template <int N, int NT, int V, bool PP, bool LN = false, bool TWL = false>
 struct Fft {
   static constexpr int PASSES = fft_pass_count(N, V);
   static constexpr int OUT = PP ? (PASSES % 2) : 0;
   static __device__ __forceinline__ void run(float2* b0, float2* b1, const float2* __restrict__ tw,
                                              int tid) {
-    fft_passes<N, 1, NT, V, PP, LN, 0>(b0, b1, tw, tid);
+    fft_passes<N, 1, NT, V, PP, LN, 0, TWL>(b0, b1, tw, tid);
   }
 };
 

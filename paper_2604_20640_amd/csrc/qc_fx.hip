@@ -258,12 +258,12 @@ fx_fused_ring_kernel(const int8_t* __restrict__ x, int64_t ld_x, const int8_t* _
                      const float* __restrict__ taps, const float2* __restrict__ tw,
                      int64_t spec_per_dump, int64_t cpd, float2* __restrict__ part) {
   using C = FusedCfg<N, NA, 1, V, false, 0>;
-  using F = Fft<N, C::NT, V, false, false>;
+  using F = Fft<N, C::NT, V, false, false, true>;
   constexpr int G = C::CHUNKS;
   constexpr int L = P * N;
   extern __shared__ float2 buf[];
   float2* b0 = buf;
-  float2* twl = buf + C::LDS;                             // twiddles, N
+  float2* twl = buf + C::LDS;                             // per-pass twiddles, N-1
   float4* tl = reinterpret_cast<float4*>(twl + N);        // taps h[0 .. L/2)
   const int tid = threadIdx.x;
   const int64_t w = blockIdx.x;
@@ -273,7 +273,7 @@ fx_fused_ring_kernel(const int8_t* __restrict__ x, int64_t ld_x, const int8_t* _
 
   // the prototype is symmetric, h[q] = h[L-1-q]: keep its first half
   for (int i = tid; i < L / 8; i += C::NT) tl[i] = reinterpret_cast<const float4*>(taps)[i];
-  for (int i = tid; i < N; i += C::NT) twl[i] = tw[i];
+  build_pass_twiddles<N, V>(twl, tw, tid, C::NT);
 
   // this thread's FIR chunks: chunk g belongs to packed pair g / GP (a
   // compile-time constant), so the antenna rows are wave-uniform and only
