@@ -41,6 +41,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision", action="store_true", help="skip the 32-antenna section")
+    ap.add_argument("--no-batched", action="store_true", help="skip the uneven-arrays section")
     ap.add_argument("--traffic", type=str, default=None,
                     help="JSON file with measured HBM bytes per fused launch")
     ap.add_argument("--copy-calib", action="store_true",
@@ -132,6 +133,65 @@ def precision_section(torch, qc, steps):
         log(f"[bench] 32-ant {prec}: {ms:.3f} ms, err {err:.2e}")
     del xd
     return res
+
+
+def batched_section(torch, qc, steps):
+    """Five uneven arrays (4..32 antennas, 512..4096 channels, 2^22 samples
+    each) in one persistent launch: eager, graph replay, and the same work as
+    separate per-array calls."""
+    from tests.util import vis_err as vis_err_local
+    n_samp = 1 << 22
+    t0 = time.time()
+    ws = synth.batched(n_samp, 4000)
+    log(f"[bench] batched arrays generated in {time.time() - t0:.1f}s")
+    descs = [{"n_ant": w.x.shape[0], "n_samp": n_samp, "n_fft": w.n_fft, "n_taps": w.n_taps,
+              "spec_per_dump": w.spec_per_dump} for w in ws]
+    xs = [torch.from_numpy(w.x).cuda() for w in ws]
+    nbytes = sum(w.x.nbytes for w in ws)
+    plan = qc.Plan(descs)
+    vis = plan.empty_vis()
+    t0 = time.time()
+    plan.autotune(xs, vis, reps=2)
+    tune_s = time.time() - t0
+    n_items, grid, knobs = plan.info()
+    reps = max(5, steps // 5)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        plan.capture_graph(xs, vis)
+    torch.cuda.synchronize()
+
+    def on_side(fn):
+        s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(side):
+            fn()                                   # untimed first call
+        torch.cuda.synchronize()
+        with torch.cuda.stream(side):
+            s0.record()
+            for _ in range(reps):
+                fn()
+            s1.record()
+        torch.cuda.synchronize()
+        return s0.elapsed_time(s1) / reps
+
+    g_ms = on_side(plan.replay)
+    plan.check()
+    e_ms = on_side(lambda: plan.execute(xs, vis))
+    plan.check()
+    sep = plan.empty_vis()
+    s_ms = on_side(lambda: plan.execute_separate(xs, sep))
+    err = max(vis_err_local(a.cpu().numpy(), b.cpu().numpy(), d["n_ant"])
+              for a, b, d in zip(vis, sep, descs))
+    log(f"[bench] batched: graph {g_ms:.3f} ms, eager plan {e_ms:.3f} ms, separate {s_ms:.3f} ms")
+    plan.close()
+    del xs
+    return {"workload": "batched_5arrays", "arrays_ant_chan": [list(a) for a in synth.BATCH_ARRAYS],
+            "n_samp_per_ant": n_samp, "input_bytes": nbytes, "graph_ms": round(g_ms, 4),
+            "plan_eager_ms": round(e_ms, 4), "separate_ms": round(s_ms, 4),
+            "graph_input_GBps": round(nbytes / g_ms / 1e6, 2),
+            "speedup_vs_separate": round(s_ms / g_ms, 3), "n_items": n_items,
+            "knobs": {"fused_items": knobs[0], "chan_mult": knobs[1], "x_split": knobs[2],
+                      "grid": knobs[3]},
+            "autotune_s": round(tune_s, 2), "vis_err_vs_separate": float(f"{err:.3e}")}
 
 
 def cpu_baseline(x, N, P, spd, sigma, tau, phi, df, gpu_vis, n_dumps=8):
@@ -268,6 +328,8 @@ def main():
     if not args.no_precision:
         del vis_check
         out["precision_32ant"] = precision_section(torch, qc, args.steps)
+    if not args.no_batched:
+        out["batched"] = batched_section(torch, qc, args.steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(x, N, P, spd, sigma, tau, phi, df, gpu_vis)
     print(json.dumps(out), flush=True)

@@ -15,7 +15,7 @@ import torch
 
 __all__ = [
     "QCError", "lib", "pfb_channelize", "xcorrelate", "xcorrelate_chan", "mad_flag",
-    "apply_delay_phase", "n_base", "PREC", "timing_enable", "timing_read", "KERNELS", "Stream", "solve_delay_phase",
+    "apply_delay_phase", "n_base", "PREC", "timing_enable", "timing_read", "KERNELS", "Stream", "solve_delay_phase", "Plan",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -34,6 +34,11 @@ class QCError(RuntimeError):
 class PfbParams(ctypes.Structure):
     _fields_ = [("n_fft", ctypes.c_int32), ("n_taps", ctypes.c_int32),
                 ("taps", ctypes.c_void_p), ("keep_nyquist", ctypes.c_int32)]
+
+
+class ArrayDesc(ctypes.Structure):
+    _fields_ = [("n_ant", ctypes.c_int32), ("n_samp", ctypes.c_int64), ("n_fft", ctypes.c_int32),
+                ("n_taps", ctypes.c_int32), ("spec_per_dump", ctypes.c_int64)]
 
 
 _lib = None
@@ -95,6 +100,24 @@ def lib() -> ctypes.CDLL:
                                            _I32, _I32, _I32, _I32, ctypes.POINTER(ctypes.c_double),
                                            ctypes.POINTER(ctypes.c_double), _P]
         L.qc_solve_delay_phase.restype = ctypes.c_int32
+        PP = ctypes.POINTER(ctypes.c_void_p)
+        for name, args in {
+            "qc_plan_create": [ctypes.POINTER(ArrayDesc), _I32, ctypes.POINTER(ctypes.c_void_p)],
+            "qc_plan_execute": [_P, PP, PP, _P],
+            "qc_plan_execute_separate": [_P, PP, PP, _P],
+            "qc_plan_check": [_P, _P],
+            "qc_plan_set_wait_timeout": [_P, _I64],
+            "qc_plan_set_wait_bias": [_P, _I32],
+            "qc_plan_capture_graph": [_P, PP, PP, _P],
+            "qc_plan_replay": [_P, _P],
+            "qc_plan_autotune": [_P, PP, PP, _I32, ctypes.c_char_p, ctypes.POINTER(_I32), _P],
+            "qc_plan_info": [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I64)],
+        }.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_int32
+        L.qc_plan_destroy.argtypes = [_P]
+        L.qc_plan_destroy.restype = None
         L.qc_timing_enable.argtypes = [ctypes.c_int32]
         L.qc_timing_enable.restype = ctypes.c_int32
         L.qc_timing_read.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
@@ -161,6 +184,83 @@ class Stream:
     def close(self):
         if getattr(self, "_h", None):
             lib().qc_stream_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Plan:
+    """Several arrays correlated in one persistent launch (qc_plan_*)."""
+
+    def __init__(self, arrays):
+        """arrays: list of dicts with n_ant, n_samp, n_fft, n_taps, spec_per_dump."""
+        n = len(arrays)
+        self.arrays = [dict(a) for a in arrays]
+        descs = (ArrayDesc * n)(*[ArrayDesc(a["n_ant"], a["n_samp"], a["n_fft"], a.get("n_taps", 4),
+                                            a["spec_per_dump"]) for a in arrays])
+        h = ctypes.c_void_p()
+        _check(lib().qc_plan_create(descs, n, ctypes.byref(h)), "qc_plan_create")
+        self._h = h
+
+    def empty_vis(self, device="cuda"):
+        out = []
+        for a in self.arrays:
+            n_dump = (a["n_samp"] // a["n_fft"]) // a["spec_per_dump"]
+            out.append(torch.empty((n_dump, n_base(a["n_ant"]), a["n_fft"] // 2),
+                                   dtype=torch.complex64, device=device))
+        return out
+
+    @staticmethod
+    def _ptrs(ts):
+        return (ctypes.c_void_p * len(ts))(*[t.data_ptr() for t in ts])
+
+    def _call(self, name, xs, viss):
+        for x in xs:
+            _check_x(x)
+            assert x.is_contiguous()
+        _check(getattr(lib(), name)(self._h, self._ptrs(xs), self._ptrs(viss), _stream()), name)
+
+    def execute(self, xs, viss):
+        self._call("qc_plan_execute", xs, viss)
+
+    def execute_separate(self, xs, viss):
+        self._call("qc_plan_execute_separate", xs, viss)
+
+    def capture_graph(self, xs, viss):
+        self._call("qc_plan_capture_graph", xs, viss)
+
+    def replay(self):
+        _check(lib().qc_plan_replay(self._h, _stream()), "qc_plan_replay")
+
+    def check(self):
+        _check(lib().qc_plan_check(self._h, _stream()), "qc_plan_check")
+
+    def set_wait_timeout(self, microseconds):
+        _check(lib().qc_plan_set_wait_timeout(self._h, int(microseconds)), "qc_plan_set_wait_timeout")
+
+    def set_wait_bias(self, n):
+        _check(lib().qc_plan_set_wait_bias(self._h, n), "qc_plan_set_wait_bias")
+
+    def autotune(self, xs, viss, reps=3, cache=None):
+        fc = _I32(0)
+        _check(lib().qc_plan_autotune(self._h, self._ptrs(xs), self._ptrs(viss), reps,
+                                      None if cache is None else cache.encode(), ctypes.byref(fc),
+                                      _stream()), "qc_plan_autotune")
+        return bool(fc.value)
+
+    def info(self):
+        n, g = _I32(0), _I32(0)
+        k = (_I64 * 4)()
+        _check(lib().qc_plan_info(self._h, ctypes.byref(n), ctypes.byref(g), k), "qc_plan_info")
+        return n.value, g.value, list(k)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().qc_plan_destroy(self._h)
             self._h = None
 
     def __del__(self):

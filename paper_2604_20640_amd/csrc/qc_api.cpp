@@ -5,8 +5,11 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
+#include <fstream>
+#include <sstream>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -16,6 +19,8 @@
 #include <vector>
 
 #include "qc_kernels.h"
+
+#include <new>
 
 namespace {
 
@@ -617,6 +622,437 @@ qc_status qc_timing_read(int32_t kernel, double* total_ms, int64_t* launches) {
   *total_ms = tot;
   *launches = (int64_t)g_trec.ev[kernel].size();
   return QC_OK;
+}
+
+}  // extern "C"
+
+// ---- batched plans ------------------------------------------------------------
+namespace {
+constexpr int PLAN_SLOTS = 16;  // descriptor slots for executions in flight (+1 for a graph)
+}
+
+struct qc_plan {
+  int device = 0;
+  int n = 0;
+  qc_array_desc desc[qc::PL_MAX_ARRAYS];
+  qc::PlArray arr[qc::PL_MAX_ARRAYS];
+  // tile knobs (set by qc_plan_autotune)
+  int64_t fused_items = 512;  // target fused items per array
+  int64_t chan_mult = 4;      // F-engine item = spectra-in-flight * chan_mult spectra
+  int64_t x_split = 2;        // X-engine k-split
+  int grid = 256;             // persistent blocks
+  int64_t wait_us = 2000000;   // time limit of one dependency wait
+  int64_t clock_khz = 0;       // device wall-clock rate
+  int wait_bias = 0;
+  std::vector<qc::PlItem> items;
+  qc::PlItem* d_items = nullptr;
+  unsigned* d_ctr = nullptr;
+  qc::PlArray* d_slots = nullptr;  // (PLAN_SLOTS + 1) * PL_MAX_ARRAYS
+  qc::PlArray* h_slots = nullptr;  // pinned staging, same shape
+  hipEvent_t slot_ev[PLAN_SLOTS] = {};
+  bool slot_used[PLAN_SLOTS] = {};
+  int next_slot = 0;
+  std::vector<void*> bufs;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+};
+
+namespace {
+
+void plan_free_buffers(qc_plan* P) {
+  if (!P->bufs.empty() || P->d_items) (void)hipDeviceSynchronize();
+  for (void* b : P->bufs) (void)hipFree(b);
+  P->bufs.clear();
+  if (P->d_items) (void)hipFree(P->d_items);
+  P->d_items = nullptr;
+}
+
+void plan_drop_graph(qc_plan* P) {
+  if (P->gexec) (void)hipGraphExecDestroy(P->gexec);
+  if (P->graph) (void)hipGraphDestroy(P->graph);
+  P->gexec = nullptr;
+  P->graph = nullptr;
+}
+
+qc_status plan_build(qc_plan* P) {
+  // a captured graph refers to the buffers and items rebuilt here
+  plan_drop_graph(P);
+  plan_free_buffers(P);
+  std::vector<qc::PlItem> first, xeng, red;
+  for (int i = 0; i < P->n; ++i) {
+    const qc_array_desc& D = P->desc[i];
+    qc::PlArray& A = P->arr[i];
+    A = qc::PlArray{};
+    const int N = D.n_fft, NA = D.n_ant, NCH = N / 2;
+    const int64_t NB = (int64_t)NA * (NA + 1) / 2;
+    A.n_samp = D.n_samp;
+    A.spd = D.spec_per_dump;
+    A.n_dump = (D.n_samp / N) / D.spec_per_dump;
+    A.n_ant = NA;
+    A.n_fft = N;
+    A.n_taps = D.n_taps;
+    TapsEntry te;
+    qc_status st = get_taps(N, D.n_taps, &te);
+    if (st != QC_OK) return st;
+    float2* tw = nullptr;
+    st = get_twiddles(N, &tw);
+    if (st != QC_OK) return st;
+    A.taps = te.dev;
+    A.tw = tw;
+    const int64_t elems = NB * NCH;
+    A.n_red_blocks = (int32_t)((elems + qc::PL_RED_BLOCK - 1) / qc::PL_RED_BLOCK);
+    void* part = nullptr;
+    if (qc::plan_fused_supported(N, NA)) {
+      A.mode = 0;
+      const int S = 8192 / (((NA + 1) / 2) * N);
+      int64_t cpd = (P->fused_items + A.n_dump - 1) / A.n_dump;
+      cpd = std::max<int64_t>(1, std::min<int64_t>(cpd, A.spd / S > 0 ? A.spd / S : 1));
+      A.n_split = cpd;
+      A.n_part_items = (int32_t)(A.n_dump * cpd);
+      A.scale = 0.25f;
+      for (int64_t w = 0; w < A.n_dump * cpd; ++w) first.push_back({qc::PL_FUSED, (uint16_t)i, (uint32_t)w});
+    } else {
+      A.mode = 1;
+      const int S = 8192 / N;
+      const int64_t ns = A.n_dump * A.spd;
+      A.spec_per_item = std::min<int64_t>(ns, (int64_t)S * P->chan_mult);
+      const int64_t nbx = (ns + A.spec_per_item - 1) / A.spec_per_item;
+      const int n_pair = (NA + 1) / 2;
+      A.n_chan_items = (int32_t)(nbx * n_pair);
+      const int64_t ks = std::max<int64_t>(1, std::min<int64_t>(P->x_split, A.spd / 16 > 0 ? A.spd / 16 : 1));
+      A.n_split = ks;
+      A.n_cgrp = (NCH + qc::PL_NT - 1) / qc::PL_NT;
+      const int nblk = (NA + 3) / 4;
+      A.n_bp = nblk * (nblk + 1) / 2;
+      A.n_part_items = (int32_t)(A.n_dump * ks * A.n_bp * A.n_cgrp);
+      A.scale = 1.0f;
+      void* chan = nullptr;
+      hipError_t e = hipMalloc(&chan, sizeof(float2) * (size_t)NA * ns * NCH);
+      if (e != hipSuccess) return fail(QC_ENOMEM, "plan spectra buffer: %s", hipGetErrorString(e));
+      P->bufs.push_back(chan);
+      A.chan = (float2*)chan;
+      for (int64_t q = 0; q < A.n_chan_items; ++q) first.push_back({qc::PL_CHAN, (uint16_t)i, (uint32_t)q});
+      for (int64_t q = 0; q < A.n_part_items; ++q) xeng.push_back({qc::PL_XENG, (uint16_t)i, (uint32_t)q});
+    }
+    hipError_t e = hipMalloc(&part, sizeof(float2) * (size_t)A.n_dump * A.n_split * elems);
+    if (e != hipSuccess) return fail(QC_ENOMEM, "plan partial buffer: %s", hipGetErrorString(e));
+    P->bufs.push_back(part);
+    A.part = (float2*)part;
+    for (int64_t q = 0; q < A.n_dump * A.n_red_blocks; ++q) red.push_back({qc::PL_REDUCE, (uint16_t)i, (uint32_t)q});
+  }
+  // spectra items of the two-pass arrays first (they feed the longest chains)
+  std::stable_sort(first.begin(), first.end(),
+                   [](const qc::PlItem& a, const qc::PlItem& b) { return a.kind > b.kind; });
+  P->items = first;
+  P->items.insert(P->items.end(), xeng.begin(), xeng.end());
+  P->items.insert(P->items.end(), red.begin(), red.end());
+  if (P->items.size() >= 0x7fffffffu) return fail(QC_EUNSUPPORTED, "too many plan items");
+  // the persistent kernel relies on these: per array, the counted items
+  // match the wait targets, and every item precedes the items that wait on it
+  for (int i = 0; i < P->n; ++i) {
+    int64_t n_chan = 0, n_part = 0, last_chan = -1, last_part = -1;
+    int64_t first_x = INT64_MAX, first_red = INT64_MAX;
+    for (size_t q = 0; q < P->items.size(); ++q) {
+      const qc::PlItem& it = P->items[q];
+      if (it.array != i) continue;
+      const int64_t pos = (int64_t)q;
+      if (it.kind == qc::PL_CHAN) { ++n_chan; last_chan = pos; }
+      if (it.kind == qc::PL_FUSED || it.kind == qc::PL_XENG) { ++n_part; last_part = pos; }
+      if (it.kind == qc::PL_XENG) first_x = std::min(first_x, pos);
+      if (it.kind == qc::PL_REDUCE) first_red = std::min(first_red, pos);
+    }
+    const qc::PlArray& A = P->arr[i];
+    if (n_chan != A.n_chan_items || n_part != A.n_part_items || last_chan >= first_x ||
+        last_part >= first_red)
+      return fail(QC_ESTATE, "internal: plan item order for array %d", i);
+  }
+  hipError_t e = hipMalloc(&P->d_items, sizeof(qc::PlItem) * P->items.size());
+  if (e != hipSuccess) return fail(QC_ENOMEM, "plan items: %s", hipGetErrorString(e));
+  e = hipMemcpy(P->d_items, P->items.data(), sizeof(qc::PlItem) * P->items.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "plan items upload");
+  return QC_OK;
+}
+
+qc_status plan_enqueue(qc_plan* P, const int8_t* const* x, float* const* vis, hipStream_t s, int slot) {
+  qc::PlArray* h = P->h_slots + (size_t)slot * qc::PL_MAX_ARRAYS;
+  qc::PlArray* d = P->d_slots + (size_t)slot * qc::PL_MAX_ARRAYS;
+  for (int i = 0; i < P->n; ++i) {
+    h[i] = P->arr[i];
+    h[i].x = x[i];
+    h[i].vis = reinterpret_cast<float2*>(vis[i]);
+  }
+  QC_HIP(hipMemcpyAsync(d, h, sizeof(qc::PlArray) * P->n, hipMemcpyHostToDevice, s), "plan descriptors");
+  qc::PlArgs a{};
+  a.arr = d;
+  a.items = P->d_items;
+  a.n_items = (int32_t)P->items.size();
+  a.wait_ticks = P->wait_us * P->clock_khz / 1000;
+  a.wait_bias = P->wait_bias;
+  a.ctr = P->d_ctr;
+  QC_HIP(qc::launch_plan(a, P->grid, s), "plan kernel");
+  return QC_OK;
+}
+
+qc_status plan_check_args(qc_plan* P, const int8_t* const* x, float* const* vis) {
+  if (!P || !x || !vis) return fail(QC_EINVAL, "NULL argument");
+  for (int i = 0; i < P->n; ++i) {
+    if (!x[i] || !vis[i]) return fail(QC_EINVAL, "array %d: NULL x or vis", i);
+    if ((reinterpret_cast<uintptr_t>(x[i]) & 3u) || (reinterpret_cast<uintptr_t>(vis[i]) & 7u))
+      return fail(QC_EINVAL, "array %d: misaligned x or vis", i);
+  }
+  return QC_OK;
+}
+
+std::string plan_signature(const qc_plan* P) {
+  std::ostringstream o;
+  for (int i = 0; i < P->n; ++i)
+    o << P->desc[i].n_ant << "x" << P->desc[i].n_samp << "x" << P->desc[i].n_fft << "x"
+      << P->desc[i].n_taps << "x" << P->desc[i].spec_per_dump << (i + 1 < P->n ? "," : "");
+  return o.str();
+}
+
+}  // namespace
+
+extern "C" {
+
+qc_status qc_plan_create(const qc_array_desc* arrays, int32_t n_arrays, qc_plan** out) {
+  g_err.clear();
+  if (!arrays || !out) return fail(QC_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (n_arrays < 1 || n_arrays > qc::PL_MAX_ARRAYS)
+    return fail(QC_EINVAL, "n_arrays must be in [1, %d]", qc::PL_MAX_ARRAYS);
+  for (int i = 0; i < n_arrays; ++i) {
+    const qc_array_desc& D = arrays[i];
+    if (D.n_ant < 1 || D.n_ant > 64) return fail(QC_EINVAL, "array %d: n_ant must be in [1, 64]", i);
+    if (!is_pow2(D.n_fft) || D.n_fft < 16 || D.n_fft > 8192)
+      return fail(QC_EINVAL, "array %d: n_fft must be a power of two in [16, 8192]", i);
+    if (D.n_taps < 1 || D.n_taps > 16) return fail(QC_EINVAL, "array %d: n_taps must be in [1, 16]", i);
+    if (D.n_samp <= 0 || D.n_samp % D.n_fft || D.n_samp > 0x7fffffffLL)
+      return fail(QC_EINVAL, "array %d: n_samp must be a positive multiple of n_fft below 2^31", i);
+    if (D.spec_per_dump < 1 || (D.n_samp / D.n_fft) < D.spec_per_dump)
+      return fail(QC_EINVAL, "array %d: need at least one full dump", i);
+  }
+  qc_plan* P = new (std::nothrow) qc_plan();
+  if (!P) return fail(QC_ENOMEM, "host allocation");
+  P->n = n_arrays;
+  for (int i = 0; i < n_arrays; ++i) P->desc[i] = arrays[i];
+  hipError_t e = hipGetDevice(&P->device);
+  int khz = 0;
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, P->device);
+  P->clock_khz = khz > 0 ? khz : 100000;
+  if (e == hipSuccess) e = hipMalloc(&P->d_ctr, sizeof(unsigned) * (2 + 2 * qc::PL_MAX_ARRAYS));
+  if (e == hipSuccess)
+    e = hipMalloc(&P->d_slots, sizeof(qc::PlArray) * (PLAN_SLOTS + 1) * qc::PL_MAX_ARRAYS);
+  if (e == hipSuccess)
+    e = hipHostMalloc(&P->h_slots, sizeof(qc::PlArray) * (PLAN_SLOTS + 1) * qc::PL_MAX_ARRAYS, 0);
+  for (int i = 0; e == hipSuccess && i < PLAN_SLOTS; ++i)
+    e = hipEventCreateWithFlags(&P->slot_ev[i], hipEventDisableTiming);
+  if (e != hipSuccess) {
+    qc_plan_destroy(P);
+    return hip_fail(e, "plan allocation");
+  }
+  qc_status st = plan_build(P);
+  if (st != QC_OK) {
+    qc_plan_destroy(P);
+    return st;
+  }
+  *out = P;
+  return QC_OK;
+}
+
+qc_status qc_plan_execute(qc_plan* P, const int8_t* const* x, float* const* vis, void* stream) {
+  g_err.clear();
+  qc_status st = plan_check_args(P, x, vis);
+  if (st != QC_OK) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int slot = P->next_slot;
+  P->next_slot = (P->next_slot + 1) % PLAN_SLOTS;
+  // the slot's staging may still be read by an earlier execution's copy
+  if (P->slot_used[slot]) QC_HIP(hipEventSynchronize(P->slot_ev[slot]), "plan slot wait");
+  QC_HIP(qc::prepare_plan(), "plan kernel attributes");
+  st = plan_enqueue(P, x, vis, s, slot);
+  if (st != QC_OK) return st;
+  QC_HIP(hipEventRecord(P->slot_ev[slot], s), "plan slot event");
+  P->slot_used[slot] = true;
+  return QC_OK;
+}
+
+qc_status qc_plan_check(qc_plan* P, void* stream) {
+  g_err.clear();
+  if (!P) return fail(QC_EINVAL, "NULL plan");
+  unsigned flag = 0;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  QC_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+  QC_HIP(hipMemcpy(&flag, P->d_ctr + 1, sizeof(unsigned), hipMemcpyDeviceToHost), "plan flag");
+  if (flag) return fail(QC_ESTATE, "a bounded dependency wait expired in the last plan execution");
+  return QC_OK;
+}
+
+qc_status qc_plan_set_wait_timeout(qc_plan* P, int64_t microseconds) {
+  g_err.clear();
+  if (!P || microseconds < 1 || microseconds > 600000000LL) return fail(QC_EINVAL, "bad plan or timeout");
+  P->wait_us = microseconds;
+  return QC_OK;
+}
+
+qc_status qc_plan_set_wait_bias(qc_plan* P, int32_t bias) {
+  g_err.clear();
+  if (!P || bias < 0) return fail(QC_EINVAL, "bad plan or bias");
+  P->wait_bias = bias;
+  return QC_OK;
+}
+
+qc_status qc_plan_info(const qc_plan* P, int32_t* n_items, int32_t* grid, int64_t* knobs4) {
+  g_err.clear();
+  if (!P) return fail(QC_EINVAL, "NULL plan");
+  if (n_items) *n_items = (int32_t)P->items.size();
+  if (grid) *grid = P->grid;
+  if (knobs4) {
+    knobs4[0] = P->fused_items;
+    knobs4[1] = P->chan_mult;
+    knobs4[2] = P->x_split;
+    knobs4[3] = P->grid;
+  }
+  return QC_OK;
+}
+
+qc_status qc_plan_execute_separate(qc_plan* P, const int8_t* const* x, float* const* vis, void* stream) {
+  g_err.clear();
+  qc_status st = plan_check_args(P, x, vis);
+  if (st != QC_OK) return st;
+  for (int i = 0; i < P->n; ++i) {
+    const qc_array_desc& D = P->desc[i];
+    qc_pfb_params pp{D.n_fft, D.n_taps, nullptr, 0};
+    st = qc_xcorrelate(x[i], D.n_samp, D.n_ant, D.n_samp, &pp, nullptr, nullptr, D.spec_per_dump, QC_F32,
+                       vis[i], 0, nullptr, stream);
+    if (st != QC_OK) return st;
+  }
+  return QC_OK;
+}
+
+qc_status qc_plan_capture_graph(qc_plan* P, const int8_t* const* x, float* const* vis, void* stream) {
+  g_err.clear();
+  qc_status st = plan_check_args(P, x, vis);
+  if (st != QC_OK) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (s == nullptr) return fail(QC_EINVAL, "graph capture needs a non-default stream");
+  plan_drop_graph(P);
+  QC_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+  QC_HIP(qc::prepare_plan(), "plan kernel attributes");
+  QC_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+  st = plan_enqueue(P, x, vis, s, PLAN_SLOTS);  // the graph's own descriptor slot
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(s, &g);
+  if (st != QC_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+  P->graph = g;
+  QC_HIP(hipGraphInstantiate(&P->gexec, g, nullptr, nullptr, 0), "hipGraphInstantiate");
+  return QC_OK;
+}
+
+qc_status qc_plan_replay(qc_plan* P, void* stream) {
+  g_err.clear();
+  if (!P || !P->gexec) return fail(QC_ESTATE, "no captured graph");
+  QC_HIP(hipGraphLaunch(P->gexec, reinterpret_cast<hipStream_t>(stream)), "hipGraphLaunch");
+  return QC_OK;
+}
+
+qc_status qc_plan_autotune(qc_plan* P, const int8_t* const* x, float* const* vis, int32_t reps,
+                           const char* cache_path, int32_t* from_cache, void* stream) {
+  g_err.clear();
+  qc_status st = plan_check_args(P, x, vis);
+  if (st != QC_OK) return st;
+  if (reps < 1) return fail(QC_EINVAL, "reps must be >= 1");
+  if (from_cache) *from_cache = 0;
+  const std::string sig = plan_signature(P);
+  if (cache_path) {
+    std::ifstream in(cache_path);
+    std::string line;
+    while (std::getline(in, line)) {
+      std::istringstream ls(line);
+      std::string k;
+      int64_t f, c, xs, g;
+      if (ls >> k >> f >> c >> xs >> g && k == sig && f > 0 && c > 0 && xs > 0 && g > 0 && g <= 4096) {
+        P->fused_items = f;
+        P->chan_mult = c;
+        P->x_split = xs;
+        P->grid = (int)g;
+        if (from_cache) *from_cache = 1;
+        return plan_build(P);
+      }
+    }
+  }
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipEvent_t a = nullptr, b = nullptr;
+  QC_HIP(hipEventCreate(&a), "hipEventCreate");
+  QC_HIP(hipEventCreate(&b), "hipEventCreate");
+  auto measure = [&](double* ms_out) -> qc_status {
+    qc_status q = plan_build(P);
+    if (q != QC_OK) return q;
+    q = qc_plan_execute(P, x, vis, stream);  // untimed
+    if (q != QC_OK) return q;
+    QC_HIP(hipEventRecord(a, s), "hipEventRecord");
+    for (int r = 0; r < reps && q == QC_OK; ++r) q = qc_plan_execute(P, x, vis, stream);
+    if (q != QC_OK) return q;
+    QC_HIP(hipEventRecord(b, s), "hipEventRecord");
+    QC_HIP(hipEventSynchronize(b), "hipEventSynchronize");
+    float ms = 0.f;
+    QC_HIP(hipEventElapsedTime(&ms, a, b), "hipEventElapsedTime");
+    *ms_out = ms / reps;
+    return qc_plan_check(P, stream);
+  };
+  // coordinate descent over the four knobs, starting from the current values
+  const std::vector<int64_t> cand[4] = {{128, 256, 512, 1024, 2048}, {1, 2, 4, 8, 16}, {1, 2, 4, 8},
+                                        {256, 512, 768, 1024}};
+  int64_t* knob[4] = {&P->fused_items, &P->chan_mult, &P->x_split, nullptr};
+  double best = 1e300;
+  st = measure(&best);
+  for (int pass = 0; st == QC_OK && pass < 2; ++pass) {
+    for (int k = 0; st == QC_OK && k < 4; ++k) {
+      const int64_t keep = k < 3 ? *knob[k] : P->grid;
+      int64_t bestv = keep;
+      for (int64_t v : cand[k]) {
+        if (v == keep) continue;
+        if (k < 3) *knob[k] = v;
+        else P->grid = (int)v;
+        double ms = 0.0;
+        st = measure(&ms);
+        if (st != QC_OK) break;
+        if (ms < best) {
+          best = ms;
+          bestv = v;
+        }
+      }
+      if (k < 3) *knob[k] = bestv;
+      else P->grid = (int)bestv;
+    }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (st != QC_OK) return st;
+  st = plan_build(P);
+  if (st != QC_OK) return st;
+  if (cache_path) {
+    std::ofstream o(cache_path, std::ios::app);
+    o << sig << " " << P->fused_items << " " << P->chan_mult << " " << P->x_split << " " << P->grid << "\n";
+  }
+  return QC_OK;
+}
+
+void qc_plan_destroy(qc_plan* P) {
+  if (!P) return;
+  (void)hipDeviceSynchronize();
+  plan_drop_graph(P);
+  plan_free_buffers(P);
+  for (auto& ev : P->slot_ev)
+    if (ev) (void)hipEventDestroy(ev);
+  if (P->d_ctr) (void)hipFree(P->d_ctr);
+  if (P->d_slots) (void)hipFree(P->d_slots);
+  if (P->h_slots) (void)hipHostFree(P->h_slots);
+  delete P;
 }
 
 }  // extern "C"

@@ -138,19 +138,21 @@ __device__ __forceinline__ void fir4_t(const int8_t* __restrict__ xa0, const int
   for (int i = 0; i < 4; ++i) out[i] = make_float2(y0[i], y1[i]);
 }
 
+// Body of the fused kernel for work unit w (chunk w % cpd of dump w / cpd),
+// run by all C::NT threads of a block on the LDS region buf.
 template <int N, int NA, int S, int V, bool PP, int OCC, int PT>
-__global__ void __launch_bounds__((FusedCfg<N, NA, S, V, PP, OCC>::NT), (OCC > 0 ? OCC : 1))
-fx_fused_kernel(const int8_t* __restrict__ x, int64_t ld_x, const int8_t* __restrict__ hist,
-                const float* __restrict__ taps, int P_rt, const float2* __restrict__ tw,
-                int64_t spec_per_dump, int64_t cpd, float2* __restrict__ part) {
+__device__ __forceinline__ void fused_body(const int8_t* __restrict__ x, int64_t ld_x,
+                                           const int8_t* __restrict__ hist,
+                                           const float* __restrict__ taps, int P_rt,
+                                           const float2* __restrict__ tw, int64_t spec_per_dump,
+                                           int64_t cpd, float2* __restrict__ part, int64_t w,
+                                           float2* buf) {
   using C = FusedCfg<N, NA, S, V, PP, OCC>;
   using F = Fft<N, C::NT, V, PP, C::LN>;
-  extern __shared__ float2 buf[];
   float2* b0 = buf;
   float2* b1 = buf + (PP ? C::BUF : 0);
   const float2* bout = F::OUT ? b1 : b0;
   const int P = PT > 0 ? PT : P_rt;
-  const int64_t w = blockIdx.x;
   const int64_t d = w / cpd, c = w % cpd;
   const int64_t m_lo = d * spec_per_dump + (c * spec_per_dump) / cpd;
   const int64_t m_hi = d * spec_per_dump + ((c + 1) * spec_per_dump) / cpd;
@@ -236,6 +238,16 @@ fx_fused_kernel(const int8_t* __restrict__ x, int64_t ld_x, const int8_t* __rest
       for (int b = 0; b < C::NB; ++b) out[(int64_t)b * C::NCH + k] = acc[cc][b];
     }
   }
+}
+
+template <int N, int NA, int S, int V, bool PP, int OCC, int PT>
+__global__ void __launch_bounds__((FusedCfg<N, NA, S, V, PP, OCC>::NT), (OCC > 0 ? OCC : 1))
+fx_fused_kernel(const int8_t* __restrict__ x, int64_t ld_x, const int8_t* __restrict__ hist,
+                const float* __restrict__ taps, int P_rt, const float2* __restrict__ tw,
+                int64_t spec_per_dump, int64_t cpd, float2* __restrict__ part) {
+  extern __shared__ float2 buf[];
+  fused_body<N, NA, S, V, PP, OCC, PT>(x, ld_x, hist, taps, P_rt, tw, spec_per_dump, cpd, part,
+                                        (int64_t)blockIdx.x, buf);
 }
 
 // Ring variant of the fused kernel (one spectrum in flight, compile-time P):
@@ -601,26 +613,27 @@ __device__ __forceinline__ uint8_t enc_e4m3(float v) {
 // ---------------------------------------------------------------------------
 // Standalone F-engine: one antenna pair per block, S spectra in flight.
 // ---------------------------------------------------------------------------
-template <int N>
+template <int N, int SS = (N >= 4096 ? 1 : 4096 / N)>
 struct ChanCfg {
-  static constexpr int S = N >= 4096 ? 1 : 4096 / N;
+  static constexpr int S = SS;
   static constexpr int NT = S * N / 16;
   static constexpr int NCH = N / 2;
   static constexpr int LDS = lds_padded_size(S * N);
 };
 
-template <int N, int PREC>
-__global__ void __launch_bounds__(ChanCfg<N>::NT)
-channelize_kernel(const int8_t* __restrict__ x, int64_t ld_x, int n_ant, int64_t n_spec,
-                  const int8_t* __restrict__ hist, const float* __restrict__ taps, int P,
-                  const float2* __restrict__ tw, int64_t spec_per_blk, const float* __restrict__ scale,
-                  void* __restrict__ out) {
-  using C = ChanCfg<N>;
-  extern __shared__ float2 buf[];
+// Body of the F-engine for antenna pair p and spectra block bx (spec_per_blk
+// spectra), run by all NT threads of a block on the LDS region buf.
+template <int N, int SS, int PREC>
+__device__ __forceinline__ void chan_body(const int8_t* __restrict__ x, int64_t ld_x, int n_ant,
+                                          int64_t n_spec, const int8_t* __restrict__ hist,
+                                          const float* __restrict__ taps, int P,
+                                          const float2* __restrict__ tw, int64_t spec_per_blk,
+                                          const float* __restrict__ scale, void* __restrict__ out,
+                                          int64_t bx, int p, float2* buf) {
+  using C = ChanCfg<N, SS>;
   const int tid = threadIdx.x;
-  const int p = blockIdx.y;
   const int a0 = 2 * p, a1 = (2 * p + 1 < n_ant) ? 2 * p + 1 : -1;
-  const int64_t m_lo = (int64_t)blockIdx.x * spec_per_blk;
+  const int64_t m_lo = bx * spec_per_blk;
   int64_t m_hi = m_lo + spec_per_blk;
   if (m_hi > n_spec) m_hi = n_spec;
   float sa = 1.f, sb = 1.f;
@@ -680,6 +693,17 @@ channelize_kernel(const int8_t* __restrict__ x, int64_t ld_x, int n_ant, int64_t
     }
     __syncthreads();
   }
+}
+
+template <int N, int PREC>
+__global__ void __launch_bounds__(ChanCfg<N>::NT)
+channelize_kernel(const int8_t* __restrict__ x, int64_t ld_x, int n_ant, int64_t n_spec,
+                  const int8_t* __restrict__ hist, const float* __restrict__ taps, int P,
+                  const float2* __restrict__ tw, int64_t spec_per_blk, const float* __restrict__ scale,
+                  void* __restrict__ out) {
+  extern __shared__ float2 buf[];
+  chan_body<N, ChanCfg<N>::S, PREC>(x, ld_x, n_ant, n_spec, hist, taps, P, tw, spec_per_blk, scale,
+                                     out, (int64_t)blockIdx.x, (int)blockIdx.y, buf);
 }
 
 template <int N>
@@ -811,16 +835,18 @@ hipError_t launch_hist_copy(const int8_t* x, int64_t ld_x, int n_ant, int64_t n_
 // X-engine on the vector ALUs (float32), any n_ant.  Thread = one channel and
 // one 4x4 antenna block pair (I <= J); spectra split into `ksplit` runs.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256)
-xeng_f32_kernel(const float2* __restrict__ v, int n_ant, int64_t n_spec, int n_chan,
-                int64_t spec_per_dump, int64_t ksplit, int n_cgrp, float2* __restrict__ part) {
+// Body of the X-engine for channel group cg (NTX channels), antenna block
+// pair bp and run dz (= dump * ksplit + split).
+template <int NTX>
+__device__ __forceinline__ void xeng_f32_body(const float2* __restrict__ v, int n_ant, int64_t n_spec,
+                                              int n_chan, int64_t spec_per_dump, int64_t ksplit,
+                                              int cg, int bp_in, int64_t dz, float2* __restrict__ part) {
   const int nblk = (n_ant + 3) / 4;
   // block pair index -> (I, J), I <= J
-  int bp = blockIdx.y, I = 0;
+  int bp = bp_in, I = 0;
   while (bp >= nblk - I) { bp -= nblk - I; ++I; }
   const int J = I + bp;
-  const int k = (int)(blockIdx.x % n_cgrp) * blockDim.x + threadIdx.x;
-  const int64_t dz = blockIdx.x / n_cgrp;
+  const int k = cg * NTX + (int)threadIdx.x;
   const int64_t d = dz / ksplit, ks = dz % ksplit;
   const int64_t m_lo = d * spec_per_dump + (ks * spec_per_dump) / ksplit;
   const int64_t m_hi = d * spec_per_dump + ((ks + 1) * spec_per_dump) / ksplit;
@@ -867,6 +893,13 @@ xeng_f32_kernel(const float2* __restrict__ v, int n_ant, int64_t n_spec, int n_c
     }
 }
 
+__global__ void __launch_bounds__(256)
+xeng_f32_kernel(const float2* __restrict__ v, int n_ant, int64_t n_spec, int n_chan,
+                int64_t spec_per_dump, int64_t ksplit, int n_cgrp, float2* __restrict__ part) {
+  xeng_f32_body<256>(v, n_ant, n_spec, n_chan, spec_per_dump, ksplit, (int)(blockIdx.x % n_cgrp),
+                     (int)blockIdx.y, (int64_t)(blockIdx.x / n_cgrp), part);
+}
+
 int64_t xeng_f32_ksplit(int n_ant, int64_t spd, int n_chan, int64_t n_dump) {
   const int nblk = (n_ant + 3) / 4;
   const int64_t waves = (int64_t)nblk * (nblk + 1) / 2 * ((n_chan + 63) / 64) * n_dump;
@@ -883,6 +916,188 @@ hipError_t launch_xeng_f32(const float2* v, int n_ant, int64_t n_spec, int n_cha
   dim3 grid((unsigned)(n_cgrp * n_dump * ksplit), (unsigned)(nblk * (nblk + 1) / 2));
   hipLaunchKernelGGL(xeng_f32_kernel, grid, dim3(256), 0, s, v, n_ant, n_spec, n_chan, spd,
                      ksplit, n_cgrp, part);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Batched plans: every array's work in one persistent launch.  Blocks of
+// PL_NT threads claim items from a queue in order (one atomic per item);
+// items that depend on others (X-engine on F-engine output, reductions on
+// partials) come later in the queue than everything they depend on, so a
+// block only ever waits for items already claimed by running blocks.  Each
+// wait is bounded in time; on expiry the error flag is set, the item is
+// skipped and still counted, and every later wait gives up at once, so
+// every block reaches the queue's end and exits.
+// ---------------------------------------------------------------------------
+bool plan_fused_supported(int n_fft, int n_ant) {
+  return (n_ant == 4 && (n_fft == 1024 || n_fft == 2048 || n_fft == 4096)) ||
+         (n_ant == 8 && (n_fft == 1024 || n_fft == 2048));
+}
+
+bool plan_chan_supported(int n_fft) { return n_fft >= 16 && n_fft <= 8192; }
+
+__global__ void plan_reset_kernel(unsigned* ctr, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) ctr[i] = 0u;
+}
+
+__device__ __noinline__ void reduce_item(const PlArray* __restrict__ Ap, int64_t index) {
+  const PlArray& A = *Ap;
+  const int64_t nb = (int64_t)A.n_ant * (A.n_ant + 1) / 2;
+  const int64_t elems = nb * (A.n_fft / 2);
+  const int64_t d = index / A.n_red_blocks, eb = index % A.n_red_blocks;
+  const int64_t e_end = min(elems, (eb + 1) * (int64_t)PL_RED_BLOCK);
+  for (int64_t e = eb * PL_RED_BLOCK + threadIdx.x; e < e_end; e += PL_NT) {
+    float2 acc = make_float2(0.f, 0.f);
+    const float2* p = A.part + d * A.n_split * elems + e;
+    for (int64_t c = 0; c < A.n_split; ++c) {
+      const float2 v = p[c * elems];
+      acc.x += v.x;
+      acc.y += v.y;
+    }
+    A.vis[d * elems + e] = make_float2(acc.x * A.scale, acc.y * A.scale);
+  }
+}
+
+template <int N, int NA>
+__device__ __noinline__ void plan_fused(const PlArray* __restrict__ Ap, int64_t w, float2* buf) {
+  const PlArray& A = *Ap;
+  constexpr int S = 8192 / (((NA + 1) / 2) * N);
+  static_assert(FusedCfg<N, NA, S, 16, false, 0>::NT == PL_NT, "plan fused tile");
+  if (A.n_taps == 4)
+    fused_body<N, NA, S, 16, false, 0, 4>(A.x, A.n_samp, nullptr, A.taps, 4, A.tw, A.spd, A.n_split,
+                                          A.part, w, buf);
+  else
+    fused_body<N, NA, S, 16, false, 0, 0>(A.x, A.n_samp, nullptr, A.taps, A.n_taps, A.tw, A.spd,
+                                          A.n_split, A.part, w, buf);
+}
+
+template <int N>
+__device__ __noinline__ void plan_chan(const PlArray* __restrict__ Ap, int64_t index, float2* buf) {
+  const PlArray& A = *Ap;
+  constexpr int S = 8192 / N;
+  static_assert(ChanCfg<N, S>::NT == PL_NT, "plan F-engine tile");
+  const int n_pair = (A.n_ant + 1) / 2;
+  const int p = (int)(index % n_pair);
+  const int64_t bx = index / n_pair;
+  const int64_t n_spec = A.n_dump * A.spd;
+  chan_body<N, S, 0>(A.x, A.n_samp, A.n_ant, n_spec, nullptr, A.taps, A.n_taps, A.tw,
+                     A.spec_per_item, nullptr, A.chan, bx, p, buf);
+}
+
+__device__ __noinline__ void xeng_item(const PlArray* __restrict__ Ap, int64_t index) {
+  const PlArray& A = *Ap;
+  // index -> (run dz, block pair bp, channel group cg)
+  const int64_t per_dz = (int64_t)A.n_bp * A.n_cgrp;
+  const int64_t dz = index / per_dz;
+  const int rem = (int)(index % per_dz);
+  xeng_f32_body<PL_NT>(A.chan, A.n_ant, A.n_dump * A.spd, A.n_fft / 2, A.spd, A.n_split,
+                       rem % A.n_cgrp, rem / A.n_cgrp, dz, A.part);
+}
+
+// Bounded dependency wait, run by the whole block.  Thread 0 polls the
+// counter with relaxed agent-scope loads (a coherent read, no cache
+// maintenance per poll) until it reaches `target`, the time limit (in ticks
+// of the constant-rate wall clock) passes, or another block has already
+// given up (error flag set).  After the barrier every wave issues one
+// agent-scope acquire fence, so the producers' results are read fresh.
+__device__ __forceinline__ bool plan_wait(const unsigned* ctr, unsigned target, unsigned* err,
+                                          int64_t limit_ticks, int* sflag) {
+  if (threadIdx.x == 0) {
+    int ok = 1;
+    if (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      const int64_t t0 = wall_clock64();
+      while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
+            wall_clock64() - t0 > limit_ticks) {
+          ok = 0;
+          atomicOr(err, 1u);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(16);
+      }
+    }
+    *sflag = ok;
+  }
+  __syncthreads();
+  const bool ok = *sflag != 0;
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  __syncthreads();
+  return ok;
+}
+
+__global__ void __launch_bounds__(PL_NT) plan_kernel(PlArgs a) {
+  extern __shared__ float2 buf[];
+  __shared__ int s_item, s_flag;
+  unsigned* err = a.ctr + 1;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = (int)atomicAdd(a.ctr, 1u);
+    __syncthreads();
+    const int it = s_item;
+    __syncthreads();
+    if (it >= a.n_items) break;
+    const PlItem item = a.items[it];
+    const PlArray* Ap = a.arr + item.array;
+    unsigned* done_part = a.ctr + 2 + 2 * item.array;
+    unsigned* done_chan = a.ctr + 3 + 2 * item.array;
+    bool ok = true;
+    if (item.kind == PL_XENG)
+      ok = plan_wait(done_chan, (unsigned)(Ap->n_chan_items + a.wait_bias), err, a.wait_ticks, &s_flag);
+    else if (item.kind == PL_REDUCE)
+      ok = plan_wait(done_part, (unsigned)(Ap->n_part_items + a.wait_bias), err, a.wait_ticks, &s_flag);
+    if (ok) {
+      const int N = Ap->n_fft, NA = Ap->n_ant;
+      if (item.kind == PL_FUSED) {
+        if (NA == 4 && N == 1024) plan_fused<1024, 4>(Ap, item.index, buf);
+        else if (NA == 4 && N == 2048) plan_fused<2048, 4>(Ap, item.index, buf);
+        else if (NA == 4 && N == 4096) plan_fused<4096, 4>(Ap, item.index, buf);
+        else if (NA == 8 && N == 1024) plan_fused<1024, 8>(Ap, item.index, buf);
+        else if (NA == 8 && N == 2048) plan_fused<2048, 8>(Ap, item.index, buf);
+      } else if (item.kind == PL_CHAN) {
+        switch (N) {
+          case 16: plan_chan<16>(Ap, item.index, buf); break;
+          case 32: plan_chan<32>(Ap, item.index, buf); break;
+          case 64: plan_chan<64>(Ap, item.index, buf); break;
+          case 128: plan_chan<128>(Ap, item.index, buf); break;
+          case 256: plan_chan<256>(Ap, item.index, buf); break;
+          case 512: plan_chan<512>(Ap, item.index, buf); break;
+          case 1024: plan_chan<1024>(Ap, item.index, buf); break;
+          case 2048: plan_chan<2048>(Ap, item.index, buf); break;
+          case 4096: plan_chan<4096>(Ap, item.index, buf); break;
+          case 8192: plan_chan<8192>(Ap, item.index, buf); break;
+        }
+      } else if (item.kind == PL_XENG) {
+        xeng_item(Ap, item.index);
+      } else {
+        reduce_item(Ap, item.index);
+      }
+    }
+    if (item.kind != PL_REDUCE) {
+      // publish: every wave writes its stores back at agent scope, then one
+      // release increment counts the item done (skipped items count too)
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __syncthreads();
+      if (threadIdx.x == 0)
+        __hip_atomic_fetch_add(item.kind == PL_CHAN ? done_chan : done_part, 1u, __ATOMIC_RELEASE,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      __syncthreads();  // LDS and s_item reuse
+    }
+  }
+}
+
+constexpr size_t PLAN_LDS = sizeof(float2) * lds_padded_size(8192);
+
+hipError_t prepare_plan() {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(plan_kernel),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)PLAN_LDS);
+}
+
+hipError_t launch_plan(const PlArgs& a, int grid, hipStream_t s) {
+  const int nctr = 2 + 2 * PL_MAX_ARRAYS;
+  hipLaunchKernelGGL(plan_reset_kernel, dim3(1), dim3(64), 0, s, a.ctr, nctr);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(plan_kernel, dim3(grid), dim3(PL_NT), PLAN_LDS, s, a);
   return hipGetLastError();
 }
 

@@ -70,4 +70,46 @@ hipError_t launch_solve(const float2* vis, const uint8_t* mask, int64_t n_time, 
                         double f0, double df, int ref, int lo, int hi, int n_lag, const float2* tw,
                         double* tau_b, double* phi_b, double* tau, double* phi, hipStream_t s);
 
+// ---- batched plans: one persistent launch over heterogeneous work items ----
+constexpr int PL_NT = 512;          // threads per block of the persistent kernel
+constexpr int PL_MAX_ARRAYS = 8;
+constexpr int PL_RED_BLOCK = 2048;  // visibilities per reduction item
+
+enum { PL_FUSED = 0, PL_CHAN = 1, PL_XENG = 2, PL_REDUCE = 3 };
+
+struct PlArray {
+  const int8_t* x;       // [n_ant][n_samp] (set per execution)
+  float2* vis;           // [n_dump][n_base][n_chan] (set per execution)
+  float2* part;          // partial visibilities [n_dump * n_split][n_base][n_chan]
+  float2* chan;          // two-pass only: float32 spectra [n_ant][n_spec][n_chan]
+  const float* taps;
+  const float2* tw;
+  int64_t n_samp, spd, n_dump, n_split;  // n_split: fused chunks per dump / X-engine k-split
+  int64_t spec_per_item;                 // two-pass: spectra per F-engine item
+  int32_t n_ant, n_fft, n_taps, mode;    // mode 0 fused, 1 two-pass
+  int32_t n_chan_items, n_part_items, n_cgrp, n_bp, n_red_blocks;
+  float scale;                           // reduction scale (1/4 for two-for-one spectra)
+};
+
+struct PlItem {
+  uint16_t kind, array;
+  uint32_t index;
+};
+
+struct PlArgs {
+  const PlArray* arr;  // device [n_arrays]
+  const PlItem* items;
+  int32_t n_items;
+  int32_t wait_bias;   // added to every wait target (failure injection; 0 in use)
+  int64_t wait_ticks;  // time limit of one dependency wait, wall-clock ticks
+  unsigned* ctr;  // [0] queue head, [1] error flag, [2+2a] partials done, [3+2a] spectra done
+};
+
+bool plan_fused_supported(int n_fft, int n_ant);
+bool plan_chan_supported(int n_fft);
+// Sets the persistent kernel's LDS limit on the current device; call before
+// launch_plan and outside stream capture.
+hipError_t prepare_plan();
+hipError_t launch_plan(const PlArgs& a, int grid, hipStream_t s);
+
 }  // namespace qc

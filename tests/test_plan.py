@@ -1,0 +1,248 @@
+"""Batched plans: uneven arrays in one persistent launch, hipGraph replay,
+autotuner, and the bounded-wait error path.
+
+Parity bar: the plan computes the same float32 sums as qc_xcorrelate, so
+against it max |V - V_ref| / sqrt(V_ii V_jj) <= 1e-6 (only the grouping of
+partial sums may differ), and against the FP64 oracle on sampled channels
+<= 1e-5 like every FP32 path."""
+
+import ctypes
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import pfb, xengine
+from tests.util import vis_err
+
+TOL = 1e-5
+
+# (n_ant, n_fft, n_spec, spec_per_dump): fused (4 ant N=1024/4096, 8 ant
+# N=2048) and two-pass (odd and larger antenna counts) arrays, ragged dumps.
+SMALL = [(4, 1024, 40, 12), (8, 2048, 21, 7), (16, 4096, 10, 5), (24, 4096, 9, 3),
+         (32, 8192, 6, 6), (3, 64, 70, 9), (4, 4096, 17, 8), (1, 256, 30, 10)]
+
+
+def _desc(n_ant, N, n_spec, spd, P=4):
+    return {"n_ant": n_ant, "n_samp": N * n_spec, "n_fft": N, "n_taps": P, "spec_per_dump": spd}
+
+
+def _x(n_ant, n_samp, seed):
+    return synth.generate(synth.array_spec(n_ant, n_samp, seed, corr=0.3, max_lag=7))
+
+
+def _chans(N, seed):
+    nch = N // 2
+    if nch <= 64:
+        return np.arange(nch)
+    rng = np.random.default_rng(seed)
+    return np.array(sorted(set(rng.choice(nch, 20, replace=False).tolist()) | {0, nch - 1}))
+
+
+def _inputs(arrays, seed=100):
+    import torch
+    hx = [_x(a["n_ant"], a["n_samp"], seed + i) for i, a in enumerate(arrays)]
+    return hx, [torch.from_numpy(h).cuda() for h in hx]
+
+
+# ---------------------------------------------------------------- CPU checks
+
+@pytest.mark.parametrize("bad", [
+    [],                                           # no arrays
+    [_desc(4, 1024, 8, 8)] * 9,                   # too many arrays
+    [_desc(0, 1024, 8, 8)],                       # no antennas
+    [_desc(65, 1024, 8, 8)],                      # too many antennas
+    [dict(_desc(4, 1024, 8, 8), n_fft=1000)],     # not a power of two
+    [dict(_desc(4, 1024, 8, 8), n_fft=8)],        # below 16
+    [dict(_desc(4, 1024, 8, 8), n_samp=1024 * 8 + 1)],   # not a multiple of n_fft
+    [_desc(4, 1024, 8, 9)],                       # no full dump
+    [dict(_desc(4, 1024, 8, 8), n_taps=0)],
+    [_desc(4, 1024, 8, 8), _desc(4, 16, 1 << 27, 8)],    # n_samp = 2^31
+])
+def test_plan_create_rejects(bad):
+    import paper_2604_20640_amd as qc
+    try:
+        L = qc.lib()
+    except OSError:
+        pytest.skip("library not built")
+    n = len(bad)
+    arr = (qc.ArrayDesc * max(n, 1))(*[qc.ArrayDesc(a["n_ant"], a["n_samp"], a["n_fft"], a["n_taps"],
+                                                     a["spec_per_dump"]) for a in bad])
+    h = ctypes.c_void_p()
+    assert L.qc_plan_create(arr, n, ctypes.byref(h)) == -1     # QC_EINVAL, before any device call
+    assert not h.value
+
+
+def test_plan_null_handles():
+    import paper_2604_20640_amd as qc
+    try:
+        L = qc.lib()
+    except OSError:
+        pytest.skip("library not built")
+    assert L.qc_plan_create(None, 1, None) == -1
+    assert L.qc_plan_set_wait_timeout(None, 5) == -1
+    assert L.qc_plan_set_wait_bias(None, 0) == -1
+    assert L.qc_plan_info(None, None, None, None) == -1
+    L.qc_plan_destroy(None)
+
+
+# ---------------------------------------------------------------- GPU parity
+
+@pytest.mark.gpu
+def test_plan_matches_xcorrelate_and_oracle(qc):
+    import torch
+    arrays = [_desc(*s) for s in SMALL]
+    hx, xs = _inputs(arrays)
+    plan = qc.Plan(arrays)
+    n_items, grid, knobs = plan.info()
+    assert n_items > len(arrays) and grid >= 1
+    vis = plan.empty_vis()
+    plan.execute(xs, vis)
+    plan.check()
+    for i, (a, h, x, v) in enumerate(zip(arrays, hx, xs, vis)):
+        na, N, spd = a["n_ant"], a["n_fft"], a["spec_per_dump"]
+        ref = qc.xcorrelate(x, N, a["n_taps"], spd)
+        torch.cuda.synchronize()
+        got = v.cpu().numpy()
+        assert got.shape == ref.shape
+        assert vis_err(got, ref.cpu().numpy(), na) <= 1e-6, i
+        ch = _chans(N, i)
+        V_ref = xengine.correlate_fast(pfb.channelize(h, N, a["n_taps"], chans=ch), spd)
+        assert vis_err(got[:, :, ch], V_ref, na) <= TOL, i
+
+
+@pytest.mark.gpu
+def test_plan_batch_workload_shapes(qc):
+    """The five uneven arrays of the batched workload, at a short length."""
+    import torch
+    arrays, hx = [], []
+    for i, (na, nch) in enumerate(synth.BATCH_ARRAYS):
+        N = 2 * nch
+        n_spec = max(8, (1 << 17) // N)
+        arrays.append(_desc(na, N, n_spec, n_spec // 2))
+        hx.append(_x(na, N * n_spec, 500 + i))
+    xs = [torch.from_numpy(h).cuda() for h in hx]
+    plan = qc.Plan(arrays)
+    vis = plan.empty_vis()
+    plan.execute(xs, vis)
+    plan.check()
+    sep = plan.empty_vis()
+    plan.execute_separate(xs, sep)
+    torch.cuda.synchronize()
+    for i, a in enumerate(arrays):
+        assert vis_err(vis[i].cpu().numpy(), sep[i].cpu().numpy(), a["n_ant"]) <= 1e-6
+    # oracle on one sampled channel set of the largest array
+    a, h = arrays[-1], hx[-1]
+    ch = _chans(a["n_fft"], 9)
+    V_ref = xengine.correlate_fast(pfb.channelize(h, a["n_fft"], 4, chans=ch), a["spec_per_dump"])
+    assert vis_err(vis[-1].cpu().numpy()[:, :, ch], V_ref, a["n_ant"]) <= TOL
+
+
+@pytest.mark.gpu
+def test_plan_is_deterministic_and_overwrites(qc):
+    import torch
+    arrays = [_desc(*s) for s in SMALL[:4]]
+    _, xs = _inputs(arrays, seed=7)
+    plan = qc.Plan(arrays)
+    v1, v2 = plan.empty_vis(), plan.empty_vis()
+    for v in v2:
+        v.fill_(123.0)
+    plan.execute(xs, v1)
+    plan.execute(xs, v2)
+    plan.check()
+    for a, b in zip(v1, v2):
+        assert torch.equal(a, b)
+
+
+@pytest.mark.gpu
+def test_plan_graph_replays(qc):
+    """Replays of the captured graph, with eager work on the same device
+    between them, each equal to the eager execution."""
+    import torch
+    arrays = [_desc(*s) for s in SMALL[:5]]
+    _, xs = _inputs(arrays, seed=11)
+    plan = qc.Plan(arrays)
+    eager = plan.empty_vis()
+    plan.execute(xs, eager)
+    plan.check()
+    vis = plan.empty_vis()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        plan.capture_graph(xs, vis)
+    torch.cuda.synchronize()
+    other = torch.from_numpy(_x(4, 1024 * 16, 3)).cuda()
+    for r in range(4):
+        for v in vis:
+            v.zero_()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            plan.replay()
+        s.synchronize()
+        plan.check()
+        for a, b in zip(vis, eager):
+            assert torch.equal(a, b), r
+        qc.xcorrelate(other, 1024, 4, 8)        # eager work between replays
+        plan.execute(xs, plan.empty_vis())
+        torch.cuda.synchronize()
+
+
+@pytest.mark.gpu
+def test_plan_capture_needs_side_stream(qc):
+    arrays = [_desc(*SMALL[0])]
+    _, xs = _inputs(arrays)
+    plan = qc.Plan(arrays)
+    with pytest.raises(qc.QCError):
+        plan.capture_graph(xs, plan.empty_vis())   # the legacy default stream cannot capture
+    with pytest.raises(qc.QCError):
+        plan.replay()                              # nothing captured
+
+
+@pytest.mark.gpu
+def test_plan_wait_timeout_reports_error(qc):
+    """Dependencies made unsatisfiable from the host: every bounded wait
+    expires, the kernel still drains, check() reports it, and the next
+    normal execution is correct again."""
+    import torch
+    arrays = [_desc(16, 1024, 12, 6), _desc(5, 256, 20, 10)]      # two-pass arrays: waits
+    _, xs = _inputs(arrays, seed=13)
+    plan = qc.Plan(arrays)
+    good = plan.empty_vis()
+    plan.execute(xs, good)
+    plan.check()
+    plan.set_wait_timeout(2000)          # 2 ms
+    plan.set_wait_bias(1)
+    bad = plan.empty_vis()
+    plan.execute(xs, bad)
+    with pytest.raises(qc.QCError) as ei:
+        plan.check()
+    assert ei.value.status == -5
+    plan.set_wait_bias(0)
+    plan.set_wait_timeout(2000000)
+    again = plan.empty_vis()
+    plan.execute(xs, again)
+    plan.check()
+    for a, b in zip(again, good):
+        assert torch.equal(a, b)
+
+
+@pytest.mark.gpu
+def test_plan_autotune_and_cache(qc, tmp_path):
+    import torch
+    arrays = [_desc(*s) for s in SMALL[:5]]
+    _, xs = _inputs(arrays, seed=17)
+    cache = str(tmp_path / "plan_tune.txt")
+    plan = qc.Plan(arrays)
+    ref = plan.empty_vis()
+    plan.execute(xs, ref)
+    plan.check()
+    vis = plan.empty_vis()
+    assert plan.autotune(xs, vis, reps=1, cache=cache) is False
+    knobs = plan.info()[2]
+    plan.execute(xs, vis)
+    plan.check()
+    for a, b, d in zip(vis, ref, arrays):
+        assert vis_err(a.cpu().numpy(), b.cpu().numpy(), d["n_ant"]) <= 1e-6
+    plan2 = qc.Plan(arrays)
+    assert plan2.autotune(xs, plan2.empty_vis(), reps=1, cache=cache) is True
+    assert plan2.info()[2] == knobs
+    torch.cuda.synchronize()
