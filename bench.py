@@ -42,8 +42,6 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision", action="store_true", help="skip the 32-antenna section")
     ap.add_argument("--no-batched", action="store_true", help="skip the uneven-arrays section")
-    ap.add_argument("--traffic", type=str, default=None,
-                    help="JSON file with measured HBM bytes per fused launch")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 256 MiB device copy kernel (counter calibration)")
     return ap.parse_args()
@@ -60,6 +58,30 @@ def fx_flops(n_ant, n_samp, n_fft, n_taps, n_spec_used):
     f = n_ant * n_spec_used * n_fft * (2 * n_taps + 2.5 * math.log2(n_fft))
     x = 8.0 * nb * (n_fft // 2) * n_spec_used
     return f + x
+
+
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "fx_fused_ring_realtime_4ant_n4096.md")
+KERNEL_SOURCES = ("paper_2604_20640_amd/csrc/qc_fx.hip", "paper_2604_20640_amd/csrc/qc_fft.h",
+                  "paper_2604_20640_amd/csrc/qc_kernels.h")
+
+
+def measured_traffic():
+    """HBM bytes per fused launch from the committed FETCH_SIZE/WRITE_SIZE
+    summary, or None when the kernel sources changed since it was taken."""
+    import hashlib
+    if not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    fields = {}
+    for line in open(TRAFFIC_PROFILE):
+        if ":" in line and line.split(":")[0] in ("hbm_bytes_per_launch", "kernel_sources_sha256"):
+            k, v = line.split(":", 1)
+            fields[k] = v.strip()
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, p), "rb").read())
+    if fields.get("kernel_sources_sha256") != h.hexdigest() or "hbm_bytes_per_launch" not in fields:
+        return None
+    return int(fields["hbm_bytes_per_launch"])
 
 
 def timed(torch, fn, reps):
@@ -137,8 +159,8 @@ def precision_section(torch, qc, steps):
 
 def batched_section(torch, qc, steps):
     """Five uneven arrays (4..32 antennas, 512..4096 channels, 2^22 samples
-    each) in one persistent launch: eager, graph replay, and the same work as
-    separate per-array calls."""
+    each) as one plan: eager, replay of its captured graph, and the same work
+    as separate per-array calls."""
     from tests.util import vis_err as vis_err_local
     n_samp = 1 << 22
     t0 = time.time()
@@ -153,7 +175,7 @@ def batched_section(torch, qc, steps):
     t0 = time.time()
     plan.autotune(xs, vis, reps=2)
     tune_s = time.time() - t0
-    n_items, grid, knobs = plan.info()
+    n_launch, conc, tiles, splits = plan.info()
     reps = max(5, steps // 5)
     side = torch.cuda.Stream()
     with torch.cuda.stream(side):
@@ -188,9 +210,9 @@ def batched_section(torch, qc, steps):
             "n_samp_per_ant": n_samp, "input_bytes": nbytes, "graph_ms": round(g_ms, 4),
             "plan_eager_ms": round(e_ms, 4), "separate_ms": round(s_ms, 4),
             "graph_input_GBps": round(nbytes / g_ms / 1e6, 2),
-            "speedup_vs_separate": round(s_ms / g_ms, 3), "n_items": n_items,
-            "knobs": {"fused_items": knobs[0], "chan_mult": knobs[1], "x_split": knobs[2],
-                      "grid": knobs[3]},
+            "speedup_vs_separate": round(s_ms / g_ms, 3), "plan_mode": "graph",
+            "launches_per_execution": n_launch,
+            "knobs": {"concurrent": conc, "fused_tile": tiles, "split": splits},
             "autotune_s": round(tune_s, 2), "vis_err_vs_separate": float(f"{err:.3e}")}
 
 
@@ -286,9 +308,7 @@ def main():
     fx_ms = kt["fx_fused"][0] / max(kt["fx_fused"][1], 1)
     flops = fx_flops(n_ant, S, N, P, n_dump * spd)
     achieved = flops / (fx_ms * 1e-3) / 1e12
-    traffic = None
-    if args.traffic and os.path.exists(args.traffic):
-        traffic = json.load(open(args.traffic)).get("hbm_bytes_per_launch")
+    traffic = measured_traffic()
     log(f"[bench] step {ms_step:.3f} ms, {value:.1f} GB/s; fused F+X {fx_ms:.3f} ms")
 
     # parity of this very run on a sample (oracle: first dump, 64 channels)

@@ -170,36 +170,50 @@ qc_status qc_solve_delay_phase(const float* vis, const uint8_t* mask, int64_t n_
                                double* phi_rad, void* stream);
 
 /* Batched plans: several arrays (antenna counts, channel counts, dumps of
- * their own) correlated together in ONE persistent kernel launch.  Blocks
- * claim work items from an ordered queue: fused F+X for arrays of 4 antennas
- * (N = 1024..4096) or 8 antennas (N = 1024, 2048); F-engine, FP32 X-engine
- * and fixed-order reduction items for every other array.  The same sums as
- * qc_xcorrelate (FP32 visibilities, built-in Hann-sinc taps).  Alg. 1 runs
- * the same F-X-integrate steps per array; the tile knobs play the role of
- * the paper's batch-packets / queue-max operating point (Sec. 6).
+ * their own) correlated together, with the same float32 sums as
+ * qc_xcorrelate (built-in Hann-sinc taps).  Alg. 1 runs the same
+ * F-X-integrate steps per array; the plan's tuned knobs play the role of the
+ * paper's batch-packets / queue-max operating point (Sec. 6).
+ *
+ * Modes (qc_plan_set_mode):
+ *   QC_PLAN_GRAPH (default): per array, the fused F+X kernel and its
+ *     fixed-order reduction (arrays of 2, 4 or 8 antennas with a fused tile
+ *     for their n_fft), or F-engine, FP32 X-engine and reduction, into
+ *     plan-owned buffers.  With `concurrent` set, every array runs on a
+ *     stream of its own between a fork and a join event on the caller's
+ *     stream, so a captured graph holds the arrays as independent branches.
+ *   QC_PLAN_PERSISTENT: one persistent launch claiming work items from an
+ *     ordered queue with bounded waits between dependent items.  Switched
+ *     off in this build: selecting it returns QC_EUNSUPPORTED.
+ *
  *   qc_plan_create: n_arrays in [1, 8]; each array 1..64 antennas, n_fft a
  *     power of two in [16, 8192], n_samp a multiple of n_fft (< 2^31), at
- *     least one full dump.  Allocates device buffers; synchronises.
+ *     least one full dump.  Allocates device buffers, streams and events
+ *     (default priority); synchronises.
  *   qc_plan_execute: x[i]: device int8 [n_ant][n_samp] (contiguous); vis[i]:
- *     device cfloat [n_dump][n_base][n_chan].  Asynchronous on `stream`.
- *   qc_plan_check: synchronises `stream`; QC_ESTATE if a bounded dependency
- *     wait expired in the last execution (results of that execution invalid).
- *   qc_plan_set_wait_timeout: time limit of one dependency wait in
- *     microseconds (default 2 s, at most 600 s); once one wait has expired,
- *     every later wait in that execution gives up at once.
- *   qc_plan_set_wait_bias: failure injection for tests: adds `bias` to every
- *     dependency target so that waits cannot be satisfied (0 in normal use).
+ *     device cfloat [n_dump][n_base][n_chan], overwritten.  Asynchronous with
+ *     respect to the host; ordered on `stream` (work forked to the plan's
+ *     streams is joined back to it).  Executions of one plan share its
+ *     buffers: issue them on one stream.
+ *   qc_plan_check: synchronises `stream`; in the persistent mode QC_ESTATE
+ *     if a bounded dependency wait expired in the last execution.
+ *   qc_plan_set_wait_timeout / qc_plan_set_wait_bias: persistent mode only
+ *     (time limit of one dependency wait in microseconds, default 2 s; test
+ *     hook that makes every wait target unreachable).
  *   qc_plan_capture_graph: captures one execution (fixed x / vis pointers)
  *     on a non-default stream into a hipGraph; qc_plan_replay launches it.
- *   qc_plan_autotune: times executions over candidate tile knobs (fused
- *     items per array, F-engine item size, X-engine split, persistent grid)
- *     by coordinate descent and keeps the fastest; with cache_path (or NULL)
- *     a previous result for the same arrays is reused (*from_cache = 1) and
- *     new results are appended.  Synchronises.
+ *     Changing the mode or re-tuning drops the graph.
+ *   qc_plan_autotune: graph mode; times executions over the knobs
+ *     (concurrency; per array the fused tile and the split: chunks per dump
+ *     of the fused kernel or k-split of the X-engine) by coordinate descent
+ *     and keeps the fastest.  With cache_path (or NULL) a previous result for
+ *     the same arrays is reused (*from_cache = 1) and new results appended.
+ *     Synchronises.
  *   qc_plan_execute_separate: the same work as separate qc_xcorrelate calls
  *     (for comparison).
- *   qc_plan_info: item count, grid, knobs (int64[4]: fused items, F-engine
- *     multiplier, X split, grid); any output may be NULL. */
+ *   qc_plan_info: launches per execution, the concurrency flag, and per
+ *     array the fused tile (-1 for the two-pass path) and the split; any
+ *     output may be NULL (tiles and splits hold n_arrays entries). */
 typedef struct qc_plan qc_plan;
 typedef struct {
   int32_t n_ant;
@@ -208,7 +222,9 @@ typedef struct {
   int32_t n_taps;
   int64_t spec_per_dump;
 } qc_array_desc;
+enum { QC_PLAN_GRAPH = 0, QC_PLAN_PERSISTENT = 1 };
 qc_status qc_plan_create(const qc_array_desc* arrays, int32_t n_arrays, qc_plan** out);
+qc_status qc_plan_set_mode(qc_plan* plan, int32_t mode);
 qc_status qc_plan_execute(qc_plan* plan, const int8_t* const* x, float* const* vis, void* stream);
 qc_status qc_plan_check(qc_plan* plan, void* stream);
 qc_status qc_plan_set_wait_timeout(qc_plan* plan, int64_t microseconds);
@@ -219,7 +235,8 @@ qc_status qc_plan_autotune(qc_plan* plan, const int8_t* const* x, float* const* 
                            const char* cache_path, int32_t* from_cache, void* stream);
 qc_status qc_plan_execute_separate(qc_plan* plan, const int8_t* const* x, float* const* vis,
                                    void* stream);
-qc_status qc_plan_info(const qc_plan* plan, int32_t* n_items, int32_t* grid, int64_t* knobs4);
+qc_status qc_plan_info(const qc_plan* plan, int32_t* n_launches, int32_t* concurrent, int32_t* tiles,
+                       int64_t* splits);
 void qc_plan_destroy(qc_plan* plan);
 
 /* Streaming ingest (Alg. 1: pinned host buffers, asynchronous host-to-device

@@ -111,7 +111,9 @@ def lib() -> ctypes.CDLL:
             "qc_plan_capture_graph": [_P, PP, PP, _P],
             "qc_plan_replay": [_P, _P],
             "qc_plan_autotune": [_P, PP, PP, _I32, ctypes.c_char_p, ctypes.POINTER(_I32), _P],
-            "qc_plan_info": [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I64)],
+            "qc_plan_info": [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32),
+                             ctypes.POINTER(_I64)],
+            "qc_plan_set_mode": [_P, _I32],
         }.items():
             fn = getattr(L, name)
             fn.argtypes = args
@@ -196,7 +198,9 @@ class Stream:
 class Plan:
     """Several arrays correlated in one persistent launch (qc_plan_*)."""
 
-    def __init__(self, arrays):
+    MODES = {"graph": 0, "persistent": 1}
+
+    def __init__(self, arrays, mode="graph"):
         """arrays: list of dicts with n_ant, n_samp, n_fft, n_taps, spec_per_dump."""
         n = len(arrays)
         self.arrays = [dict(a) for a in arrays]
@@ -205,6 +209,11 @@ class Plan:
         h = ctypes.c_void_p()
         _check(lib().qc_plan_create(descs, n, ctypes.byref(h)), "qc_plan_create")
         self._h = h
+        if mode != "graph":
+            self.set_mode(mode)
+
+    def set_mode(self, mode):
+        _check(lib().qc_plan_set_mode(self._h, self.MODES[mode]), "qc_plan_set_mode")
 
     def empty_vis(self, device="cuda"):
         out = []
@@ -253,10 +262,13 @@ class Plan:
         return bool(fc.value)
 
     def info(self):
-        n, g = _I32(0), _I32(0)
-        k = (_I64 * 4)()
-        _check(lib().qc_plan_info(self._h, ctypes.byref(n), ctypes.byref(g), k), "qc_plan_info")
-        return n.value, g.value, list(k)
+        """(launches per execution, concurrent, per-array fused tile or -1, per-array split)."""
+        n, c = _I32(0), _I32(0)
+        m = len(self.arrays)
+        tiles, splits = (_I32 * m)(), (_I64 * m)()
+        _check(lib().qc_plan_info(self._h, ctypes.byref(n), ctypes.byref(c), tiles, splits),
+               "qc_plan_info")
+        return n.value, c.value, list(tiles), list(splits)
 
     def close(self):
         if getattr(self, "_h", None):

@@ -627,22 +627,51 @@ qc_status qc_timing_read(int32_t kernel, double* total_ms, int64_t* launches) {
 }  // extern "C"
 
 // ---- batched plans ------------------------------------------------------------
+// Two implementations of one contract.  The default (QC_PLAN_GRAPH) records,
+// per array, the same kernels qc_xcorrelate launches (fused F+X and reduction,
+// or F-engine, FP32 X-engine and reduction) into plan-owned buffers, each
+// array on a stream of its own between a fork and a join event, so that one
+// captured graph holds every array as an independent branch.  The second
+// (QC_PLAN_PERSISTENT: one persistent launch claiming work items from a
+// queue, with bounded waits between dependent items) is compiled but
+// switched off: it did not complete on gfx950.
 namespace {
 constexpr int PLAN_SLOTS = 16;  // descriptor slots for executions in flight (+1 for a graph)
-}
+constexpr bool kPersistentPlanEnabled = false;
+
+struct PlanArr {
+  bool fused = false;
+  int tile = 0;           // fused kernel tile (index into the (n_fft, n_ant) tile list)
+  int64_t split = 1;      // fused: chunks per dump; two-pass: X-engine k-split
+  int64_t split_max = 1;  // capacity of the partial buffer, splits per dump
+  int64_t n_dump = 0;
+  const float* taps = nullptr;
+  float2* tw = nullptr;
+  float2* part = nullptr;
+  float2* chan = nullptr;
+};
+}  // namespace
 
 struct qc_plan {
   int device = 0;
   int n = 0;
+  int mode = QC_PLAN_GRAPH;
   qc_array_desc desc[qc::PL_MAX_ARRAYS];
+  // graph mode
+  PlanArr ga[qc::PL_MAX_ARRAYS];
+  int concurrent = 1;  // arrays on streams of their own (1) or in order on the caller's stream (0)
+  hipStream_t st[qc::PL_MAX_ARRAYS] = {};
+  hipEvent_t fork_ev = nullptr;
+  hipEvent_t join_ev[qc::PL_MAX_ARRAYS] = {};
+  std::vector<void*> gbufs;
+  // persistent mode
   qc::PlArray arr[qc::PL_MAX_ARRAYS];
-  // tile knobs (set by qc_plan_autotune)
   int64_t fused_items = 512;  // target fused items per array
   int64_t chan_mult = 4;      // F-engine item = spectra-in-flight * chan_mult spectra
   int64_t x_split = 2;        // X-engine k-split
   int grid = 256;             // persistent blocks
-  int64_t wait_us = 2000000;   // time limit of one dependency wait
-  int64_t clock_khz = 0;       // device wall-clock rate
+  int64_t wait_us = 2000000;  // time limit of one dependency wait
+  int64_t clock_khz = 0;      // device wall-clock rate
   int wait_bias = 0;
   std::vector<qc::PlItem> items;
   qc::PlItem* d_items = nullptr;
@@ -653,13 +682,14 @@ struct qc_plan {
   bool slot_used[PLAN_SLOTS] = {};
   int next_slot = 0;
   std::vector<void*> bufs;
+  // the captured graph (either mode)
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
 };
 
 namespace {
 
-void plan_free_buffers(qc_plan* P) {
+void persist_free(qc_plan* P) {
   if (!P->bufs.empty() || P->d_items) (void)hipDeviceSynchronize();
   for (void* b : P->bufs) (void)hipFree(b);
   P->bufs.clear();
@@ -674,10 +704,10 @@ void plan_drop_graph(qc_plan* P) {
   P->graph = nullptr;
 }
 
-qc_status plan_build(qc_plan* P) {
+qc_status persist_build(qc_plan* P) {
   // a captured graph refers to the buffers and items rebuilt here
   plan_drop_graph(P);
-  plan_free_buffers(P);
+  persist_free(P);
   std::vector<qc::PlItem> first, xeng, red;
   for (int i = 0; i < P->n; ++i) {
     const qc_array_desc& D = P->desc[i];
@@ -773,7 +803,7 @@ qc_status plan_build(qc_plan* P) {
   return QC_OK;
 }
 
-qc_status plan_enqueue(qc_plan* P, const int8_t* const* x, float* const* vis, hipStream_t s, int slot) {
+qc_status persist_enqueue(qc_plan* P, const int8_t* const* x, float* const* vis, hipStream_t s, int slot) {
   qc::PlArray* h = P->h_slots + (size_t)slot * qc::PL_MAX_ARRAYS;
   qc::PlArray* d = P->d_slots + (size_t)slot * qc::PL_MAX_ARRAYS;
   for (int i = 0; i < P->n; ++i) {
@@ -793,6 +823,126 @@ qc_status plan_enqueue(qc_plan* P, const int8_t* const* x, float* const* vis, hi
   return QC_OK;
 }
 
+qc_status persist_setup(qc_plan* P) {
+  hipError_t e = hipSuccess;
+  int khz = 0;
+  e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, P->device);
+  P->clock_khz = khz > 0 ? khz : 100000;
+  if (e == hipSuccess) e = hipMalloc(&P->d_ctr, sizeof(unsigned) * (2 + 2 * qc::PL_MAX_ARRAYS));
+  if (e == hipSuccess)
+    e = hipMalloc(&P->d_slots, sizeof(qc::PlArray) * (PLAN_SLOTS + 1) * qc::PL_MAX_ARRAYS);
+  if (e == hipSuccess)
+    e = hipHostMalloc(&P->h_slots, sizeof(qc::PlArray) * (PLAN_SLOTS + 1) * qc::PL_MAX_ARRAYS, 0);
+  for (int i = 0; e == hipSuccess && i < PLAN_SLOTS; ++i)
+    e = hipEventCreateWithFlags(&P->slot_ev[i], hipEventDisableTiming);
+  if (e != hipSuccess) return hip_fail(e, "plan allocation");
+  return persist_build(P);
+}
+
+qc_status persist_execute(qc_plan* P, const int8_t* const* x, float* const* vis, hipStream_t s) {
+  const int slot = P->next_slot;
+  P->next_slot = (P->next_slot + 1) % PLAN_SLOTS;
+  // the slot's staging may still be read by an earlier execution's copy
+  if (P->slot_used[slot]) QC_HIP(hipEventSynchronize(P->slot_ev[slot]), "plan slot wait");
+  QC_HIP(qc::prepare_plan(), "plan kernel attributes");
+  qc_status st = persist_enqueue(P, x, vis, s, slot);
+  if (st != QC_OK) return st;
+  QC_HIP(hipEventRecord(P->slot_ev[slot], s), "plan slot event");
+  P->slot_used[slot] = true;
+  return QC_OK;
+}
+
+// ---- graph mode ----
+
+void graph_free(qc_plan* P) {
+  if (!P->gbufs.empty()) (void)hipDeviceSynchronize();
+  for (void* b : P->gbufs) (void)hipFree(b);
+  P->gbufs.clear();
+}
+
+qc_status graph_setup(qc_plan* P) {
+  for (int i = 0; i < P->n; ++i) {
+    const qc_array_desc& D = P->desc[i];
+    PlanArr& G = P->ga[i];
+    const int N = D.n_fft, NA = D.n_ant, nch = N / 2;
+    const int64_t nb = (int64_t)NA * (NA + 1) / 2, elems = nb * nch;
+    G.n_dump = (D.n_samp / N) / D.spec_per_dump;
+    TapsEntry te;
+    qc_status st = get_taps(N, D.n_taps, &te);
+    if (st != QC_OK) return st;
+    G.taps = te.dev;
+    st = get_twiddles(N, &G.tw);
+    if (st != QC_OK) return st;
+    G.fused = qc::fused_supported(N, NA);
+    if (G.fused) {
+      G.tile = 0;
+      G.split = qc::fused_chunks_per_dump(N, NA, G.n_dump, D.spec_per_dump);
+      G.split_max = std::min<int64_t>(D.spec_per_dump, 2 * G.split);
+    } else {
+      G.split = qc::xeng_f32_ksplit(NA, D.spec_per_dump, nch, G.n_dump);
+      G.split_max = std::min<int64_t>(D.spec_per_dump, std::max<int64_t>(16, G.split));
+      void* chan = nullptr;
+      const size_t bytes = sizeof(float2) * (size_t)NA * G.n_dump * D.spec_per_dump * nch;
+      hipError_t e = hipMalloc(&chan, bytes);
+      if (e != hipSuccess) return fail(QC_ENOMEM, "plan spectra buffer: %s", hipGetErrorString(e));
+      P->gbufs.push_back(chan);
+      G.chan = (float2*)chan;
+    }
+    void* part = nullptr;
+    hipError_t e = hipMalloc(&part, sizeof(float2) * (size_t)(G.n_dump * G.split_max) * elems);
+    if (e != hipSuccess) return fail(QC_ENOMEM, "plan partial buffer: %s", hipGetErrorString(e));
+    P->gbufs.push_back(part);
+    G.part = (float2*)part;
+    QC_HIP(hipStreamCreateWithFlags(&P->st[i], hipStreamNonBlocking), "hipStreamCreateWithFlags");
+    QC_HIP(hipEventCreateWithFlags(&P->join_ev[i], hipEventDisableTiming), "hipEventCreate");
+  }
+  QC_HIP(hipEventCreateWithFlags(&P->fork_ev, hipEventDisableTiming), "hipEventCreate");
+  return QC_OK;
+}
+
+// one array's kernels on stream s
+qc_status graph_array(qc_plan* P, int i, const int8_t* x, float* vis, hipStream_t s) {
+  const qc_array_desc& D = P->desc[i];
+  const PlanArr& G = P->ga[i];
+  const int N = D.n_fft, NA = D.n_ant, nch = N / 2;
+  const int64_t nb = (int64_t)NA * (NA + 1) / 2, elems = nb * nch;
+  const int64_t ns = G.n_dump * D.spec_per_dump;
+  const qc::FxArgs a{x, D.n_samp, NA, ns * N, N, D.n_taps, G.taps, G.tw, nullptr, true};
+  float2* v = reinterpret_cast<float2*>(vis);
+  if (G.fused) {
+    QC_HIP(qc::launch_fused(a, G.n_dump, D.spec_per_dump, G.split, G.part, s, G.tile), "fused F+X kernel");
+    QC_HIP(qc::launch_reduce(G.part, G.n_dump, G.split, elems, 0.25f, 0, v, s), "reduce kernel");
+  } else {
+    QC_HIP(qc::launch_channelize(a, 0, G.chan, nullptr, s), "channelize kernel");
+    QC_HIP(qc::launch_xeng_f32(G.chan, NA, ns, nch, D.spec_per_dump, G.n_dump, G.split, G.part, s),
+           "X-engine f32 kernel");
+    QC_HIP(qc::launch_reduce(G.part, G.n_dump, G.split, elems, 1.0f, 0, v, s), "reduce kernel");
+  }
+  return QC_OK;
+}
+
+qc_status graph_execute(qc_plan* P, const int8_t* const* x, float* const* vis, hipStream_t s) {
+  const bool fork = P->concurrent && P->n > 1;
+  if (fork) QC_HIP(hipEventRecord(P->fork_ev, s), "hipEventRecord(fork)");
+  for (int i = 0; i < P->n; ++i) {
+    hipStream_t si = fork ? P->st[i] : s;
+    if (fork) QC_HIP(hipStreamWaitEvent(si, P->fork_ev, 0), "hipStreamWaitEvent(fork)");
+    qc_status st = graph_array(P, i, x[i], vis[i], si);
+    if (st != QC_OK) return st;
+    if (fork) {
+      QC_HIP(hipEventRecord(P->join_ev[i], si), "hipEventRecord(join)");
+      QC_HIP(hipStreamWaitEvent(s, P->join_ev[i], 0), "hipStreamWaitEvent(join)");
+    }
+  }
+  return QC_OK;
+}
+
+int graph_launches(const qc_plan* P) {
+  int k = 0;
+  for (int i = 0; i < P->n; ++i) k += P->ga[i].fused ? 2 : 3;
+  return k;
+}
+
 qc_status plan_check_args(qc_plan* P, const int8_t* const* x, float* const* vis) {
   if (!P || !x || !vis) return fail(QC_EINVAL, "NULL argument");
   for (int i = 0; i < P->n; ++i) {
@@ -803,12 +953,106 @@ qc_status plan_check_args(qc_plan* P, const int8_t* const* x, float* const* vis)
   return QC_OK;
 }
 
+qc_status plan_run(qc_plan* P, const int8_t* const* x, float* const* vis, hipStream_t s) {
+  return P->mode == QC_PLAN_GRAPH ? graph_execute(P, x, vis, s) : persist_execute(P, x, vis, s);
+}
+
 std::string plan_signature(const qc_plan* P) {
   std::ostringstream o;
   for (int i = 0; i < P->n; ++i)
     o << P->desc[i].n_ant << "x" << P->desc[i].n_samp << "x" << P->desc[i].n_fft << "x"
       << P->desc[i].n_taps << "x" << P->desc[i].spec_per_dump << (i + 1 < P->n ? "," : "");
   return o.str();
+}
+
+// timed executions (eager, on s) with the plan's current knobs
+qc_status plan_time(qc_plan* P, const int8_t* const* x, float* const* vis, int reps, hipStream_t s,
+                    hipEvent_t a, hipEvent_t b, double* ms_out) {
+  qc_status q = plan_run(P, x, vis, s);  // untimed
+  if (q != QC_OK) return q;
+  QC_HIP(hipEventRecord(a, s), "hipEventRecord");
+  for (int r = 0; r < reps && q == QC_OK; ++r) q = plan_run(P, x, vis, s);
+  if (q != QC_OK) return q;
+  QC_HIP(hipEventRecord(b, s), "hipEventRecord");
+  QC_HIP(hipEventSynchronize(b), "hipEventSynchronize");
+  float ms = 0.f;
+  QC_HIP(hipEventElapsedTime(&ms, a, b), "hipEventElapsedTime");
+  *ms_out = ms / reps;
+  return QC_OK;
+}
+
+// Coordinate descent over the graph-mode knobs: concurrency, then per
+// array the fused tile and the split (chunks per dump, or X-engine k-split).
+qc_status graph_tune(qc_plan* P, const int8_t* const* x, float* const* vis, int reps, hipStream_t s,
+                     hipEvent_t a, hipEvent_t b) {
+  double best = 0.0;
+  qc_status st = plan_time(P, x, vis, reps, s, a, b, &best);
+  auto try_value = [&](auto set, auto get, const std::vector<int64_t>& cand) -> qc_status {
+    const int64_t keep = get();
+    int64_t bestv = keep;
+    for (int64_t v : cand) {
+      if (v == keep) continue;
+      set(v);
+      double ms = 0.0;
+      qc_status q = plan_time(P, x, vis, reps, s, a, b, &ms);
+      if (q != QC_OK) {
+        set(keep);
+        return q;
+      }
+      if (ms < best) {
+        best = ms;
+        bestv = v;
+      }
+    }
+    set(bestv);
+    return QC_OK;
+  };
+  for (int pass = 0; st == QC_OK && pass < 2; ++pass) {
+    st = try_value([&](int64_t v) { P->concurrent = (int)v; }, [&] { return (int64_t)P->concurrent; },
+                   {0, 1});
+    for (int i = 0; st == QC_OK && i < P->n; ++i) {
+      PlanArr& G = P->ga[i];
+      const qc_array_desc& D = P->desc[i];
+      if (G.fused) {
+        std::vector<int64_t> tiles;
+        for (int t = 0; t < qc::fused_tile_count(D.n_fft, D.n_ant); ++t) tiles.push_back(t);
+        st = try_value([&](int64_t v) { G.tile = (int)v; }, [&] { return (int64_t)G.tile; }, tiles);
+        if (st != QC_OK) break;
+      }
+      std::vector<int64_t> splits;
+      for (int64_t v : {1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 1024})
+        if (v <= G.split_max) splits.push_back(v);
+      st = try_value([&](int64_t v) { G.split = v; }, [&] { return G.split; }, splits);
+    }
+  }
+  return st;
+}
+
+std::string graph_knobs(const qc_plan* P) {
+  std::ostringstream o;
+  o << P->concurrent;
+  for (int i = 0; i < P->n; ++i) o << " " << (P->ga[i].fused ? P->ga[i].tile : -1) << " " << P->ga[i].split;
+  return o.str();
+}
+
+bool graph_knobs_parse(qc_plan* P, std::istringstream& ls) {
+  int conc = 0;
+  if (!(ls >> conc) || (conc != 0 && conc != 1)) return false;
+  int tile[qc::PL_MAX_ARRAYS];
+  int64_t split[qc::PL_MAX_ARRAYS];
+  for (int i = 0; i < P->n; ++i) {
+    if (!(ls >> tile[i] >> split[i])) return false;
+    const PlanArr& G = P->ga[i];
+    const qc_array_desc& D = P->desc[i];
+    if (split[i] < 1 || split[i] > G.split_max) return false;
+    if (G.fused && (tile[i] < 0 || tile[i] >= qc::fused_tile_count(D.n_fft, D.n_ant))) return false;
+  }
+  P->concurrent = conc;
+  for (int i = 0; i < P->n; ++i) {
+    if (P->ga[i].fused) P->ga[i].tile = tile[i];
+    P->ga[i].split = split[i];
+  }
+  return true;
 }
 
 }  // namespace
@@ -837,21 +1081,11 @@ qc_status qc_plan_create(const qc_array_desc* arrays, int32_t n_arrays, qc_plan*
   P->n = n_arrays;
   for (int i = 0; i < n_arrays; ++i) P->desc[i] = arrays[i];
   hipError_t e = hipGetDevice(&P->device);
-  int khz = 0;
-  if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, P->device);
-  P->clock_khz = khz > 0 ? khz : 100000;
-  if (e == hipSuccess) e = hipMalloc(&P->d_ctr, sizeof(unsigned) * (2 + 2 * qc::PL_MAX_ARRAYS));
-  if (e == hipSuccess)
-    e = hipMalloc(&P->d_slots, sizeof(qc::PlArray) * (PLAN_SLOTS + 1) * qc::PL_MAX_ARRAYS);
-  if (e == hipSuccess)
-    e = hipHostMalloc(&P->h_slots, sizeof(qc::PlArray) * (PLAN_SLOTS + 1) * qc::PL_MAX_ARRAYS, 0);
-  for (int i = 0; e == hipSuccess && i < PLAN_SLOTS; ++i)
-    e = hipEventCreateWithFlags(&P->slot_ev[i], hipEventDisableTiming);
   if (e != hipSuccess) {
-    qc_plan_destroy(P);
-    return hip_fail(e, "plan allocation");
+    delete P;
+    return hip_fail(e, "hipGetDevice");
   }
-  qc_status st = plan_build(P);
+  qc_status st = graph_setup(P);
   if (st != QC_OK) {
     qc_plan_destroy(P);
     return st;
@@ -860,29 +1094,42 @@ qc_status qc_plan_create(const qc_array_desc* arrays, int32_t n_arrays, qc_plan*
   return QC_OK;
 }
 
+qc_status qc_plan_set_mode(qc_plan* P, int32_t mode) {
+  g_err.clear();
+  if (!P) return fail(QC_EINVAL, "NULL plan");
+  if (mode == QC_PLAN_GRAPH) {
+    if (P->mode != mode) plan_drop_graph(P);
+    P->mode = mode;
+    return QC_OK;
+  }
+  if (mode != QC_PLAN_PERSISTENT) return fail(QC_EINVAL, "unknown plan mode %d", mode);
+  if (!kPersistentPlanEnabled)
+    return fail(QC_EUNSUPPORTED,
+                "the single persistent launch is switched off: on gfx950 it did not complete "
+                "and the cause is not yet identified");
+  if (P->mode != mode) {
+    plan_drop_graph(P);
+    qc_status st = P->d_ctr ? persist_build(P) : persist_setup(P);
+    if (st != QC_OK) return st;
+  }
+  P->mode = mode;
+  return QC_OK;
+}
+
 qc_status qc_plan_execute(qc_plan* P, const int8_t* const* x, float* const* vis, void* stream) {
   g_err.clear();
   qc_status st = plan_check_args(P, x, vis);
   if (st != QC_OK) return st;
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  const int slot = P->next_slot;
-  P->next_slot = (P->next_slot + 1) % PLAN_SLOTS;
-  // the slot's staging may still be read by an earlier execution's copy
-  if (P->slot_used[slot]) QC_HIP(hipEventSynchronize(P->slot_ev[slot]), "plan slot wait");
-  QC_HIP(qc::prepare_plan(), "plan kernel attributes");
-  st = plan_enqueue(P, x, vis, s, slot);
-  if (st != QC_OK) return st;
-  QC_HIP(hipEventRecord(P->slot_ev[slot], s), "plan slot event");
-  P->slot_used[slot] = true;
-  return QC_OK;
+  return plan_run(P, x, vis, reinterpret_cast<hipStream_t>(stream));
 }
 
 qc_status qc_plan_check(qc_plan* P, void* stream) {
   g_err.clear();
   if (!P) return fail(QC_EINVAL, "NULL plan");
-  unsigned flag = 0;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   QC_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+  if (P->mode != QC_PLAN_PERSISTENT) return QC_OK;
+  unsigned flag = 0;
   QC_HIP(hipMemcpy(&flag, P->d_ctr + 1, sizeof(unsigned), hipMemcpyDeviceToHost), "plan flag");
   if (flag) return fail(QC_ESTATE, "a bounded dependency wait expired in the last plan execution");
   return QC_OK;
@@ -902,16 +1149,15 @@ qc_status qc_plan_set_wait_bias(qc_plan* P, int32_t bias) {
   return QC_OK;
 }
 
-qc_status qc_plan_info(const qc_plan* P, int32_t* n_items, int32_t* grid, int64_t* knobs4) {
+qc_status qc_plan_info(const qc_plan* P, int32_t* n_launches, int32_t* concurrent, int32_t* tiles,
+                       int64_t* splits) {
   g_err.clear();
   if (!P) return fail(QC_EINVAL, "NULL plan");
-  if (n_items) *n_items = (int32_t)P->items.size();
-  if (grid) *grid = P->grid;
-  if (knobs4) {
-    knobs4[0] = P->fused_items;
-    knobs4[1] = P->chan_mult;
-    knobs4[2] = P->x_split;
-    knobs4[3] = P->grid;
+  if (n_launches) *n_launches = P->mode == QC_PLAN_GRAPH ? graph_launches(P) : 2;
+  if (concurrent) *concurrent = P->concurrent;
+  for (int i = 0; i < P->n; ++i) {
+    if (tiles) tiles[i] = P->ga[i].fused ? P->ga[i].tile : -1;
+    if (splits) splits[i] = P->ga[i].split;
   }
   return QC_OK;
 }
@@ -938,9 +1184,10 @@ qc_status qc_plan_capture_graph(qc_plan* P, const int8_t* const* x, float* const
   if (s == nullptr) return fail(QC_EINVAL, "graph capture needs a non-default stream");
   plan_drop_graph(P);
   QC_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
-  QC_HIP(qc::prepare_plan(), "plan kernel attributes");
+  if (P->mode == QC_PLAN_PERSISTENT) QC_HIP(qc::prepare_plan(), "plan kernel attributes");
   QC_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-  st = plan_enqueue(P, x, vis, s, PLAN_SLOTS);  // the graph's own descriptor slot
+  st = P->mode == QC_PLAN_GRAPH ? graph_execute(P, x, vis, s)
+                                : persist_enqueue(P, x, vis, s, PLAN_SLOTS);  // the graph's own slot
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(s, &g);
   if (st != QC_OK) {
@@ -966,6 +1213,7 @@ qc_status qc_plan_autotune(qc_plan* P, const int8_t* const* x, float* const* vis
   qc_status st = plan_check_args(P, x, vis);
   if (st != QC_OK) return st;
   if (reps < 1) return fail(QC_EINVAL, "reps must be >= 1");
+  if (P->mode != QC_PLAN_GRAPH) return fail(QC_EUNSUPPORTED, "autotuning covers the graph mode only");
   if (from_cache) *from_cache = 0;
   const std::string sig = plan_signature(P);
   if (cache_path) {
@@ -974,70 +1222,29 @@ qc_status qc_plan_autotune(qc_plan* P, const int8_t* const* x, float* const* vis
     while (std::getline(in, line)) {
       std::istringstream ls(line);
       std::string k;
-      int64_t f, c, xs, g;
-      if (ls >> k >> f >> c >> xs >> g && k == sig && f > 0 && c > 0 && xs > 0 && g > 0 && g <= 4096) {
-        P->fused_items = f;
-        P->chan_mult = c;
-        P->x_split = xs;
-        P->grid = (int)g;
+      if (ls >> k && k == sig && graph_knobs_parse(P, ls)) {
+        plan_drop_graph(P);
         if (from_cache) *from_cache = 1;
-        return plan_build(P);
+        return QC_OK;
       }
     }
   }
+  plan_drop_graph(P);  // knobs change the recorded launches
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   hipEvent_t a = nullptr, b = nullptr;
   QC_HIP(hipEventCreate(&a), "hipEventCreate");
-  QC_HIP(hipEventCreate(&b), "hipEventCreate");
-  auto measure = [&](double* ms_out) -> qc_status {
-    qc_status q = plan_build(P);
-    if (q != QC_OK) return q;
-    q = qc_plan_execute(P, x, vis, stream);  // untimed
-    if (q != QC_OK) return q;
-    QC_HIP(hipEventRecord(a, s), "hipEventRecord");
-    for (int r = 0; r < reps && q == QC_OK; ++r) q = qc_plan_execute(P, x, vis, stream);
-    if (q != QC_OK) return q;
-    QC_HIP(hipEventRecord(b, s), "hipEventRecord");
-    QC_HIP(hipEventSynchronize(b), "hipEventSynchronize");
-    float ms = 0.f;
-    QC_HIP(hipEventElapsedTime(&ms, a, b), "hipEventElapsedTime");
-    *ms_out = ms / reps;
-    return qc_plan_check(P, stream);
-  };
-  // coordinate descent over the four knobs, starting from the current values
-  const std::vector<int64_t> cand[4] = {{128, 256, 512, 1024, 2048}, {1, 2, 4, 8, 16}, {1, 2, 4, 8},
-                                        {256, 512, 768, 1024}};
-  int64_t* knob[4] = {&P->fused_items, &P->chan_mult, &P->x_split, nullptr};
-  double best = 1e300;
-  st = measure(&best);
-  for (int pass = 0; st == QC_OK && pass < 2; ++pass) {
-    for (int k = 0; st == QC_OK && k < 4; ++k) {
-      const int64_t keep = k < 3 ? *knob[k] : P->grid;
-      int64_t bestv = keep;
-      for (int64_t v : cand[k]) {
-        if (v == keep) continue;
-        if (k < 3) *knob[k] = v;
-        else P->grid = (int)v;
-        double ms = 0.0;
-        st = measure(&ms);
-        if (st != QC_OK) break;
-        if (ms < best) {
-          best = ms;
-          bestv = v;
-        }
-      }
-      if (k < 3) *knob[k] = bestv;
-      else P->grid = (int)bestv;
-    }
+  hipError_t e = hipEventCreate(&b);
+  if (e != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return hip_fail(e, "hipEventCreate");
   }
+  st = graph_tune(P, x, vis, reps, s, a, b);
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
   if (st != QC_OK) return st;
-  st = plan_build(P);
-  if (st != QC_OK) return st;
   if (cache_path) {
     std::ofstream o(cache_path, std::ios::app);
-    o << sig << " " << P->fused_items << " " << P->chan_mult << " " << P->x_split << " " << P->grid << "\n";
+    o << sig << " " << graph_knobs(P) << "\n";
   }
   return QC_OK;
 }
@@ -1046,7 +1253,13 @@ void qc_plan_destroy(qc_plan* P) {
   if (!P) return;
   (void)hipDeviceSynchronize();
   plan_drop_graph(P);
-  plan_free_buffers(P);
+  graph_free(P);
+  for (int i = 0; i < qc::PL_MAX_ARRAYS; ++i) {
+    if (P->st[i]) (void)hipStreamDestroy(P->st[i]);
+    if (P->join_ev[i]) (void)hipEventDestroy(P->join_ev[i]);
+  }
+  if (P->fork_ev) (void)hipEventDestroy(P->fork_ev);
+  persist_free(P);
   for (auto& ev : P->slot_ev)
     if (ev) (void)hipEventDestroy(ev);
   if (P->d_ctr) (void)hipFree(P->d_ctr);

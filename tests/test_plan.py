@@ -1,10 +1,15 @@
-"""Batched plans: uneven arrays in one persistent launch, hipGraph replay,
-autotuner, and the bounded-wait error path.
+"""Batched plans: uneven arrays correlated together, hipGraph replay,
+autotuner, and (persistent mode) the bounded-wait error path.
 
 Parity bar: the plan computes the same float32 sums as qc_xcorrelate, so
 against it max |V - V_ref| / sqrt(V_ii V_jj) <= 1e-6 (only the grouping of
 partial sums may differ), and against the FP64 oracle on sampled channels
-<= 1e-5 like every FP32 path."""
+<= 1e-5 like every FP32 path.
+
+The persistent mode (one launch, work-item queue, waits between dependent
+items) did not complete on the GPU in either of two runs (> 120 s, the
+second with time-bounded waits); its cause is not identified, the library
+rejects the mode, and its cases below are skipped."""
 
 import ctypes
 
@@ -16,6 +21,10 @@ from oracle import pfb, xengine
 from tests.util import vis_err
 
 TOL = 1e-5
+
+PERSISTENT_OFF = ("persistent plan mode switched off: its kernel did not complete on gfx950 "
+                  "(two runs, > 120 s); cause not identified")
+MODES = ["graph", pytest.param("persistent", marks=pytest.mark.skip(reason=PERSISTENT_OFF))]
 
 # (n_ant, n_fft, n_spec, spec_per_dump): fused (4 ant N=1024/4096, 8 ant
 # N=2048) and two-pass (odd and larger antenna counts) arrays, ragged dumps.
@@ -80,22 +89,25 @@ def test_plan_null_handles():
     except OSError:
         pytest.skip("library not built")
     assert L.qc_plan_create(None, 1, None) == -1
+    assert L.qc_plan_set_mode(None, 0) == -1
     assert L.qc_plan_set_wait_timeout(None, 5) == -1
     assert L.qc_plan_set_wait_bias(None, 0) == -1
-    assert L.qc_plan_info(None, None, None, None) == -1
+    assert L.qc_plan_info(None, None, None, None, None) == -1
     L.qc_plan_destroy(None)
 
 
 # ---------------------------------------------------------------- GPU parity
 
 @pytest.mark.gpu
-def test_plan_matches_xcorrelate_and_oracle(qc):
+@pytest.mark.parametrize("mode", MODES)
+def test_plan_matches_xcorrelate_and_oracle(qc, mode):
     import torch
     arrays = [_desc(*s) for s in SMALL]
     hx, xs = _inputs(arrays)
-    plan = qc.Plan(arrays)
-    n_items, grid, knobs = plan.info()
-    assert n_items > len(arrays) and grid >= 1
+    plan = qc.Plan(arrays, mode)
+    n_launch, conc, tiles, splits = plan.info()
+    assert n_launch >= 2 * len(arrays) and conc in (0, 1) and min(splits) >= 1
+    assert [t >= 0 for t in tiles] == [qc.fx_tile_count(a["n_fft"], a["n_ant"]) > 0 for a in arrays]
     vis = plan.empty_vis()
     plan.execute(xs, vis)
     plan.check()
@@ -112,7 +124,8 @@ def test_plan_matches_xcorrelate_and_oracle(qc):
 
 
 @pytest.mark.gpu
-def test_plan_batch_workload_shapes(qc):
+@pytest.mark.parametrize("mode", MODES)
+def test_plan_batch_workload_shapes(qc, mode):
     """The five uneven arrays of the batched workload, at a short length."""
     import torch
     arrays, hx = [], []
@@ -122,7 +135,7 @@ def test_plan_batch_workload_shapes(qc):
         arrays.append(_desc(na, N, n_spec, n_spec // 2))
         hx.append(_x(na, N * n_spec, 500 + i))
     xs = [torch.from_numpy(h).cuda() for h in hx]
-    plan = qc.Plan(arrays)
+    plan = qc.Plan(arrays, mode)
     vis = plan.empty_vis()
     plan.execute(xs, vis)
     plan.check()
@@ -139,11 +152,12 @@ def test_plan_batch_workload_shapes(qc):
 
 
 @pytest.mark.gpu
-def test_plan_is_deterministic_and_overwrites(qc):
+@pytest.mark.parametrize("mode", MODES)
+def test_plan_is_deterministic_and_overwrites(qc, mode):
     import torch
     arrays = [_desc(*s) for s in SMALL[:4]]
     _, xs = _inputs(arrays, seed=7)
-    plan = qc.Plan(arrays)
+    plan = qc.Plan(arrays, mode)
     v1, v2 = plan.empty_vis(), plan.empty_vis()
     for v in v2:
         v.fill_(123.0)
@@ -155,13 +169,14 @@ def test_plan_is_deterministic_and_overwrites(qc):
 
 
 @pytest.mark.gpu
-def test_plan_graph_replays(qc):
+@pytest.mark.parametrize("mode", MODES)
+def test_plan_graph_replays(qc, mode):
     """Replays of the captured graph, with eager work on the same device
     between them, each equal to the eager execution."""
     import torch
     arrays = [_desc(*s) for s in SMALL[:5]]
     _, xs = _inputs(arrays, seed=11)
-    plan = qc.Plan(arrays)
+    plan = qc.Plan(arrays, mode)
     eager = plan.empty_vis()
     plan.execute(xs, eager)
     plan.check()
@@ -198,6 +213,7 @@ def test_plan_capture_needs_side_stream(qc):
 
 
 @pytest.mark.gpu
+@pytest.mark.skip(reason=PERSISTENT_OFF)
 def test_plan_wait_timeout_reports_error(qc):
     """Dependencies made unsatisfiable from the host: every bounded wait
     expires, the kernel still drains, check() reports it, and the next
@@ -205,7 +221,7 @@ def test_plan_wait_timeout_reports_error(qc):
     import torch
     arrays = [_desc(16, 1024, 12, 6), _desc(5, 256, 20, 10)]      # two-pass arrays: waits
     _, xs = _inputs(arrays, seed=13)
-    plan = qc.Plan(arrays)
+    plan = qc.Plan(arrays, "persistent")
     good = plan.empty_vis()
     plan.execute(xs, good)
     plan.check()
@@ -237,12 +253,54 @@ def test_plan_autotune_and_cache(qc, tmp_path):
     plan.check()
     vis = plan.empty_vis()
     assert plan.autotune(xs, vis, reps=1, cache=cache) is False
-    knobs = plan.info()[2]
+    knobs = plan.info()
     plan.execute(xs, vis)
     plan.check()
     for a, b, d in zip(vis, ref, arrays):
         assert vis_err(a.cpu().numpy(), b.cpu().numpy(), d["n_ant"]) <= 1e-6
     plan2 = qc.Plan(arrays)
     assert plan2.autotune(xs, plan2.empty_vis(), reps=1, cache=cache) is True
-    assert plan2.info()[2] == knobs
+    assert plan2.info() == knobs
     torch.cuda.synchronize()
+
+
+@pytest.mark.gpu
+def test_plan_serial_equals_concurrent(qc):
+    """Arrays forked to streams of their own or run in order on the caller's
+    stream: identical sums (same kernels, same splits)."""
+    import os
+    import tempfile
+
+    import torch
+    arrays = [_desc(*s) for s in SMALL]
+    _, xs = _inputs(arrays, seed=23)
+    plan = qc.Plan(arrays)
+    a = plan.empty_vis()
+    plan.execute(xs, a)
+    plan.check()
+    n, conc, tiles, splits = plan.info()
+    assert conc == 1
+    # switch concurrency off through a cache entry (the tuner's own format)
+    sig = ",".join(f"{d['n_ant']}x{d['n_samp']}x{d['n_fft']}x{d['n_taps']}x{d['spec_per_dump']}"
+                   for d in arrays)
+    knobs = " ".join(f"{t} {s}" for t, s in zip(tiles, splits))
+    with tempfile.TemporaryDirectory() as td:
+        path = os.path.join(td, "c.txt")
+        with open(path, "w") as f:
+            f.write(f"{sig} 0 {knobs}\n")
+        assert plan.autotune(xs, plan.empty_vis(), reps=1, cache=path) is True
+    assert plan.info()[1] == 0
+    b = plan.empty_vis()
+    plan.execute(xs, b)
+    plan.check()
+    for u, v in zip(a, b):
+        assert torch.equal(u, v)
+
+
+@pytest.mark.gpu
+def test_plan_persistent_mode_rejected(qc):
+    plan = qc.Plan([_desc(*SMALL[0])])
+    with pytest.raises(qc.QCError) as ei:
+        plan.set_mode("persistent")
+    assert ei.value.status == -2                      # QC_EUNSUPPORTED
+    assert plan.info()[0] == 2                        # still the graph mode
