@@ -42,6 +42,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision", action="store_true", help="skip the 32-antenna section")
     ap.add_argument("--no-batched", action="store_true", help="skip the uneven-arrays section")
+    ap.add_argument("--no-stream", action="store_true", help="skip the host-streaming section")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 256 MiB device copy kernel (counter calibration)")
     return ap.parse_args()
@@ -155,6 +156,52 @@ def precision_section(torch, qc, steps):
         log(f"[bench] 32-ant {prec}: {ms:.3f} ms, err {err:.2e}")
     del xd
     return res
+
+
+def stream_section(torch, qc, x, N, P, spd, vis_ref, reps=3):
+    """The real-time stream pushed from page-locked host memory as 16 chunks
+    of 64 MiB (4 antennas x 2^24 samples, one dump each) through the
+    streaming API: PCIe-inclusive input rate, next to the plain
+    host-to-device copy rate of the same bytes."""
+    n_ant, S = x.shape
+    chunk = 1 << 24
+    n_chunk = S // chunk
+    host = torch.empty((n_chunk, n_ant, chunk), dtype=torch.int8, pin_memory=True)
+    host.copy_(torch.from_numpy(x).view(n_ant, n_chunk, chunk).transpose(0, 1))
+    dev = torch.empty((n_chunk, n_ant, chunk), dtype=torch.int8, device="cuda")
+    copy_ms = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        dev.copy_(host, non_blocking=True)
+        torch.cuda.synchronize()
+        copy_ms.append((time.perf_counter() - t0) * 1e3)
+    del dev
+    nd = (chunk // N) // spd
+    vis = torch.empty((n_chunk * nd, n_ant * (n_ant + 1) // 2, N // 2), dtype=torch.complex64,
+                      device="cuda")
+    st = qc.Stream(n_ant, chunk, N, P, spd, depth=4)
+    seq = 0
+    run_ms = []
+    for r in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for c in range(n_chunk):
+            st.push(host[c], seq, vis[c * nd:(c + 1) * nd])
+            seq += 1
+        st.sync()
+        run_ms.append((time.perf_counter() - t0) * 1e3)
+        seq += 1          # a gap: the next pass starts a fresh stream (zero history)
+    st.close()
+    from tests.util import vis_err as vis_err_local
+    err = vis_err_local(vis.cpu().numpy(), vis_ref.cpu().numpy(), n_ant)
+    ms, cms = min(run_ms), min(copy_ms)
+    log(f"[bench] streamed from pinned host: {ms:.2f} ms ({x.nbytes / ms / 1e6:.1f} GB/s); "
+        f"plain H2D copy {cms:.2f} ms")
+    return {"workload": "realtime_4ant_n4096 streamed", "chunks": n_chunk, "chunk_bytes": n_ant * chunk,
+            "ms": round(ms, 3), "input_GBps_pcie_inclusive": round(x.nbytes / ms / 1e6, 2),
+            "h2d_copy_ms": round(cms, 3), "h2d_copy_GBps": round(x.nbytes / cms / 1e6, 2),
+            "vis_err_vs_resident": float(f"{err:.3e}")}
 
 
 def batched_section(torch, qc, steps):
@@ -345,6 +392,8 @@ def main():
         "fused_tile": {"chosen": best_tile, "ms_per_tile": [round(v, 4) for v in tile_ms]},
         "wall_s_timed_region": round(t_wall, 4),
     }
+    if not args.no_stream:
+        out["stream"] = stream_section(torch, qc, x, N, P, spd, vis_check)
     if not args.no_precision:
         del vis_check
         out["precision_32ant"] = precision_section(torch, qc, args.steps)

@@ -16,11 +16,13 @@ Each module states the passage of the paper it follows:
   and the three-step delay/phase solve (Sec. 7, steps 1-3, eq. 3).
 * :mod:`oracle.quant`  -- reduced-precision quantisers used to build the
   quantisation-aware reference for the MFMA X-engine.
+* :mod:`oracle.cnn`    -- the learned RFI flagger beside MAD (Sec. 5 RFI
+  structure, Sec. 7 MAD): forward, backpropagation, loss, Adam.
 
 Everything is float64 (complex128) unless a function says otherwise.  Where
 the paper is silent the reading taken is stated in the function docstring.
 """
 
-from . import pfb, xengine, mad, calib, quant  # noqa: F401
+from . import pfb, xengine, mad, calib, quant, cnn  # noqa: F401
 
-__all__ = ["pfb", "xengine", "mad", "calib", "quant"]
+__all__ = ["pfb", "xengine", "mad", "calib", "quant", "cnn"]
