@@ -306,6 +306,46 @@ enum {
 qc_status qc_timing_enable(int32_t on);
 qc_status qc_timing_read(int32_t kernel, double* total_ms, int64_t* launches);
 
+/* Learned RFI flagger beside MAD.  MAD thresholds visibility amplitude
+ * (Sec. 7, eq. 2); RFI is structured in time and frequency (Sec. 5: lines,
+ * bursts).  A four-layer convolutional network over one baseline's
+ * (time x channel) amplitude plane learns that structure:
+ *   L1 3x3 1->32 ReLU, L2 5x5 32->32 ReLU, L3 5x5 dilation 2 32->32 ReLU,
+ *   L4 1x1 32->1 logit; stride 1, zero 'same' padding, cross-correlation.
+ * Parameters: device float32[qc_cnn_param_count()] = W1[32][1][3][3], b1[32],
+ * W2[32][32][5][5], b2[32], W3[32][32][5][5], b3[32], W4[1][32][1][1], b4[1].
+ * Activations are float32, accumulation float32.
+ *   qc_cnn_normalize: vis [n_time][n_base][n_chan] cfloat -> x, device float
+ *     [n_base][n_time][n_chan]: A = |V| (float32), r = (A - med)/(1.4826 MAD)
+ *     over the baseline's plane (exact order statistics, scale 1 if MAD = 0),
+ *     x = sign(r) log1p|r|.
+ *   qc_cnn_forward: x [n_img][H][W] -> logits [n_img][H][W].
+ *   qc_cnn_grad: mean over cells of the binary cross-entropy of the logits
+ *     against labels (uint8 [n_img][H][W], nonzero = RFI), positives weighted
+ *     by pos_weight; writes the gradient (float[param_count]) and the loss
+ *     (one float), both device memory.  Deterministic.
+ *   qc_cnn_adam: Adam with bias correction, step >= 1; m, v: device float
+ *     [param_count], zero before step 1.
+ *   qc_cnn_train_step: qc_cnn_grad then qc_cnn_adam (beta 0.9/0.999, eps 1e-8).
+ *   qc_cnn_flag: normalise, forward and flag (logit > logit_threshold) every
+ *     baseline; mask: device uint8 [n_time][n_base][n_chan] like qc_mad_flag.
+ * All asynchronous on `stream`; n_img*H*W and n_time*n_chan below 2^31. */
+int32_t qc_cnn_param_count(void);
+qc_status qc_cnn_normalize(const float* vis, int64_t n_time, int64_t n_base, int32_t n_chan, float* x,
+                           void* stream);
+qc_status qc_cnn_forward(const float* params, const float* x, int32_t n_img, int32_t height,
+                         int32_t width, float* logits, void* stream);
+qc_status qc_cnn_grad(const float* params, const float* x, const uint8_t* labels, int32_t n_img,
+                      int32_t height, int32_t width, float pos_weight, float* grad, float* loss,
+                      void* stream);
+qc_status qc_cnn_adam(float* params, const float* grad, float* m, float* v, int64_t step, float lr,
+                      float beta1, float beta2, float eps, void* stream);
+qc_status qc_cnn_train_step(float* params, float* m, float* v, int64_t step, const float* x,
+                            const uint8_t* labels, int32_t n_img, int32_t height, int32_t width,
+                            float pos_weight, float lr, float* loss, void* stream);
+qc_status qc_cnn_flag(const float* params, const float* vis, int64_t n_time, int64_t n_base,
+                      int32_t n_chan, float logit_threshold, uint8_t* mask, void* stream);
+
 /* Human-readable name of a status code (static storage). */
 const char* qc_status_string(qc_status s);
 /* Thread-local detail of the last failure in this thread ("" if none). */

@@ -15,7 +15,9 @@ import torch
 
 __all__ = [
     "QCError", "lib", "pfb_channelize", "xcorrelate", "xcorrelate_chan", "mad_flag",
-    "apply_delay_phase", "n_base", "PREC", "timing_enable", "timing_read", "KERNELS", "Stream", "solve_delay_phase", "Plan",
+    "apply_delay_phase", "n_base", "PREC", "timing_enable", "timing_read", "KERNELS", "Stream",
+    "solve_delay_phase", "Plan", "cnn_param_count", "cnn_normalize", "cnn_forward", "cnn_grad", "cnn_adam",
+    "cnn_train_step", "cnn_flag",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -120,6 +122,20 @@ def lib() -> ctypes.CDLL:
             fn.restype = ctypes.c_int32
         L.qc_plan_destroy.argtypes = [_P]
         L.qc_plan_destroy.restype = None
+        _F = ctypes.c_float
+        for name, args in {
+            "qc_cnn_normalize": [_P, _I64, _I64, _I32, _P, _P],
+            "qc_cnn_forward": [_P, _P, _I32, _I32, _I32, _P, _P],
+            "qc_cnn_grad": [_P, _P, _P, _I32, _I32, _I32, _F, _P, _P, _P],
+            "qc_cnn_adam": [_P, _P, _P, _P, _I64, _F, _F, _F, _F, _P],
+            "qc_cnn_train_step": [_P, _P, _P, _I64, _P, _P, _I32, _I32, _I32, _F, _F, _P, _P],
+            "qc_cnn_flag": [_P, _P, _I64, _I64, _I32, _F, _P, _P],
+        }.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_int32
+        L.qc_cnn_param_count.argtypes = []
+        L.qc_cnn_param_count.restype = ctypes.c_int32
         L.qc_timing_enable.argtypes = [ctypes.c_int32]
         L.qc_timing_enable.restype = ctypes.c_int32
         L.qc_timing_read.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
@@ -280,6 +296,78 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+# ---- learned RFI flagger ----
+
+def cnn_param_count():
+    return int(lib().qc_cnn_param_count())
+
+
+def _dev_f32(t, name):
+    assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous(), name
+
+
+def cnn_normalize(vis, out=None):
+    """complex64 vis [n_time, n_base, n_chan] -> float32 images [n_base, n_time, n_chan]."""
+    assert vis.dtype == torch.complex64 and vis.is_cuda and vis.is_contiguous()
+    n_time, nb, n_chan = vis.shape
+    if out is None:
+        out = torch.empty((nb, n_time, n_chan), dtype=torch.float32, device=vis.device)
+    _check(lib().qc_cnn_normalize(_ptr(vis), n_time, nb, n_chan, _ptr(out), _stream()), "qc_cnn_normalize")
+    return out
+
+
+def cnn_forward(params, x, out=None):
+    """Logits [n, H, W] for normalised images x [n, H, W]."""
+    _dev_f32(params, "params")
+    _dev_f32(x, "x")
+    n, H, W = x.shape
+    if out is None:
+        out = torch.empty_like(x)
+    _check(lib().qc_cnn_forward(_ptr(params), _ptr(x), n, H, W, _ptr(out), _stream()), "qc_cnn_forward")
+    return out
+
+
+def cnn_grad(params, x, labels, pos_weight, grad=None, loss=None):
+    """(grad [P], loss [1]) of the weighted BCE for images x and uint8 labels."""
+    _dev_f32(params, "params")
+    _dev_f32(x, "x")
+    assert labels.is_cuda and labels.dtype == torch.uint8 and labels.shape == x.shape and labels.is_contiguous()
+    n, H, W = x.shape
+    if grad is None:
+        grad = torch.empty_like(params)
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float32, device=x.device)
+    _check(lib().qc_cnn_grad(_ptr(params), _ptr(x), _ptr(labels), n, H, W, float(pos_weight), _ptr(grad),
+                             _ptr(loss), _stream()), "qc_cnn_grad")
+    return grad, loss
+
+
+def cnn_adam(params, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    _check(lib().qc_cnn_adam(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), int(step), float(lr), float(beta1),
+                             float(beta2), float(eps), _stream()), "qc_cnn_adam")
+
+
+def cnn_train_step(params, m, v, step, x, labels, pos_weight, lr=1e-3, loss=None):
+    n, H, W = x.shape
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float32, device=x.device)
+    _check(lib().qc_cnn_train_step(_ptr(params), _ptr(m), _ptr(v), int(step), _ptr(x), _ptr(labels), n, H, W,
+                                   float(pos_weight), float(lr), _ptr(loss), _stream()), "qc_cnn_train_step")
+    return loss
+
+
+def cnn_flag(params, vis, threshold=0.0, mask=None):
+    """uint8 mask [n_time, n_base, n_chan] from the network (logit > threshold)."""
+    _dev_f32(params, "params")
+    assert vis.dtype == torch.complex64 and vis.is_cuda and vis.is_contiguous()
+    n_time, nb, n_chan = vis.shape
+    if mask is None:
+        mask = torch.empty(vis.shape, dtype=torch.uint8, device=vis.device)
+    _check(lib().qc_cnn_flag(_ptr(params), _ptr(vis), n_time, nb, n_chan, float(threshold), _ptr(mask),
+                             _stream()), "qc_cnn_flag")
+    return mask
 
 
 KERNELS = {"fx_fused": 0, "channelize": 1, "xeng_f32": 2, "xeng_mfma": 3, "reduce": 4,

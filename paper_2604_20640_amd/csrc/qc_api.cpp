@@ -466,7 +466,7 @@ qc_status qc_mad_flag(const float* vis, int64_t n_time, int64_t n_base, int32_t 
   if (npop > 0x7fffffffLL) return fail(QC_EINVAL, "too many populations");
   KTimer t(QC_KERNEL_MAD, reinterpret_cast<hipStream_t>(stream));
   QC_HIP(qc::launch_mad(reinterpret_cast<const float2*>(vis), n_time, n_base, n_chan, sigma, population,
-                        mask, thresh_out, reinterpret_cast<hipStream_t>(stream)),
+                        mask, thresh_out, nullptr, reinterpret_cast<hipStream_t>(stream)),
          "MAD kernel");
   return QC_OK;
 }
@@ -1266,6 +1266,232 @@ void qc_plan_destroy(qc_plan* P) {
   if (P->d_slots) (void)hipFree(P->d_slots);
   if (P->h_slots) (void)hipHostFree(P->h_slots);
   delete P;
+}
+
+}  // extern "C"
+
+// ---- learned RFI flagger ------------------------------------------------------
+namespace {
+
+qc_status ensure_device() {
+  int dev = 0;
+  QC_HIP(hipGetDevice(&dev), "hipGetDevice");
+  std::lock_guard<std::mutex> lk(g_mu);
+  return device_init_locked(dev);
+}
+
+qc_status cnn_check_img(const void* params, const float* x, int32_t n_img, int32_t H, int32_t W) {
+  if (!params || !x) return fail(QC_EINVAL, "params or x is NULL");
+  if (n_img < 1 || H < 1 || W < 1) return fail(QC_EINVAL, "n_img, height and width must be >= 1");
+  if ((int64_t)n_img * H * W > 0x7fffffffLL) return fail(QC_EINVAL, "n_img * height * width must be < 2^31");
+  if ((reinterpret_cast<uintptr_t>(params) | reinterpret_cast<uintptr_t>(x)) & 3u)
+    return fail(QC_EINVAL, "params and x must be 4-byte aligned");
+  return QC_OK;
+}
+
+// Packed weights of L1..L3 (forward) and, with bwd, of L2 and L3 (backward data).
+struct CnnPacked {
+  AsyncBuf buf;
+  float *w1 = nullptr, *w2 = nullptr, *w3 = nullptr, *w2b = nullptr, *w3b = nullptr;
+};
+
+qc_status cnn_pack_all(const float* p, bool bwd, CnnPacked& pk, hipStream_t s) {
+  const size_t n1 = 9 * 32, n2 = 25 * 32 * 32;
+  qc_status st = alloc_async(pk.buf, sizeof(float) * (n1 + (bwd ? 4 : 2) * n2), s);
+  if (st != QC_OK) return st;
+  float* b = (float*)pk.buf.p;
+  pk.w1 = b;
+  pk.w2 = b + n1;
+  pk.w3 = pk.w2 + n2;
+  QC_HIP(qc::cnn_pack(p + qc::CNN_OFF_L1, 1, 32, 3, 0, pk.w1, s), "pack L1");
+  QC_HIP(qc::cnn_pack(p + qc::CNN_OFF_L2, 32, 32, 5, 0, pk.w2, s), "pack L2");
+  QC_HIP(qc::cnn_pack(p + qc::CNN_OFF_L3, 32, 32, 5, 0, pk.w3, s), "pack L3");
+  if (bwd) {
+    pk.w2b = pk.w3 + n2;
+    pk.w3b = pk.w2b + n2;
+    QC_HIP(qc::cnn_pack(p + qc::CNN_OFF_L2, 32, 32, 5, 1, pk.w2b, s), "pack L2 (backward)");
+    QC_HIP(qc::cnn_pack(p + qc::CNN_OFF_L3, 32, 32, 5, 1, pk.w3b, s), "pack L3 (backward)");
+  }
+  return QC_OK;
+}
+
+// Forward of images [n][H][W]: a1 and a2/a3 ping-pong in A and B.
+qc_status cnn_forward_chunk(const float* p, const CnnPacked& pk, const float* x, int64_t n, int H, int W,
+                            float* A, float* B, float* logits, float thr, int64_t img0, int64_t n_base,
+                            uint8_t* mask, hipStream_t s) {
+  QC_HIP(qc::cnn_conv(1, 0, x, pk.w1, p + qc::CNN_OFF_L1 + 288, nullptr, n, H, W, A, s), "conv L1");
+  QC_HIP(qc::cnn_conv(2, 0, A, pk.w2, p + qc::CNN_OFF_L2 + 25600, nullptr, n, H, W, B, s), "conv L2");
+  QC_HIP(qc::cnn_conv(3, 0, B, pk.w3, p + qc::CNN_OFF_L3 + 25600, nullptr, n, H, W, A, s), "conv L3");
+  QC_HIP(qc::cnn_head(A, p + qc::CNN_OFF_L4, n, H, W, logits, thr, img0, n_base, mask, s), "head");
+  return QC_OK;
+}
+
+constexpr int64_t CNN_CHUNK_BYTES = (int64_t)1 << 30;  // per activation buffer
+
+int64_t cnn_chunk_images(int64_t H, int64_t W) {
+  const int64_t per = 32 * H * W * (int64_t)sizeof(float);
+  const int64_t c = CNN_CHUNK_BYTES / per;
+  return c < 1 ? 1 : c;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t qc_cnn_param_count(void) { return qc::CNN_PARAMS; }
+
+qc_status qc_cnn_normalize(const float* vis, int64_t n_time, int64_t n_base, int32_t n_chan, float* x,
+                           void* stream) {
+  g_err.clear();
+  if (!vis || !x) return fail(QC_EINVAL, "vis or x is NULL");
+  if (n_time < 1 || n_base < 1 || n_chan < 1) return fail(QC_EINVAL, "sizes must be >= 1");
+  if (n_base > 0x7fffffffLL) return fail(QC_EINVAL, "too many baselines");
+  if (reinterpret_cast<uintptr_t>(vis) & 7u) return fail(QC_EINVAL, "vis must be 8-byte aligned");
+  qc_status st = ensure_device();
+  if (st != QC_OK) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  AsyncBuf stats;
+  st = alloc_async(stats, sizeof(double) * 2 * n_base, s);
+  if (st != QC_OK) return st;
+  const float2* v = reinterpret_cast<const float2*>(vis);
+  QC_HIP(qc::launch_mad(v, n_time, n_base, n_chan, 0.f, 0, nullptr, nullptr, (double*)stats.p, s), "MAD stats");
+  QC_HIP(qc::cnn_normalize(v, (const double*)stats.p, n_time, n_base, n_chan, 0, n_base, x, s), "normalise");
+  return QC_OK;
+}
+
+qc_status qc_cnn_forward(const float* params, const float* x, int32_t n_img, int32_t H, int32_t W,
+                         float* logits, void* stream) {
+  g_err.clear();
+  qc_status st = cnn_check_img(params, x, n_img, H, W);
+  if (st != QC_OK) return st;
+  if (!logits) return fail(QC_EINVAL, "logits is NULL");
+  st = ensure_device();
+  if (st != QC_OK) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  CnnPacked pk;
+  st = cnn_pack_all(params, false, pk, s);
+  if (st != QC_OK) return st;
+  const int64_t chunk = std::min<int64_t>(n_img, cnn_chunk_images(H, W));
+  const size_t abytes = sizeof(float) * 32 * (size_t)chunk * H * W;
+  AsyncBuf A, B;
+  if ((st = alloc_async(A, abytes, s)) != QC_OK || (st = alloc_async(B, abytes, s)) != QC_OK) return st;
+  const int64_t hw = (int64_t)H * W;
+  for (int64_t i0 = 0; i0 < n_img; i0 += chunk) {
+    const int64_t n = std::min<int64_t>(chunk, n_img - i0);
+    st = cnn_forward_chunk(params, pk, x + i0 * hw, n, H, W, (float*)A.p, (float*)B.p, logits + i0 * hw, 0.f, 0,
+                           0, nullptr, s);
+    if (st != QC_OK) return st;
+  }
+  return QC_OK;
+}
+
+qc_status qc_cnn_grad(const float* params, const float* x, const uint8_t* labels, int32_t n_img, int32_t H,
+                      int32_t W, float pos_weight, float* grad, float* loss, void* stream) {
+  g_err.clear();
+  qc_status st = cnn_check_img(params, x, n_img, H, W);
+  if (st != QC_OK) return st;
+  if (!labels || !grad || !loss) return fail(QC_EINVAL, "labels, grad or loss is NULL");
+  if (!(pos_weight > 0.f) || !std::isfinite(pos_weight)) return fail(QC_EINVAL, "pos_weight must be > 0");
+  const int64_t act = 32 * (int64_t)n_img * H * W;
+  if (act * (int64_t)sizeof(float) > ((int64_t)8 << 30))
+    return fail(QC_EINVAL, "batch too large: one activation would exceed 8 GiB");
+  st = ensure_device();
+  if (st != QC_OK) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  CnnPacked pk;
+  st = cnn_pack_all(params, true, pk, s);
+  if (st != QC_OK) return st;
+  const int64_t hw = (int64_t)H * W;
+  const int64_t wblocks = qc::cnn_wgrad_blocks(n_img, H, W);
+  const int64_t hblocks = qc::cnn_head_bwd_blocks((int64_t)n_img * hw);
+  const size_t part_floats = std::max<size_t>((size_t)wblocks * 25632, (size_t)hblocks * 34);
+  AsyncBuf a1, a2, a3, z, gA, gB, part;
+  const size_t ab = sizeof(float) * (size_t)act;
+  if ((st = alloc_async(a1, ab, s)) != QC_OK || (st = alloc_async(a2, ab, s)) != QC_OK ||
+      (st = alloc_async(a3, ab, s)) != QC_OK || (st = alloc_async(gA, ab, s)) != QC_OK ||
+      (st = alloc_async(gB, ab, s)) != QC_OK || (st = alloc_async(z, sizeof(float) * n_img * hw, s)) != QC_OK ||
+      (st = alloc_async(part, sizeof(float) * part_floats, s)) != QC_OK)
+    return st;
+  float *A1 = (float*)a1.p, *A2 = (float*)a2.p, *A3 = (float*)a3.p, *Z = (float*)z.p;
+  float *GA = (float*)gA.p, *GB = (float*)gB.p, *PT = (float*)part.p;
+  const float* p = params;
+  QC_HIP(qc::cnn_conv(1, 0, x, pk.w1, p + qc::CNN_OFF_L1 + 288, nullptr, n_img, H, W, A1, s), "conv L1");
+  QC_HIP(qc::cnn_conv(2, 0, A1, pk.w2, p + qc::CNN_OFF_L2 + 25600, nullptr, n_img, H, W, A2, s), "conv L2");
+  QC_HIP(qc::cnn_conv(3, 0, A2, pk.w3, p + qc::CNN_OFF_L3 + 25600, nullptr, n_img, H, W, A3, s), "conv L3");
+  QC_HIP(qc::cnn_head(A3, p + qc::CNN_OFF_L4, n_img, H, W, Z, 0.f, 0, 0, nullptr, s), "head");
+  QC_HIP(qc::cnn_head_bwd(Z, labels, A3, p + qc::CNN_OFF_L4, n_img, H, W, pos_weight, GA, PT,
+                          grad + qc::CNN_OFF_L4, loss, s),
+         "loss and head backward");
+  QC_HIP(qc::cnn_wgrad(3, A2, GA, n_img, H, W, PT, grad + qc::CNN_OFF_L3, s), "L3 weight gradient");
+  QC_HIP(qc::cnn_conv(3, 1, GA, pk.w3b, nullptr, A2, n_img, H, W, GB, s), "L3 backward data");
+  QC_HIP(qc::cnn_wgrad(2, A1, GB, n_img, H, W, PT, grad + qc::CNN_OFF_L2, s), "L2 weight gradient");
+  QC_HIP(qc::cnn_conv(2, 1, GB, pk.w2b, nullptr, A1, n_img, H, W, GA, s), "L2 backward data");
+  QC_HIP(qc::cnn_wgrad(1, x, GA, n_img, H, W, PT, grad + qc::CNN_OFF_L1, s), "L1 weight gradient");
+  return QC_OK;
+}
+
+qc_status qc_cnn_adam(float* params, const float* grad, float* m, float* v, int64_t step, float lr, float beta1,
+                      float beta2, float eps, void* stream) {
+  g_err.clear();
+  if (!params || !grad || !m || !v) return fail(QC_EINVAL, "NULL argument");
+  if (step < 1) return fail(QC_EINVAL, "step must be >= 1");
+  if (!(lr > 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+    return fail(QC_EINVAL, "bad Adam hyper-parameters");
+  QC_HIP(qc::cnn_adam(params, grad, m, v, qc::CNN_PARAMS, step, lr, beta1, beta2, eps,
+                      reinterpret_cast<hipStream_t>(stream)),
+         "Adam kernel");
+  return QC_OK;
+}
+
+qc_status qc_cnn_train_step(float* params, float* m, float* v, int64_t step, const float* x,
+                            const uint8_t* labels, int32_t n_img, int32_t H, int32_t W, float pos_weight,
+                            float lr, float* loss, void* stream) {
+  g_err.clear();
+  if (!m || !v) return fail(QC_EINVAL, "m or v is NULL");
+  if (step < 1) return fail(QC_EINVAL, "step must be >= 1");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  AsyncBuf g;
+  qc_status st = alloc_async(g, sizeof(float) * qc::CNN_PARAMS, s);
+  if (st != QC_OK) return st;
+  st = qc_cnn_grad(params, x, labels, n_img, H, W, pos_weight, (float*)g.p, loss, stream);
+  if (st != QC_OK) return st;
+  return qc_cnn_adam(params, (const float*)g.p, m, v, step, lr, 0.9f, 0.999f, 1e-8f, stream);
+}
+
+qc_status qc_cnn_flag(const float* params, const float* vis, int64_t n_time, int64_t n_base, int32_t n_chan,
+                      float logit_threshold, uint8_t* mask, void* stream) {
+  g_err.clear();
+  if (!params || !vis || !mask) return fail(QC_EINVAL, "params, vis or mask is NULL");
+  if (n_time < 1 || n_base < 1 || n_chan < 1) return fail(QC_EINVAL, "sizes must be >= 1");
+  if (n_time * n_chan > 0x7fffffffLL || n_base > 0x7fffffffLL) return fail(QC_EINVAL, "plane too large");
+  if (reinterpret_cast<uintptr_t>(vis) & 7u) return fail(QC_EINVAL, "vis must be 8-byte aligned");
+  if (!std::isfinite(logit_threshold)) return fail(QC_EINVAL, "threshold must be finite");
+  qc_status st = ensure_device();
+  if (st != QC_OK) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int H = (int)n_time, W = n_chan;
+  const int64_t hw = (int64_t)H * W;
+  AsyncBuf stats;
+  if ((st = alloc_async(stats, sizeof(double) * 2 * n_base, s)) != QC_OK) return st;
+  const float2* v = reinterpret_cast<const float2*>(vis);
+  QC_HIP(qc::launch_mad(v, n_time, n_base, n_chan, 0.f, 0, nullptr, nullptr, (double*)stats.p, s), "MAD stats");
+  CnnPacked pk;
+  if ((st = cnn_pack_all(params, false, pk, s)) != QC_OK) return st;
+  const int64_t chunk = std::min<int64_t>(n_base, cnn_chunk_images(H, W));
+  AsyncBuf X, A, B;
+  if ((st = alloc_async(X, sizeof(float) * (size_t)chunk * hw, s)) != QC_OK ||
+      (st = alloc_async(A, sizeof(float) * 32 * (size_t)chunk * hw, s)) != QC_OK ||
+      (st = alloc_async(B, sizeof(float) * 32 * (size_t)chunk * hw, s)) != QC_OK)
+    return st;
+  for (int64_t b0 = 0; b0 < n_base; b0 += chunk) {
+    const int64_t n = std::min<int64_t>(chunk, n_base - b0);
+    QC_HIP(qc::cnn_normalize(v, (const double*)stats.p, n_time, n_base, n_chan, b0, n, (float*)X.p, s),
+           "normalise");
+    st = cnn_forward_chunk(params, pk, (const float*)X.p, n, H, W, (float*)A.p, (float*)B.p, nullptr,
+                           logit_threshold, b0, n_base, mask, s);
+    if (st != QC_OK) return st;
+  }
+  return QC_OK;
 }
 
 }  // extern "C"

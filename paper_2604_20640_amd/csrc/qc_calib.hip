@@ -133,7 +133,8 @@ __device__ K radix_select(int64_t count, int64_t k, KeyFn key, unsigned* hist, u
 template <int NT, int DB>
 __global__ void __launch_bounds__(NT)
 mad_kernel(const float2* __restrict__ vis, int64_t n_time, int64_t n_base, int n_chan, float sigma,
-           int population, int64_t cap, uint8_t* __restrict__ mask, double* __restrict__ thresh) {
+           int population, int64_t cap, uint8_t* __restrict__ mask, double* __restrict__ thresh,
+           double* __restrict__ stats) {
   __shared__ unsigned hist[1 << DB];
   __shared__ unsigned wsum[NT / 64];
   __shared__ unsigned long long sh[2];
@@ -171,8 +172,15 @@ mad_kernel(const float2* __restrict__ vis, int64_t n_time, int64_t n_base, int n
       (__longlong_as_double((long long)d1) + __longlong_as_double((long long)d2)) / 2.0;
   const double c = (double)sigma * 1.4826;
   const double T = med + c * madv;
-  for (int64_t i = threadIdx.x; i < n; i += NT) mask[pop.off(i)] = (double)amp(i) > T ? 1 : 0;
-  if (thresh && threadIdx.x == 0) thresh[id] = T;
+  if (mask)
+    for (int64_t i = threadIdx.x; i < n; i += NT) mask[pop.off(i)] = (double)amp(i) > T ? 1 : 0;
+  if (threadIdx.x == 0) {
+    if (thresh) thresh[id] = T;
+    if (stats) {
+      stats[2 * id] = med;
+      stats[2 * id + 1] = madv;
+    }
+  }
 }
 
 #pragma clang fp contract(on)
@@ -181,14 +189,14 @@ constexpr int64_t MAD_CAP_BIG = 36864;   // floats cached in LDS (144 KiB)
 constexpr int64_t MAD_CAP_SMALL = 2048;
 
 hipError_t launch_mad(const float2* vis, int64_t n_time, int64_t n_base, int n_chan, float sigma,
-                      int population, uint8_t* mask, double* thresh, hipStream_t s) {
+                      int population, uint8_t* mask, double* thresh, double* stats, hipStream_t s) {
   const int64_t npop = population == 0 ? n_base : population == 1 ? n_base * n_chan : n_time * n_base;
   const int64_t count = population == 0 ? n_time * n_chan : population == 1 ? n_time : n_chan;
   if (npop <= 0) return hipSuccess;
   if (count <= MAD_CAP_SMALL) {
     const size_t lds = (size_t)count * sizeof(float);
     hipLaunchKernelGGL((mad_kernel<64, 8>), dim3((unsigned)npop), dim3(64), lds, s, vis, n_time,
-                       n_base, n_chan, sigma, population, MAD_CAP_SMALL, mask, thresh);
+                       n_base, n_chan, sigma, population, MAD_CAP_SMALL, mask, thresh, stats);
   } else {
     const int64_t cap = count <= MAD_CAP_BIG ? count : 0;
     const size_t lds = (size_t)cap * sizeof(float);
@@ -196,7 +204,7 @@ hipError_t launch_mad(const float2* vis, int64_t n_time, int64_t n_base, int n_c
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((mad_kernel<1024, 11>), dim3((unsigned)npop), dim3(1024), lds, s, vis, n_time,
-                       n_base, n_chan, sigma, population, cap, mask, thresh);
+                       n_base, n_chan, sigma, population, cap, mask, thresh, stats);
   }
   return hipGetLastError();
 }

@@ -56,9 +56,9 @@ hipError_t launch_xeng_mfma(const void* v, int prec, const float* scale, int n_a
                             int64_t ksplit, float2* part, hipStream_t s);
 int64_t xeng_mfma_ksplit(int n_ant, int64_t spec_per_dump, int n_chan, int64_t n_dump);
 
-// MAD flagging.
+// MAD flagging.  mask, thresh and stats ([pop][2]: median, MAD) may be null.
 hipError_t launch_mad(const float2* vis, int64_t n_time, int64_t n_base, int n_chan, float sigma,
-                      int population, uint8_t* mask, double* thresh, hipStream_t s);
+                      int population, uint8_t* mask, double* thresh, double* stats, hipStream_t s);
 
 // Delay/phase application; tau/phi host arrays of n_ant doubles (n_ant <= 64).
 hipError_t launch_apply(float2* vis, int64_t n_time, int n_ant, int n_chan, double f0, double df,
@@ -111,5 +111,32 @@ bool plan_chan_supported(int n_fft);
 // launch_plan and outside stream capture.
 hipError_t prepare_plan();
 hipError_t launch_plan(const PlArgs& a, int grid, hipStream_t s);
+
+// ---- learned RFI flagger ----
+constexpr int CNN_PARAMS = 51617;
+constexpr int CNN_OFF_L1 = 0, CNN_OFF_L2 = 320, CNN_OFF_L3 = 25952, CNN_OFF_L4 = 51584;
+// Repack W[o][i][ky][kx] for the convolution kernel (flip: backward data).
+hipError_t cnn_pack(const float* w, int CI, int CO, int K, int flip, float* p, hipStream_t s);
+// dir 0: layer 1..3 forward with bias and ReLU; dir 1: backward data of
+// layer 2 or 3, gated by gate > 0 (the activation of the layer below).
+hipError_t cnn_conv(int layer, int dir, const float* in, const float* wp, const float* b, const float* gate,
+                    int64_t n_img, int H, int W, float* out, hipStream_t s);
+int64_t cnn_wgrad_blocks(int64_t n_img, int H, int W);
+// Weight and bias gradient of layer 1..3 into dst (flat W then b); part
+// holds cnn_wgrad_blocks() * (weights + biases) floats.
+hipError_t cnn_wgrad(int layer, const float* a, const float* g, int64_t n_img, int H, int W, float* part,
+                     float* dst, hipStream_t s);
+// Output layer: logits and/or a flag mask in [time][baseline][chan] layout.
+hipError_t cnn_head(const float* a3, const float* w4, int64_t n_img, int H, int W, float* logits, float thr,
+                    int64_t img0, int64_t n_base, uint8_t* mask, hipStream_t s);
+int64_t cnn_head_bwd_blocks(int64_t n_total);
+// Loss, dW4/db4 (grad4[33]) and g3; part holds cnn_head_bwd_blocks() * 34 floats.
+hipError_t cnn_head_bwd(const float* logits, const uint8_t* labels, const float* a3, const float* w4,
+                        int64_t n_img, int H, int W, float pos_weight, float* g3, float* part, float* grad4,
+                        float* loss, hipStream_t s);
+hipError_t cnn_adam(float* w, const float* g, float* m, float* v, int n, int64_t step, float lr, float b1,
+                    float b2, float eps, hipStream_t s);
+hipError_t cnn_normalize(const float2* vis, const double* stats, int64_t n_time, int64_t n_base, int n_chan,
+                         int64_t b0, int64_t nb, float* x, hipStream_t s);
 
 }  // namespace qc

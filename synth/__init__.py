@@ -47,6 +47,9 @@ class StreamSpec:
     lines: list = field(default_factory=list)     # [(cycles_per_sample, amp, phase)]
     bursts: list = field(default_factory=list)    # [(start_sample, length, rms)]
     period: int = 0   # tone and line frequencies are multiples of 1/period
+    # linear chirps [(start_sample, length, f0, f1, amp, phase)]: frequency
+    # f0 -> f1 (cycles per sample) over the length, common to all antennas
+    chirps: list = field(default_factory=list)
 
 
 def _common_component(spec: StreamSpec, lo: int, hi: int, max_lag: int) -> np.ndarray:
@@ -95,6 +98,12 @@ def _fill_chunk(spec: StreamSpec, x: np.ndarray, lo: int, lags, max_lag, periodi
         if a < b:
             r = _rng(spec.seed, 3, bi).standard_normal(blen, dtype=np.float32)
             common[a - lo:b - lo] += np.float32(rms) * r[a - b0:b - b0]
+    for (c0, clen, f0, f1, amp, phase) in spec.chirps:
+        a, b = max(lo, c0), min(hi, c0 + clen)
+        if a < b:
+            t = np.arange(a - c0, b - c0, dtype=np.float64)
+            cyc = f0 * t + 0.5 * (f1 - f0) / clen * t * t
+            common[a - lo:b - lo] += (amp * np.cos(2.0 * np.pi * np.mod(cyc, 1.0) + phase)).astype(np.float32)
     cpre = _common_component(spec, lo, hi, max_lag) if spec.corr else None
     k_corr = np.float32(math.sqrt(spec.corr) * spec.sigma)
     sig = np.float32(spec.sigma)
@@ -220,3 +229,92 @@ def batched(n_samp=1 << 22, seed=4000):
         out.append(Workload(f"batch_{na}ant_{nch}ch", generate(spec), 2 * nch, 4,
                             n_samp // (2 * nch), {"lags": spec.lags}))
     return out
+
+
+# ---- streams with known injected RFI (training and judging the flagger) ------
+
+# Nominal tap sums of the 4-tap Hann-sinc prototype, used only to set the
+# injected amplitudes: sum h ~ N and sum h^2 ~ 0.8 N.
+_SUM_H, _SUM_H2 = 1.0, 0.8
+
+
+def _line_amp(snr, sigma, n_fft):
+    """Amplitude of a bin-centred tone whose channel power is snr times the
+    channel's noise power: A = 2 sigma sqrt(snr sum h^2) / sum h."""
+    return 2.0 * sigma * math.sqrt(snr * _SUM_H2 * n_fft) / (_SUM_H * n_fft)
+
+
+def rfi_realisation(seed, n_ant=32, n_samp=1 << 24, n_fft=4096, spec_per_dump=16, n_taps=4, corr=0.1,
+                    n_lines=6, burst_frac=0.03, n_chirps=3, snr_range=(1.0, 50.0)):
+    """Stream with injected RFI and its truth mask per (integration, channel).
+
+    RFI is common to all antennas (one emitter), with log-uniform per-channel
+    SNR (power in an affected channel over that channel's noise power, before
+    integration):
+      * persistent narrowband lines, bin-centred: truth = the line's channel
+        in every integration;
+      * broadband bursts of 1-64 spectra (white, rms sigma sqrt(snr)), about
+        burst_frac of the spectra: truth = every channel of each integration
+        holding a spectrum whose filter window overlaps the burst;
+      * linear chirps over 256-2048 spectra (at most half the stream)
+        sweeping 20-400 channels: truth =
+        the channels swept while the window's central half (blocks m-2 and
+        m-1 of spectrum m) passes, in that spectrum's integration.
+    Returns (StreamSpec, truth uint8 [n_int, n_fft/2], params).
+    """
+    rng = _rng(seed, 11, 0)
+    nch = n_fft // 2
+    M = n_samp // n_fft
+    n_int = M // spec_per_dump
+    sigma = 16.0
+    lo_s, hi_s = math.log(snr_range[0]), math.log(snr_range[1])
+
+    def snr():
+        return float(math.exp(rng.uniform(lo_s, hi_s)))
+
+    lags = tuple(int(v) for v in rng.integers(0, 41, n_ant))
+    truth = np.zeros((n_int, nch), np.uint8)
+    chans = rng.choice(np.arange(8, nch - 8), n_lines, replace=False)
+    lines, line_snr = [], []
+    for k in sorted(int(c) for c in chans):
+        sn = snr()
+        lines.append((k / n_fft, _line_amp(sn, sigma, n_fft), float(rng.uniform(-np.pi, np.pi))))
+        line_snr.append(sn)
+        truth[:, k] = 1
+    bursts, covered = [], 0
+    target = int(round(burst_frac * M))
+    while covered < target:
+        blen = int(rng.integers(1, 65))
+        m0 = int(rng.integers(0, M - blen))
+        s0, s1 = m0 * n_fft, (m0 + blen) * n_fft
+        bursts.append((s0, s1 - s0, sigma * math.sqrt(snr())))
+        covered += blen
+        m_first = s0 // n_fft
+        m_last = min(M - 1, (s1 - 1) // n_fft + n_taps - 1)
+        truth[m_first // spec_per_dump:m_last // spec_per_dump + 1, :] = 1
+    chirps = []
+    for _ in range(n_chirps):
+        clen_spec = int(rng.integers(min(256, M // 4), min(2048, M // 2) + 1))
+        m0 = int(rng.integers(0, M - clen_spec))
+        k0 = float(rng.integers(8, nch - 8))
+        span = float(rng.integers(20, 401)) * (1 if rng.random() < 0.5 else -1)
+        k1 = min(max(k0 + span, 4.0), nch - 4.0)
+        c0, clen = m0 * n_fft, clen_spec * n_fft
+        chirps.append((c0, clen, k0 / n_fft, k1 / n_fft, _line_amp(snr(), sigma, n_fft),
+                       float(rng.uniform(-np.pi, np.pi))))
+        for m in range(m0, min(M, m0 + clen_spec + n_taps)):
+            a = max(0, (m - 2) * n_fft - c0)
+            b = min(clen, m * n_fft - c0)
+            if a >= b:
+                continue
+            ka = k0 + (k1 - k0) * a / clen
+            kb = k0 + (k1 - k0) * b / clen
+            lo_k = int(math.floor(min(ka, kb) + 0.5))
+            hi_k = int(math.floor(max(ka, kb) + 0.5))
+            truth[m // spec_per_dump, max(0, lo_k):min(nch, hi_k + 1)] = 1
+    spec = StreamSpec(n_ant, n_samp, seed, sigma=sigma, corr=corr, lags=lags, lines=lines, bursts=bursts,
+                      period=n_fft, chirps=chirps)
+    params = {"lags": lags, "line_snr": line_snr, "n_bursts": len(bursts), "chirps": chirps,
+              "n_int": n_int, "n_chan": nch, "spec_per_dump": spec_per_dump, "n_fft": n_fft,
+              "n_taps": n_taps}
+    return spec, truth, params

@@ -50,3 +50,34 @@ def test_realtime_recipe():
     assert covered >= 0.05 * M
     assert all(0 <= l <= 40 for l in params["lags"])
     assert np.allclose(params["tau_s"], np.array(params["lags"]) * 1e-9)
+
+
+def test_rfi_realisation_truth_and_determinism():
+    spec, truth, params = synth.rfi_realisation(3, n_ant=2, n_samp=1 << 20, n_lines=3, n_chirps=1,
+                                                burst_frac=0.02)
+    n_int = (1 << 20) // 4096 // 16
+    assert truth.shape == (n_int, 2048) and truth.dtype == np.uint8
+    # every line channel is flagged in every integration
+    for (f, amp, ph) in spec.lines:
+        assert truth[:, int(round(f * 4096))].all()
+    # bursts flag whole integrations
+    full = truth.all(axis=1)
+    assert full.any() and params["n_bursts"] >= 1
+    a = synth.generate(spec)
+    b = synth.generate(spec)
+    assert np.array_equal(a, b)
+    spec2, truth2, _ = synth.rfi_realisation(3, n_ant=2, n_samp=1 << 20, n_lines=3, n_chirps=1,
+                                             burst_frac=0.02)
+    assert np.array_equal(truth, truth2)
+
+
+def test_chirp_instantaneous_frequency():
+    """A lone chirp: phase increments sweep linearly from f0 to f1."""
+    L = 1 << 16
+    spec = synth.StreamSpec(1, L, 1, sigma=0.0, corr=0.0, chirps=[(0, L, 0.01, 0.05, 100.0, 0.3)])
+    x = synth.generate(spec, threads=1).astype(np.float64)[0]
+    # zero crossings per unit time ~ 2 f: count them in a window at the start and end
+    def freq(seg):
+        return np.count_nonzero(np.diff(np.signbit(seg))) / (2.0 * seg.size)
+    assert abs(freq(x[:4096]) - (0.01 + 0.04 * 2048 / L)) < 2e-3
+    assert abs(freq(x[-4096:]) - (0.05 - 0.04 * 2048 / L)) < 2e-3
