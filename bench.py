@@ -43,6 +43,7 @@ def parse():
     ap.add_argument("--no-precision", action="store_true", help="skip the 32-antenna section")
     ap.add_argument("--no-batched", action="store_true", help="skip the uneven-arrays section")
     ap.add_argument("--no-stream", action="store_true", help="skip the host-streaming section")
+    ap.add_argument("--no-flagger", action="store_true", help="skip the learned-flagger section")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 256 MiB device copy kernel (counter calibration)")
     return ap.parse_args()
@@ -62,8 +63,7 @@ def fx_flops(n_ant, n_samp, n_fft, n_taps, n_spec_used):
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "fx_fused_ring_realtime_4ant_n4096.md")
-KERNEL_SOURCES = ("paper_2604_20640_amd/csrc/qc_fx.hip", "paper_2604_20640_amd/csrc/qc_fft.h",
-                  "paper_2604_20640_amd/csrc/qc_kernels.h")
+KERNEL_SOURCES = ("paper_2604_20640_amd/csrc/qc_fx.hip", "paper_2604_20640_amd/csrc/qc_fft.h")
 
 
 def measured_traffic():
@@ -202,6 +202,47 @@ def stream_section(torch, qc, x, N, P, spd, vis_ref, reps=3):
             "ms": round(ms, 3), "input_GBps_pcie_inclusive": round(x.nbytes / ms / 1e6, 2),
             "h2d_copy_ms": round(cms, 3), "h2d_copy_GBps": round(x.nbytes / cms / 1e6, 2),
             "vis_err_vs_resident": float(f"{err:.3e}")}
+
+
+CNN_FLOP_PER_CELL = 2 * (9 * 32 + 25 * 32 * 32 * 2 + 32)   # multiply-adds of L1..L4, x2
+
+
+def flagger_section(torch, qc, steps):
+    """Learned RFI flagger beside MAD: trained on 8 realisations of 8-antenna
+    streams with injected RFI (2^24 samples, N = 4096, 16 spectra per
+    integration), judged on a 32-antenna realisation (528 baselines x 256
+    integrations x 2048 channels): masks against the truth, the network
+    judged by MAD, and the inference rate."""
+    from paper_2604_20640_amd import flagger
+    t0 = time.time()
+    sets = [flagger.realise(s, 8) for s in range(8)]
+    sampler = flagger.TileSampler(sets, seed=1)
+    del sets
+    gen_s = time.time() - t0
+    t0 = time.time()
+    params, info = flagger.train(sampler, steps=600, batch=32, lr=1e-3, log=log, log_every=200)
+    torch.cuda.synchronize()
+    train_s = time.time() - t0
+    del sampler
+    vis, truth, _ = flagger.realise(200, 32)
+    quality = flagger.evaluate(params, vis, truth)
+    mask = torch.empty(vis.shape, dtype=torch.uint8, device="cuda")
+    reps = max(2, steps // 50)
+    ms = timed(torch, lambda: qc.cnn_flag(params, vis, 0.0, mask), reps)
+    mad_mask = torch.empty_like(mask)
+    mad_ms = timed(torch, lambda: qc.mad_flag(vis, 5.0, 0, mask=mad_mask), reps)
+    cells = vis.numel()
+    tflops = cells * CNN_FLOP_PER_CELL / (ms * 1e-3) / 1e12
+    log(f"[bench] flagger: inference {ms:.1f} ms for {cells} cells ({tflops:.1f} TFLOP/s); MAD {mad_ms:.2f} ms; "
+        f"{quality}")
+    del vis
+    return {"workload": "flagger_32ant_528bl_256int_2048ch", "train": {
+                "realisations": 8, "n_ant": 8, "steps": 600, "batch": 32, "tile": [64, 256],
+                "pos_weight": round(info["pos_weight"], 3), "final_loss": info["losses"][-1][1],
+                "train_s": round(train_s, 2), "data_s": round(gen_s, 2)},
+            "quality": quality, "inference_ms": round(ms, 3),
+            "cells_per_s": round(cells / (ms * 1e-3), 1), "inference_TFLOPs": round(tflops, 2),
+            "inference_flop_per_cell": CNN_FLOP_PER_CELL, "mad_ms": round(mad_ms, 3)}
 
 
 def batched_section(torch, qc, steps):
@@ -399,6 +440,8 @@ def main():
         out["precision_32ant"] = precision_section(torch, qc, args.steps)
     if not args.no_batched:
         out["batched"] = batched_section(torch, qc, args.steps)
+    if not args.no_flagger:
+        out["flagger"] = flagger_section(torch, qc, args.steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(x, N, P, spd, sigma, tau, phi, df, gpu_vis)
     print(json.dumps(out), flush=True)
