@@ -28,6 +28,8 @@ def _vis(shape, seed, outliers=0.01, ties=False):
     ((5, 6, 31), 2),         # per (baseline, time) over channel
     ((1, 1, 1), 0),          # single value
     ((2, 1, 1), 0),          # two values
+    ((9, 2, 8192), 0),       # 73728 per plane: beyond the LDS cache (re-read from HBM)
+    ((256, 1, 2048), 0),     # the flagger's plane: 524288 per baseline
 ])
 def test_mad_bit_exact(qc, shape, pop):
     import torch
