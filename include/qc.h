@@ -306,6 +306,15 @@ enum {
 qc_status qc_timing_enable(int32_t on);
 qc_status qc_timing_read(int32_t kernel, double* total_ms, int64_t* launches);
 
+/* F-engine kernel choice (process-wide; not thread-safe against concurrent
+ * calls): 0 (default) uses the register-ring kernel where it applies (P = 4,
+ * built-in taps, n_fft 1024..4096: the fused ring tile's FIR and transform,
+ * writing spectra out), 1 always the plain kernel.  Both compute the same
+ * sums (Sec. 4.2 F-engine); the choice only affects speed.  Used by
+ * qc_pfb_channelize and the two-pass paths of qc_xcorrelate. */
+qc_status qc_channelize_set_variant(int32_t variant);
+int32_t qc_channelize_get_variant(void);
+
 /* Learned RFI flagger beside MAD.  MAD thresholds visibility amplitude
  * (Sec. 7, eq. 2); RFI is structured in time and frequency (Sec. 5: lines,
  * bursts).  A four-layer convolutional network over one baseline's

@@ -17,7 +17,7 @@ __all__ = [
     "QCError", "lib", "pfb_channelize", "xcorrelate", "xcorrelate_chan", "mad_flag",
     "apply_delay_phase", "n_base", "PREC", "timing_enable", "timing_read", "KERNELS", "Stream",
     "solve_delay_phase", "Plan", "cnn_param_count", "cnn_normalize", "cnn_forward", "cnn_grad", "cnn_adam",
-    "cnn_train_step", "cnn_flag",
+    "cnn_train_step", "cnn_flag", "channelize_variant",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -134,6 +134,10 @@ def lib() -> ctypes.CDLL:
             fn = getattr(L, name)
             fn.argtypes = args
             fn.restype = ctypes.c_int32
+        L.qc_channelize_set_variant.argtypes = [_I32]
+        L.qc_channelize_set_variant.restype = ctypes.c_int32
+        L.qc_channelize_get_variant.argtypes = []
+        L.qc_channelize_get_variant.restype = ctypes.c_int32
         L.qc_cnn_param_count.argtypes = []
         L.qc_cnn_param_count.restype = ctypes.c_int32
         L.qc_timing_enable.argtypes = [ctypes.c_int32]
@@ -296,6 +300,13 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def channelize_variant(v=None):
+    """Get (and with v, set) the F-engine kernel choice: 0 ring where it applies, 1 plain."""
+    if v is not None:
+        _check(lib().qc_channelize_set_variant(int(v)), "qc_channelize_set_variant")
+    return int(lib().qc_channelize_get_variant())
 
 
 # ---- learned RFI flagger ----

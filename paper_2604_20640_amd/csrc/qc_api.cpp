@@ -1340,6 +1340,15 @@ extern "C" {
 
 int32_t qc_cnn_param_count(void) { return qc::CNN_PARAMS; }
 
+qc_status qc_channelize_set_variant(int32_t variant) {
+  g_err.clear();
+  if (variant < 0 || variant > 1) return fail(QC_EINVAL, "variant must be 0 or 1");
+  qc::set_channelize_variant(variant);
+  return QC_OK;
+}
+
+int32_t qc_channelize_get_variant(void) { return qc::get_channelize_variant(); }
+
 qc_status qc_cnn_normalize(const float* vis, int64_t n_time, int64_t n_base, int32_t n_chan, float* x,
                            void* stream) {
   g_err.clear();

@@ -706,6 +706,179 @@ channelize_kernel(const int8_t* __restrict__ x, int64_t ld_x, int n_ant, int64_t
                                      out, (int64_t)blockIdx.x, (int)blockIdx.y, buf);
 }
 
+// Ring variant of the F-engine: the fused ring tile's FIR and transform
+// (register ring of the last P blocks, next block prefetched, half of the
+// symmetric prototype and per-pass twiddles in LDS) for a group of four
+// antennas (two packed transforms), writing the separated spectra out
+// instead of correlating them.  Block = (antenna group, run of spectra).
+template <int N, int V, int P, int PREC>
+__global__ void __launch_bounds__((FusedCfg<N, 4, 1, V, false, 0>::NT))
+chan_ring_kernel(const int8_t* __restrict__ x, int64_t ld_x, int n_ant, const int8_t* __restrict__ hist,
+                 const float* __restrict__ taps, const float2* __restrict__ tw, int64_t n_spec,
+                 int64_t spb, int64_t chunks, const float* __restrict__ scale, void* __restrict__ out) {
+  using C = FusedCfg<N, 4, 1, V, false, 0>;
+  using F = Fft<N, C::NT, V, false, false, true>;
+  constexpr int G = C::CHUNKS;
+  constexpr int L = P * N;
+  constexpr int NCH = N / 2;
+  extern __shared__ float2 buf[];
+  float2* b0 = buf;
+  float2* twl = buf + C::LDS;
+  float4* tl = reinterpret_cast<float4*>(twl + N);
+  const int tid = threadIdx.x;
+  const int grp = (int)(blockIdx.x / chunks);
+  const int64_t chk = blockIdx.x % chunks;
+  const int a_base = 4 * grp;
+  const int64_t m_lo = chk * spb;
+  const int64_t m_hi = m_lo + spb < n_spec ? m_lo + spb : n_spec;
+
+  for (int i = tid; i < L / 8; i += C::NT) tl[i] = reinterpret_cast<const float4*>(taps)[i];
+  build_pass_twiddles<N, V>(twl, tw, tid, C::NT);
+
+  constexpr int GP = G / C::NP;
+  static_assert(GP * C::NP == G && GP * C::NT * 4 == N, "ring chunk mapping");
+  int cn0[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) cn0[g] = 4 * (tid + (g % GP) * C::NT);
+  auto load_blk = [&](int g, int which, int64_t blk) -> uint32_t {
+    const int a = a_base + 2 * (g / GP) + which;
+    if (a >= n_ant) return 0u;
+    if (blk >= 0) return *reinterpret_cast<const uint32_t*>(x + (int64_t)a * ld_x + (int)blk * N + cn0[g]);
+    if (!hist) return 0u;
+    return *reinterpret_cast<const uint32_t*>(hist + (int64_t)a * (P - 1) * N + (int)(blk + P - 1) * N + cn0[g]);
+  };
+  uint32_t ring[P][G][2];
+#pragma unroll
+  for (int q = 0; q < P; ++q)
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int64_t blk = m_lo - P + 1 + q;
+      ring[q][g][0] = load_blk(g, 0, blk);
+      ring[q][g][1] = load_blk(g, 1, blk);
+    }
+  float hs[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int a = a_base + i;
+    hs[i] = 0.5f * ((PREC != 0 && a < n_ant) ? scale[a] : 1.f);
+  }
+  __syncthreads();  // taps and twiddles in LDS
+
+  for (int64_t m = m_lo; m < m_hi; ++m) {
+    uint32_t nxt[G][2];
+    const bool more = m + 1 < m_hi;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      nxt[g][0] = more ? load_blk(g, 0, m + 1) : 0u;
+      nxt[g][1] = more ? load_blk(g, 1, m + 1) : 0u;
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      float y0[4] = {0.f, 0.f, 0.f, 0.f}, y1[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int q = 0; q < P; ++q) {
+        float4 h;
+        if (2 * q < P) {
+          h = tl[(q * N + cn0[g]) / 4];
+        } else {
+          const float4 r = tl[(L - q * N - cn0[g] - 4) / 4];
+          h = make_float4(r.w, r.z, r.y, r.x);
+        }
+        const uint32_t w0 = ring[q][g][0], w1 = ring[q][g][1];
+        y0[0] += h.x * sbyte(w0, 0);
+        y0[1] += h.y * sbyte(w0, 1);
+        y0[2] += h.z * sbyte(w0, 2);
+        y0[3] += h.w * sbyte(w0, 3);
+        y1[0] += h.x * sbyte(w1, 0);
+        y1[1] += h.y * sbyte(w1, 1);
+        y1[2] += h.z * sbyte(w1, 2);
+        y1[3] += h.w * sbyte(w1, 3);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) b0[lds_pad((g / GP) * N + cn0[g] + i)] = make_float2(y0[i], y1[i]);
+    }
+    __syncthreads();
+    F::run(b0, b0, twl, tid);
+#pragma unroll
+    for (int cc = 0; cc < C::CPT; ++cc) {
+      const int k = tid + cc * C::NT;
+      if (NCH % C::NT == 0 || k < NCH) {
+        const int kn = (N - k) & (N - 1);
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+          float2 ya, yb;
+          separate(b0[lds_pad(p * N + k)], b0[lds_pad(p * N + kn)], ya, yb);
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            const int a = a_base + 2 * p + u;
+            if (a < n_ant) {
+              const float2 y = u ? yb : ya;
+              const float hh = hs[2 * p + u];
+              const int64_t idx = ((int64_t)a * n_spec + m) * NCH + k;
+              if constexpr (PREC == 0) {
+                reinterpret_cast<float2*>(out)[idx] = make_float2(y.x * hh, y.y * hh);
+              } else if constexpr (PREC == 1) {
+                reinterpret_cast<uint32_t*>(out)[idx] = enc_f16(y.x * hh) | (enc_f16(y.y * hh) << 16);
+              } else if constexpr (PREC == 2) {
+                reinterpret_cast<uint32_t*>(out)[idx] = enc_bf16(y.x * hh) | (enc_bf16(y.y * hh) << 16);
+              } else {
+                reinterpret_cast<uint16_t*>(out)[idx] =
+                    (uint16_t)(enc_e4m3(y.x * hh) | ((uint16_t)enc_e4m3(y.y * hh) << 8));
+              }
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q + 1 < P; ++q)
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        ring[q][g][0] = ring[q + 1][g][0];
+        ring[q][g][1] = ring[q + 1][g][1];
+      }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      ring[P - 1][g][0] = nxt[g][0];
+      ring[P - 1][g][1] = nxt[g][1];
+    }
+  }
+}
+
+template <int N, int PREC>
+static hipError_t launch_chan_ring_p(const FxArgs& a, void* out, const float* scale, hipStream_t s) {
+  constexpr int V = 16;
+  using RC = RingCfg<N, 4, V, 4>;
+  using C = FusedCfg<N, 4, 1, V, false, 0>;
+  static_assert(RC::LDS_BYTES <= 160 * 1024, "channelize ring: LDS");
+  const int64_t n_spec = a.n_samp / N;
+  const int groups = (a.n_ant + 3) / 4;
+  // runs of at least 16 spectra (the ring reloads P-1 blocks per run),
+  // about 2048 blocks in total
+  int64_t spb = (n_spec * groups + 2047) / 2048;
+  if (spb < 16) spb = 16;
+  const int64_t chunks = (n_spec + spb - 1) / spb;
+  if ((int64_t)groups * chunks > 0x7fffffffLL) return hipErrorInvalidValue;
+  const void* k = reinterpret_cast<const void*>(chan_ring_kernel<N, V, 4, PREC>);
+  hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)RC::LDS_BYTES);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((chan_ring_kernel<N, V, 4, PREC>), dim3((unsigned)(groups * chunks)), dim3(C::NT),
+                     RC::LDS_BYTES, s, a.x, a.ld_x, a.n_ant, a.hist, a.taps, a.tw, n_spec, spb, chunks, scale,
+                     out);
+  return hipGetLastError();
+}
+
+template <int N>
+static hipError_t launch_chan_ring(const FxArgs& a, int prec, void* out, const float* scale, hipStream_t s) {
+  switch (prec) {
+    case 0: return launch_chan_ring_p<N, 0>(a, out, scale, s);
+    case 1: return launch_chan_ring_p<N, 1>(a, out, scale, s);
+    case 2: return launch_chan_ring_p<N, 2>(a, out, scale, s);
+    default: return launch_chan_ring_p<N, 3>(a, out, scale, s);
+  }
+}
+
 template <int N>
 static hipError_t launch_chan_t(const FxArgs& a, int prec, void* out, const float* scale,
                                 hipStream_t s) {
@@ -741,8 +914,21 @@ static hipError_t launch_chan_t(const FxArgs& a, int prec, void* out, const floa
   return hipGetLastError();
 }
 
+static int g_chan_variant = 0;  // 0: ring variant where it applies, 1: always the plain kernel
+
+void set_channelize_variant(int v) { g_chan_variant = v; }
+int get_channelize_variant() { return g_chan_variant; }
+
 hipError_t launch_channelize(const FxArgs& a, int prec, void* out, const float* scale,
                              hipStream_t s) {
+  if (g_chan_variant == 0 && a.n_taps == 4 && a.taps_symmetric) {
+    switch (a.n_fft) {
+      case 1024: return launch_chan_ring<1024>(a, prec, out, scale, s);
+      case 2048: return launch_chan_ring<2048>(a, prec, out, scale, s);
+      case 4096: return launch_chan_ring<4096>(a, prec, out, scale, s);
+      default: break;
+    }
+  }
   switch (a.n_fft) {
     case 4: return launch_chan_t<4>(a, prec, out, scale, s);
     case 8: return launch_chan_t<8>(a, prec, out, scale, s);

@@ -33,6 +33,10 @@ hipError_t launch_reduce(const float2* part, int64_t n_dump, int64_t cpd, int64_
                          float scale, int accumulate, float2* vis, hipStream_t s);
 
 // Standalone F-engine.  out layout [n_ant][n_spec][n_chan]; prec 0..3 as qc_prec.
+// Variant 0 uses the ring kernel where it applies (P = 4, built-in taps,
+// N = 1024..4096), 1 always the plain kernel.
+void set_channelize_variant(int v);
+int get_channelize_variant();
 hipError_t launch_channelize(const FxArgs& a, int prec, void* out, const float* scale,
                              hipStream_t s);
 

@@ -193,3 +193,52 @@ def test_autotune_picks_a_tile(qc):
     qc.fx_set_tile(1024, 4, 0)
     with pytest.raises(qc.QCError):
         qc.fx_set_tile(1024, 4, 99)
+
+
+RING_CHAN = [(4096, 5, 20), (2048, 9, 18), (1024, 4, 33), (4096, 32, 6), (1024, 1, 17)]
+
+
+@pytest.mark.parametrize("N,n_ant,n_spec", RING_CHAN)
+def test_channelize_ring_matches_oracle(qc, N, n_ant, n_spec):
+    """The register-ring F-engine (P = 4, built-in taps), including odd
+    antenna groups and a carried history."""
+    import torch
+    P = 4
+    x = _stream(n_ant, N * n_spec, seed=70 + N + n_ant)
+    chans = _chans(N, n=24)
+    assert qc.channelize_variant() == 0
+    xd = torch.from_numpy(x).cuda()
+    out, _ = qc.pfb_channelize(xd, N, P)
+    X_ref = pfb.channelize(x, N, P, chans=chans)
+    rms = np.sqrt(np.mean(np.abs(X_ref) ** 2))
+    assert np.max(np.abs(out.cpu().numpy()[:, :, chans] - X_ref)) / rms <= TOL
+    # second half with the first half's history
+    cut = N * (n_spec // 2)
+    hist = torch.zeros((n_ant, (P - 1) * N), dtype=torch.int8, device="cuda")
+    qc.pfb_channelize(xd[:, :cut].contiguous(), N, P, hist_out=hist)
+    o2, _ = qc.pfb_channelize(xd[:, cut:].contiguous(), N, P, hist=hist)
+    torch.cuda.synchronize()
+    assert np.max(np.abs(o2.cpu().numpy() - out.cpu().numpy()[:, n_spec // 2:])) / rms <= 1e-6
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16", "bf16", "fp8"])
+def test_channelize_variants_agree(qc, prec):
+    import torch
+    N, n_ant, n_spec, P = 4096, 6, 12, 4
+    xd = torch.from_numpy(_stream(n_ant, N * n_spec, seed=99)).cuda()
+    try:
+        qc.channelize_variant(1)
+        a, sa = qc.pfb_channelize(xd, N, P, out_prec=prec)
+        qc.channelize_variant(0)
+        b, sb = qc.pfb_channelize(xd, N, P, out_prec=prec)
+        torch.cuda.synchronize()
+    finally:
+        qc.channelize_variant(0)
+    a, b = a.cpu().numpy(), b.cpu().numpy()
+    if prec == "f32":
+        rms = np.sqrt(np.mean(np.abs(a) ** 2))
+        assert np.max(np.abs(a - b)) / rms <= 1e-6
+    else:
+        assert np.array_equal(sa.cpu().numpy(), sb.cpu().numpy())
+        # identical up to rare rounding-boundary flips of the requantiser
+        assert np.mean(a != b) <= 1e-3
