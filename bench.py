@@ -225,24 +225,27 @@ def flagger_section(torch, qc, steps):
     train_s = time.time() - t0
     del sampler
     vis, truth, _ = flagger.realise(200, 32)
-    quality = flagger.evaluate(params, vis, truth)
+    quality = {act: flagger.evaluate(params, vis, truth, act=act) for act in ("f32", "f16")}
     mask = torch.empty(vis.shape, dtype=torch.uint8, device="cuda")
     reps = max(2, steps // 50)
-    ms = timed(torch, lambda: qc.cnn_flag(params, vis, 0.0, mask), reps)
+    cells = vis.numel()
+    infer = {}
+    for act in ("f32", "f16"):
+        ms = timed(torch, lambda: qc.cnn_flag(params, vis, 0.0, mask, act=act), reps)
+        tflops = cells * CNN_FLOP_PER_CELL / (ms * 1e-3) / 1e12
+        infer[act] = {"ms": round(ms, 3), "cells_per_s": round(cells / (ms * 1e-3), 1),
+                      "TFLOPs": round(tflops, 2)}
+        log(f"[bench] flagger {act}: inference {ms:.1f} ms for {cells} cells ({tflops:.1f} TFLOP/s)")
     mad_mask = torch.empty_like(mask)
     mad_ms = timed(torch, lambda: qc.mad_flag(vis, 5.0, 0, mask=mad_mask), reps)
-    cells = vis.numel()
-    tflops = cells * CNN_FLOP_PER_CELL / (ms * 1e-3) / 1e12
-    log(f"[bench] flagger: inference {ms:.1f} ms for {cells} cells ({tflops:.1f} TFLOP/s); MAD {mad_ms:.2f} ms; "
-        f"{quality}")
+    log(f"[bench] flagger: MAD {mad_ms:.2f} ms; {quality}")
     del vis
     return {"workload": "flagger_32ant_528bl_256int_2048ch", "train": {
                 "realisations": 8, "n_ant": 8, "steps": 600, "batch": 32, "tile": [64, 256],
                 "pos_weight": round(info["pos_weight"], 3), "final_loss": info["losses"][-1][1],
                 "train_s": round(train_s, 2), "data_s": round(gen_s, 2)},
-            "quality": quality, "inference_ms": round(ms, 3),
-            "cells_per_s": round(cells / (ms * 1e-3), 1), "inference_TFLOPs": round(tflops, 2),
-            "inference_flop_per_cell": CNN_FLOP_PER_CELL, "mad_ms": round(mad_ms, 3)}
+            "quality": quality, "inference": infer, "inference_flop_per_cell": CNN_FLOP_PER_CELL,
+            "mad_ms": round(mad_ms, 3)}
 
 
 def batched_section(torch, qc, steps):

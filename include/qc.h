@@ -328,7 +328,9 @@ int32_t qc_channelize_get_variant(void);
  *     [n_base][n_time][n_chan]: A = |V| (float32), r = (A - med)/(1.4826 MAD)
  *     over the baseline's plane (exact order statistics, scale 1 if MAD = 0),
  *     x = sign(r) log1p|r|.
- *   qc_cnn_forward: x [n_img][H][W] -> logits [n_img][H][W].
+ *   qc_cnn_forward: x [n_img][H][W] -> logits [n_img][H][W].  act_prec 0:
+ *     float32 activations on the vector ALUs; 1: half activations with
+ *     float32 accumulation, L2 and L3 on the matrix cores (inference only).
  *   qc_cnn_grad: mean over cells of the binary cross-entropy of the logits
  *     against labels (uint8 [n_img][H][W], nonzero = RFI), positives weighted
  *     by pos_weight; writes the gradient (float[param_count]) and the loss
@@ -336,14 +338,15 @@ int32_t qc_channelize_get_variant(void);
  *   qc_cnn_adam: Adam with bias correction, step >= 1; m, v: device float
  *     [param_count], zero before step 1.
  *   qc_cnn_train_step: qc_cnn_grad then qc_cnn_adam (beta 0.9/0.999, eps 1e-8).
- *   qc_cnn_flag: normalise, forward and flag (logit > logit_threshold) every
- *     baseline; mask: device uint8 [n_time][n_base][n_chan] like qc_mad_flag.
+ *   qc_cnn_flag: normalise, forward (act_prec as for qc_cnn_forward) and
+ *     flag (logit > logit_threshold) every baseline; mask: device uint8
+ *     [n_time][n_base][n_chan] like qc_mad_flag.
  * All asynchronous on `stream`; n_img*H*W and n_time*n_chan below 2^31. */
 int32_t qc_cnn_param_count(void);
 qc_status qc_cnn_normalize(const float* vis, int64_t n_time, int64_t n_base, int32_t n_chan, float* x,
                            void* stream);
 qc_status qc_cnn_forward(const float* params, const float* x, int32_t n_img, int32_t height,
-                         int32_t width, float* logits, void* stream);
+                         int32_t width, int32_t act_prec, float* logits, void* stream);
 qc_status qc_cnn_grad(const float* params, const float* x, const uint8_t* labels, int32_t n_img,
                       int32_t height, int32_t width, float pos_weight, float* grad, float* loss,
                       void* stream);
@@ -353,7 +356,8 @@ qc_status qc_cnn_train_step(float* params, float* m, float* v, int64_t step, con
                             const uint8_t* labels, int32_t n_img, int32_t height, int32_t width,
                             float pos_weight, float lr, float* loss, void* stream);
 qc_status qc_cnn_flag(const float* params, const float* vis, int64_t n_time, int64_t n_base,
-                      int32_t n_chan, float logit_threshold, uint8_t* mask, void* stream);
+                      int32_t n_chan, float logit_threshold, int32_t act_prec, uint8_t* mask,
+                      void* stream);
 
 /* Human-readable name of a status code (static storage). */
 const char* qc_status_string(qc_status s);

@@ -125,11 +125,11 @@ def lib() -> ctypes.CDLL:
         _F = ctypes.c_float
         for name, args in {
             "qc_cnn_normalize": [_P, _I64, _I64, _I32, _P, _P],
-            "qc_cnn_forward": [_P, _P, _I32, _I32, _I32, _P, _P],
+            "qc_cnn_forward": [_P, _P, _I32, _I32, _I32, _I32, _P, _P],
             "qc_cnn_grad": [_P, _P, _P, _I32, _I32, _I32, _F, _P, _P, _P],
             "qc_cnn_adam": [_P, _P, _P, _P, _I64, _F, _F, _F, _F, _P],
             "qc_cnn_train_step": [_P, _P, _P, _I64, _P, _P, _I32, _I32, _I32, _F, _F, _P, _P],
-            "qc_cnn_flag": [_P, _P, _I64, _I64, _I32, _F, _P, _P],
+            "qc_cnn_flag": [_P, _P, _I64, _I64, _I32, _F, _I32, _P, _P],
         }.items():
             fn = getattr(L, name)
             fn.argtypes = args
@@ -329,14 +329,19 @@ def cnn_normalize(vis, out=None):
     return out
 
 
-def cnn_forward(params, x, out=None):
-    """Logits [n, H, W] for normalised images x [n, H, W]."""
+ACT_PREC = {"f32": 0, "f16": 1}
+
+
+def cnn_forward(params, x, out=None, act="f32"):
+    """Logits [n, H, W] for normalised images x [n, H, W]; act "f16" runs
+    half activations on the matrix cores."""
     _dev_f32(params, "params")
     _dev_f32(x, "x")
     n, H, W = x.shape
     if out is None:
         out = torch.empty_like(x)
-    _check(lib().qc_cnn_forward(_ptr(params), _ptr(x), n, H, W, _ptr(out), _stream()), "qc_cnn_forward")
+    _check(lib().qc_cnn_forward(_ptr(params), _ptr(x), n, H, W, ACT_PREC[act], _ptr(out), _stream()),
+           "qc_cnn_forward")
     return out
 
 
@@ -369,15 +374,15 @@ def cnn_train_step(params, m, v, step, x, labels, pos_weight, lr=1e-3, loss=None
     return loss
 
 
-def cnn_flag(params, vis, threshold=0.0, mask=None):
+def cnn_flag(params, vis, threshold=0.0, mask=None, act="f32"):
     """uint8 mask [n_time, n_base, n_chan] from the network (logit > threshold)."""
     _dev_f32(params, "params")
     assert vis.dtype == torch.complex64 and vis.is_cuda and vis.is_contiguous()
     n_time, nb, n_chan = vis.shape
     if mask is None:
         mask = torch.empty(vis.shape, dtype=torch.uint8, device=vis.device)
-    _check(lib().qc_cnn_flag(_ptr(params), _ptr(vis), n_time, nb, n_chan, float(threshold), _ptr(mask),
-                             _stream()), "qc_cnn_flag")
+    _check(lib().qc_cnn_flag(_ptr(params), _ptr(vis), n_time, nb, n_chan, float(threshold), ACT_PREC[act],
+                             _ptr(mask), _stream()), "qc_cnn_flag")
     return mask
 
 

@@ -1328,10 +1328,33 @@ qc_status cnn_forward_chunk(const float* p, const CnnPacked& pk, const float* x,
 
 constexpr int64_t CNN_CHUNK_BYTES = (int64_t)1 << 30;  // per activation buffer
 
-int64_t cnn_chunk_images(int64_t H, int64_t W) {
-  const int64_t per = 32 * H * W * (int64_t)sizeof(float);
+int64_t cnn_chunk_images(int64_t H, int64_t W, int64_t bytes_per = sizeof(float)) {
+  const int64_t per = 32 * H * W * bytes_per;
   const int64_t c = CNN_CHUNK_BYTES / per;
   return c < 1 ? 1 : c;
+}
+
+// Workspace of the half-activation path: matrix-core weights of L2 and L3
+// and two NHWC half activation buffers for `chunk` images.
+struct CnnHalf {
+  AsyncBuf w, a, b;
+  int64_t chunk = 1;
+  _Float16* w2() const { return (_Float16*)w.p; }
+  _Float16* w3() const { return (_Float16*)w.p + 50 * 64 * 8; }
+  _Float16* A() const { return (_Float16*)a.p; }
+  _Float16* B() const { return (_Float16*)b.p; }
+};
+
+qc_status cnn_half_setup(const float* params, int64_t n_img, int H, int W, CnnHalf& hf, hipStream_t s) {
+  hf.chunk = std::min<int64_t>(n_img, cnn_chunk_images(H, W, 2));
+  const size_t ab = sizeof(_Float16) * 32 * (size_t)hf.chunk * H * W;
+  qc_status st;
+  if ((st = alloc_async(hf.w, sizeof(_Float16) * 2 * 50 * 64 * 8, s)) != QC_OK ||
+      (st = alloc_async(hf.a, ab, s)) != QC_OK || (st = alloc_async(hf.b, ab, s)) != QC_OK)
+    return st;
+  QC_HIP(qc::cnn_pack_mfma(params + qc::CNN_OFF_L2, hf.w2(), s), "pack L2 (matrix cores)");
+  QC_HIP(qc::cnn_pack_mfma(params + qc::CNN_OFF_L3, hf.w3(), s), "pack L3 (matrix cores)");
+  return QC_OK;
 }
 
 }  // namespace
@@ -1369,14 +1392,27 @@ qc_status qc_cnn_normalize(const float* vis, int64_t n_time, int64_t n_base, int
 }
 
 qc_status qc_cnn_forward(const float* params, const float* x, int32_t n_img, int32_t H, int32_t W,
-                         float* logits, void* stream) {
+                         int32_t act_prec, float* logits, void* stream) {
   g_err.clear();
   qc_status st = cnn_check_img(params, x, n_img, H, W);
   if (st != QC_OK) return st;
   if (!logits) return fail(QC_EINVAL, "logits is NULL");
+  if (act_prec != 0 && act_prec != 1) return fail(QC_EINVAL, "act_prec must be 0 (float32) or 1 (half)");
   st = ensure_device();
   if (st != QC_OK) return st;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (act_prec == 1) {
+    CnnHalf hf;
+    if ((st = cnn_half_setup(params, n_img, H, W, hf, s)) != QC_OK) return st;
+    const int64_t hw = (int64_t)H * W;
+    for (int64_t i0 = 0; i0 < n_img; i0 += hf.chunk) {
+      const int64_t n = std::min<int64_t>(hf.chunk, n_img - i0);
+      QC_HIP(qc::cnn_forward_f16(params, hf.w2(), hf.w3(), x + i0 * hw, n, H, W, hf.A(), hf.B(), logits + i0 * hw,
+                                 0.f, 0, 0, nullptr, s),
+             "half forward");
+    }
+    return QC_OK;
+  }
   CnnPacked pk;
   st = cnn_pack_all(params, false, pk, s);
   if (st != QC_OK) return st;
@@ -1468,9 +1504,10 @@ qc_status qc_cnn_train_step(float* params, float* m, float* v, int64_t step, con
 }
 
 qc_status qc_cnn_flag(const float* params, const float* vis, int64_t n_time, int64_t n_base, int32_t n_chan,
-                      float logit_threshold, uint8_t* mask, void* stream) {
+                      float logit_threshold, int32_t act_prec, uint8_t* mask, void* stream) {
   g_err.clear();
   if (!params || !vis || !mask) return fail(QC_EINVAL, "params, vis or mask is NULL");
+  if (act_prec != 0 && act_prec != 1) return fail(QC_EINVAL, "act_prec must be 0 (float32) or 1 (half)");
   if (n_time < 1 || n_base < 1 || n_chan < 1) return fail(QC_EINVAL, "sizes must be >= 1");
   if (n_time * n_chan > 0x7fffffffLL || n_base > 0x7fffffffLL) return fail(QC_EINVAL, "plane too large");
   if (reinterpret_cast<uintptr_t>(vis) & 7u) return fail(QC_EINVAL, "vis must be 8-byte aligned");
@@ -1484,6 +1521,21 @@ qc_status qc_cnn_flag(const float* params, const float* vis, int64_t n_time, int
   if ((st = alloc_async(stats, sizeof(double) * 2 * n_base, s)) != QC_OK) return st;
   const float2* v = reinterpret_cast<const float2*>(vis);
   QC_HIP(qc::launch_mad(v, n_time, n_base, n_chan, 0.f, 0, nullptr, nullptr, (double*)stats.p, s), "MAD stats");
+  if (act_prec == 1) {
+    CnnHalf hf;
+    if ((st = cnn_half_setup(params, n_base, H, W, hf, s)) != QC_OK) return st;
+    AsyncBuf X;
+    if ((st = alloc_async(X, sizeof(float) * (size_t)hf.chunk * hw, s)) != QC_OK) return st;
+    for (int64_t b0 = 0; b0 < n_base; b0 += hf.chunk) {
+      const int64_t n = std::min<int64_t>(hf.chunk, n_base - b0);
+      QC_HIP(qc::cnn_normalize(v, (const double*)stats.p, n_time, n_base, n_chan, b0, n, (float*)X.p, s),
+             "normalise");
+      QC_HIP(qc::cnn_forward_f16(params, hf.w2(), hf.w3(), (const float*)X.p, n, H, W, hf.A(), hf.B(), nullptr,
+                                 logit_threshold, b0, n_base, mask, s),
+             "half forward");
+    }
+    return QC_OK;
+  }
   CnnPacked pk;
   if ((st = cnn_pack_all(params, false, pk, s)) != QC_OK) return st;
   const int64_t chunk = std::min<int64_t>(n_base, cnn_chunk_images(H, W));

@@ -371,6 +371,162 @@ __global__ void cnn_normalize_kernel(const float2* __restrict__ vis, const doubl
   x[e] = (float)xv;
 }
 
+// ---------------------------------------------------------------------------
+// FP16-activation inference path (FP32 accumulation), activations NHWC:
+// [image][row][col][32] half.  L2 and L3 run on the matrix cores as an
+// implicit GEMM: C[co][pixel] += sum over (tap, ci) of W[co][ci][tap] *
+// in[pixel + tap offset][ci], one v_mfma_f32_32x32x16_f16 per 16 input
+// channels of a tap.  Operand layout: lane l holds row/column l % 32 and
+// reduction slots 8*(l/32)..+7 (A: weights of output channel l%32; B: the
+// 8 input channels of pixel l%32, 16 contiguous bytes in NHWC).
+// ---------------------------------------------------------------------------
+typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
+typedef float float16_t __attribute__((ext_vector_type(16)));
+
+constexpr int MT_H = 16;     // tile rows (8 waves x 2 rows)
+constexpr int MT_W = 32;     // tile columns (one MFMA column block)
+constexpr int MT_NT = 512;
+constexpr int MT_PS = 40;    // LDS pixel stride in halves (80 B: conflict-free 16-byte reads)
+constexpr int MT_SLICES = 50;  // 25 taps x 2 halves of the input channels
+
+// Weights of a 5x5 32->32 layer in A-operand order: [slice][lane][8 halves],
+// slice = tap*2 + h, lane l: output channel l%32, input channels
+// 16h + 8(l/32) .. +7.
+__global__ void cnn_pack_mfma_kernel(const float* __restrict__ w, _Float16* __restrict__ p) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;  // over 50*64*8
+  if (e >= MT_SLICES * 64 * 8) return;
+  const int j = e % 8, lane = (e / 8) % 64, sl = e / 512;
+  const int tap = sl / 2, h = sl % 2;
+  const int co = lane % 32, ci = 16 * h + 8 * (lane / 32) + j;
+  p[e] = (_Float16)w[(co * 32 + ci) * 25 + tap];
+}
+
+template <int D>
+__global__ void __launch_bounds__(MT_NT)
+cnn_mfma_conv_kernel(const _Float16* __restrict__ in, const _Float16* __restrict__ wp,
+                     const float* __restrict__ bias, int H, int W, int tiles_x, int tiles_per_img,
+                     int64_t n_tiles, _Float16* __restrict__ out) {
+  constexpr int R = 2 * D;  // D*(5-1)/2
+  constexpr int LH = MT_H + 2 * R, LW = MT_W + 2 * R;
+  extern __shared__ uint4 smem[];
+  uint4* sw = smem;                                       // [50][64] 16-byte operands
+  _Float16* st = reinterpret_cast<_Float16*>(smem + MT_SLICES * 64);  // [LH][LW][MT_PS]
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  for (int i = t; i < MT_SLICES * 64; i += MT_NT) sw[i] = reinterpret_cast<const uint4*>(wp)[i];
+  const int px = lane & 31, kh = lane >> 5;
+  float bco[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) bco[r] = bias[8 * (r >> 2) + 4 * kh + (r & 3)];
+  for (int64_t tl = blockIdx.x; tl < n_tiles; tl += gridDim.x) {
+    const int64_t n = tl / tiles_per_img;
+    const int tt = (int)(tl % tiles_per_img);
+    const int y0 = (tt / tiles_x) * MT_H, x0 = (tt % tiles_x) * MT_W;
+    __syncthreads();  // previous tile's reads done (and weights stored)
+    // stage the input tile with its halo: 4 16-byte chunks per pixel
+    for (int e = t; e < LH * LW * 4; e += MT_NT) {
+      const int c4 = e & 3, pix = e >> 2;
+      const int r = pix / LW, q = pix % LW;
+      const int y = y0 + r - R, x = x0 + q - R;
+      uint4 v = make_uint4(0u, 0u, 0u, 0u);
+      if (y >= 0 && y < H && x >= 0 && x < W)
+        v = reinterpret_cast<const uint4*>(in + (((n * H + y) * (int64_t)W + x) * 32))[c4];
+      *reinterpret_cast<uint4*>(st + (r * LW + q) * MT_PS + 8 * c4) = v;
+    }
+    __syncthreads();
+    float16_t acc[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[u][r] = 0.f;
+#pragma unroll 5
+    for (int sl = 0; sl < MT_SLICES; ++sl) {
+      const int tap = sl >> 1, h = sl & 1;
+      const int ky = tap / 5, kx = tap % 5;
+      const half8_t a = __builtin_bit_cast(half8_t, sw[sl * 64 + lane]);
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int row = 2 * wave + u + ky * D;
+        const half8_t b = __builtin_bit_cast(
+            half8_t, *reinterpret_cast<const uint4*>(st + (row * LW + px + kx * D) * MT_PS + 16 * h + 8 * kh));
+        acc[u] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, acc[u], 0, 0, 0);
+      }
+    }
+    // epilogue: bias, ReLU, half; lane holds output channels
+    // {8g + 4kh + i} of pixel px for g, i < 4
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int y = y0 + 2 * wave + u, x = x0 + px;
+      if (y < H && x < W) {
+        _Float16* o = out + ((n * H + y) * (int64_t)W + x) * 32;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
+          half4_t v;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) v[i] = (_Float16)fmaxf(acc[u][4 * g + i] + bco[4 * g + i], 0.f);
+          *reinterpret_cast<half4_t*>(o + 8 * g + 4 * kh) = v;
+        }
+      }
+    }
+  }
+}
+
+// L1 (3x3, 1 -> 32, ReLU) from the float32 image to NHWC half.
+__global__ void __launch_bounds__(256)
+cnn_l1_nhwc_kernel(const float* __restrict__ x, const float* __restrict__ w1, const float* __restrict__ b1,
+                   int H, int W, int64_t n_pix, _Float16* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n_pix) return;
+  const int64_t hw = (int64_t)H * W;
+  const int64_t n = e / hw;
+  const int y = (int)((e % hw) / W), xx = (int)(e % W);
+  float v[9];
+#pragma unroll
+  for (int ky = 0; ky < 3; ++ky)
+#pragma unroll
+    for (int kx = 0; kx < 3; ++kx) {
+      const int yy = y + ky - 1, xc = xx + kx - 1;
+      v[ky * 3 + kx] = (yy >= 0 && yy < H && xc >= 0 && xc < W) ? x[n * hw + (int64_t)yy * W + xc] : 0.f;
+    }
+  typedef _Float16 half8v __attribute__((ext_vector_type(8)));
+#pragma unroll
+  for (int c8 = 0; c8 < 4; ++c8) {
+    half8v o;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int co = 8 * c8 + i;
+      float a = b1[co];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) a = fmaf(w1[co * 9 + k], v[k], a);
+      o[i] = (_Float16)fmaxf(a, 0.f);
+    }
+    *reinterpret_cast<half8v*>(out + e * 32 + 8 * c8) = o;
+  }
+}
+
+// L4 (1x1, 32 -> 1) from NHWC half: logits and/or the flag mask.
+__global__ void cnn_head_nhwc_kernel(const _Float16* __restrict__ a, const float* __restrict__ w4, int H, int W,
+                                     int64_t n_pix, float* __restrict__ logits, float thr, int64_t img0,
+                                     int64_t n_base, uint8_t* __restrict__ mask) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n_pix) return;
+  typedef _Float16 half8v __attribute__((ext_vector_type(8)));
+  float z = w4[32];
+#pragma unroll
+  for (int c8 = 0; c8 < 4; ++c8) {
+    const half8v v = reinterpret_cast<const half8v*>(a + e * 32)[c8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) z = fmaf(w4[8 * c8 + i], (float)v[i], z);
+  }
+  if (logits) logits[e] = z;
+  if (mask) {
+    const int64_t hw = (int64_t)H * W;
+    const int64_t n = e / hw, p = e % hw;
+    const int64_t tt = p / W, f = p % W;
+    mask[(tt * n_base + (img0 + n)) * W + f] = z > thr ? 1 : 0;
+  }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -491,6 +647,50 @@ hipError_t cnn_adam(float* w, const float* g, float* m, float* v, int n, int64_t
   const double c2 = 1.0 - std::pow((double)b2, (double)step);
   hipLaunchKernelGGL(cnn_adam_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, s, w, g, m, v, n, lr, b1, b2, eps,
                      (float)c1, (float)c2);
+  return hipGetLastError();
+}
+
+hipError_t cnn_pack_mfma(const float* w, _Float16* p, hipStream_t s) {
+  hipLaunchKernelGGL(cnn_pack_mfma_kernel, dim3(ceil_div(MT_SLICES * 64 * 8, 256)), dim3(256), 0, s, w, p);
+  return hipGetLastError();
+}
+
+size_t cnn_mfma_lds_bytes(int D) {
+  const int R = 2 * D;
+  return sizeof(uint4) * MT_SLICES * 64 + sizeof(_Float16) * (MT_H + 2 * R) * (MT_W + 2 * R) * MT_PS;
+}
+
+// Inference forward with half activations: x [n][H][W] float32 ->
+// logits / mask.  A and B hold n*H*W*32 halves each.
+hipError_t cnn_forward_f16(const float* params, const _Float16* w2p, const _Float16* w3p, const float* x,
+                           int64_t n_img, int H, int W, _Float16* A, _Float16* B, float* logits, float thr,
+                           int64_t img0, int64_t n_base, uint8_t* mask, hipStream_t s) {
+  const int64_t n_pix = n_img * H * W;
+  if (n_pix <= 0) return hipSuccess;
+  hipLaunchKernelGGL(cnn_l1_nhwc_kernel, dim3((unsigned)ceil_div(n_pix, 256)), dim3(256), 0, s, x,
+                     params + CNN_OFF_L1, params + CNN_OFF_L1 + 288, H, W, n_pix, A);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int tx = ceil_div(W, MT_W), ty = ceil_div(H, MT_H);
+  const int64_t n_tiles = n_img * tx * ty;
+  const unsigned grid = (unsigned)(n_tiles < 1024 ? n_tiles : 1024);
+  const size_t l2 = cnn_mfma_lds_bytes(1), l3 = cnn_mfma_lds_bytes(2);
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(cnn_mfma_conv_kernel<1>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)l2);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(cnn_mfma_conv_kernel<2>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)l3);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(cnn_mfma_conv_kernel<1>, dim3(grid), dim3(MT_NT), l2, s, A, w2p, params + CNN_OFF_L2 + 25600,
+                     H, W, tx, tx * ty, n_tiles, B);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(cnn_mfma_conv_kernel<2>, dim3(grid), dim3(MT_NT), l3, s, B, w3p, params + CNN_OFF_L3 + 25600,
+                     H, W, tx, tx * ty, n_tiles, A);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(cnn_head_nhwc_kernel, dim3((unsigned)ceil_div(n_pix, 256)), dim3(256), 0, s, A,
+                     params + CNN_OFF_L4, H, W, n_pix, logits, thr, img0, n_base, mask);
   return hipGetLastError();
 }
 

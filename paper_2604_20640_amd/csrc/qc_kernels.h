@@ -142,5 +142,11 @@ hipError_t cnn_adam(float* w, const float* g, float* m, float* v, int n, int64_t
                     float b2, float eps, hipStream_t s);
 hipError_t cnn_normalize(const float2* vis, const double* stats, int64_t n_time, int64_t n_base, int n_chan,
                          int64_t b0, int64_t nb, float* x, hipStream_t s);
+// Half-activation inference: weights of L2/L3 packed by cnn_pack_mfma
+// (50*64*8 halves each); A, B: n_img*H*W*32 halves.
+hipError_t cnn_pack_mfma(const float* w, _Float16* p, hipStream_t s);
+hipError_t cnn_forward_f16(const float* params, const _Float16* w2p, const _Float16* w3p, const float* x,
+                           int64_t n_img, int H, int W, _Float16* A, _Float16* B, float* logits, float thr,
+                           int64_t img0, int64_t n_base, uint8_t* mask, hipStream_t s);
 
 }  // namespace qc

@@ -106,9 +106,9 @@ def _rates(pred, ref):
             "flagged_frac": round(float(pred.float().mean()), 5)}
 
 
-def evaluate(params, vis, truth, sigma=5.0, threshold=0.0):
+def evaluate(params, vis, truth, sigma=5.0, threshold=0.0, act="f32"):
     """CNN and MAD masks against the truth, and the CNN judged by MAD."""
-    cnn = qc.cnn_flag(params, vis, threshold).bool()
+    cnn = qc.cnn_flag(params, vis, threshold, act=act).bool()
     mad, _ = qc.mad_flag(vis, sigma, 0)
     mad = mad.bool()
     tr = truth.bool()[:, None, :].expand_as(cnn)

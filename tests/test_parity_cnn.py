@@ -8,6 +8,12 @@ Bars (float32 kernels against a float64 reference):
   * loss: relative 1e-5;  Adam: relative 1e-6;  normalised input: 1e-6 abs;
   * flags: equal wherever the oracle's logit is farther than 1e-3 from the
     threshold (a float32 logit may fall on the other side of it only there).
+Half-activation inference (L2/L3 on the matrix cores) is compared with the
+oracle's forward pass with the same roundings inserted (L2/L3 weights and
+the L1..L3 activations rounded to binary16, round to nearest even): the
+remaining difference is float32 accumulation order plus the rare activation
+that rounds to the neighbouring half, bounded by 2e-3 * max(1, max|z|);
+against the unrounded oracle it is within 3e-2 * max(1, max|z|).
 """
 
 import ctypes
@@ -46,15 +52,17 @@ def test_cnn_entry_points_reject_bad_arguments():
     except OSError:
         pytest.skip("library not built")
     assert L.qc_cnn_param_count() == cnn.param_count()
-    assert L.qc_cnn_forward(None, None, 1, 8, 8, None, None) == -1
+    assert L.qc_cnn_forward(None, None, 1, 8, 8, 0, None, None) == -1
     buf = ctypes.create_string_buffer(64)
     p = ctypes.cast(buf, ctypes.c_void_p)
-    assert L.qc_cnn_forward(p, p, 0, 8, 8, p, None) == -1              # no images
-    assert L.qc_cnn_forward(p, p, 1 << 20, 1 << 10, 1 << 10, p, None) == -1   # > 2^31 cells
+    assert L.qc_cnn_forward(p, p, 0, 8, 8, 0, p, None) == -1           # no images
+    assert L.qc_cnn_forward(p, p, 1 << 20, 1 << 10, 1 << 10, 0, p, None) == -1   # > 2^31 cells
+    assert L.qc_cnn_forward(p, p, 1, 8, 8, 2, p, None) == -1           # unknown activation type
     assert L.qc_cnn_grad(p, p, p, 1, 8, 8, -1.0, p, p, None) == -1     # pos_weight <= 0
     assert L.qc_cnn_adam(p, p, p, p, 0, 1e-3, 0.9, 0.999, 1e-8, None) == -1   # step 0
     assert L.qc_cnn_adam(p, p, p, p, 1, 1e-3, 1.0, 0.999, 1e-8, None) == -1   # beta1 = 1
-    assert L.qc_cnn_flag(p, p, 0, 1, 8, 0.0, p, None) == -1
+    assert L.qc_cnn_flag(p, p, 0, 1, 8, 0.0, 0, p, None) == -1
+    assert L.qc_cnn_flag(p, p, 4, 1, 8, 0.0, 5, p, None) == -1
     assert L.qc_cnn_normalize(None, 4, 1, 8, p, None) == -1
 
 
@@ -182,3 +190,57 @@ def test_train_steps_reduce_the_loss(qc):
     qc.cnn_adam(p2, g, m2, v2, 61, lr=3e-3)
     torch.cuda.synchronize()
     assert torch.equal(p, p2) and torch.equal(m, m2) and torch.equal(v, v2)
+
+
+def _forward_half_ref(p, x):
+    """Oracle forward with the half-activation path's roundings."""
+    P = cnn.unflatten(p.astype(np.float64))
+    r16 = lambda a: a.astype(np.float16).astype(np.float64)  # noqa: E731
+    h = np.asarray(x, np.float64)[None]
+    for li, (_, _, _, dil) in enumerate(cnn.LAYERS):
+        w = P[2 * li]
+        if li in (1, 2):
+            w = r16(w)
+        z = cnn.conv2d(h, w, P[2 * li + 1], dil)
+        h = r16(np.maximum(z, 0.0)) if li < 3 else z
+    return h[0]
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("n,H,W", [(2, 13, 37), (1, 16, 32), (1, 40, 70), (3, 5, 9), (1, 1, 1)])
+def test_forward_half_matches_oracle(qc, n, H, W):
+    import torch
+    p = _params(n * 31 + H)
+    x = np.random.default_rng(H + 7 * W).normal(0, 1.0, (n, H, W)).astype(np.float32)
+    z = qc.cnn_forward(_t(p), _t(x), act="f16")
+    torch.cuda.synchronize()
+    z = z.cpu().numpy()
+    for i in range(n):
+        zq = _forward_half_ref(p, x[i])
+        zr, _ = cnn.forward(p.astype(np.float64), x[i].astype(np.float64))
+        scale = max(1.0, np.max(np.abs(zr)))
+        assert np.max(np.abs(z[i] - zq)) <= 2e-3 * scale, (i, np.max(np.abs(z[i] - zq)))
+        assert np.max(np.abs(z[i] - zr)) <= 3e-2 * scale
+
+
+@pytest.mark.gpu
+def test_flag_half_agrees_with_float(qc):
+    import torch
+    rng = np.random.default_rng(5)
+    vis = (rng.normal(size=(64, 4, 256)) + 1j * rng.normal(size=(64, 4, 256)))
+    vis[:, :, 40] *= 25.0
+    vis[10, :, :] *= 15.0
+    vis = _t(vis.astype(np.complex64))
+    p = _t(_params(17))
+    m32 = qc.cnn_flag(p, vis, 0.0, act="f32")
+    m16 = qc.cnn_flag(p, vis, 0.0, act="f16")
+    x = qc.cnn_normalize(vis)
+    z = qc.cnn_forward(p, x)
+    torch.cuda.synchronize()
+    zc = z.cpu().numpy().transpose(1, 0, 2)          # [time][baseline][chan]
+    # decided the same way wherever the float32 logit is beyond the half
+    # path's error bound (3e-2 * max(1, max|z|)) from the threshold
+    clear = np.abs(zc) > 3e-2 * max(1.0, np.abs(zc).max())
+    assert np.array_equal(m32.cpu().numpy()[clear], m16.cpu().numpy()[clear])
+    assert clear.mean() > 0.5
+    assert np.mean(m32.cpu().numpy() == m16.cpu().numpy()) > 0.98
