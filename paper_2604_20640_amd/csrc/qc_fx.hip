@@ -323,6 +323,20 @@ fx_fused_ring_kernel(const int8_t* __restrict__ x, int64_t ld_x, const int8_t* _
 #pragma unroll
     for (int b = 0; b < C::NB; ++b) acc[cc][b] = make_float2(0.f, 0.f);
   __syncthreads();  // taps in LDS
+  // the taps of this thread's GP distinct chunk positions stay in registers
+  // for the whole run (chunks g and g + GP share a position)
+  float4 hr[GP][P];
+#pragma unroll
+  for (int g = 0; g < GP; ++g)
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+      if (2 * q < P) {
+        hr[g][q] = tl[(q * N + cn0[g]) / 4];
+      } else {
+        const float4 r = tl[(L - q * N - cn0[g] - 4) / 4];
+        hr[g][q] = make_float4(r.w, r.z, r.y, r.x);
+      }
+    }
 
   for (int64_t m = m_lo; m < m_hi; ++m) {
     // prefetch block m+1 (consumed at the end of this iteration)
@@ -339,14 +353,7 @@ fx_fused_ring_kernel(const int8_t* __restrict__ x, int64_t ld_x, const int8_t* _
       float y0[4] = {0.f, 0.f, 0.f, 0.f}, y1[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int q = 0; q < P; ++q) {
-        float4 h;
-        if (2 * q < P) {
-          h = tl[(q * N + cn0[g]) / 4];
-        } else {
-          // h[qN+n+i] = h[L-1-qN-n-i]: the mirrored float4, reversed
-          const float4 r = tl[(L - q * N - cn0[g] - 4) / 4];
-          h = make_float4(r.w, r.z, r.y, r.x);
-        }
+        const float4 h = hr[g % GP][q];
         const uint32_t w0 = ring[q][g][0], w1 = ring[q][g][1];
         y0[0] += h.x * sbyte(w0, 0);
         y0[1] += h.y * sbyte(w0, 1);
@@ -763,6 +770,18 @@ chan_ring_kernel(const int8_t* __restrict__ x, int64_t ld_x, int n_ant, const in
     hs[i] = 0.5f * ((PREC != 0 && a < n_ant) ? scale[a] : 1.f);
   }
   __syncthreads();  // taps and twiddles in LDS
+  float4 hr[GP][P];   // taps of the thread's distinct chunk positions
+#pragma unroll
+  for (int g = 0; g < GP; ++g)
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+      if (2 * q < P) {
+        hr[g][q] = tl[(q * N + cn0[g]) / 4];
+      } else {
+        const float4 r = tl[(L - q * N - cn0[g] - 4) / 4];
+        hr[g][q] = make_float4(r.w, r.z, r.y, r.x);
+      }
+    }
 
   for (int64_t m = m_lo; m < m_hi; ++m) {
     uint32_t nxt[G][2];
@@ -777,13 +796,7 @@ chan_ring_kernel(const int8_t* __restrict__ x, int64_t ld_x, int n_ant, const in
       float y0[4] = {0.f, 0.f, 0.f, 0.f}, y1[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int q = 0; q < P; ++q) {
-        float4 h;
-        if (2 * q < P) {
-          h = tl[(q * N + cn0[g]) / 4];
-        } else {
-          const float4 r = tl[(L - q * N - cn0[g] - 4) / 4];
-          h = make_float4(r.w, r.z, r.y, r.x);
-        }
+        const float4 h = hr[g % GP][q];
         const uint32_t w0 = ring[q][g][0], w1 = ring[q][g][1];
         y0[0] += h.x * sbyte(w0, 0);
         y0[1] += h.y * sbyte(w0, 1);
