@@ -602,19 +602,13 @@ __device__ __forceinline__ uint16_t enc_bf16(float v) {
 }
 
 // OCP E4M3 ("fn"): bias 7, 3 mantissa bits, max 448, subnormal step 2^-9.
-__device__ __forceinline__ uint8_t enc_e4m3(float v) {
-  const uint32_t sign = (__float_as_uint(v) >> 24) & 0x80u;
-  float a = fminf(fabsf(v), 448.f);
-  uint32_t code;
-  if (a < 0.015625f) {                       // below 2^-6: subnormal grid of 2^-9
-    code = (uint32_t)__builtin_rintf(a * 512.f);  // 0..8 (8 = min normal)
-  } else {
-    uint32_t u = __float_as_uint(a);
-    u += 0x7ffffu + ((u >> 20) & 1u);
-    const int e = (int)(u >> 23) - 127;      // -6 .. 8
-    code = ((uint32_t)(e + 7) << 3) | ((u >> 20) & 7u);
-  }
-  return (uint8_t)(code | sign);
+// Two values to OCP E4M3 (re in the low byte, im in the high byte): the
+// hardware conversion rounds to nearest even; values are clamped to the
+// largest finite magnitude, 448, first (saturating, never NaN).
+__device__ __forceinline__ uint16_t enc_e4m3x2(float re, float im) {
+  const float a = fminf(fmaxf(re, -448.f), 448.f);
+  const float b = fminf(fmaxf(im, -448.f), 448.f);
+  return (uint16_t)__builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
 }
 
 // ---------------------------------------------------------------------------
@@ -693,8 +687,8 @@ __device__ __forceinline__ void chan_body(const int8_t* __restrict__ x, int64_t 
           if (a1 >= 0) o[ib] = enc(yb.x * hb) | (enc(yb.y * hb) << 16);
         } else {
           uint16_t* o = reinterpret_cast<uint16_t*>(out);
-          o[ia] = (uint16_t)(enc_e4m3(ya.x * ha) | ((uint16_t)enc_e4m3(ya.y * ha) << 8));
-          if (a1 >= 0) o[ib] = (uint16_t)(enc_e4m3(yb.x * hb) | ((uint16_t)enc_e4m3(yb.y * hb) << 8));
+          o[ia] = enc_e4m3x2(ya.x * ha, ya.y * ha);
+          if (a1 >= 0) o[ib] = enc_e4m3x2(yb.x * hb, yb.y * hb);
         }
       }
     }
@@ -835,8 +829,7 @@ chan_ring_kernel(const int8_t* __restrict__ x, int64_t ld_x, int n_ant, const in
               } else if constexpr (PREC == 2) {
                 reinterpret_cast<uint32_t*>(out)[idx] = enc_bf16(y.x * hh) | (enc_bf16(y.y * hh) << 16);
               } else {
-                reinterpret_cast<uint16_t*>(out)[idx] =
-                    (uint16_t)(enc_e4m3(y.x * hh) | ((uint16_t)enc_e4m3(y.y * hh) << 8));
+                reinterpret_cast<uint16_t*>(out)[idx] = enc_e4m3x2(y.x * hh, y.y * hh);
               }
             }
           }
