@@ -5,7 +5,8 @@
 // statistics found by radix selection (most significant digit first) over
 // the bit patterns of non-negative floats, whose unsigned order equals their
 // numeric order: float32 amplitudes and float64 deviations |A - median|.
-// Even counts average the two middle order statistics.  One workgroup
+// Even counts average the two middle order statistics; the upper one comes
+// from the lower by one counting pass.  One workgroup
 // handles one population; its amplitudes are cached in LDS when they fit
 // (1024 threads and 11-bit digits for large populations, one wave and 8-bit
 // digits for small ones).
@@ -101,12 +102,45 @@ __device__ __forceinline__ void find_digit(const unsigned* hist, int64_t kk, uns
 // first.  KEY(i) returns the unsigned key of element i; W is the key width.
 template <int NT, int DB, typename K, typename KeyFn>
 __device__ K radix_select(int64_t count, int64_t k, KeyFn key, unsigned* hist, unsigned* wsum,
-                          unsigned long long* sh) {
+                          unsigned long long* sh, unsigned long long* red) {
   constexpr int W = (int)sizeof(K) * 8;
   constexpr int NBINS = 1 << DB;
-  K prefix = 0, mask = 0;
+  // the leading bits that every key shares need no histogram pass (and
+  // would send every count of the first pass to one bin): start below them
+  K kmin = ~(K)0, kmax = 0;
+  for (int64_t i = threadIdx.x; i < count; i += NT) {
+    const K kv = key(i);
+    kmin = kv < kmin ? kv : kmin;
+    kmax = kv > kmax ? kv : kmax;
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    const K a = (K)__shfl_down((unsigned long long)kmin, d);
+    const K b = (K)__shfl_down((unsigned long long)kmax, d);
+    kmin = a < kmin ? a : kmin;
+    kmax = b > kmax ? b : kmax;
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[2 * (threadIdx.x >> 6)] = (unsigned long long)kmin;
+    red[2 * (threadIdx.x >> 6) + 1] = (unsigned long long)kmax;
+  }
+  __syncthreads();
+  kmin = ~(K)0;
+  kmax = 0;
+  for (int w = 0; w < NT / 64; ++w) {
+    const K a = (K)red[2 * w], b = (K)red[2 * w + 1];
+    kmin = a < kmin ? a : kmin;
+    kmax = b > kmax ? b : kmax;
+  }
+  __syncthreads();
+  const K diff = kmin ^ kmax;
+  if (diff == 0) return kmin;
+  int top = W - 1;  // highest differing bit
+  while (!((diff >> top) & (K)1)) --top;
+  const K low = (top + 1 >= W) ? ~(K)0 : (((K)1 << (top + 1)) - 1);
+  K prefix = kmin & ~low, mask = ~low;
   int64_t kk = k;
-  for (int hi = W; hi > 0; hi -= DB) {
+  for (int hi = top + 1; hi > 0; hi -= DB) {
     const int width = hi >= DB ? DB : hi;
     const int shift = hi - width;
     const K dmask = (K)((1u << width) - 1u);
@@ -126,6 +160,42 @@ __device__ K radix_select(int64_t count, int64_t k, KeyFn key, unsigned* hist, u
   return prefix;
 }
 
+// The order statistic of rank k+1 given the one of rank k (key kk): kk
+// itself if more than k+1 keys are <= kk, else the smallest key above kk.
+// One pass: a count and a minimum, reduced over the block.
+template <int NT, typename K, typename KeyFn>
+__device__ K next_rank(int64_t count, int64_t k, K kk, KeyFn key, unsigned long long* red) {
+  constexpr int NW = NT / 64;
+  unsigned long long le = 0;
+  K mn = ~(K)0;
+  for (int64_t i = threadIdx.x; i < count; i += NT) {
+    const K kv = key(i);
+    if (kv <= kk) ++le;
+    else if (kv < mn) mn = kv;
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    le += __shfl_down(le, d);
+    const K o = (K)__shfl_down((unsigned long long)mn, d);
+    mn = o < mn ? o : mn;
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[2 * wave] = le;
+    red[2 * wave + 1] = (unsigned long long)mn;
+  }
+  __syncthreads();
+  unsigned long long tle = 0;
+  K tmn = ~(K)0;
+  for (int w = 0; w < NW; ++w) {
+    tle += red[2 * w];
+    const K o = (K)red[2 * w + 1];
+    tmn = o < tmn ? o : tmn;
+  }
+  __syncthreads();
+  return (int64_t)tle > k + 1 ? kk : tmn;
+}
+
 }  // namespace
 
 // One block per population.  Amplitudes are cached in dynamic LDS when the
@@ -138,6 +208,7 @@ mad_kernel(const float2* __restrict__ vis, int64_t n_time, int64_t n_base, int n
   __shared__ unsigned hist[1 << DB];
   __shared__ unsigned wsum[NT / 64];
   __shared__ unsigned long long sh[2];
+  __shared__ unsigned long long red[2 * (NT / 64)];
   extern __shared__ float acache[];
   const int64_t id = blockIdx.x;
   Pop pop;
@@ -160,14 +231,14 @@ mad_kernel(const float2* __restrict__ vis, int64_t n_time, int64_t n_base, int n
   const AmpSrc amp{vis, pop, cached ? acache : nullptr};
   const int64_t k1 = (n - 1) / 2, k2 = n / 2;
   auto akey = [&](int64_t i) -> uint32_t { return __float_as_uint(amp(i)); };
-  const uint32_t a1 = radix_select<NT, DB, uint32_t>(n, k1, akey, hist, wsum, sh);
-  const uint32_t a2 = (k2 == k1) ? a1 : radix_select<NT, DB, uint32_t>(n, k2, akey, hist, wsum, sh);
+  const uint32_t a1 = radix_select<NT, DB, uint32_t>(n, k1, akey, hist, wsum, sh, red);
+  const uint32_t a2 = (k2 == k1) ? a1 : next_rank<NT, uint32_t>(n, k1, a1, akey, red);
   const double med = ((double)__uint_as_float(a1) + (double)__uint_as_float(a2)) / 2.0;
   auto dkey = [&](int64_t i) -> uint64_t {
     return (uint64_t)__double_as_longlong(fabs((double)amp(i) - med));
   };
-  const uint64_t d1 = radix_select<NT, DB, uint64_t>(n, k1, dkey, hist, wsum, sh);
-  const uint64_t d2 = (k2 == k1) ? d1 : radix_select<NT, DB, uint64_t>(n, k2, dkey, hist, wsum, sh);
+  const uint64_t d1 = radix_select<NT, DB, uint64_t>(n, k1, dkey, hist, wsum, sh, red);
+  const uint64_t d2 = (k2 == k1) ? d1 : next_rank<NT, uint64_t>(n, k1, d1, dkey, red);
   const double madv =
       (__longlong_as_double((long long)d1) + __longlong_as_double((long long)d2)) / 2.0;
   const double c = (double)sigma * 1.4826;
