@@ -1,0 +1,156 @@
+"""Parity at the workloads' full sizes, in the launch configurations the
+benchmark times, on outputs the oracle can compute one by one:
+
+* real-time stream, 4 antennas x 2^28 samples, N = 4096, 16 dumps of 4096
+  spectra (fused ring kernel): sampled dumps and channels, <= 1e-5; MAD on
+  the full visibilities, bit-exact;
+* 32 antennas x 2^24 samples, one dump: ring F-engine + FP32 X-engine
+  (<= 1e-5) and + FP16 matrix-core X-engine (<= 1e-3) on sampled channels;
+* five uneven arrays x 2^22 samples as one plan: sampled channels, <= 1e-5;
+* the flagger over a 32-antenna plane (528 baselines x 256 integrations x
+  2048 channels): normalisation on sampled baselines (1e-6) and logits at
+  sampled pixels (float32 1e-5, half activations 3e-2 of the logit scale),
+  the oracle evaluating each pixel on the 15 x 15 neighbourhood that
+  determines it (the layers' receptive field), zero-padded like the image.
+"""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import cnn, mad, pfb, xengine
+from tests.util import vis_err
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle_vis(x, N, P, spd, chans, dumps, block=512):
+    """FP64 visibilities of the given dumps and channels, in blocks of
+    spectra with the history taken from the stream itself."""
+    n_ant = x.shape[0]
+    out = []
+    for d in dumps:
+        acc = None
+        for m0 in range(d * spd, (d + 1) * spd, block):
+            m1 = min(m0 + block, (d + 1) * spd)
+            lo = m0 * N
+            hist = None
+            if m0 > 0:
+                hist = np.zeros((n_ant, (P - 1) * N), np.int64)
+                h0 = max(0, lo - (P - 1) * N)
+                hist[:, (P - 1) * N - (lo - h0):] = x[:, h0:lo]
+            X = pfb.channelize(x[:, lo:m1 * N], N, P, hist=hist, chans=chans)
+            V = xengine.correlate_fast(X, m1 - m0)[0]
+            acc = V if acc is None else acc + V
+        out.append(acc)
+    return np.stack(out)
+
+
+def test_realtime_full_size(qc):
+    import torch
+    spec, params = synth.realtime_spec(1 << 28, 2000)
+    x = synth.generate(spec)
+    N, P, spd = 4096, 4, 4096
+    xd = torch.from_numpy(x).cuda()
+    vis = qc.xcorrelate(xd, N, P, spd)
+    torch.cuda.synchronize()
+    assert vis.shape == (16, 10, 2048)
+    chans = np.array(sorted({0, 1, params["line_chans"][3], 1000, 2047}))
+    V_ref = _oracle_vis(x, N, P, spd, chans, [0, 15])
+    V = vis.cpu().numpy()
+    assert vis_err(V[[0, 15]][:, :, chans], V_ref, 4) <= 1e-5
+    # MAD over the full visibilities, bit-exact
+    m, T = qc.mad_flag(vis, 5.0, 0)
+    m_ref, T_ref = mad.mad_flag(V, 5.0, 0)
+    assert np.array_equal(m.cpu().numpy(), m_ref) and np.array_equal(T.cpu().numpy(), T_ref)
+    assert m_ref[:, :, params["line_chans"]].mean() > 0.5
+
+
+def test_precision_32ant_full_size(qc):
+    import torch
+    x = synth.generate(synth.array_spec(32, 1 << 24, 3000))
+    N, P = 4096, 4
+    spd = (1 << 24) // N
+    xd = torch.from_numpy(x).cuda()
+    chans = np.array([0, 777, 2047])
+    V_ref = _oracle_vis(x, N, P, spd, chans, [0], block=256)
+    for prec, tol in (("f32", 1e-5), ("f16", 1e-3)):
+        V = qc.xcorrelate(xd, N, P, spd, x_prec=prec)
+        torch.cuda.synchronize()
+        assert vis_err(V.cpu().numpy()[:, :, chans], V_ref, 32) <= tol, prec
+
+
+def test_batched_full_size(qc):
+    import torch
+    ws = synth.batched(1 << 22, 4000)
+    descs = [{"n_ant": w.x.shape[0], "n_samp": 1 << 22, "n_fft": w.n_fft, "n_taps": w.n_taps,
+              "spec_per_dump": w.spec_per_dump} for w in ws]
+    plan = qc.Plan(descs)
+    vis = plan.empty_vis()
+    plan.execute([torch.from_numpy(w.x).cuda() for w in ws], vis)
+    plan.check()
+    for w, v in zip(ws, vis):
+        nch = w.n_fft // 2
+        chans = np.array([1, nch // 3, nch - 1])
+        V_ref = _oracle_vis(w.x, w.n_fft, w.n_taps, w.spec_per_dump, chans, [0], block=256)
+        assert vis_err(v.cpu().numpy()[:, :, chans], V_ref, w.x.shape[0]) <= 1e-5, w.name
+
+
+def _params(seed):
+    rng = np.random.default_rng(seed)
+    parts = []
+    for s in cnn.param_shapes():
+        if len(s) == 4:
+            parts.append(rng.normal(0, np.sqrt(2.0 / (s[1] * s[2] * s[3])), s))
+        else:
+            parts.append(rng.normal(0, 0.05, s))
+    return cnn.flatten(parts).astype(np.float32)
+
+
+def test_flagger_full_plane(qc):
+    import torch
+    from paper_2604_20640_amd import flagger
+    vis, truth, _ = flagger.realise(200, 32)
+    assert vis.shape == (256, 528, 2048)
+    p = _params(11)
+    pd = torch.from_numpy(p).cuda()
+    X = qc.cnn_normalize(vis)
+    z32 = qc.cnn_forward(pd, X)
+    z16 = qc.cnn_forward(pd, X, act="f16")
+    torch.cuda.synchronize()
+    V = vis.cpu().numpy()
+    Xg, Z32, Z16 = X.cpu().numpy(), z32.cpu().numpy(), z16.cpu().numpy()
+    rng = np.random.default_rng(4)
+    R = 7                                   # receptive-field radius of the four layers
+    for b in [0, 1, 527] + list(rng.choice(528, 3, replace=False)):
+        Xr = cnn.normalize_plane(V[:, b, :])
+        assert np.max(np.abs(Xg[b] - Xr)) <= 1e-6
+        Xp = np.pad(Xr, R)
+        pts = [(0, 0), (255, 2047), (0, 1000), (128, 0)] + \
+              [tuple(t) for t in zip(rng.integers(0, 256, 4), rng.integers(0, 2048, 4))]
+        zr = []
+        for (t, f) in pts:
+            crop = Xp[t:t + 2 * R + 1, f:f + 2 * R + 1]
+            zr.append(_logit_at_centre(p, crop, t, f, 256, 2048, R))
+        zr = np.array(zr)
+        g32 = np.array([Z32[b, t, f] for t, f in pts])
+        g16 = np.array([Z16[b, t, f] for t, f in pts])
+        scale = max(1.0, np.max(np.abs(zr)))
+        assert np.max(np.abs(g32 - zr)) <= 1e-5 * scale, b
+        assert np.max(np.abs(g16 - zr)) <= 3e-2 * scale, b
+
+
+def _logit_at_centre(p, crop, t, f, H, W, R):
+    """Logit at the crop's centre, each layer's zero padding applied at the
+    image border (the crop may extend past it)."""
+    P = cnn.unflatten(p.astype(np.float64))
+    size = crop.shape[0]
+    ys = np.arange(t - R, t - R + size)[:, None]
+    xs = np.arange(f - R, f - R + size)[None, :]
+    inside = ((ys >= 0) & (ys < H) & (xs >= 0) & (xs < W)).astype(np.float64)
+    h = (crop * inside)[None]
+    for li, (_, _, _, dil) in enumerate(cnn.LAYERS):
+        z = cnn.conv2d(h, P[2 * li], P[2 * li + 1], dil)
+        h = np.maximum(z, 0.0) if li < 3 else z
+        h = h * inside[None]              # outside the image every layer sees zeros
+    return h[0, R, R]
