@@ -115,6 +115,13 @@ qc_status device_init_locked(int dev) {
   return QC_OK;
 }
 
+qc_status ensure_device() {
+  int dev = 0;
+  QC_HIP(hipGetDevice(&dev), "hipGetDevice");
+  std::lock_guard<std::mutex> lk(g_mu);
+  return device_init_locked(dev);
+}
+
 qc_status get_twiddles(int N, float2** out) {
   int dev = 0;
   QC_HIP(hipGetDevice(&dev), "hipGetDevice");
@@ -464,9 +471,17 @@ qc_status qc_mad_flag(const float* vis, int64_t n_time, int64_t n_base, int32_t 
   if (reinterpret_cast<uintptr_t>(vis) & 7u) return fail(QC_EINVAL, "vis must be 8-byte aligned");
   const int64_t npop = population == 0 ? n_base : population == 1 ? n_base * n_chan : n_time * n_base;
   if (npop > 0x7fffffffLL) return fail(QC_EINVAL, "too many populations");
-  KTimer t(QC_KERNEL_MAD, reinterpret_cast<hipStream_t>(stream));
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  AsyncBuf amp;
+  const int64_t na = qc::mad_scratch_floats(n_time, n_base, n_chan, population);
+  if (na > 0) {
+    qc_status st = ensure_device();
+    if (st != QC_OK) return st;
+    if ((st = alloc_async(amp, sizeof(float) * (size_t)na, s)) != QC_OK) return st;
+  }
+  KTimer t(QC_KERNEL_MAD, s);
   QC_HIP(qc::launch_mad(reinterpret_cast<const float2*>(vis), n_time, n_base, n_chan, sigma, population,
-                        mask, thresh_out, nullptr, reinterpret_cast<hipStream_t>(stream)),
+                        mask, thresh_out, nullptr, (float*)amp.p, s),
          "MAD kernel");
   return QC_OK;
 }
@@ -1273,13 +1288,6 @@ void qc_plan_destroy(qc_plan* P) {
 // ---- learned RFI flagger ------------------------------------------------------
 namespace {
 
-qc_status ensure_device() {
-  int dev = 0;
-  QC_HIP(hipGetDevice(&dev), "hipGetDevice");
-  std::lock_guard<std::mutex> lk(g_mu);
-  return device_init_locked(dev);
-}
-
 qc_status cnn_check_img(const void* params, const float* x, int32_t n_img, int32_t H, int32_t W) {
   if (!params || !x) return fail(QC_EINVAL, "params or x is NULL");
   if (n_img < 1 || H < 1 || W < 1) return fail(QC_EINVAL, "n_img, height and width must be >= 1");
@@ -1386,7 +1394,11 @@ qc_status qc_cnn_normalize(const float* vis, int64_t n_time, int64_t n_base, int
   st = alloc_async(stats, sizeof(double) * 2 * n_base, s);
   if (st != QC_OK) return st;
   const float2* v = reinterpret_cast<const float2*>(vis);
-  QC_HIP(qc::launch_mad(v, n_time, n_base, n_chan, 0.f, 0, nullptr, nullptr, (double*)stats.p, s), "MAD stats");
+  AsyncBuf amp;
+  const int64_t na = qc::mad_scratch_floats(n_time, n_base, n_chan, 0);
+  if (na > 0 && (st = alloc_async(amp, sizeof(float) * (size_t)na, s)) != QC_OK) return st;
+  QC_HIP(qc::launch_mad(v, n_time, n_base, n_chan, 0.f, 0, nullptr, nullptr, (double*)stats.p, (float*)amp.p, s),
+         "MAD stats");
   QC_HIP(qc::cnn_normalize(v, (const double*)stats.p, n_time, n_base, n_chan, 0, n_base, x, s), "normalise");
   return QC_OK;
 }
@@ -1520,7 +1532,14 @@ qc_status qc_cnn_flag(const float* params, const float* vis, int64_t n_time, int
   AsyncBuf stats;
   if ((st = alloc_async(stats, sizeof(double) * 2 * n_base, s)) != QC_OK) return st;
   const float2* v = reinterpret_cast<const float2*>(vis);
-  QC_HIP(qc::launch_mad(v, n_time, n_base, n_chan, 0.f, 0, nullptr, nullptr, (double*)stats.p, s), "MAD stats");
+  {
+    AsyncBuf amp;
+    const int64_t na = qc::mad_scratch_floats(n_time, n_base, n_chan, 0);
+    if (na > 0 && (st = alloc_async(amp, sizeof(float) * (size_t)na, s)) != QC_OK) return st;
+    QC_HIP(qc::launch_mad(v, n_time, n_base, n_chan, 0.f, 0, nullptr, nullptr, (double*)stats.p, (float*)amp.p,
+                          s),
+           "MAD stats");
+  }
   if (act_prec == 1) {
     CnnHalf hf;
     if ((st = cnn_half_setup(params, n_base, H, W, hf, s)) != QC_OK) return st;

@@ -41,11 +41,12 @@ __device__ __forceinline__ float amp_f32(float2 v) {
   return (float)sqrt(re * re + im * im);
 }
 
-// Amplitudes of a population: from an LDS cache when it fits, else from vis.
+// Amplitudes of a population: from an LDS cache when it fits, else from a
+// materialised amplitude array, else recomputed from vis.
 struct AmpSrc {
   const float2* vis;
   Pop pop;
-  const float* cache;  // null when not cached
+  const float* cache;  // LDS copy, or the population's slice of the materialised array; may be null
   __device__ __forceinline__ float operator()(int64_t i) const {
     return cache ? cache[i] : amp_f32(vis[pop.off(i)]);
   }
@@ -196,39 +197,52 @@ __device__ K next_rank(int64_t count, int64_t k, K kk, KeyFn key, unsigned long 
   return (int64_t)tle > k + 1 ? kk : tmn;
 }
 
+__device__ __forceinline__ Pop make_pop(int64_t id, int64_t n_time, int64_t n_base, int n_chan,
+                                        int population) {
+  const int64_t plane = n_base * (int64_t)n_chan;
+  if (population == 0) return Pop{id * n_chan, n_time * n_chan, n_chan, 1, plane};
+  if (population == 1) {
+    const int64_t b = id / n_chan, k = id % n_chan;
+    return Pop{b * n_chan + k, n_time, 1, 0, plane};
+  }
+  const int64_t t = id / n_base, b = id % n_base;
+  return Pop{t * plane + b * n_chan, n_chan, n_chan, 1, 0};
+}
+
 }  // namespace
 
 // One block per population.  Amplitudes are cached in dynamic LDS when the
 // population has at most `cap` members.
+// Amplitudes of every population, each population contiguous:
+// amp[id * count + i] = |V| of its element i (as amp_f32).
+__global__ void mad_amp_kernel(const float2* __restrict__ vis, int64_t n_time, int64_t n_base, int n_chan,
+                               int population, int64_t count, int64_t total, float* __restrict__ amp) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const int64_t id = e / count, i = e % count;
+  amp[e] = amp_f32(vis[make_pop(id, n_time, n_base, n_chan, population).off(i)]);
+}
+
 template <int NT, int DB>
 __global__ void __launch_bounds__(NT)
 mad_kernel(const float2* __restrict__ vis, int64_t n_time, int64_t n_base, int n_chan, float sigma,
-           int population, int64_t cap, uint8_t* __restrict__ mask, double* __restrict__ thresh,
-           double* __restrict__ stats) {
+           int population, int64_t cap, const float* __restrict__ gamp, uint8_t* __restrict__ mask,
+           double* __restrict__ thresh, double* __restrict__ stats) {
   __shared__ unsigned hist[1 << DB];
   __shared__ unsigned wsum[NT / 64];
   __shared__ unsigned long long sh[2];
   __shared__ unsigned long long red[2 * (NT / 64)];
   extern __shared__ float acache[];
   const int64_t id = blockIdx.x;
-  Pop pop;
-  const int64_t plane = n_base * (int64_t)n_chan;
-  if (population == 0) {
-    pop = Pop{id * n_chan, n_time * n_chan, n_chan, 1, plane};
-  } else if (population == 1) {
-    const int64_t b = id / n_chan, k = id % n_chan;
-    pop = Pop{b * n_chan + k, n_time, 1, 0, plane};
-  } else {
-    const int64_t t = id / n_base, b = id % n_base;
-    pop = Pop{t * plane + b * n_chan, n_chan, n_chan, 1, 0};
-  }
+  const Pop pop = make_pop(id, n_time, n_base, n_chan, population);
   const int64_t n = pop.count;
   const bool cached = n <= cap;
   if (cached) {
-    for (int64_t i = threadIdx.x; i < n; i += NT) acache[i] = amp_f32(vis[pop.off(i)]);
+    for (int64_t i = threadIdx.x; i < n; i += NT)
+      acache[i] = gamp ? gamp[id * n + i] : amp_f32(vis[pop.off(i)]);
     __syncthreads();
   }
-  const AmpSrc amp{vis, pop, cached ? acache : nullptr};
+  const AmpSrc amp{vis, pop, cached ? acache : (gamp ? gamp + id * n : nullptr)};
   const int64_t k1 = (n - 1) / 2, k2 = n / 2;
   auto akey = [&](int64_t i) -> uint32_t { return __float_as_uint(amp(i)); };
   const uint32_t a1 = radix_select<NT, DB, uint32_t>(n, k1, akey, hist, wsum, sh, red);
@@ -259,23 +273,41 @@ mad_kernel(const float2* __restrict__ vis, int64_t n_time, int64_t n_base, int n
 constexpr int64_t MAD_CAP_BIG = 36864;   // floats cached in LDS (144 KiB)
 constexpr int64_t MAD_CAP_SMALL = 2048;
 
+int64_t mad_scratch_floats(int64_t n_time, int64_t n_base, int n_chan, int population) {
+  const int64_t npop = population == 0 ? n_base : population == 1 ? n_base * n_chan : n_time * n_base;
+  const int64_t count = population == 0 ? n_time * n_chan : population == 1 ? n_time : n_chan;
+  return count > MAD_CAP_BIG ? npop * count : 0;
+}
+
 hipError_t launch_mad(const float2* vis, int64_t n_time, int64_t n_base, int n_chan, float sigma,
-                      int population, uint8_t* mask, double* thresh, double* stats, hipStream_t s) {
+                      int population, uint8_t* mask, double* thresh, double* stats, float* amp_scratch,
+                      hipStream_t s) {
   const int64_t npop = population == 0 ? n_base : population == 1 ? n_base * n_chan : n_time * n_base;
   const int64_t count = population == 0 ? n_time * n_chan : population == 1 ? n_time : n_chan;
   if (npop <= 0) return hipSuccess;
   if (count <= MAD_CAP_SMALL) {
     const size_t lds = (size_t)count * sizeof(float);
     hipLaunchKernelGGL((mad_kernel<64, 8>), dim3((unsigned)npop), dim3(64), lds, s, vis, n_time,
-                       n_base, n_chan, sigma, population, MAD_CAP_SMALL, mask, thresh, stats);
+                       n_base, n_chan, sigma, population, MAD_CAP_SMALL, nullptr, mask, thresh, stats);
   } else {
     const int64_t cap = count <= MAD_CAP_BIG ? count : 0;
+    const float* gamp = nullptr;
+    if (cap == 0 && amp_scratch) {
+      // populations beyond the LDS cache: their amplitudes are formed once
+      // and every selection pass reads 4 bytes instead of 8 and a square root
+      const int64_t total = npop * count;
+      hipLaunchKernelGGL(mad_amp_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, vis, n_time,
+                         n_base, n_chan, population, count, total, amp_scratch);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      gamp = amp_scratch;
+    }
     const size_t lds = (size_t)cap * sizeof(float);
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(mad_kernel<1024, 11>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((mad_kernel<1024, 11>), dim3((unsigned)npop), dim3(1024), lds, s, vis, n_time,
-                       n_base, n_chan, sigma, population, cap, mask, thresh, stats);
+                       n_base, n_chan, sigma, population, cap, gamp, mask, thresh, stats);
   }
   return hipGetLastError();
 }
