@@ -11,6 +11,9 @@
  *   MAD flags : T = median(A) + sigma * 1.4826 * MAD(A), flag A > T (Sec. 7 eq. 2).
  *   Delay/phase application: V_ij *= exp(+i[2 pi f (tau_i - tau_j) + phi_i - phi_j])
  *               (Sec. 4.1 step 2 and eq. 1; Sec. 7 delay and phase steps).
+ *   Beside it: streaming ingest (Alg. 1), a matrix-core X-engine in reduced
+ *   precision, the float64 delay/phase solve (Sec. 7), batched plans for
+ *   several arrays and a learned RFI flagger judged by MAD.
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -98,8 +101,13 @@ qc_status qc_pfb_channelize(const int8_t* x, int64_t ld_x, int32_t n_ant, int64_
 /* Fused F+X from int8 (the hot path; Sec. 4.2, Alg. 1 F-Engine, X-Engine and
  * Integration steps).
  *   spec_per_dump: spectra integrated per dump (>= 1).
- *   x_prec  : QC_F32 only for the fused path (reduced precision runs through
- *             qc_pfb_channelize + qc_xcorrelate_chan).
+ *   x_prec  : QC_F32: the fused F+X kernel where a fused tile exists (2, 4 or
+ *             8 antennas for the tabulated n_fft), else the F-engine then the
+ *             FP32 X-engine.  QC_F16 / QC_BF16 / QC_FP8_E4M3: the F-engine
+ *             writes requantised spectra (as qc_pfb_channelize), then the
+ *             matrix-core X-engine (as qc_xcorrelate_chan); needs n_ant <= 32
+ *             and n_chan % 32 == 0.  Work buffers come from the device's
+ *             stream-ordered memory pool.
  *   vis     : device cfloat [n_dump][n_base][n_chan], n_dump = n_spec / spec_per_dump;
  *             a trailing partial dump is not integrated.
  *   accumulate: nonzero adds into vis, zero overwrites it.
@@ -133,7 +141,9 @@ qc_status qc_xcorrelate_chan(const void* v, qc_prec prec, const float* scale, in
  *                [n_time][n_base] (2), or NULL.
  * Amplitudes are |V| formed in float64 and rounded once to float32; medians,
  * the MAD and T = med + (sigma*1.4826)*MAD are float64, the even-count median
- * is the mean of the two middle values, and MAD = 0 gives T = median. */
+ * is the mean of the two middle values, and MAD = 0 gives T = median.
+ * Populations of more than 36864 values take a work buffer of 4 bytes per
+ * visibility from the stream-ordered memory pool. */
 qc_status qc_mad_flag(const float* vis, int64_t n_time, int64_t n_base, int32_t n_chan,
                       float sigma, int32_t population, uint8_t* mask, double* thresh_out,
                       void* stream);

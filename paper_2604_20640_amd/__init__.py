@@ -216,7 +216,9 @@ class Stream:
 
 
 class Plan:
-    """Several arrays correlated in one persistent launch (qc_plan_*)."""
+    """Several arrays correlated together (qc_plan_*): per-array kernels on
+    streams of their own, capturable as one hipGraph; the persistent
+    single-launch mode is switched off in the library."""
 
     MODES = {"graph": 0, "persistent": 1}
 
