@@ -325,6 +325,20 @@ qc_status qc_timing_read(int32_t kernel, double* total_ms, int64_t* launches);
 qc_status qc_channelize_set_variant(int32_t variant);
 int32_t qc_channelize_get_variant(void);
 
+/* Float32 X-engine kernel choice (process-wide; not thread-safe against
+ * concurrent calls).  The matrix-core kernel forms each channel's Gram
+ * matrix on 32 x 32 tiles with v_mfma_f32_32x32x2_f32 (needs n_ant <= 32,
+ * n_chan % 16 == 0 and v 16-byte aligned); the vector-ALU kernel takes
+ * 4 x 4 antenna blocks per thread and serves every shape.  0 (default):
+ * matrix cores for 17..32 antennas, where its fixed 32 x 32 cost beats the
+ * block pairs; 1: always the vector ALU; 2: matrix cores wherever
+ * supported.  Both sum the same products in float32 (Sec. 4.1 eq. 1); the
+ * choice affects rounding order and speed only.  Used by
+ * qc_xcorrelate_chan (QC_F32), the two-pass path of qc_xcorrelate and
+ * batched plans. */
+qc_status qc_xengine_set_variant(int32_t variant);
+int32_t qc_xengine_get_variant(void);
+
 /* Learned RFI flagger beside MAD.  MAD thresholds visibility amplitude
  * (Sec. 7, eq. 2); RFI is structured in time and frequency (Sec. 5: lines,
  * bursts).  A four-layer convolutional network over one baseline's

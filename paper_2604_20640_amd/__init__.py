@@ -138,6 +138,10 @@ def lib() -> ctypes.CDLL:
         L.qc_channelize_set_variant.restype = ctypes.c_int32
         L.qc_channelize_get_variant.argtypes = []
         L.qc_channelize_get_variant.restype = ctypes.c_int32
+        L.qc_xengine_set_variant.argtypes = [_I32]
+        L.qc_xengine_set_variant.restype = ctypes.c_int32
+        L.qc_xengine_get_variant.argtypes = []
+        L.qc_xengine_get_variant.restype = ctypes.c_int32
         L.qc_cnn_param_count.argtypes = []
         L.qc_cnn_param_count.restype = ctypes.c_int32
         L.qc_timing_enable.argtypes = [ctypes.c_int32]
@@ -309,6 +313,14 @@ def channelize_variant(v=None):
     if v is not None:
         _check(lib().qc_channelize_set_variant(int(v)), "qc_channelize_set_variant")
     return int(lib().qc_channelize_get_variant())
+
+
+def xengine_variant(v=None):
+    """Get (and with v, set) the float32 X-engine kernel choice: 0 matrix cores
+    for 17..32 antennas, 1 vector ALU, 2 matrix cores wherever supported."""
+    if v is not None:
+        _check(lib().qc_xengine_set_variant(int(v)), "qc_xengine_set_variant")
+    return int(lib().qc_xengine_get_variant())
 
 
 # ---- learned RFI flagger ----

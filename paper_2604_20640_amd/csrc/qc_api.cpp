@@ -295,9 +295,14 @@ qc_status channelize_impl(const Resolved& r, qc_prec out_prec, void* out, float*
       if (st != QC_OK) return st;
     }
     const int64_t n_use = a.n_samp < (1 << 20) ? a.n_samp : (1 << 20);
-    if (n_use > 0)
-      QC_HIP(qc::launch_scales(a.x, a.ld_x, a.n_ant, n_use, s2, prec_target(out_prec), scale_out, s),
+    if (n_use > 0) {
+      AsyncBuf sp;
+      qc_status st = alloc_async(sp, (size_t)a.n_ant * qc::SC_BLOCKS * sizeof(unsigned long long), s);
+      if (st != QC_OK) return st;
+      QC_HIP(qc::launch_scales(a.x, a.ld_x, a.n_ant, n_use, s2, prec_target(out_prec),
+                               (unsigned long long*)sp.p, scale_out, s),
              "scales kernel");
+    }
   }
   if (a.n_samp > 0) {
     KTimer t(QC_KERNEL_CHANNELIZE, s);
@@ -437,11 +442,11 @@ qc_status qc_xcorrelate_chan(const void* v, qc_prec prec, const float* scale, in
     }
     KTimer t(QC_KERNEL_REDUCE, s);
     QC_HIP(qc::launch_reduce((const float2*)part.p, n_dump, ks, nb * n_chan, 1.0f, accumulate,
-                             reinterpret_cast<float2*>(vis), s),
+                             reinterpret_cast<float2*>(vis), s, qc::xeng_f32_tile(n_ant, n_chan, v), nb),
            "reduce kernel");
     return QC_OK;
   }
-  const int64_t ks = qc::xeng_mfma_ksplit(n_ant, spec_per_dump, n_chan, n_dump);
+  const int64_t ks = qc::xeng_mfma_ksplit((int)prec, n_ant, spec_per_dump, n_chan, n_dump);
   if (ks <= 0)
     return fail(QC_EUNSUPPORTED, "matrix-core X-engine needs n_ant <= 32 and n_chan %% 32 == 0");
   if (reinterpret_cast<uintptr_t>(v) & 15u) return fail(QC_EINVAL, "v must be 16-byte aligned");
@@ -456,7 +461,7 @@ qc_status qc_xcorrelate_chan(const void* v, qc_prec prec, const float* scale, in
   }
   KTimer t(QC_KERNEL_REDUCE, s);
   QC_HIP(qc::launch_reduce((const float2*)part.p, n_dump, ks, nb * n_chan, 1.0f, accumulate,
-                           reinterpret_cast<float2*>(vis), s),
+                           reinterpret_cast<float2*>(vis), s, qc::XM_TILE, nb),
          "reduce kernel");
   return QC_OK;
 }
@@ -931,7 +936,9 @@ qc_status graph_array(qc_plan* P, int i, const int8_t* x, float* vis, hipStream_
     QC_HIP(qc::launch_channelize(a, 0, G.chan, nullptr, s), "channelize kernel");
     QC_HIP(qc::launch_xeng_f32(G.chan, NA, ns, nch, D.spec_per_dump, G.n_dump, G.split, G.part, s),
            "X-engine f32 kernel");
-    QC_HIP(qc::launch_reduce(G.part, G.n_dump, G.split, elems, 1.0f, 0, v, s), "reduce kernel");
+    QC_HIP(qc::launch_reduce(G.part, G.n_dump, G.split, elems, 1.0f, 0, v, s,
+                             qc::xeng_f32_tile(NA, nch, G.chan), nb),
+           "reduce kernel");
   }
   return QC_OK;
 }
@@ -1379,6 +1386,15 @@ qc_status qc_channelize_set_variant(int32_t variant) {
 }
 
 int32_t qc_channelize_get_variant(void) { return qc::get_channelize_variant(); }
+
+qc_status qc_xengine_set_variant(int32_t variant) {
+  g_err.clear();
+  if (variant < 0 || variant > 2) return fail(QC_EINVAL, "variant must be 0, 1 or 2");
+  qc::set_xeng_f32_variant(variant);
+  return QC_OK;
+}
+
+int32_t qc_xengine_get_variant(void) { return qc::get_xeng_f32_variant(); }
 
 qc_status qc_cnn_normalize(const float* vis, int64_t n_time, int64_t n_base, int32_t n_chan, float* x,
                            void* stream) {

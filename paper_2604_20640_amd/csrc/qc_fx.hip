@@ -552,9 +552,13 @@ hipError_t launch_fused(const FxArgs& a, int64_t n_dump, int64_t spd, int64_t cp
 // ---------------------------------------------------------------------------
 // Fixed-order reduction of partials.
 // ---------------------------------------------------------------------------
+// Sum of the cpd partials of each dump.  Partials are [dump*cpd][elems];
+// with tile > 0 each partial is tile-major, [n_chan/tile][nb][tile] (one
+// X-engine workgroup's output per tile), and the sum lands in the
+// [nb][n_chan] layout of the visibilities.
 __global__ void reduce_partials_kernel(const float2* __restrict__ part, int64_t cpd, int64_t elems,
-                                       int64_t bx_per_dump, float scale, int accumulate,
-                                       float2* __restrict__ vis) {
+                                       int64_t bx_per_dump, float scale, int accumulate, int tile,
+                                       int64_t nb, int64_t n_chan, float2* __restrict__ vis) {
   const int64_t d = blockIdx.x / bx_per_dump;
   const int64_t bx = blockIdx.x % bx_per_dump;
   for (int64_t e = bx * blockDim.x + threadIdx.x; e < elems; e += bx_per_dump * blockDim.x) {
@@ -567,7 +571,13 @@ __global__ void reduce_partials_kernel(const float2* __restrict__ part, int64_t 
     }
     sacc.x *= scale;
     sacc.y *= scale;
-    float2* o = vis + d * elems + e;
+    int64_t oe = e;
+    if (tile > 0) {
+      const int64_t t = e / tile, col = e - t * tile;
+      const int64_t cb = t / nb, b = t - cb * nb;
+      oe = b * n_chan + cb * tile + col;
+    }
+    float2* o = vis + d * elems + oe;
     if (accumulate) {
       const float2 old = *o;
       sacc.x += old.x;
@@ -578,12 +588,14 @@ __global__ void reduce_partials_kernel(const float2* __restrict__ part, int64_t 
 }
 
 hipError_t launch_reduce(const float2* part, int64_t n_dump, int64_t cpd, int64_t elems,
-                         float scale, int accumulate, float2* vis, hipStream_t s) {
+                         float scale, int accumulate, float2* vis, hipStream_t s, int tile, int64_t nb) {
   if (n_dump <= 0 || elems <= 0) return hipSuccess;
+  if (tile > 0 && (nb <= 0 || elems % (nb * tile) != 0)) return hipErrorInvalidValue;
   int64_t bx = (elems + 255) / 256;
   if (bx > 4096) bx = 4096;
+  const int64_t n_chan = tile > 0 ? elems / nb : 0;
   hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)(bx * n_dump)), dim3(256), 0, s, part, cpd,
-                     elems, bx, scale, accumulate, vis);
+                     elems, bx, scale, accumulate, tile, nb, n_chan, vis);
   return hipGetLastError();
 }
 
@@ -953,45 +965,59 @@ hipError_t launch_channelize(const FxArgs& a, int prec, void* out, const float* 
 }
 
 // ---------------------------------------------------------------------------
-// Per-antenna power-of-two scale from the input power.
+// Per-antenna power-of-two scale from the input power: the sum of squares of
+// the first n_use samples, split over SC_BLOCKS workgroups per antenna
+// (exact 64-bit integer partials, so the split does not change the sum),
+// then one thread per antenna turns the total into the scale.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(1024)
-scales_kernel(const int8_t* __restrict__ x, int64_t ld_x, int64_t n_use, double sum_h2,
-              double target, float* __restrict__ scale_out) {
-  __shared__ unsigned long long red[1024];
-  const int a = blockIdx.x;
-  const uint32_t* xa = reinterpret_cast<const uint32_t*>(x + (int64_t)a * ld_x);
+__global__ void __launch_bounds__(256)
+scales_partial_kernel(const int8_t* __restrict__ x, int64_t ld_x, int64_t n_use,
+                      unsigned long long* __restrict__ part) {
+  __shared__ unsigned long long red[4];
+  const int a = blockIdx.y;
+  const int8_t* xa = x + (int64_t)a * ld_x;
+  const uint32_t* xw = reinterpret_cast<const uint32_t*>(xa);
+  const int64_t nw = n_use / 4;
+  const int64_t w0 = nw * blockIdx.x / SC_BLOCKS, w1 = nw * (blockIdx.x + 1) / SC_BLOCKS;
   unsigned long long acc = 0;
-  for (int64_t n = threadIdx.x; n < n_use / 4; n += blockDim.x) {
-    const uint32_t w = xa[n];
+  for (int64_t w = w0 + threadIdx.x; w < w1; w += 256) {
+    const uint32_t v = xw[w];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int v = (int)(int8_t)((w >> (8 * i)) & 0xffu);
-      acc += (unsigned long long)(v * v);
+      const int b = (int)(int8_t)((v >> (8 * i)) & 0xffu);
+      acc += (unsigned long long)(b * b);
     }
   }
-  red[threadIdx.x] = acc;
+  if (blockIdx.x == SC_BLOCKS - 1 && threadIdx.x == 0)
+    for (int64_t n = nw * 4; n < n_use; ++n) acc += (unsigned long long)((int)xa[n] * (int)xa[n]);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
   __syncthreads();
-  for (int st = 512; st > 0; st >>= 1) {
-    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
-    __syncthreads();
+  if (threadIdx.x == 0) part[(int64_t)a * SC_BLOCKS + blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ void scales_finish_kernel(const unsigned long long* __restrict__ part, int n_ant, int64_t n_use,
+                                     double sum_h2, double target, float* __restrict__ scale_out) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= n_ant) return;
+  unsigned long long tot = 0;
+  for (int b = 0; b < SC_BLOCKS; ++b) tot += part[(int64_t)a * SC_BLOCKS + b];
+  const double pw = (double)tot / (double)n_use;
+  const double rms = sqrt(pw * sum_h2);
+  float sc = 1.f;
+  if (rms > 0.0) {
+    const double e = rint(log2(target / rms));
+    sc = (float)ldexp(1.0, (int)e);
   }
-  if (threadIdx.x == 0) {
-    const double pw = (double)red[0] / (double)n_use;
-    const double rms = sqrt(pw * sum_h2);
-    float sc = 1.f;
-    if (rms > 0.0) {
-      const double e = rint(log2(target / rms));
-      sc = (float)ldexp(1.0, (int)e);
-    }
-    scale_out[a] = sc;
-  }
+  scale_out[a] = sc;
 }
 
 hipError_t launch_scales(const int8_t* x, int64_t ld_x, int n_ant, int64_t n_use, double sum_h2,
-                         double target, float* scale_out, hipStream_t s) {
-  hipLaunchKernelGGL(scales_kernel, dim3(n_ant), dim3(1024), 0, s, x, ld_x, n_use, sum_h2, target,
-                     scale_out);
+                         double target, unsigned long long* part, float* scale_out, hipStream_t s) {
+  hipLaunchKernelGGL(scales_partial_kernel, dim3(SC_BLOCKS, n_ant), dim3(256), 0, s, x, ld_x, n_use, part);
+  hipLaunchKernelGGL(scales_finish_kernel, dim3((n_ant + 255) / 256), dim3(256), 0, s, part, n_ant, n_use,
+                     sum_h2, target, scale_out);
   return hipGetLastError();
 }
 
@@ -1092,7 +1118,17 @@ xeng_f32_kernel(const float2* __restrict__ v, int n_ant, int64_t n_spec, int n_c
                      (int)blockIdx.y, (int64_t)(blockIdx.x / n_cgrp), part);
 }
 
-int64_t xeng_f32_ksplit(int n_ant, int64_t spd, int n_chan, int64_t n_dump) {
+static int g_xef_variant = 0;
+
+void set_xeng_f32_variant(int v) { g_xef_variant = v; }
+int get_xeng_f32_variant() { return g_xef_variant; }
+
+bool xeng_f32_use_mfma(int n_ant, int n_chan, const void* v) {
+  if (g_xef_variant == 1 || !xeng_f32_mfma_supported(n_ant, n_chan, v)) return false;
+  return g_xef_variant == 2 || n_ant >= XEF_MFMA_MIN_ANT;
+}
+
+static int64_t xeng_f32_valu_ksplit(int n_ant, int64_t spd, int n_chan, int64_t n_dump) {
   const int nblk = (n_ant + 3) / 4;
   const int64_t waves = (int64_t)nblk * (nblk + 1) / 2 * ((n_chan + 63) / 64) * n_dump;
   int64_t ks = (8192 + waves - 1) / waves;
@@ -1101,8 +1137,21 @@ int64_t xeng_f32_ksplit(int n_ant, int64_t spd, int n_chan, int64_t n_dump) {
   return ks < 1 ? 1 : ks;
 }
 
+int xeng_f32_tile(int n_ant, int n_chan, const void* v) {
+  return xeng_f32_use_mfma(n_ant, n_chan, v) ? 16 : 0;
+}
+
+int64_t xeng_f32_ksplit(int n_ant, int64_t spd, int n_chan, int64_t n_dump) {
+  // any 16-byte aligned address stands for the buffer the caller will pass
+  if (xeng_f32_use_mfma(n_ant, n_chan, reinterpret_cast<const void*>(uintptr_t(256))))
+    return xeng_f32_mfma_ksplit(n_ant, spd, n_chan, n_dump);
+  return xeng_f32_valu_ksplit(n_ant, spd, n_chan, n_dump);
+}
+
 hipError_t launch_xeng_f32(const float2* v, int n_ant, int64_t n_spec, int n_chan, int64_t spd,
                            int64_t n_dump, int64_t ksplit, float2* part, hipStream_t s) {
+  if (xeng_f32_use_mfma(n_ant, n_chan, v))
+    return launch_xeng_f32_mfma(v, n_ant, n_spec, n_chan, spd, n_dump, ksplit, part, s);
   const int nblk = (n_ant + 3) / 4;
   const int n_cgrp = (n_chan + 255) / 256;
   dim3 grid((unsigned)(n_cgrp * n_dump * ksplit), (unsigned)(nblk * (nblk + 1) / 2));

@@ -29,8 +29,11 @@ hipError_t launch_fused(const FxArgs& a, int64_t n_dump, int64_t spec_per_dump,
 
 // Deterministic reduction of per-chunk partials:
 // vis[d][e] = (accumulate ? vis[d][e] : 0) + scale * sum_c part[d*cpd + c][e].
+// tile > 0: each partial is tile-major, [n_chan/tile][nb][tile], and e is
+// mapped to the [nb][n_chan] position of the visibilities.
 hipError_t launch_reduce(const float2* part, int64_t n_dump, int64_t cpd, int64_t elems,
-                         float scale, int accumulate, float2* vis, hipStream_t s);
+                         float scale, int accumulate, float2* vis, hipStream_t s, int tile = 0,
+                         int64_t nb = 0);
 
 // Standalone F-engine.  out layout [n_ant][n_spec][n_chan]; prec 0..3 as qc_prec.
 // Variant 0 uses the ring kernel where it applies (P = 4, built-in taps,
@@ -40,25 +43,46 @@ int get_channelize_variant();
 hipError_t launch_channelize(const FxArgs& a, int prec, void* out, const float* scale,
                              hipStream_t s);
 
-// Per-antenna power-of-two scales for requantised output.
+// Per-antenna power-of-two scales for requantised output from the first
+// n_use samples; part holds n_ant * SC_BLOCKS partial sums (scratch).
+constexpr int SC_BLOCKS = 64;
 hipError_t launch_scales(const int8_t* x, int64_t ld_x, int n_ant, int64_t n_use, double sum_h2,
-                         double target, float* scale_out, hipStream_t s);
+                         double target, unsigned long long* part, float* scale_out, hipStream_t s);
 
 // Copy the last (P-1)N samples of (hist ++ x) to hist_out.
 hipError_t launch_hist_copy(const int8_t* x, int64_t ld_x, int n_ant, int64_t n_samp,
                             const int8_t* hist, int64_t keep, int8_t* hist_out, hipStream_t s);
 
-// X-engine (vector ALU, float32) over v[n_ant][n_spec][n_chan] cfloat.
+// X-engine (float32) over v[n_ant][n_spec][n_chan] cfloat, on the matrix
+// cores (32x32 tiles; n_ant <= 32, n_chan % 16 == 0, v 16-byte aligned) or
+// the vector ALU.  Variant: 0 = matrix cores for XEF_MFMA_MIN_ANT..32
+// antennas, 1 = always the vector ALU, 2 = matrix cores wherever supported.
+// xeng_f32_ksplit sizes the partial buffer for the kernel that
+// launch_xeng_f32 picks for a 16-byte aligned v.
+constexpr int XEF_MFMA_MIN_ANT = 17;
+void set_xeng_f32_variant(int v);
+int get_xeng_f32_variant();
+bool xeng_f32_use_mfma(int n_ant, int n_chan, const void* v);
+// Partial layout launch_xeng_f32 writes for v: 0 = [nb][n_chan], else the
+// tile width of the tile-major layout (see launch_reduce).
+int xeng_f32_tile(int n_ant, int n_chan, const void* v);
 int64_t xeng_f32_ksplit(int n_ant, int64_t spec_per_dump, int n_chan, int64_t n_dump);
 hipError_t launch_xeng_f32(const float2* v, int n_ant, int64_t n_spec, int n_chan,
                            int64_t spec_per_dump, int64_t n_dump, int64_t ksplit, float2* part,
                            hipStream_t s);
+bool xeng_f32_mfma_supported(int n_ant, int n_chan, const void* v);
+int64_t xeng_f32_mfma_ksplit(int n_ant, int64_t spec_per_dump, int n_chan, int64_t n_dump);
+hipError_t launch_xeng_f32_mfma(const float2* v, int n_ant, int64_t n_spec, int n_chan,
+                                int64_t spec_per_dump, int64_t n_dump, int64_t ksplit, float2* part,
+                                hipStream_t s);
 
-// X-engine on matrix cores over requantised v (prec 1..3).
+// X-engine on matrix cores over requantised v (prec 1..3); partials are
+// tile-major with tile XM_TILE.
+constexpr int XM_TILE = 32;
 hipError_t launch_xeng_mfma(const void* v, int prec, const float* scale, int n_ant,
                             int64_t n_spec, int n_chan, int64_t spec_per_dump, int64_t n_dump,
                             int64_t ksplit, float2* part, hipStream_t s);
-int64_t xeng_mfma_ksplit(int n_ant, int64_t spec_per_dump, int n_chan, int64_t n_dump);
+int64_t xeng_mfma_ksplit(int prec, int n_ant, int64_t spec_per_dump, int n_chan, int64_t n_dump);
 
 // MAD flagging.  mask, thresh and stats ([pop][2]: median, MAD) may be null.
 // Populations too large for the LDS cache read their amplitudes from

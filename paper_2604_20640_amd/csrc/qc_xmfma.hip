@@ -1,4 +1,4 @@
-// X-engine on the gfx950 matrix cores for requantised channelised voltages.
+// X-engine on the gfx950 matrix cores.
 //
 // The X-engine of arXiv 2604.20640 (Sec. 4.1 eq. 1; Sec. 4.2) forms
 // V_ij[k] = sum_m X_i,m[k] conj(X_j,m[k]).  Per channel this is a complex
@@ -6,17 +6,33 @@
 //   Re G = A A^T + B B^T,   Im G = B A^T - A B^T.
 // With antennas as rows and spectra as the reduction dimension, each term
 // is a real 32x32xK product; A (or B) serves as both the left and the right
-// MFMA operand because the gfx950 32x32x16 operand layouts coincide
-// (lane l holds row/column l%32, reduction slots 8*(l/32)..+7).  The
-// subtraction uses a sign-flipped A.  Inputs are FP16, BF16 or OCP E4M3
-// (power-of-two per-antenna scales s_a); products accumulate in FP32 and the
-// result is divided exactly by s_i s_j.
+// MFMA operand because the gfx950 32x32 operand layouts coincide (lane l
+// holds row/column l%32 and a run of reduction slots chosen by l/32).
 //
-// Tiling: a workgroup of 8 waves owns 32 channels and a run of spectra; per
-// step of 16 spectra it stages the [32 ant][16 spec][32 chan] tile through
-// LDS, transposed to [chan][ant][spec] so each lane reads its 8 spectra as
-// one contiguous run; each wave then issues 4 MFMAs for each of its 4
-// channels.  n_ant <= 32 and n_chan % 32 == 0.
+// Precisions:
+//   * float32 (complex64 input): v_mfma_f32_32x32x2_f32, three products per
+//     pair of spectra: A A^T + B B^T into Re, P = B A^T into P; at the end
+//     Im = P - P^T (AB^T = (BA^T)^T), the transpose taken through LDS;
+//   * FP16 / BF16 / OCP E4M3 (power-of-two per-antenna scales s_a):
+//     v_mfma_f32_32x32x16_{f16,bf16,fp8_fp8}, four products per 16 spectra
+//     (the subtraction uses a sign-flipped A), FP32 accumulation; the result
+//     is divided exactly by s_i s_j.
+//
+// Staging: a workgroup of 8 waves owns CB channels (16 for float32, 32
+// otherwise) and a run of spectra.  The input is read as (antenna, spectrum)
+// rows of CB channels (128 bytes; 64 for E4M3) by direct global -> LDS
+// loads (global_load_lds_dwordx4: no registers hold data in flight), in
+// stages of 64 KiB, double-buffered: the loads of stage s+1 are in flight
+// while the matrix cores consume stage s.  Each 1 KiB group of 64 lanes'
+// loads lands as one LDS chunk; which rows go into which chunk is chosen so
+// that a lane's operand reads are contiguous runs, and chunks are padded by
+// 16 bytes so that consecutive antennas' operand reads fall in different
+// banks.  The two stage buffers are distinct LDS objects and the loop is
+// unrolled by two, so the compiler can tell that operand reads of one stage
+// never alias the loads in flight into the other, and waits only where the
+// code says so.  At the end each block's partial visibilities are assembled
+// in the freed stage buffers as [baseline][CB channels] rows and written as
+// whole rows.  n_ant <= 32, n_chan % CB == 0, v 16-byte aligned.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -29,16 +45,52 @@ namespace {
 typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float float16_t __attribute__((ext_vector_type(16)));
+typedef __attribute__((address_space(3))) void lds_void_t;
 
-constexpr int XM_NT = 512;     // 8 waves
-constexpr int XM_CB = 32;      // channels per workgroup
-constexpr int XM_KS = 16;      // spectra per step
-constexpr int XM_NA = 32;      // antenna rows of the tile
+constexpr int XM_NT = 512;              // 8 waves
+constexpr int XM_NA = 32;               // antenna rows of the tile
+constexpr int XM_CHUNK = 1024 + 16;     // LDS bytes per chunk (64 lanes x 16 B + pad)
+constexpr int XM_NCHUNK = 64;           // chunks per stage (64 KiB of data)
+// Output staging reuses the stage buffers: up to 528 baselines (32
+// antennas) as two halves of XM_HALF rows, each row CB channels plus an
+// 8-byte pad; float32 keeps its P tiles ([8 waves][32][33] floats) in
+// front of its rows.
+constexpr int XM_HALF = 264;
+constexpr int XM_PT = 32 * 33;
+constexpr int XM_PTILES = 8 * XM_PT * 4;
+constexpr int xm_max(int a, int b) { return a > b ? a : b; }
+constexpr int XM_STAGE = xm_max(xm_max(XM_NCHUNK * XM_CHUNK, XM_HALF * (32 * 8 + 8)),
+                                XM_PTILES + XM_HALF * (16 * 8 + 8));
+constexpr int XM_CPW = XM_NCHUNK / (XM_NT / 64);  // chunks each wave loads per stage
 
-// LDS row (one channel) in 32-bit words for 16-bit pairs: 32 ant x 16 spec + pad
-constexpr int XM_CSTR16 = XM_NA * XM_KS + 4;
-// LDS row in 16-bit units for fp8 pairs
-constexpr int XM_CSTR8 = XM_NA * XM_KS + 8;
+// Per precision: channels per workgroup, bytes per complex sample,
+// spectra per stage.
+template <int PREC>
+struct XmCfg {
+  static constexpr int CB = PREC == 0 ? 16 : 32;
+  static constexpr int EB = PREC == 0 ? 8 : PREC == 3 ? 2 : 4;
+  static constexpr int KS = PREC == 3 ? 32 : 16;
+  static constexpr int RB = CB * EB;        // bytes of one (antenna, spectrum) row
+  static constexpr int GPR = RB / 16;       // 16-byte granules per row
+  static_assert(XM_NA * KS * RB == XM_NCHUNK * 1024, "stage = 64 chunks of 1 KiB");
+};
+
+// Row r of chunk j holds antenna j % 32 at spectrum offset row_spec(j, r):
+//   float32:    chunk half h = j/32 holds spectra 2r + h   (k-slot h of k-step r)
+//   FP16/BF16:  chunk half h holds spectra 8h + r          (lane half h's 8 slots)
+//   E4M3:       chunk half g holds spectra 16g + r         (k-group g of the stage)
+template <int PREC>
+__device__ __forceinline__ int row_spec(int j, int r) {
+  const int h = j >> 5;
+  if constexpr (PREC == 0) return 2 * r + h;
+  else if constexpr (PREC == 3) return 16 * h + r;
+  else return 8 * h + r;
+}
+
+__device__ __forceinline__ void wait_vmem_all() {
+  // s_waitcnt vmcnt(0), expcnt and lgkmcnt left at their maxima
+  __builtin_amdgcn_s_waitcnt(0x0F70);
+}
 
 template <int PREC>
 struct Op;
@@ -65,6 +117,64 @@ struct Op<3> {  // FP8 E4M3
   }
 };
 
+// Four products of one channel from eight 16-bit complex samples per lane
+// (w[p] = re | im << 16 of spectrum 8h + p).
+template <int PREC>
+__device__ __forceinline__ void gram16(const uint32_t (&w)[8], float16_t& accR, float16_t& accI) {
+  uint4 re, im;
+  re.x = __builtin_amdgcn_perm(w[1], w[0], 0x05040100u);
+  re.y = __builtin_amdgcn_perm(w[3], w[2], 0x05040100u);
+  re.z = __builtin_amdgcn_perm(w[5], w[4], 0x05040100u);
+  re.w = __builtin_amdgcn_perm(w[7], w[6], 0x05040100u);
+  im.x = __builtin_amdgcn_perm(w[1], w[0], 0x07060302u);
+  im.y = __builtin_amdgcn_perm(w[3], w[2], 0x07060302u);
+  im.z = __builtin_amdgcn_perm(w[5], w[4], 0x07060302u);
+  im.w = __builtin_amdgcn_perm(w[7], w[6], 0x07060302u);
+  const uint4 nre = make_uint4(re.x ^ 0x80008000u, re.y ^ 0x80008000u, re.z ^ 0x80008000u, re.w ^ 0x80008000u);
+  accR = Op<PREC>::mfma(re, re, accR);
+  accR = Op<PREC>::mfma(im, im, accR);
+  accI = Op<PREC>::mfma(im, re, accI);
+  accI = Op<PREC>::mfma(nre, im, accI);
+}
+
+// The same for E4M3 pairs: raw[p] holds four channels' (re, im) byte pairs
+// of spectrum 8h + p; channel e's pair is 16-bit half (e & 1) of word e >> 1.
+__device__ __forceinline__ void gram8(const uint2 (&raw)[8], int e, float16_t& accR, float16_t& accI) {
+  const uint32_t s = 2u * (uint32_t)(e & 1);
+  // bytes (re_p, re_p+1, im_p, im_p+1) from words of spectra p (low) and p+1 (high)
+  const uint32_t sel = s | ((4u + s) << 8) | ((s + 1u) << 16) | ((5u + s) << 24);
+  uint32_t t[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const uint32_t lo = (e >> 1) ? raw[2 * q].y : raw[2 * q].x;
+    const uint32_t hi = (e >> 1) ? raw[2 * q + 1].y : raw[2 * q + 1].x;
+    t[q] = __builtin_amdgcn_perm(hi, lo, sel);
+  }
+  uint2 re, im;
+  re.x = __builtin_amdgcn_perm(t[1], t[0], 0x05040100u);
+  re.y = __builtin_amdgcn_perm(t[3], t[2], 0x05040100u);
+  im.x = __builtin_amdgcn_perm(t[1], t[0], 0x07060302u);
+  im.y = __builtin_amdgcn_perm(t[3], t[2], 0x07060302u);
+  const uint2 nre = make_uint2(re.x ^ 0x80808080u, re.y ^ 0x80808080u);
+  accR = Op<3>::mfma(re, re, accR);
+  accR = Op<3>::mfma(im, im, accR);
+  accI = Op<3>::mfma(im, re, accI);
+  accI = Op<3>::mfma(nre, im, accI);
+}
+
+// Stages [s_lo, s_hi) of dump d for split ks: stage boundaries are
+// multiples of KS spectra, so only a dump's last stage can be ragged.
+template <int KS>
+__device__ __forceinline__ void split_range(int64_t spd, int64_t ksplit, int64_t dz, int64_t& m_lo,
+                                            int64_t& m_hi) {
+  const int64_t d = dz / ksplit, ks = dz % ksplit;
+  const int64_t nst = (spd + KS - 1) / KS;
+  const int64_t s_lo = ks * nst / ksplit, s_hi = (ks + 1) * nst / ksplit;
+  m_lo = d * spd + s_lo * KS;
+  const int64_t e = s_hi * KS < spd ? s_hi * KS : spd;
+  m_hi = d * spd + e;
+}
+
 }  // namespace
 
 template <int PREC>
@@ -72,178 +182,241 @@ __global__ void __launch_bounds__(XM_NT)
 xeng_mfma_kernel(const void* __restrict__ vin, const float* __restrict__ scale, int n_ant,
                  int64_t n_spec, int n_chan, int64_t spec_per_dump, int64_t ksplit, int n_cb,
                  float2* __restrict__ part) {
-  constexpr bool F8 = (PREC == 3);
-  // 16-bit formats: 4 bytes per complex; fp8: 2 bytes
-  constexpr int CB_BYTES = F8 ? 2 : 4;
-  constexpr int CHUNKS_PER_ROW = XM_CB * CB_BYTES / 16;       // 16-byte chunks per (ant, spec)
-  constexpr int CHUNKS = XM_NA * XM_KS * CHUNKS_PER_ROW;      // per tile
-  constexpr int CPT = CHUNKS / XM_NT;                         // per thread
-  constexpr int CH_PER_CHUNK = 16 / CB_BYTES;                 // channels per chunk
-  extern __shared__ uint32_t lds[];  // xm_lds_bytes(PREC)
+  using C = XmCfg<PREC>;
+  __shared__ __attribute__((aligned(16))) uint8_t st0[XM_STAGE];
+  __shared__ __attribute__((aligned(16))) uint8_t st1[XM_STAGE];
 
   const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int cb = (int)(blockIdx.x % n_cb);
   const int64_t dz = blockIdx.x / n_cb;
-  const int64_t d = dz / ksplit, ks = dz % ksplit;
-  const int64_t m_lo = d * spec_per_dump + (ks * spec_per_dump) / ksplit;
-  const int64_t m_hi = d * spec_per_dump + ((ks + 1) * spec_per_dump) / ksplit;
-  const uint8_t* vb = reinterpret_cast<const uint8_t*>(vin);
+  int64_t m_lo, m_hi;
+  split_range<C::KS>(spec_per_dump, ksplit, dz, m_lo, m_hi);
+  const int64_t n_st = (m_hi - m_lo + C::KS - 1) / C::KS;
+  const uint8_t* vb = reinterpret_cast<const uint8_t*>(vin) + (int64_t)cb * C::RB;
+  const int64_t row_pitch = (int64_t)n_chan * C::EB;
 
-  float16_t accR[4], accI[4];
+  // float32: per wave two channels, Re and P; otherwise four channels, Re and Im
+  constexpr int NCW = PREC == 0 ? 2 : 4;
+  float16_t accR[NCW], accI[NCW];
 #pragma unroll
-  for (int c = 0; c < 4; ++c)
+  for (int c = 0; c < NCW; ++c)
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       accR[c][r] = 0.f;
       accI[c][r] = 0.f;
     }
 
-  uint4 pre[CPT];
-  auto gload = [&](int64_t m0) {
+  // One stage of loads: chunk j = wave*CPW + u, lane -> (row, granule).
+  // Rows of antennas >= n_ant are not loaded (their products only reach
+  // discarded outputs); rows past m_hi load row m_hi-1 and are zeroed later.
+  // The source address is a wave-uniform base (antenna, stage) plus a
+  // 32-bit lane offset (row, granule).
+  auto issue = [&](uint8_t* dst, int64_t m0) {
+    const int r = lane / C::GPR, g = lane % C::GPR;
+    const int64_t left = m_hi - 1 - m0;
+    const int lim = left < C::KS ? (int)left : C::KS;
 #pragma unroll
-    for (int i = 0; i < CPT; ++i) {
-      const int q = tid + i * XM_NT;
-      const int ch = q % CHUNKS_PER_ROW;
-      const int m = (q / CHUNKS_PER_ROW) % XM_KS;
-      const int a = q / (CHUNKS_PER_ROW * XM_KS);
-      const int64_t mm = m0 + m;
-      if (a < n_ant && mm < m_hi) {
-        const int64_t off = (((int64_t)a * n_spec + mm) * n_chan + (int64_t)cb * XM_CB) * CB_BYTES + ch * 16;
-        pre[i] = *reinterpret_cast<const uint4*>(vb + off);
-      } else {
-        pre[i] = make_uint4(0u, 0u, 0u, 0u);
+    for (int u = 0; u < XM_CPW; ++u) {
+      const int j = wave * XM_CPW + u;
+      const int a = j & 31;
+      if (a < n_ant) {
+        int rs = row_spec<PREC>(j, r);
+        rs = rs < lim ? rs : lim;
+        const uint8_t* base = vb + ((int64_t)a * n_spec + m0) * row_pitch;
+        const uint32_t off = (uint32_t)rs * (uint32_t)row_pitch + (uint32_t)(g * 16);
+        __builtin_amdgcn_global_load_lds(base + off, (lds_void_t*)(dst + j * XM_CHUNK), 16, 0, 0);
       }
     }
   };
-  auto lstore = [&]() {
+  auto zero_tail = [&](uint8_t* cur, int64_t m0) {
+    for (int q = tid; q < XM_NCHUNK * 64; q += XM_NT) {
+      const int j = q >> 6, i = q & 63;
+      if (m0 + row_spec<PREC>(j, i / C::GPR) >= m_hi)
+        *reinterpret_cast<uint4*>(cur + j * XM_CHUNK + i * 16) = make_uint4(0u, 0u, 0u, 0u);
+    }
+  };
+  const int ra = lane & 31, rh = lane >> 5;
+  auto compute = [&](const uint8_t* cur) {
+    if constexpr (PREC == 0) {
+      const uint8_t* p = cur + (rh * 32 + ra) * XM_CHUNK + wave * 16;
 #pragma unroll
-    for (int i = 0; i < CPT; ++i) {
-      const int q = tid + i * XM_NT;
-      const int ch = q % CHUNKS_PER_ROW;
-      const int m = (q / CHUNKS_PER_ROW) % XM_KS;
-      const int a = q / (CHUNKS_PER_ROW * XM_KS);
-      const uint32_t w[4] = {pre[i].x, pre[i].y, pre[i].z, pre[i].w};
-      if constexpr (!F8) {
+      for (int t = 0; t < 8; ++t) {
+        const float4 q = *reinterpret_cast<const float4*>(p + t * 128);
+        // channel 2*wave: (q.x, q.y); channel 2*wave+1: (q.z, q.w)
+        accR[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(q.x, q.x, accR[0], 0, 0, 0);
+        accR[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(q.y, q.y, accR[0], 0, 0, 0);
+        accI[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(q.y, q.x, accI[0], 0, 0, 0);
+        accR[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(q.z, q.z, accR[1], 0, 0, 0);
+        accR[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(q.w, q.w, accR[1], 0, 0, 0);
+        accI[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(q.w, q.z, accI[1], 0, 0, 0);
+      }
+    } else if constexpr (PREC == 3) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int c = ch * CH_PER_CHUNK + e;
-          lds[c * XM_CSTR16 + a * XM_KS + m] = w[e];
-        }
-      } else {
-        uint16_t* l16 = reinterpret_cast<uint16_t*>(lds);
+      for (int g = 0; g < 2; ++g) {
+        const uint8_t* p = cur + (g * 32 + ra) * XM_CHUNK + (8 * rh) * 64 + wave * 8;
+        uint2 raw[8];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int c = ch * CH_PER_CHUNK + e;
-          l16[c * XM_CSTR8 + a * XM_KS + m] = (uint16_t)(w[e >> 1] >> (16 * (e & 1)));
-        }
+        for (int q = 0; q < 8; ++q) raw[q] = *reinterpret_cast<const uint2*>(p + q * 64);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) gram8(raw, e, accR[e], accI[e]);
+      }
+    } else {
+      const uint8_t* p = cur + (rh * 32 + ra) * XM_CHUNK + wave * 16;
+      uint4 raw[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) raw[q] = *reinterpret_cast<const uint4*>(p + q * 128);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        uint32_t w[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) w[q] = e == 0 ? raw[q].x : e == 1 ? raw[q].y : e == 2 ? raw[q].z : raw[q].w;
+        gram16<PREC>(w, accR[e], accI[e]);
       }
     }
+  };
+  // wait for the current stage, release the other buffer, refill it, compute
+  auto step = [&](uint8_t* cur, uint8_t* nxt, int64_t s) {
+    wait_vmem_all();
+    __syncthreads();
+    const int64_t m0 = m_lo + s * C::KS;
+    if (m0 + C::KS > m_hi) {
+      zero_tail(cur, m0);
+      __syncthreads();
+    }
+    if (s + 1 < n_st) issue(nxt, m0 + C::KS);
+    compute(cur);
   };
 
-  const int ra = lane & 31, rh = lane >> 5;
-  int64_t m0 = m_lo;
-  if (m0 < m_hi) gload(m0);
-  for (; m0 < m_hi; m0 += XM_KS) {
-    __syncthreads();
-    lstore();
-    __syncthreads();
-    if (m0 + XM_KS < m_hi) gload(m0 + XM_KS);
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int ch = wave * 4 + c;
-      if constexpr (!F8) {
-        const uint4* p = reinterpret_cast<const uint4*>(&lds[ch * XM_CSTR16 + ra * XM_KS + 8 * rh]);
-        const uint4 u0 = p[0], u1 = p[1];
-        const uint32_t w[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
-        uint4 re, im;
-        re.x = __builtin_amdgcn_perm(w[1], w[0], 0x05040100u);
-        re.y = __builtin_amdgcn_perm(w[3], w[2], 0x05040100u);
-        re.z = __builtin_amdgcn_perm(w[5], w[4], 0x05040100u);
-        re.w = __builtin_amdgcn_perm(w[7], w[6], 0x05040100u);
-        im.x = __builtin_amdgcn_perm(w[1], w[0], 0x07060302u);
-        im.y = __builtin_amdgcn_perm(w[3], w[2], 0x07060302u);
-        im.z = __builtin_amdgcn_perm(w[5], w[4], 0x07060302u);
-        im.w = __builtin_amdgcn_perm(w[7], w[6], 0x07060302u);
-        const uint4 nre = make_uint4(re.x ^ 0x80008000u, re.y ^ 0x80008000u, re.z ^ 0x80008000u,
-                                     re.w ^ 0x80008000u);
-        accR[c] = Op<PREC>::mfma(re, re, accR[c]);
-        accR[c] = Op<PREC>::mfma(im, im, accR[c]);
-        accI[c] = Op<PREC>::mfma(im, re, accI[c]);
-        accI[c] = Op<PREC>::mfma(nre, im, accI[c]);
-      } else {
-        const uint16_t* l16 = reinterpret_cast<const uint16_t*>(lds);
-        const uint4 u = *reinterpret_cast<const uint4*>(&l16[ch * XM_CSTR8 + ra * XM_KS + 8 * rh]);
-        uint2 re, im;
-        re.x = __builtin_amdgcn_perm(u.y, u.x, 0x06040200u);
-        re.y = __builtin_amdgcn_perm(u.w, u.z, 0x06040200u);
-        im.x = __builtin_amdgcn_perm(u.y, u.x, 0x07050301u);
-        im.y = __builtin_amdgcn_perm(u.w, u.z, 0x07050301u);
-        const uint2 nre = make_uint2(re.x ^ 0x80808080u, re.y ^ 0x80808080u);
-        accR[c] = Op<PREC>::mfma(re, re, accR[c]);
-        accR[c] = Op<PREC>::mfma(im, im, accR[c]);
-        accI[c] = Op<PREC>::mfma(im, re, accI[c]);
-        accI[c] = Op<PREC>::mfma(nre, im, accI[c]);
-      }
-    }
+  if (n_st > 0) issue(st0, m_lo);
+  int64_t s = 0;
+  for (; s + 1 < n_st; s += 2) {
+    step(st0, st1, s);
+    step(st1, st0, s + 1);
   }
-  // write the upper triangle, unscaled by 1/(s_i s_j)
+  if (s < n_st) step(st0, st1, s);  // odd count: the last stage sits in st0
+
+  // Output: the block's [baseline][CB channels] tile is assembled in LDS
+  // (rows of baselines < XM_HALF in st0, the rest in st1; each row padded
+  // by 8 bytes so that the lanes of one Gram row, which hold consecutive
+  // baselines, write different banks) and leaves as one contiguous run:
+  // partials are tile-major, [dz][n_chan / CB][nb][CB].
   const int nb = n_ant * (n_ant + 1) / 2;
-  float2* out = part + dz * (int64_t)nb * n_chan;
+  float2* out = part + dz * (int64_t)nb * n_chan + (int64_t)cb * nb * C::CB;
   const int j = lane & 31;
-  const float inv_j = j < n_ant ? 1.0f / scale[j] : 0.f;
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    const int k = cb * XM_CB + wave * 4 + c;
+  constexpr int PITCH = C::CB * 8 + 8;                  // bytes per staged row
+  constexpr int TOFF = PREC == 0 ? XM_PTILES : 0;       // float32: P tiles first
+  auto trow = [&](int b) -> float2* {
+    uint8_t* base = b < XM_HALF ? st0 : st1;
+    return reinterpret_cast<float2*>(base + TOFF + (b < XM_HALF ? b : b - XM_HALF) * PITCH);
+  };
+  __syncthreads();  // all waves are done reading the stages
+  if constexpr (PREC == 0) {
+    // Im = P - P^T: every wave puts its P tiles in LDS (channel 0 in st0,
+    // channel 1 in st1; [wave][i][j] with a padded row of 33 floats)
+    float* pt0 = reinterpret_cast<float*>(st0) + wave * XM_PT;
+    float* pt1 = reinterpret_cast<float*>(st1) + wave * XM_PT;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int i = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-      if (i <= j && j < n_ant) {
-        const float inv = (1.0f / scale[i]) * inv_j;
-        const int b = i * n_ant - i * (i - 1) / 2 + (j - i);
-        out[(int64_t)b * n_chan + k] = make_float2(accR[c][r] * inv, i == j ? 0.f : accI[c][r] * inv);
+      pt0[i * 33 + j] = accI[0][r];
+      pt1[i * 33 + j] = accI[1][r];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const float* pt = c ? pt1 : pt0;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int i = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        if (i <= j && j < n_ant) {
+          const int b = i * n_ant - i * (i - 1) / 2 + (j - i);
+          const float im = i == j ? 0.f : accI[c][r] - pt[j * 33 + i];
+          trow(b)[2 * wave + c] = make_float2(accR[c][r], im);
+        }
+      }
+    }
+  } else {
+    // unscaled by 1/(s_i s_j)
+    const float inv_j = j < n_ant ? 1.0f / scale[j] : 0.f;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int i = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        if (i <= j && j < n_ant) {
+          const float inv = (1.0f / scale[i]) * inv_j;
+          const int b = i * n_ant - i * (i - 1) / 2 + (j - i);
+          trow(b)[4 * wave + c] = make_float2(accR[c][r] * inv, i == j ? 0.f : accI[c][r] * inv);
+        }
       }
     }
   }
+  __syncthreads();
+  for (int q = tid; q < nb * C::CB; q += XM_NT) out[q] = trow(q / C::CB)[q % C::CB];
 }
 
-int64_t xeng_mfma_ksplit(int n_ant, int64_t spd, int n_chan, int64_t n_dump) {
-  if (n_ant > XM_NA || n_chan % XM_CB != 0) return 0;
-  const int64_t blocks = (int64_t)(n_chan / XM_CB) * n_dump;
-  int64_t ks = (1024 + blocks - 1) / blocks;
-  const int64_t maxk = spd / 64 > 0 ? spd / 64 : 1;
+namespace {
+
+constexpr int xm_cb(int prec) { return prec == 0 ? 16 : 32; }
+constexpr int xm_ks(int prec) { return prec == 3 ? 32 : 16; }
+
+// Splits of each dump's stages so that the grid holds about one workgroup
+// per CU (one is resident at a time: 136 KiB of LDS) with at least four
+// stages each; fewer splits also mean fewer partials to reduce.
+int64_t xm_ksplit(int prec, int n_ant, int64_t spd, int n_chan, int64_t n_dump) {
+  if (n_ant < 1 || n_ant > XM_NA || n_chan % xm_cb(prec) != 0) return 0;
+  const int64_t blocks = (int64_t)(n_chan / xm_cb(prec)) * n_dump;
+  int64_t ks = (256 + blocks - 1) / blocks;
+  const int64_t nst = (spd + xm_ks(prec) - 1) / xm_ks(prec);
+  const int64_t maxk = nst / 4 > 0 ? nst / 4 : 1;
   if (ks > maxk) ks = maxk;
   return ks < 1 ? 1 : ks;
 }
 
-static constexpr size_t xm_lds_bytes(int prec) {
-  return prec == 3 ? (size_t)XM_CB * XM_CSTR8 * 2 : (size_t)XM_CB * XM_CSTR16 * 4;
+template <int PREC>
+hipError_t launch_xm_t(const void* v, const float* scale, int n_ant, int64_t n_spec, int n_chan,
+                       int64_t spd, int64_t n_dump, int64_t ksplit, float2* part, hipStream_t s) {
+  const int n_cb = n_chan / XmCfg<PREC>::CB;
+  const int64_t blocks = (int64_t)n_cb * n_dump * ksplit;
+  if (blocks <= 0 || blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(xeng_mfma_kernel<PREC>, dim3((unsigned)blocks), dim3(XM_NT), 0, s, v, scale, n_ant,
+                     n_spec, n_chan, spd, ksplit, n_cb, part);
+  return hipGetLastError();
 }
 
-template <int PREC>
-static hipError_t launch_xm_t(dim3 grid, const void* v, const float* scale, int n_ant, int64_t n_spec,
-                              int n_chan, int64_t spd, int64_t ksplit, int n_cb, float2* part,
-                              hipStream_t s) {
-  const size_t lds = xm_lds_bytes(PREC);
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(xeng_mfma_kernel<PREC>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(xeng_mfma_kernel<PREC>, grid, dim3(XM_NT), lds, s, v, scale, n_ant, n_spec,
-                     n_chan, spd, ksplit, n_cb, part);
-  return hipGetLastError();
+}  // namespace
+
+int64_t xeng_mfma_ksplit(int prec, int n_ant, int64_t spd, int n_chan, int64_t n_dump) {
+  return prec >= 1 && prec <= 3 ? xm_ksplit(prec, n_ant, spd, n_chan, n_dump) : 0;
 }
 
 hipError_t launch_xeng_mfma(const void* v, int prec, const float* scale, int n_ant, int64_t n_spec,
                             int n_chan, int64_t spd, int64_t n_dump, int64_t ksplit, float2* part,
                             hipStream_t s) {
-  const int n_cb = n_chan / XM_CB;
-  dim3 grid((unsigned)(n_cb * n_dump * ksplit));
+  if (n_ant < 1 || n_ant > XM_NA || n_chan % 32 != 0 || (reinterpret_cast<uintptr_t>(v) & 15u))
+    return hipErrorInvalidValue;
   switch (prec) {
-    case 1: return launch_xm_t<1>(grid, v, scale, n_ant, n_spec, n_chan, spd, ksplit, n_cb, part, s);
-    case 2: return launch_xm_t<2>(grid, v, scale, n_ant, n_spec, n_chan, spd, ksplit, n_cb, part, s);
-    case 3: return launch_xm_t<3>(grid, v, scale, n_ant, n_spec, n_chan, spd, ksplit, n_cb, part, s);
+    case 1: return launch_xm_t<1>(v, scale, n_ant, n_spec, n_chan, spd, n_dump, ksplit, part, s);
+    case 2: return launch_xm_t<2>(v, scale, n_ant, n_spec, n_chan, spd, n_dump, ksplit, part, s);
+    case 3: return launch_xm_t<3>(v, scale, n_ant, n_spec, n_chan, spd, n_dump, ksplit, part, s);
   }
   return hipErrorInvalidValue;
+}
+
+bool xeng_f32_mfma_supported(int n_ant, int n_chan, const void* v) {
+  return n_ant >= 1 && n_ant <= XM_NA && n_chan % 16 == 0 && (reinterpret_cast<uintptr_t>(v) & 15u) == 0;
+}
+
+int64_t xeng_f32_mfma_ksplit(int n_ant, int64_t spd, int n_chan, int64_t n_dump) {
+  return xm_ksplit(0, n_ant, spd, n_chan, n_dump);
+}
+
+hipError_t launch_xeng_f32_mfma(const float2* v, int n_ant, int64_t n_spec, int n_chan, int64_t spd,
+                                int64_t n_dump, int64_t ksplit, float2* part, hipStream_t s) {
+  if (!xeng_f32_mfma_supported(n_ant, n_chan, v)) return hipErrorInvalidValue;
+  return launch_xm_t<0>(v, nullptr, n_ant, n_spec, n_chan, spd, n_dump, ksplit, part, s);
 }
 
 }  // namespace qc

@@ -121,3 +121,18 @@ def test_zero_dumps_is_noop():
     st = qc.lib().qc_xcorrelate(ctypes.c_void_p(0x1000), 4096, 4, 4096, ctypes.byref(p), None, None,
                                 8, 0, None, 0, ctypes.byref(nd), None)
     assert st == 0 and nd.value == 0
+
+
+def test_kernel_variant_switches():
+    # host-side state only: range checks and round trips, defaults restored
+    L = qc.lib()
+    assert L.qc_xengine_get_variant() == 0 and L.qc_channelize_get_variant() == 0
+    for bad in (-1, 3):
+        assert L.qc_xengine_set_variant(bad) == QC_EINVAL
+    assert L.qc_channelize_set_variant(2) == QC_EINVAL
+    try:
+        for v in (1, 2, 0):
+            assert L.qc_xengine_set_variant(v) == 0 and L.qc_xengine_get_variant() == v
+    finally:
+        L.qc_xengine_set_variant(0)
+    assert qc.xengine_variant() == 0

@@ -242,3 +242,60 @@ def test_channelize_variants_agree(qc, prec):
         assert np.array_equal(sa.cpu().numpy(), sb.cpu().numpy())
         # identical up to rare rounding-boundary flips of the requantiser
         assert np.mean(a != b) <= 1e-3
+
+
+# Float32 X-engine on both kernels over the same complex64 spectra: the
+# vector-ALU kernel (variant 1) and the matrix-core kernel (variant 2; it
+# serves n_ant <= 32 with n_chan % 16 == 0, other shapes fall back to the
+# vector ALU).  Ragged stages (spec_per_dump not a multiple of the 16
+# spectra one stage holds), trailing spectra past the last dump, antenna
+# counts from 1 to 32 and several dumps.  With the inputs exact, the only
+# error is the float32 summation: bar 2e-6 of sqrt(V_ii V_jj).
+XENG_F32 = [
+    (32, 128, 20, 10),
+    (17, 256, 35, 33),
+    (24, 512, 64, 64),
+    (5, 64, 50, 16),
+    (32, 2048, 40, 40),
+    (1, 32, 33, 11),
+    (31, 64, 48, 17),
+    (3, 16, 50, 7),       # 8 channels: vector ALU under either variant
+]
+
+
+@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("n_ant,N,n_spec,spd", XENG_F32)
+def test_xengine_f32_kernels_match_oracle(qc, variant, n_ant, N, n_spec, spd):
+    import torch
+    x = _stream(n_ant, N * n_spec, seed=500 + n_ant + N)
+    X = pfb.channelize(x, N, 4).astype(np.complex64)
+    v = torch.from_numpy(X).cuda()
+    old = qc.xengine_variant()
+    try:
+        qc.xengine_variant(variant)
+        V = qc.xcorrelate_chan(v, "f32", None, n_ant, n_spec, N // 2, spd)
+        torch.cuda.synchronize()
+    finally:
+        qc.xengine_variant(old)
+    V_ref = xengine.correlate_fast(X, spd)
+    assert V.shape == V_ref.shape
+    err = vis_err(V.cpu().numpy(), V_ref, n_ant)
+    assert err <= 2e-6, err
+
+
+def test_xengine_f32_default_variant(qc):
+    """Default: matrix cores from 17 antennas, vector ALU below; both paths
+    of the default agree with the explicit variants bit for bit."""
+    import torch
+    assert qc.xengine_variant() == 0
+    for n_ant, expect in ((16, 1), (17, 2), (32, 2)):
+        N, n_spec, spd = 256, 32, 32
+        X = pfb.channelize(_stream(n_ant, N * n_spec, seed=n_ant), N, 4).astype(np.complex64)
+        v = torch.from_numpy(X).cuda()
+        a = qc.xcorrelate_chan(v, "f32", None, n_ant, n_spec, N // 2, spd).cpu().numpy()
+        try:
+            qc.xengine_variant(expect)
+            b = qc.xcorrelate_chan(v, "f32", None, n_ant, n_spec, N // 2, spd).cpu().numpy()
+        finally:
+            qc.xengine_variant(0)
+        assert np.array_equal(a, b), n_ant

@@ -159,3 +159,25 @@ def test_mfma_rejects_unsupported(qc):
     scale = torch.ones(40, device="cuda")
     with pytest.raises(qc.QCError):
         qc.xcorrelate_chan(v, "f16", scale, 40, 8, 64, 8)     # 40 antennas > 32
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("N,n_samp", [(16, 16 * 81), (64, (1 << 20) + 64 * 65)])
+def test_scales_strided_and_past_prefix(qc, prec, N, n_samp):
+    """Scales over a strided view (row stride a multiple of 4 but not of
+    16), with a loud stretch at the end of the stream: it counts when the
+    stream is shorter than the 2^20-sample prefix the scales are taken
+    from, and is ignored when it lies past that prefix."""
+    import torch
+    n_ant, P = 3, 4
+    W = n_samp + 12
+    rng = np.random.default_rng(n_samp)
+    full = rng.integers(-40, 41, (n_ant, W)).astype(np.int8)
+    full[1] //= 3                                  # different powers per antenna
+    full[2, n_samp - 64:n_samp] = 127
+    x = full[:, :n_samp]
+    xd = torch.from_numpy(full).cuda()[:, :n_samp]
+    assert xd.stride(0) == W
+    _, scale = qc.pfb_channelize(xd, N, P, out_prec=prec)
+    s_ref = quant.pow2_scales(x, pfb.hann_sinc_taps(N, P), QNAME[prec])
+    assert np.array_equal(scale.cpu().numpy().astype(np.float64), s_ref)
