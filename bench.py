@@ -63,13 +63,27 @@ def fx_flops(n_ant, n_samp, n_fft, n_taps, n_spec_used):
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "fx_fused_ring_realtime_4ant_n4096.md")
-KERNEL_SOURCES = ("paper_2604_20640_amd/csrc/qc_fx.hip", "paper_2604_20640_amd/csrc/qc_fft.h")
+# The fused kernels' source: their section of qc_fx.hip and the FFT header.
+FUSED_SECTION = ("paper_2604_20640_amd/csrc/qc_fx.hip", "// ==== fused F+X kernels ====",
+                 "// ==== end of fused F+X kernels ====")
+FFT_HEADER = "paper_2604_20640_amd/csrc/qc_fft.h"
+
+
+def fused_source_sha256():
+    """SHA-256 of the fused kernels' source text (section, then FFT header)."""
+    import hashlib
+    path, begin, end = FUSED_SECTION
+    text = open(os.path.join(ROOT, path), "rb").read()
+    i, j = text.index(begin.encode()), text.index(end.encode())
+    h = hashlib.sha256()
+    h.update(text[i:j])
+    h.update(open(os.path.join(ROOT, FFT_HEADER), "rb").read())
+    return h.hexdigest()
 
 
 def measured_traffic():
     """HBM bytes per fused launch from the committed FETCH_SIZE/WRITE_SIZE
     summary, or None when the kernel sources changed since it was taken."""
-    import hashlib
     if not os.path.exists(TRAFFIC_PROFILE):
         return None
     fields = {}
@@ -77,10 +91,7 @@ def measured_traffic():
         if ":" in line and line.split(":")[0] in ("hbm_bytes_per_launch", "kernel_sources_sha256"):
             k, v = line.split(":", 1)
             fields[k] = v.strip()
-    h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
-        h.update(open(os.path.join(ROOT, p), "rb").read())
-    if fields.get("kernel_sources_sha256") != h.hexdigest() or "hbm_bytes_per_launch" not in fields:
+    if fields.get("kernel_sources_sha256") != fused_source_sha256() or "hbm_bytes_per_launch" not in fields:
         return None
     return int(fields["hbm_bytes_per_launch"])
 

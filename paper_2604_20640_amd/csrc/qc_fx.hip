@@ -24,6 +24,8 @@
 
 namespace qc {
 
+// ==== fused F+X kernels ====================================================
+
 // ---------------------------------------------------------------------------
 // int8 block loads (4 consecutive samples as one dword)
 // ---------------------------------------------------------------------------
@@ -548,6 +550,8 @@ hipError_t launch_fused(const FxArgs& a, int64_t n_dump, int64_t spd, int64_t cp
 #undef QC_CASE
   return hipErrorInvalidValue;
 }
+
+// ==== end of fused F+X kernels =============================================
 
 // ---------------------------------------------------------------------------
 // Fixed-order reduction of partials.
