@@ -724,16 +724,27 @@ channelize_kernel(const int8_t* __restrict__ x, int64_t ld_x, int n_ant, int64_t
 }
 
 // Ring variant of the F-engine: the fused ring tile's FIR and transform
-// (register ring of the last P blocks, next block prefetched, half of the
-// symmetric prototype and per-pass twiddles in LDS) for a group of four
-// antennas (two packed transforms), writing the separated spectra out
-// instead of correlating them.  Block = (antenna group, run of spectra).
-template <int N, int V, int P, int PREC>
-__global__ void __launch_bounds__((FusedCfg<N, 4, 1, V, false, 0>::NT))
+// (register ring of the last P blocks, next block prefetched, taps in
+// registers, per-pass twiddles in LDS) for a group of NA antennas (NA/2
+// packed transforms: four antennas up to N = 4096, two at N = 8192),
+// writing the separated spectra out instead of correlating them.
+// Block = (antenna group, run of spectra).  The half of the symmetric
+// prototype the threads pick their taps from is staged once through the
+// transform buffer, so LDS holds only the buffer and the twiddles.
+template <int N, int NA, int V, int P>
+struct ChanRingCfg {
+  using C = FusedCfg<N, NA, 1, V, false, 0>;
+  static constexpr int TAPS = P * N / 2;  // floats: half of a symmetric prototype
+  static_assert(sizeof(float) * TAPS <= sizeof(float2) * C::LDS, "taps staged in the transform buffer");
+  static constexpr size_t LDS_BYTES = sizeof(float2) * (C::LDS + N);  // transforms, twiddles
+};
+
+template <int N, int NA, int V, int P, int PREC>
+__global__ void __launch_bounds__((FusedCfg<N, NA, 1, V, false, 0>::NT))
 chan_ring_kernel(const int8_t* __restrict__ x, int64_t ld_x, int n_ant, const int8_t* __restrict__ hist,
                  const float* __restrict__ taps, const float2* __restrict__ tw, int64_t n_spec,
                  int64_t spb, int64_t chunks, const float* __restrict__ scale, void* __restrict__ out) {
-  using C = FusedCfg<N, 4, 1, V, false, 0>;
+  using C = FusedCfg<N, NA, 1, V, false, 0>;
   using F = Fft<N, C::NT, V, false, false, true>;
   constexpr int G = C::CHUNKS;
   constexpr int L = P * N;
@@ -741,11 +752,11 @@ chan_ring_kernel(const int8_t* __restrict__ x, int64_t ld_x, int n_ant, const in
   extern __shared__ float2 buf[];
   float2* b0 = buf;
   float2* twl = buf + C::LDS;
-  float4* tl = reinterpret_cast<float4*>(twl + N);
+  float4* tl = reinterpret_cast<float4*>(b0);  // taps, until they are in registers
   const int tid = threadIdx.x;
   const int grp = (int)(blockIdx.x / chunks);
   const int64_t chk = blockIdx.x % chunks;
-  const int a_base = 4 * grp;
+  const int a_base = NA * grp;
   const int64_t m_lo = chk * spb;
   const int64_t m_hi = m_lo + spb < n_spec ? m_lo + spb : n_spec;
 
@@ -773,9 +784,9 @@ chan_ring_kernel(const int8_t* __restrict__ x, int64_t ld_x, int n_ant, const in
       ring[q][g][0] = load_blk(g, 0, blk);
       ring[q][g][1] = load_blk(g, 1, blk);
     }
-  float hs[4];
+  float hs[NA];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
+  for (int i = 0; i < NA; ++i) {
     const int a = a_base + i;
     hs[i] = 0.5f * ((PREC != 0 && a < n_ant) ? scale[a] : 1.f);
   }
@@ -792,6 +803,7 @@ chan_ring_kernel(const int8_t* __restrict__ x, int64_t ld_x, int n_ant, const in
         hr[g][q] = make_float4(r.w, r.z, r.y, r.x);
       }
     }
+  __syncthreads();  // the transform buffer is free for the FIR output
 
   for (int64_t m = m_lo; m < m_hi; ++m) {
     uint32_t nxt[G][2];
@@ -828,7 +840,7 @@ chan_ring_kernel(const int8_t* __restrict__ x, int64_t ld_x, int n_ant, const in
       if (NCH % C::NT == 0 || k < NCH) {
         const int kn = (N - k) & (N - 1);
 #pragma unroll
-        for (int p = 0; p < 2; ++p) {
+        for (int p = 0; p < C::NP; ++p) {
           float2 ya, yb;
           separate(b0[lds_pad(p * N + k)], b0[lds_pad(p * N + kn)], ya, yb);
 #pragma unroll
@@ -868,36 +880,40 @@ chan_ring_kernel(const int8_t* __restrict__ x, int64_t ld_x, int n_ant, const in
   }
 }
 
-template <int N, int PREC>
+template <int N, int NA, int PREC>
 static hipError_t launch_chan_ring_p(const FxArgs& a, void* out, const float* scale, hipStream_t s) {
   constexpr int V = 16;
-  using RC = RingCfg<N, 4, V, 4>;
-  using C = FusedCfg<N, 4, 1, V, false, 0>;
+  using RC = ChanRingCfg<N, NA, V, 4>;
+  using C = FusedCfg<N, NA, 1, V, false, 0>;
   static_assert(RC::LDS_BYTES <= 160 * 1024, "channelize ring: LDS");
   const int64_t n_spec = a.n_samp / N;
-  const int groups = (a.n_ant + 3) / 4;
-  // runs of at least 16 spectra (the ring reloads P-1 blocks per run),
-  // about 2048 blocks in total
-  int64_t spb = (n_spec * groups + 2047) / 2048;
+  const int groups = (a.n_ant + NA - 1) / NA;
+  // runs of at least 16 spectra (the ring reloads P-1 blocks per run and
+  // each workgroup rebuilds its twiddle tables), about 512 workgroups in
+  // total: two rounds of one resident workgroup per CU
+  int64_t spb = (n_spec * groups + 511) / 512;
   if (spb < 16) spb = 16;
   const int64_t chunks = (n_spec + spb - 1) / spb;
   if ((int64_t)groups * chunks > 0x7fffffffLL) return hipErrorInvalidValue;
-  const void* k = reinterpret_cast<const void*>(chan_ring_kernel<N, V, 4, PREC>);
+  const void* k = reinterpret_cast<const void*>(chan_ring_kernel<N, NA, V, 4, PREC>);
   hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)RC::LDS_BYTES);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((chan_ring_kernel<N, V, 4, PREC>), dim3((unsigned)(groups * chunks)), dim3(C::NT),
+  hipLaunchKernelGGL((chan_ring_kernel<N, NA, V, 4, PREC>), dim3((unsigned)(groups * chunks)), dim3(C::NT),
                      RC::LDS_BYTES, s, a.x, a.ld_x, a.n_ant, a.hist, a.taps, a.tw, n_spec, spb, chunks, scale,
                      out);
   return hipGetLastError();
 }
 
+// Four antennas (two packed transforms) per workgroup up to N = 4096; at
+// N = 8192 two antennas, so one transform and the twiddles fit in LDS.
 template <int N>
 static hipError_t launch_chan_ring(const FxArgs& a, int prec, void* out, const float* scale, hipStream_t s) {
+  constexpr int NA = N >= 8192 ? 2 : 4;
   switch (prec) {
-    case 0: return launch_chan_ring_p<N, 0>(a, out, scale, s);
-    case 1: return launch_chan_ring_p<N, 1>(a, out, scale, s);
-    case 2: return launch_chan_ring_p<N, 2>(a, out, scale, s);
-    default: return launch_chan_ring_p<N, 3>(a, out, scale, s);
+    case 0: return launch_chan_ring_p<N, NA, 0>(a, out, scale, s);
+    case 1: return launch_chan_ring_p<N, NA, 1>(a, out, scale, s);
+    case 2: return launch_chan_ring_p<N, NA, 2>(a, out, scale, s);
+    default: return launch_chan_ring_p<N, NA, 3>(a, out, scale, s);
   }
 }
 
@@ -948,6 +964,7 @@ hipError_t launch_channelize(const FxArgs& a, int prec, void* out, const float* 
       case 1024: return launch_chan_ring<1024>(a, prec, out, scale, s);
       case 2048: return launch_chan_ring<2048>(a, prec, out, scale, s);
       case 4096: return launch_chan_ring<4096>(a, prec, out, scale, s);
+      case 8192: return launch_chan_ring<8192>(a, prec, out, scale, s);
       default: break;
     }
   }

@@ -195,7 +195,10 @@ def test_autotune_picks_a_tile(qc):
         qc.fx_set_tile(1024, 4, 99)
 
 
-RING_CHAN = [(4096, 5, 20), (2048, 9, 18), (1024, 4, 33), (4096, 32, 6), (1024, 1, 17)]
+# N = 8192 runs two antennas (one packed transform) per workgroup; odd
+# counts leave the second half of the last transform empty.
+RING_CHAN = [(4096, 5, 20), (2048, 9, 18), (1024, 4, 33), (4096, 32, 6), (1024, 1, 17),
+             (8192, 3, 9), (8192, 2, 12), (8192, 1, 5)]
 
 
 @pytest.mark.parametrize("N,n_ant,n_spec", RING_CHAN)
@@ -222,9 +225,10 @@ def test_channelize_ring_matches_oracle(qc, N, n_ant, n_spec):
 
 
 @pytest.mark.parametrize("prec", ["f32", "f16", "bf16", "fp8"])
-def test_channelize_variants_agree(qc, prec):
+@pytest.mark.parametrize("N,n_ant,n_spec", [(4096, 6, 12), (8192, 5, 10)])
+def test_channelize_variants_agree(qc, prec, N, n_ant, n_spec):
     import torch
-    N, n_ant, n_spec, P = 4096, 6, 12, 4
+    P = 4
     xd = torch.from_numpy(_stream(n_ant, N * n_spec, seed=99)).cuda()
     try:
         qc.channelize_variant(1)
