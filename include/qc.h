@@ -327,12 +327,13 @@ int32_t qc_channelize_get_variant(void);
 
 /* Float32 X-engine kernel choice (process-wide; not thread-safe against
  * concurrent calls).  The matrix-core kernel forms each channel's Gram
- * matrix on 32 x 32 tiles with v_mfma_f32_32x32x2_f32 (needs n_ant <= 32,
- * n_chan % 16 == 0 and v 16-byte aligned); the vector-ALU kernel takes
- * 4 x 4 antenna blocks per thread and serves every shape.  0 (default):
- * matrix cores for 17..32 antennas, where its fixed 32 x 32 cost beats the
- * block pairs; 1: always the vector ALU; 2: matrix cores wherever
- * supported.  Both sum the same products in float32 (Sec. 4.1 eq. 1); the
+ * matrix on 16 x 16 tiles with v_mfma_f32_16x16x4_f32 up to 16 antennas
+ * and on 32 x 32 tiles with v_mfma_f32_32x32x2_f32 above (needs
+ * n_ant <= 32, n_chan % 16 == 0 and v 16-byte aligned); the vector-ALU
+ * kernel takes 4 x 4 antenna blocks per thread and serves every shape.
+ * 0 (default): matrix cores for 5..32 antennas, where the fixed tile cost
+ * beats the block pairs; 1: always the vector ALU; 2: matrix cores
+ * wherever supported.  Both sum the same products in float32 (Sec. 4.1 eq. 1); the
  * choice affects rounding order and speed only.  Used by
  * qc_xcorrelate_chan (QC_F32), the two-pass path of qc_xcorrelate and
  * batched plans. */

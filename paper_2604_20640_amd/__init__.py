@@ -317,7 +317,7 @@ def channelize_variant(v=None):
 
 def xengine_variant(v=None):
     """Get (and with v, set) the float32 X-engine kernel choice: 0 matrix cores
-    for 17..32 antennas, 1 vector ALU, 2 matrix cores wherever supported."""
+    for 5..32 antennas, 1 vector ALU, 2 matrix cores wherever supported."""
     if v is not None:
         _check(lib().qc_xengine_set_variant(int(v)), "qc_xengine_set_variant")
     return int(lib().qc_xengine_get_variant())

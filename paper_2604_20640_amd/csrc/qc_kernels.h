@@ -54,12 +54,13 @@ hipError_t launch_hist_copy(const int8_t* x, int64_t ld_x, int n_ant, int64_t n_
                             const int8_t* hist, int64_t keep, int8_t* hist_out, hipStream_t s);
 
 // X-engine (float32) over v[n_ant][n_spec][n_chan] cfloat, on the matrix
-// cores (32x32 tiles; n_ant <= 32, n_chan % 16 == 0, v 16-byte aligned) or
+// cores (16x16 tiles up to 16 antennas, 32x32 above; n_ant <= 32,
+// n_chan % 16 == 0, v 16-byte aligned) or
 // the vector ALU.  Variant: 0 = matrix cores for XEF_MFMA_MIN_ANT..32
 // antennas, 1 = always the vector ALU, 2 = matrix cores wherever supported.
 // xeng_f32_ksplit sizes the partial buffer for the kernel that
 // launch_xeng_f32 picks for a 16-byte aligned v.
-constexpr int XEF_MFMA_MIN_ANT = 17;
+constexpr int XEF_MFMA_MIN_ANT = 5;
 void set_xeng_f32_variant(int v);
 int get_xeng_f32_variant();
 bool xeng_f32_use_mfma(int n_ant, int n_chan, const void* v);

@@ -12,7 +12,9 @@
 // Precisions:
 //   * float32 (complex64 input): v_mfma_f32_32x32x2_f32, three products per
 //     pair of spectra: A A^T + B B^T into Re, P = B A^T into P; at the end
-//     Im = P - P^T (AB^T = (BA^T)^T), the transpose taken through LDS;
+//     Im = P - P^T (AB^T = (BA^T)^T), the transpose taken through LDS.  Up
+//     to 16 antennas the same on 16 x 16 tiles with v_mfma_f32_16x16x4_f32
+//     (a quarter of the matrix work);
 //   * FP16 / BF16 / OCP E4M3 (power-of-two per-antenna scales s_a):
 //     v_mfma_f32_32x32x16_{f16,bf16,fp8_fp8}, four products per 16 spectra
 //     (the subtraction uses a sign-flipped A), FP32 accumulation; the result
@@ -36,6 +38,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "qc_kernels.h"
 
 namespace qc {
@@ -45,6 +49,7 @@ namespace {
 typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float float16_t __attribute__((ext_vector_type(16)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) void lds_void_t;
 
 constexpr int XM_NT = 512;              // 8 waves
@@ -63,28 +68,42 @@ constexpr int XM_STAGE = xm_max(xm_max(XM_NCHUNK * XM_CHUNK, XM_HALF * (32 * 8 +
                                 XM_PTILES + XM_HALF * (16 * 8 + 8));
 constexpr int XM_CPW = XM_NCHUNK / (XM_NT / 64);  // chunks each wave loads per stage
 
-// Per precision: channels per workgroup, bytes per complex sample,
-// spectra per stage.
+// Kernel codes: 0 float32 on 32 x 32 tiles, 1 FP16, 2 BF16, 3 E4M3, 4
+// float32 on 16 x 16 tiles (v_mfma_f32_16x16x4_f32, up to 16 antennas).
+// Per code: antennas of the tile, channels per workgroup, bytes per complex
+// sample, spectra per stage, accumulator floats per lane.
 template <int PREC>
 struct XmCfg {
-  static constexpr int CB = PREC == 0 ? 16 : 32;
-  static constexpr int EB = PREC == 0 ? 8 : PREC == 3 ? 2 : 4;
-  static constexpr int KS = PREC == 3 ? 32 : 16;
+  static constexpr bool F32 = PREC == 0 || PREC == 4;
+  static constexpr int TA = PREC == 4 ? 16 : 32;
+  static constexpr int CB = F32 ? 16 : 32;
+  static constexpr int EB = F32 ? 8 : PREC == 3 ? 2 : 4;
+  static constexpr int KS = (PREC == 3 || PREC == 4) ? 32 : 16;
+  static constexpr int ACC = TA == 32 ? 16 : 4;
   static constexpr int RB = CB * EB;        // bytes of one (antenna, spectrum) row
   static constexpr int GPR = RB / 16;       // 16-byte granules per row
-  static_assert(XM_NA * KS * RB == XM_NCHUNK * 1024, "stage = 64 chunks of 1 KiB");
+  static_assert(TA * KS * RB == XM_NCHUNK * 1024, "stage = 64 chunks of 1 KiB");
 };
 
-// Row r of chunk j holds antenna j % 32 at spectrum offset row_spec(j, r):
-//   float32:    chunk half h = j/32 holds spectra 2r + h   (k-slot h of k-step r)
-//   FP16/BF16:  chunk half h holds spectra 8h + r          (lane half h's 8 slots)
-//   E4M3:       chunk half g holds spectra 16g + r         (k-group g of the stage)
+// Row r of chunk j holds antenna j % TA at spectrum offset row_spec(j, r):
+//   float32, 32 x 32: chunk half h = j/32 holds spectra 2r + h  (k-slot h of k-step r)
+//   float32, 16 x 16: chunk quarter h = j/16 holds spectra 4r + h
+//   FP16/BF16:        chunk half h holds spectra 8h + r          (lane half h's 8 slots)
+//   E4M3:             chunk half g holds spectra 16g + r         (k-group g of the stage)
 template <int PREC>
 __device__ __forceinline__ int row_spec(int j, int r) {
+  if constexpr (PREC == 4) return 4 * r + (j >> 4);
   const int h = j >> 5;
   if constexpr (PREC == 0) return 2 * r + h;
   else if constexpr (PREC == 3) return 16 * h + r;
   else return 8 * h + r;
+}
+
+// Gram row of accumulator slot r in lane l (its column is l % TA).
+template <int TA>
+__device__ __forceinline__ int acc_row(int l, int r) {
+  if constexpr (TA == 32) return 8 * (r >> 2) + 4 * (l >> 5) + (r & 3);
+  else return 4 * (l >> 4) + r;
 }
 
 __device__ __forceinline__ void wait_vmem_all() {
@@ -198,12 +217,13 @@ xeng_mfma_kernel(const void* __restrict__ vin, const float* __restrict__ scale, 
   const int64_t row_pitch = (int64_t)n_chan * C::EB;
 
   // float32: per wave two channels, Re and P; otherwise four channels, Re and Im
-  constexpr int NCW = PREC == 0 ? 2 : 4;
-  float16_t accR[NCW], accI[NCW];
+  constexpr int NCW = C::F32 ? 2 : 4;
+  using Acc = typename std::conditional<C::TA == 32, float16_t, float4_t>::type;
+  Acc accR[NCW], accI[NCW];
 #pragma unroll
   for (int c = 0; c < NCW; ++c)
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
+    for (int r = 0; r < C::ACC; ++r) {
       accR[c][r] = 0.f;
       accI[c][r] = 0.f;
     }
@@ -220,7 +240,7 @@ xeng_mfma_kernel(const void* __restrict__ vin, const float* __restrict__ scale, 
 #pragma unroll
     for (int u = 0; u < XM_CPW; ++u) {
       const int j = wave * XM_CPW + u;
-      const int a = j & 31;
+      const int a = j & (C::TA - 1);
       if (a < n_ant) {
         int rs = row_spec<PREC>(j, r);
         rs = rs < lim ? rs : lim;
@@ -239,7 +259,20 @@ xeng_mfma_kernel(const void* __restrict__ vin, const float* __restrict__ scale, 
   };
   const int ra = lane & 31, rh = lane >> 5;
   auto compute = [&](const uint8_t* cur) {
-    if constexpr (PREC == 0) {
+    if constexpr (PREC == 4) {
+      // lane (antenna l % 16, k-slot l / 16); k-step t covers spectra 4t..4t+3
+      const uint8_t* p = cur + ((lane >> 4) * 16 + (lane & 15)) * XM_CHUNK + wave * 16;
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const float4 q = *reinterpret_cast<const float4*>(p + t * 128);
+        accR[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(q.x, q.x, accR[0], 0, 0, 0);
+        accR[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(q.y, q.y, accR[0], 0, 0, 0);
+        accI[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(q.y, q.x, accI[0], 0, 0, 0);
+        accR[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(q.z, q.z, accR[1], 0, 0, 0);
+        accR[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(q.w, q.w, accR[1], 0, 0, 0);
+        accI[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(q.w, q.z, accI[1], 0, 0, 0);
+      }
+    } else if constexpr (PREC == 0) {
       const uint8_t* p = cur + (rh * 32 + ra) * XM_CHUNK + wave * 16;
 #pragma unroll
       for (int t = 0; t < 8; ++t) {
@@ -304,35 +337,36 @@ xeng_mfma_kernel(const void* __restrict__ vin, const float* __restrict__ scale, 
   // partials are tile-major, [dz][n_chan / CB][nb][CB].
   const int nb = n_ant * (n_ant + 1) / 2;
   float2* out = part + dz * (int64_t)nb * n_chan + (int64_t)cb * nb * C::CB;
-  const int j = lane & 31;
+  const int j = lane & (C::TA - 1);
   constexpr int PITCH = C::CB * 8 + 8;                  // bytes per staged row
-  constexpr int TOFF = PREC == 0 ? XM_PTILES : 0;       // float32: P tiles first
+  constexpr int TOFF = C::F32 ? XM_PTILES : 0;          // float32: P tiles first
   auto trow = [&](int b) -> float2* {
     uint8_t* base = b < XM_HALF ? st0 : st1;
     return reinterpret_cast<float2*>(base + TOFF + (b < XM_HALF ? b : b - XM_HALF) * PITCH);
   };
   __syncthreads();  // all waves are done reading the stages
-  if constexpr (PREC == 0) {
+  if constexpr (C::F32) {
     // Im = P - P^T: every wave puts its P tiles in LDS (channel 0 in st0,
-    // channel 1 in st1; [wave][i][j] with a padded row of 33 floats)
+    // channel 1 in st1; [wave][i][j] with a padded row of TA + 1 floats)
+    constexpr int PP = C::TA + 1;
     float* pt0 = reinterpret_cast<float*>(st0) + wave * XM_PT;
     float* pt1 = reinterpret_cast<float*>(st1) + wave * XM_PT;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int i = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-      pt0[i * 33 + j] = accI[0][r];
-      pt1[i * 33 + j] = accI[1][r];
+    for (int r = 0; r < C::ACC; ++r) {
+      const int i = acc_row<C::TA>(lane, r);
+      pt0[i * PP + j] = accI[0][r];
+      pt1[i * PP + j] = accI[1][r];
     }
     __syncthreads();
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
       const float* pt = c ? pt1 : pt0;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int i = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+      for (int r = 0; r < C::ACC; ++r) {
+        const int i = acc_row<C::TA>(lane, r);
         if (i <= j && j < n_ant) {
           const int b = i * n_ant - i * (i - 1) / 2 + (j - i);
-          const float im = i == j ? 0.f : accI[c][r] - pt[j * 33 + i];
+          const float im = i == j ? 0.f : accI[c][r] - pt[j * PP + i];
           trow(b)[2 * wave + c] = make_float2(accR[c][r], im);
         }
       }
@@ -343,8 +377,8 @@ xeng_mfma_kernel(const void* __restrict__ vin, const float* __restrict__ scale, 
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int i = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+      for (int r = 0; r < C::ACC; ++r) {
+        const int i = acc_row<C::TA>(lane, r);
         if (i <= j && j < n_ant) {
           const float inv = (1.0f / scale[i]) * inv_j;
           const int b = i * n_ant - i * (i - 1) / 2 + (j - i);
@@ -359,14 +393,15 @@ xeng_mfma_kernel(const void* __restrict__ vin, const float* __restrict__ scale, 
 
 namespace {
 
-constexpr int xm_cb(int prec) { return prec == 0 ? 16 : 32; }
-constexpr int xm_ks(int prec) { return prec == 3 ? 32 : 16; }
+constexpr int xm_cb(int prec) { return prec == 0 || prec == 4 ? 16 : 32; }
+constexpr int xm_ks(int prec) { return prec == 3 || prec == 4 ? 32 : 16; }
+constexpr int xm_ta(int prec) { return prec == 4 ? 16 : XM_NA; }
 
 // Splits of each dump's stages so that the grid holds about one workgroup
 // per CU (one is resident at a time: 136 KiB of LDS) with at least four
 // stages each; fewer splits also mean fewer partials to reduce.
 int64_t xm_ksplit(int prec, int n_ant, int64_t spd, int n_chan, int64_t n_dump) {
-  if (n_ant < 1 || n_ant > XM_NA || n_chan % xm_cb(prec) != 0) return 0;
+  if (n_ant < 1 || n_ant > xm_ta(prec) || n_chan % xm_cb(prec) != 0) return 0;
   const int64_t blocks = (int64_t)(n_chan / xm_cb(prec)) * n_dump;
   int64_t ks = (256 + blocks - 1) / blocks;
   const int64_t nst = (spd + xm_ks(prec) - 1) / xm_ks(prec);
@@ -409,13 +444,18 @@ bool xeng_f32_mfma_supported(int n_ant, int n_chan, const void* v) {
   return n_ant >= 1 && n_ant <= XM_NA && n_chan % 16 == 0 && (reinterpret_cast<uintptr_t>(v) & 15u) == 0;
 }
 
+// float32: 16 x 16 tiles (a quarter of the matrix work) up to 16 antennas
+static int xm_f32_code(int n_ant) { return n_ant <= 16 ? 4 : 0; }
+
 int64_t xeng_f32_mfma_ksplit(int n_ant, int64_t spd, int n_chan, int64_t n_dump) {
-  return xm_ksplit(0, n_ant, spd, n_chan, n_dump);
+  return xm_ksplit(xm_f32_code(n_ant), n_ant, spd, n_chan, n_dump);
 }
 
 hipError_t launch_xeng_f32_mfma(const float2* v, int n_ant, int64_t n_spec, int n_chan, int64_t spd,
                                 int64_t n_dump, int64_t ksplit, float2* part, hipStream_t s) {
   if (!xeng_f32_mfma_supported(n_ant, n_chan, v)) return hipErrorInvalidValue;
+  if (xm_f32_code(n_ant) == 4)
+    return launch_xm_t<4>(v, nullptr, n_ant, n_spec, n_chan, spd, n_dump, ksplit, part, s);
   return launch_xm_t<0>(v, nullptr, n_ant, n_spec, n_chan, spd, n_dump, ksplit, part, s);
 }
 

@@ -250,8 +250,8 @@ def test_channelize_variants_agree(qc, prec, N, n_ant, n_spec):
 
 # Float32 X-engine on both kernels over the same complex64 spectra: the
 # vector-ALU kernel (variant 1) and the matrix-core kernel (variant 2; it
-# serves n_ant <= 32 with n_chan % 16 == 0, other shapes fall back to the
-# vector ALU).  Ragged stages (spec_per_dump not a multiple of the 16
+# serves n_ant <= 32 with n_chan % 16 == 0 on 32 x 32 tiles, or 16 x 16
+# tiles up to 16 antennas; other shapes fall back to the vector ALU).  Ragged stages (spec_per_dump not a multiple of the 16
 # spectra one stage holds), trailing spectra past the last dump, antenna
 # counts from 1 to 32 and several dumps.  With the inputs exact, the only
 # error is the float32 summation: bar 2e-6 of sqrt(V_ii V_jj).
@@ -263,6 +263,9 @@ XENG_F32 = [
     (32, 2048, 40, 40),
     (1, 32, 33, 11),
     (31, 64, 48, 17),
+    (16, 256, 70, 35),    # up to 16 antennas the matrix cores use 16 x 16 tiles
+    (12, 128, 64, 64),
+    (9, 512, 40, 33),
     (3, 16, 50, 7),       # 8 channels: vector ALU under either variant
 ]
 
@@ -288,11 +291,11 @@ def test_xengine_f32_kernels_match_oracle(qc, variant, n_ant, N, n_spec, spd):
 
 
 def test_xengine_f32_default_variant(qc):
-    """Default: matrix cores from 17 antennas, vector ALU below; both paths
+    """Default: matrix cores from 5 antennas, vector ALU below; both paths
     of the default agree with the explicit variants bit for bit."""
     import torch
     assert qc.xengine_variant() == 0
-    for n_ant, expect in ((16, 1), (17, 2), (32, 2)):
+    for n_ant, expect in ((4, 1), (5, 2), (16, 2), (17, 2), (32, 2)):
         N, n_spec, spd = 256, 32, 32
         X = pfb.channelize(_stream(n_ant, N * n_spec, seed=n_ant), N, 4).astype(np.complex64)
         v = torch.from_numpy(X).cuda()
