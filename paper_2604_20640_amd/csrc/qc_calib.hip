@@ -5,11 +5,17 @@
 // statistics found by radix selection (most significant digit first) over
 // the bit patterns of non-negative floats, whose unsigned order equals their
 // numeric order: float32 amplitudes and float64 deviations |A - median|.
-// Even counts average the two middle order statistics; the upper one comes
-// from the lower by one counting pass.  One workgroup
-// handles one population; its amplitudes are cached in LDS when they fit
-// (1024 threads and 11-bit digits for large populations, one wave and 8-bit
-// digits for small ones).
+// The key range comes for free (amplitudes: a min/max taken while they are
+// loaded; deviations: [0, the larger deviation of the extreme amplitudes]),
+// so bits shared by the whole range need no pass.  Once the digit holding
+// the wanted rank contains at most SEL_CAND keys, one pass gathers them and
+// one wave ranks them.  Even counts average the two middle order
+// statistics; the upper one is read off the same candidates when it lies
+// among them (else one counting pass finds it).  One workgroup handles one
+// population (1024 threads and 11-bit digits for large populations, one
+// wave and 8-bit digits for small ones); large populations get their
+// amplitudes formed once by a whole-GPU pass and cached in LDS when they
+// fit.
 //
 // Delay/phase application (Sec. 4.1 step 2 and eq. 1; Sec. 7 delay and phase
 // corrections): V_ij[k] *= exp(+i [2 pi f_k (tau_i - tau_j) + phi_i - phi_j]).
@@ -32,6 +38,13 @@ namespace {
 struct Pop {
   int64_t base, count, inner_n, s_inner, s_outer;
   __device__ __forceinline__ int64_t off(int64_t i) const {
+    // 32-bit division when the index and the inner extent fit (every
+    // population but the very largest): a fraction of the 64-bit sequence
+    if (i <= 0x7fffffffLL && inner_n <= 0x7fffffffLL) {
+      const uint32_t q = (uint32_t)i / (uint32_t)inner_n;
+      const uint32_t r = (uint32_t)i - q * (uint32_t)inner_n;
+      return base + (int64_t)q * s_outer + (int64_t)r * s_inner;
+    }
     return base + (i / inner_n) * s_outer + (i % inner_n) * s_inner;
   }
 };
@@ -99,43 +112,37 @@ __device__ __forceinline__ void find_digit(const unsigned* hist, int64_t kk, uns
   __syncthreads();
 }
 
+// Keys of a selection that are still candidates once few remain: they are
+// gathered and ranked by one wave instead of further histogram passes.
+constexpr int SEL_CAND = 64;
+
+struct SelScratch {
+  unsigned* hist;            // 2^DB bins
+  unsigned* wsum;            // NT / 64
+  unsigned long long* sh;    // 4
+  unsigned long long* red;   // 2 * NT / 64
+  unsigned long long* cand;  // SEL_CAND
+  unsigned* ncand;           // 1
+};
+
 // k-th smallest (0-based) key of the population, most significant digit
-// first.  KEY(i) returns the unsigned key of element i; W is the key width.
+// first, for keys known to lie in [kmin, kmax].  KEY(i) returns the unsigned
+// key of element i.  Bits that every key in the range shares need no pass.
+// When the digit that holds rank k contains at most SEL_CAND keys, one pass
+// gathers them and one wave ranks them.  With want2, the key of rank k+1 is
+// also returned (has2) when it lies among the same candidates.
 template <int NT, int DB, typename K, typename KeyFn>
-__device__ K radix_select(int64_t count, int64_t k, KeyFn key, unsigned* hist, unsigned* wsum,
-                          unsigned long long* sh, unsigned long long* red) {
+__device__ K radix_select(int64_t count, int64_t k, K kmin, K kmax, KeyFn key, const SelScratch& sc,
+                          bool want2, K& v2, bool& has2) {
   constexpr int W = (int)sizeof(K) * 8;
   constexpr int NBINS = 1 << DB;
-  // the leading bits that every key shares need no histogram pass (and
-  // would send every count of the first pass to one bin): start below them
-  K kmin = ~(K)0, kmax = 0;
-  for (int64_t i = threadIdx.x; i < count; i += NT) {
-    const K kv = key(i);
-    kmin = kv < kmin ? kv : kmin;
-    kmax = kv > kmax ? kv : kmax;
-  }
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) {
-    const K a = (K)__shfl_down((unsigned long long)kmin, d);
-    const K b = (K)__shfl_down((unsigned long long)kmax, d);
-    kmin = a < kmin ? a : kmin;
-    kmax = b > kmax ? b : kmax;
-  }
-  if ((threadIdx.x & 63) == 0) {
-    red[2 * (threadIdx.x >> 6)] = (unsigned long long)kmin;
-    red[2 * (threadIdx.x >> 6) + 1] = (unsigned long long)kmax;
-  }
-  __syncthreads();
-  kmin = ~(K)0;
-  kmax = 0;
-  for (int w = 0; w < NT / 64; ++w) {
-    const K a = (K)red[2 * w], b = (K)red[2 * w + 1];
-    kmin = a < kmin ? a : kmin;
-    kmax = b > kmax ? b : kmax;
-  }
-  __syncthreads();
+  has2 = false;
   const K diff = kmin ^ kmax;
-  if (diff == 0) return kmin;
+  if (diff == 0) {  // every key equals kmin
+    v2 = kmin;
+    has2 = true;
+    return kmin;
+  }
   int top = W - 1;  // highest differing bit
   while (!((diff >> top) & (K)1)) --top;
   const K low = (top + 1 >= W) ? ~(K)0 : (((K)1 << (top + 1)) - 1);
@@ -145,20 +152,80 @@ __device__ K radix_select(int64_t count, int64_t k, KeyFn key, unsigned* hist, u
     const int width = hi >= DB ? DB : hi;
     const int shift = hi - width;
     const K dmask = (K)((1u << width) - 1u);
-    for (int i = threadIdx.x; i < NBINS; i += NT) hist[i] = 0;
+    for (int i = threadIdx.x; i < NBINS; i += NT) sc.hist[i] = 0;
     __syncthreads();
     for (int64_t i = threadIdx.x; i < count; i += NT) {
       const K kv = key(i);
-      if ((kv & mask) == prefix) atomicAdd(&hist[(unsigned)((kv >> shift) & dmask)], 1u);
+      if ((kv & mask) == prefix) atomicAdd(&sc.hist[(unsigned)((kv >> shift) & dmask)], 1u);
     }
     __syncthreads();
-    find_digit<NT, NBINS>(hist, kk, wsum, sh);
-    prefix |= (K)sh[0] << shift;
+    find_digit<NT, NBINS>(sc.hist, kk, sc.wsum, sc.sh);
+    const unsigned digit = (unsigned)sc.sh[0];
+    int64_t c = sc.hist[digit];  // keys sharing the extended prefix
+    prefix |= (K)digit << shift;
     mask |= dmask << shift;
-    kk = (int64_t)sh[1];
+    kk = (int64_t)sc.sh[1];
     __syncthreads();
+    if (shift == 0) {  // all bits resolved: the key is the prefix, repeated c times
+      if (want2 && kk + 1 < c) {
+        v2 = prefix;
+        has2 = true;
+      }
+      return prefix;
+    }
+    if (c <= SEL_CAND) {
+      // With rank k the largest key of its digit, rank k+1 is the smallest
+      // key of the next non-empty digit of this pass: gather that digit
+      // too when both fit.
+      K prefix2 = prefix;
+      int64_t c2 = 0;
+      if (want2 && kk + 1 == c) {
+        if (threadIdx.x == 0) *sc.ncand = NBINS;
+        __syncthreads();
+        for (int b = (int)digit + 1 + threadIdx.x; b < NBINS; b += NT)
+          if (sc.hist[b] != 0u) atomicMin(sc.ncand, (unsigned)b);
+        __syncthreads();
+        const unsigned d2 = *sc.ncand;
+        if (d2 < (unsigned)NBINS && c + (int64_t)sc.hist[d2] <= SEL_CAND) {
+          prefix2 = (prefix & ~(dmask << shift)) | ((K)d2 << shift);
+          c2 = sc.hist[d2];
+        }
+        __syncthreads();
+      }
+      if (threadIdx.x == 0) *sc.ncand = 0;
+      __syncthreads();
+      for (int64_t i = threadIdx.x; i < count; i += NT) {
+        const K kv = key(i);
+        const K km = kv & mask;
+        if (km == prefix || (c2 > 0 && km == prefix2))
+          sc.cand[atomicAdd(sc.ncand, 1u)] = (unsigned long long)kv;
+      }
+      c += c2;
+      __syncthreads();
+      if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        const K mine = lane < c ? (K)sc.cand[lane] : ~(K)0;
+        int64_t less = 0, same = 0;
+        for (int t = 0; t < (int)c; ++t) {
+          const K o = (K)sc.cand[t];
+          less += o < mine;
+          same += o == mine;
+        }
+        // a lane whose key covers rank kk (ties write the same value)
+        if (lane < c && less <= kk && kk < less + same) sc.sh[2] = (unsigned long long)mine;
+        if (lane < c && less <= kk + 1 && kk + 1 < less + same) sc.sh[3] = (unsigned long long)mine;
+      }
+      __syncthreads();
+      const K v1 = (K)sc.sh[2];
+      if (want2 && kk + 1 < c) {
+        v2 = (K)sc.sh[3];
+        has2 = true;
+      }
+      __syncthreads();
+      return v1;
+    }
   }
-  return prefix;
+  return prefix;  // not reached: the last pass has shift == 0
 }
 
 // The order statistic of rank k+1 given the one of rank k (key kk): kk
@@ -219,7 +286,15 @@ __global__ void mad_amp_kernel(const float2* __restrict__ vis, int64_t n_time, i
                                int population, int64_t count, int64_t total, float* __restrict__ amp) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= total) return;
-  const int64_t id = e / count, i = e % count;
+  int64_t id, i;
+  if (total <= 0x7fffffffLL) {  // 32-bit division
+    const uint32_t q = (uint32_t)e / (uint32_t)count;
+    id = q;
+    i = (uint32_t)e - q * (uint32_t)count;
+  } else {
+    id = e / count;
+    i = e % count;
+  }
   amp[e] = amp_f32(vis[make_pop(id, n_time, n_base, n_chan, population).off(i)]);
 }
 
@@ -230,35 +305,110 @@ mad_kernel(const float2* __restrict__ vis, int64_t n_time, int64_t n_base, int n
            double* __restrict__ thresh, double* __restrict__ stats) {
   __shared__ unsigned hist[1 << DB];
   __shared__ unsigned wsum[NT / 64];
-  __shared__ unsigned long long sh[2];
+  __shared__ unsigned long long sh[4];
   __shared__ unsigned long long red[2 * (NT / 64)];
+  __shared__ unsigned long long cand[SEL_CAND];
+  __shared__ unsigned ncand;
   extern __shared__ float acache[];
+  const SelScratch sc{hist, wsum, sh, red, cand, &ncand};
   const int64_t id = blockIdx.x;
   const Pop pop = make_pop(id, n_time, n_base, n_chan, population);
   const int64_t n = pop.count;
   const bool cached = n <= cap;
-  if (cached) {
-    for (int64_t i = threadIdx.x; i < n; i += NT)
-      acache[i] = gamp ? gamp[id * n + i] : amp_f32(vis[pop.off(i)]);
-    __syncthreads();
-  }
   const AmpSrc amp{vis, pop, cached ? acache : (gamp ? gamp + id * n : nullptr)};
+  // one pass: the amplitudes into the LDS cache (when they fit) and the
+  // range of their keys
+  uint32_t amin = ~0u, amax = 0u;
+  {
+    // eight loads in flight per thread before their amplitudes are formed
+    constexpr int U = 8;
+    for (int64_t i0 = threadIdx.x; i0 < n; i0 += (int64_t)U * NT) {
+      float a[U];
+      if (gamp) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int64_t i = i0 + (int64_t)u * NT;
+          a[u] = i < n ? gamp[id * n + i] : 0.f;
+        }
+      } else {
+        float2 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int64_t i = i0 + (int64_t)u * NT;
+          v[u] = i < n ? vis[pop.off(i)] : make_float2(0.f, 0.f);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) a[u] = amp_f32(v[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t i = i0 + (int64_t)u * NT;
+        if (i < n) {
+          if (cached) acache[i] = a[u];
+          const uint32_t kv = __float_as_uint(a[u]);
+          amin = kv < amin ? kv : amin;
+          amax = kv > amax ? kv : amax;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    const uint32_t a = __shfl_down(amin, d), b = __shfl_down(amax, d);
+    amin = a < amin ? a : amin;
+    amax = b > amax ? b : amax;
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[2 * (threadIdx.x >> 6)] = amin;
+    red[2 * (threadIdx.x >> 6) + 1] = amax;
+  }
+  __syncthreads();
+  amin = ~0u;
+  amax = 0u;
+  for (int w = 0; w < NT / 64; ++w) {
+    amin = (uint32_t)red[2 * w] < amin ? (uint32_t)red[2 * w] : amin;
+    amax = (uint32_t)red[2 * w + 1] > amax ? (uint32_t)red[2 * w + 1] : amax;
+  }
+  __syncthreads();
   const int64_t k1 = (n - 1) / 2, k2 = n / 2;
   auto akey = [&](int64_t i) -> uint32_t { return __float_as_uint(amp(i)); };
-  const uint32_t a1 = radix_select<NT, DB, uint32_t>(n, k1, akey, hist, wsum, sh, red);
-  const uint32_t a2 = (k2 == k1) ? a1 : next_rank<NT, uint32_t>(n, k1, a1, akey, red);
+  uint32_t a2;
+  bool has2;
+  const uint32_t a1 = radix_select<NT, DB, uint32_t>(n, k1, amin, amax, akey, sc, k2 != k1, a2, has2);
+  if (k2 == k1) a2 = a1;
+  else if (!has2) a2 = next_rank<NT, uint32_t>(n, k1, a1, akey, red);
   const double med = ((double)__uint_as_float(a1) + (double)__uint_as_float(a2)) / 2.0;
   auto dkey = [&](int64_t i) -> uint64_t {
     return (uint64_t)__double_as_longlong(fabs((double)amp(i) - med));
   };
-  const uint64_t d1 = radix_select<NT, DB, uint64_t>(n, k1, dkey, hist, wsum, sh, red);
-  const uint64_t d2 = (k2 == k1) ? d1 : next_rank<NT, uint64_t>(n, k1, d1, dkey, red);
+  // deviations lie in [0, the larger deviation of the two extreme amplitudes]
+  const double dlo = fabs((double)__uint_as_float(amin) - med);
+  const double dhi = fabs((double)__uint_as_float(amax) - med);
+  const uint64_t dmax = (uint64_t)__double_as_longlong(dlo > dhi ? dlo : dhi);
+  uint64_t d2;
+  const uint64_t d1 = radix_select<NT, DB, uint64_t>(n, k1, 0ull, dmax, dkey, sc, k2 != k1, d2, has2);
+  if (k2 == k1) d2 = d1;
+  else if (!has2) d2 = next_rank<NT, uint64_t>(n, k1, d1, dkey, red);
   const double madv =
       (__longlong_as_double((long long)d1) + __longlong_as_double((long long)d2)) / 2.0;
   const double c = (double)sigma * 1.4826;
   const double T = med + c * madv;
-  if (mask)
-    for (int64_t i = threadIdx.x; i < n; i += NT) mask[pop.off(i)] = (double)amp(i) > T ? 1 : 0;
+  if (mask) {
+    if (pop.inner_n >= NT) {
+      // element i = q * inner_n + r; a step of NT carries into q at most once
+      int64_t q = 0, r = threadIdx.x;
+      for (int64_t i = threadIdx.x; i < n; i += NT) {
+        mask[pop.base + q * pop.s_outer + r * pop.s_inner] = (double)amp(i) > T ? 1 : 0;
+        r += NT;
+        if (r >= pop.inner_n) {
+          r -= pop.inner_n;
+          ++q;
+        }
+      }
+    } else {
+      for (int64_t i = threadIdx.x; i < n; i += NT) mask[pop.off(i)] = (double)amp(i) > T ? 1 : 0;
+    }
+  }
   if (threadIdx.x == 0) {
     if (thresh) thresh[id] = T;
     if (stats) {
@@ -276,7 +426,7 @@ constexpr int64_t MAD_CAP_SMALL = 2048;
 int64_t mad_scratch_floats(int64_t n_time, int64_t n_base, int n_chan, int population) {
   const int64_t npop = population == 0 ? n_base : population == 1 ? n_base * n_chan : n_time * n_base;
   const int64_t count = population == 0 ? n_time * n_chan : population == 1 ? n_time : n_chan;
-  return count > MAD_CAP_BIG ? npop * count : 0;
+  return count > MAD_CAP_SMALL ? npop * count : 0;
 }
 
 hipError_t launch_mad(const float2* vis, int64_t n_time, int64_t n_base, int n_chan, float sigma,
@@ -292,9 +442,11 @@ hipError_t launch_mad(const float2* vis, int64_t n_time, int64_t n_base, int n_c
   } else {
     const int64_t cap = count <= MAD_CAP_BIG ? count : 0;
     const float* gamp = nullptr;
-    if (cap == 0 && amp_scratch) {
-      // populations beyond the LDS cache: their amplitudes are formed once
-      // and every selection pass reads 4 bytes instead of 8 and a square root
+    if (amp_scratch) {
+      // the amplitudes are formed once, by the whole GPU: the selection
+      // workgroups (one per population) then load 4 contiguous bytes per
+      // element instead of forming a float64 square root each, and
+      // populations beyond the LDS cache read 4 bytes per pass
       const int64_t total = npop * count;
       hipLaunchKernelGGL(mad_amp_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, vis, n_time,
                          n_base, n_chan, population, count, total, amp_scratch);

@@ -86,8 +86,9 @@ hipError_t launch_xeng_mfma(const void* v, int prec, const float* scale, int n_a
 int64_t xeng_mfma_ksplit(int prec, int n_ant, int64_t spec_per_dump, int n_chan, int64_t n_dump);
 
 // MAD flagging.  mask, thresh and stats ([pop][2]: median, MAD) may be null.
-// Populations too large for the LDS cache read their amplitudes from
-// amp_scratch (mad_scratch_floats() floats; null: recomputed from vis).
+// Populations above the single-wave size take their amplitudes from
+// amp_scratch (mad_scratch_floats() floats), formed there first by one
+// whole-GPU pass; null: each workgroup forms them from vis.
 int64_t mad_scratch_floats(int64_t n_time, int64_t n_base, int n_chan, int population);
 hipError_t launch_mad(const float2* vis, int64_t n_time, int64_t n_base, int n_chan, float sigma,
                       int population, uint8_t* mask, double* thresh, double* stats, float* amp_scratch,
