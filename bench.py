@@ -9,9 +9,13 @@ flagging (5 sigma, per baseline) -> per-antenna delay/phase application.
 
 Prints one JSON line: input GB/s (10^9 B/s) with a roofline record of the
 dominant kernel (fused F+X, timed by HIP events around its own launches on
-its own stream), the 32-antenna X-engine comparison (FP32 vector ALUs vs
-FP16/BF16/E4M3 matrix cores, with visibility errors against the FP64
-oracle), and the FP64 oracle timed on the host cores on a bounded sample.
+its own stream), and sections for the other steps: the same stream pushed
+from pinned host memory, the delay/phase solve (checked against the
+injected lags and the oracle's solve, timed beside it), the 32-antenna
+X-engine comparison (float32 vs FP16/BF16/E4M3 on the matrix cores, with
+visibility errors against the FP64 oracle), five uneven arrays as one
+plan, and the learned flagger; then the FP64 oracle timed on the host
+cores on a bounded sample.
 """
 
 from __future__ import annotations
@@ -343,6 +347,51 @@ def cpu_baseline(x, N, P, spd, sigma, tau, phi, df, gpu_vis, n_dumps=8):
             "seconds": round(dt, 2), "gpu_vs_oracle_err_on_sample": float(f"{err:.3e}")}
 
 
+def solve_section(torch, qc, vis, n_ant, df, fs, sigma, reps):
+    """Delay/phase solve (Sec. 7): the real-time visibilities flagged by MAD
+    -> per-antenna delays and phases against antenna 0, checked against the
+    oracle's solve of the same input (timed beside it).  Then the 32-antenna
+    precision plane (496 cross baselines, no RFI), checked against its
+    injected lags.  The real-time stream's RFI is common to all antennas
+    (zero lag), and the lines MAD leaves unflagged pull its delays towards
+    zero, so lag recovery is judged on the clean stream."""
+    from oracle import calib
+    n_chan = vis.shape[2]
+    lo, hi = 16, n_chan - 16
+    mask, _ = qc.mad_flag(vis, sigma, 0)
+    qc.solve_delay_phase(vis, n_ant, 0.0, df, 0, lo, hi, mask=mask)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        tau, phi = qc.solve_delay_phase(vis, n_ant, 0.0, df, 0, lo, hi, mask=mask)
+    gpu_ms = (time.perf_counter() - t0) / reps * 1e3
+    V, M = vis.cpu().numpy(), mask.cpu().numpy()
+    t0 = time.perf_counter()
+    tau_o, phi_o = calib.solve_delay_phase(V, M, n_ant, 0.0, df, 0, lo, hi)
+    oracle_ms = (time.perf_counter() - t0) * 1e3
+    res = {"workload": f"realtime_{n_ant}ant: {V.shape[0]} dumps x {V.shape[1]} baselines x {n_chan} ch",
+           "gpu_ms_synchronous": round(gpu_ms, 4), "oracle_ms": round(oracle_ms, 2),
+           "max_tau_diff_vs_oracle_samples": float(f"{np.max(np.abs(tau - tau_o)) * fs:.3e}"),
+           "max_phi_diff_vs_oracle_rad": float(f"{np.max(np.abs(calib.wrap(phi - phi_o))):.3e}")}
+    # 32 antennas: the precision workload's float32 visibilities
+    spec32 = synth.array_spec(32, 1 << 24, 3000)
+    x32 = synth.generate(spec32)
+    N = 4096
+    V32 = qc.xcorrelate(torch.from_numpy(x32).cuda(), N, 4, (1 << 24) // N)
+    del x32
+    qc.solve_delay_phase(V32, 32, 0.0, fs / N, 0, lo, hi)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        tau32, _ = qc.solve_delay_phase(V32, 32, 0.0, fs / N, 0, lo, hi)
+    res["gpu_ms_synchronous_32ant"] = round((time.perf_counter() - t0) / reps * 1e3, 4)
+    inj = np.array(spec32.lags, np.float64) - spec32.lags[0]
+    res["max_tau_err_vs_injected_samples_32ant"] = float(f"{np.max(np.abs(tau32 * fs - inj)):.3e}")
+    log(f"[bench] solve: {gpu_ms:.3f} ms (4 ant), {res['gpu_ms_synchronous_32ant']:.3f} ms (32 ant); "
+        f"oracle {oracle_ms:.1f} ms (4 ant)")
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -449,6 +498,7 @@ def main():
     }
     if not args.no_stream:
         out["stream"] = stream_section(torch, qc, x, N, P, spd, vis_check)
+    out["solve"] = solve_section(torch, qc, vis_check, n_ant, df, fs, sigma, max(3, args.steps // 10))
     if not args.no_precision:
         del vis_check
         out["precision_32ant"] = precision_section(torch, qc, args.steps)
