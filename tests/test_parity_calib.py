@@ -41,6 +41,58 @@ def test_mad_bit_exact(qc, shape, pop):
         assert np.array_equal(T.cpu().numpy(), T_ref)
 
 
+def _tie_plane(shape, pop, pattern, rng):
+    """Real-valued visibilities (amplitude exactly |v|) with a tie structure
+    inside every population:
+    0: half the values 1, half 2 (the middle pair straddles two large
+       groups of equal keys, every deviation equals 0.5);
+    1: 30 % 1, 40 % 2, 30 % 3 (the median inside a group);
+    2: half exactly 1, half spread over (1, 2) (the middle pair at the
+       edge of a tie group);
+    3: a spread with two huge outliers."""
+    n_time, n_base, n_chan = shape
+    npop = {0: n_base, 1: n_base * n_chan, 2: n_time * n_base}[pop]
+    n = {0: n_time * n_chan, 1: n_time, 2: n_chan}[pop]
+    A = np.empty((npop, n))
+    idx = np.arange(n)
+    for q in range(npop):
+        if pattern == 0:
+            a = np.where(idx < n // 2, 1.0, 2.0)
+        elif pattern == 1:
+            a = np.where(idx < 3 * n // 10, 1.0, np.where(idx < 7 * n // 10, 2.0, 3.0))
+        elif pattern == 2:
+            a = np.where(idx < n // 2, 1.0, 1.0 + rng.uniform(0.01, 0.99, n))
+        else:
+            a = rng.uniform(0.5, 1.5, n)
+            a[rng.choice(n, min(2, n), replace=False)] = 1e6
+        A[q] = rng.permutation(a) * rng.choice([-1.0, 1.0], n)
+    if pop == 0:
+        V = A.reshape(n_base, n_time, n_chan).transpose(1, 0, 2)
+    elif pop == 1:
+        V = A.reshape(n_base, n_chan, n_time).transpose(2, 0, 1)
+    else:
+        V = A.reshape(n_time, n_base, n_chan)
+    return np.ascontiguousarray(V).astype(np.float32).astype(np.complex64)
+
+
+@pytest.mark.parametrize("shape,pop", [((8, 2, 512), 0), ((4, 3, 4096), 2), ((1, 2, 100), 0),
+                                       ((64, 2, 5), 1)])
+def test_mad_tie_structures(qc, shape, pop):
+    """Bit-exact on populations whose middle order statistics sit at or
+    inside large groups of equal amplitudes: the selection resolves every
+    bit, or ranks k and k+1 fall in different digits too large to gather,
+    and the counting pass finds rank k+1 (single-wave and 1024-thread
+    kernels)."""
+    import torch
+    rng = np.random.default_rng(11)
+    for pattern in range(4):
+        v = _tie_plane(shape, pop, pattern, rng)
+        m_ref, T_ref = mad.mad_flag(v, 5.0, pop)
+        m, T = qc.mad_flag(torch.from_numpy(v).cuda(), 5.0, pop)
+        assert np.array_equal(T.cpu().numpy(), T_ref), pattern
+        assert np.array_equal(m.cpu().numpy(), m_ref), pattern
+
+
 def test_mad_sigma_zero_and_constant(qc):
     import torch
     v = np.full((4, 2, 16), 3 + 4j, np.complex64)
