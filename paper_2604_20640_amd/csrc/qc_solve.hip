@@ -13,10 +13,10 @@
 //     tau = tau_c - slope / 2 pi;
 //   * residual phase: phi = -arg of the band's mean vector of
 //     V e^{+2 pi i f_k tau} (float64 sum).
-// Per antenna (one thread): float64 least squares of tau_i - tau_j = tau_b
-// over the cross baselines with the reference antenna at zero; phases start
-// from the reference-antenna baselines and are refined by least squares on
-// the wrapped residuals.
+// Per antenna: float64 least squares of tau_i - tau_j = tau_b over the cross
+// baselines with the reference antenna at zero (closed form, one thread per
+// antenna); phases start from the reference-antenna baselines and are
+// refined by least squares on the wrapped residuals.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -206,82 +206,62 @@ solve_baseline_kernel(const float2* __restrict__ vis, const uint8_t* __restrict_
   }
 }
 
-// Solves A z = r (A symmetric positive definite, n <= 63) in place by
-// Gaussian elimination with partial pivoting; A is n x n row-major.
-__device__ void gauss_solve(double* A, double* r, int n) {
-  for (int c = 0; c < n; ++c) {
-    int p = c;
-    for (int q = c + 1; q < n; ++q)
-      if (fabs(A[q * n + c]) > fabs(A[p * n + c])) p = q;
-    if (p != c) {
-      for (int q = 0; q < n; ++q) {
-        const double t = A[c * n + q];
-        A[c * n + q] = A[p * n + q];
-        A[p * n + q] = t;
-      }
-      const double t = r[c];
-      r[c] = r[p];
-      r[p] = t;
-    }
-    for (int q = c + 1; q < n; ++q) {
-      const double f = A[q * n + c] / A[c * n + c];
-      for (int e = c; e < n; ++e) A[q * n + e] -= f * A[c * n + e];
-      r[q] -= f * r[c];
-    }
-  }
-  for (int c = n - 1; c >= 0; --c) {
-    double s = r[c];
-    for (int e = c + 1; e < n; ++e) s -= A[c * n + e] * r[e];
-    r[c] = s / A[c * n + c];
-  }
-}
-
+// Per-antenna least squares over the cross baselines, the reference antenna
+// fixed at zero.  With unit weights on every cross baseline the normal
+// matrix of the F = n - 1 free antennas is N = n I - 1 1^T (an antenna is
+// on n - 1 baselines; two free antennas share one), and
+// (n I - 1 1^T)(I + 1 1^T) = n I + (n - 1 - F) 1 1^T = n I, so the
+// solution of N x = r is x = (r + sum(r) 1) / n.  One thread per antenna
+// forms its right-hand side r = G^T b (baselines in row-major order).
 __global__ void solve_antenna_kernel(const double* __restrict__ tau_b, const double* __restrict__ phi_b,
                                      int n_ant, int ref, double* __restrict__ tau_out,
                                      double* __restrict__ phi_out) {
   extern __shared__ double sm[];
-  if (threadIdx.x != 0) return;
-  const int F = n_ant - 1;
-  double* A = sm;              // F x F
-  double* A2 = A + F * F;      // F x F copy for the second solve
-  double* rt = A2 + F * F;     // F
-  double* rp = rt + F;         // F
-  double* phi0 = rp + F;       // n_ant
-  auto col = [&](int a) { return a < ref ? a : a - 1; };
-  for (int q = 0; q < F * F; ++q) A[q] = 0.0;
-  for (int q = 0; q < F; ++q) rt[q] = rp[q] = 0.0;
-  for (int a = 0; a < n_ant; ++a) phi0[a] = 0.0;
-  int r = 0;
-  for (int i = 0; i < n_ant; ++i)
-    for (int j = i + 1; j < n_ant; ++j, ++r) {
-      if (j == ref) phi0[i] = phi_b[r];
-      else if (i == ref) phi0[j] = -phi_b[r];
-    }
-  r = 0;
-  for (int i = 0; i < n_ant; ++i)
-    for (int j = i + 1; j < n_ant; ++j, ++r) {
-      const double res = wrap_pi(phi_b[r] - (phi0[i] - phi0[j]));
-      if (i != ref) {
-        A[col(i) * F + col(i)] += 1.0;
-        rt[col(i)] += tau_b[r];
-        rp[col(i)] += res;
-      }
-      if (j != ref) {
-        A[col(j) * F + col(j)] += 1.0;
-        rt[col(j)] -= tau_b[r];
-        rp[col(j)] -= res;
-      }
-      if (i != ref && j != ref) {
-        A[col(i) * F + col(j)] -= 1.0;
-        A[col(j) * F + col(i)] -= 1.0;
+  double* phi0 = sm;            // n_ant: first phases, from the reference baselines
+  double* rt = phi0 + n_ant;    // n_ant: right-hand sides (delay)
+  double* rp = rt + n_ant;      // n_ant: right-hand sides (phase residual)
+  __shared__ double tot[2];
+  const int n = n_ant;
+  // index of cross baseline (i, j), i < j, in row-major order
+  auto cb = [&](int i, int j) { return i * n - i * (i + 1) / 2 + (j - i - 1); };
+  for (int a = threadIdx.x; a < n; a += blockDim.x)
+    phi0[a] = a == ref ? 0.0 : a < ref ? phi_b[cb(a, ref)] : -phi_b[cb(ref, a)];
+  __syncthreads();
+  for (int a = threadIdx.x; a < n; a += blockDim.x) {
+    double st = 0.0, sp = 0.0;
+    if (a != ref) {
+      for (int b = 0; b < n; ++b) {
+        if (b == a) continue;
+        const int i = a < b ? a : b, j = a < b ? b : a;
+        const int r = cb(i, j);
+        const double res = wrap_pi(phi_b[r] - (phi0[i] - phi0[j]));
+        if (a == i) {
+          st += tau_b[r];
+          sp += res;
+        } else {
+          st -= tau_b[r];
+          sp -= res;
+        }
       }
     }
-  for (int q = 0; q < F * F; ++q) A2[q] = A[q];
-  gauss_solve(A, rt, F);
-  gauss_solve(A2, rp, F);
-  for (int a = 0; a < n_ant; ++a) {
-    tau_out[a] = a == ref ? 0.0 : rt[col(a)];
-    phi_out[a] = a == ref ? wrap_pi(phi0[a]) : wrap_pi(phi0[a] + rp[col(a)]);
+    rt[a] = st;
+    rp[a] = sp;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0, q = 0.0;
+    for (int a = 0; a < n; ++a)
+      if (a != ref) {
+        t += rt[a];
+        q += rp[a];
+      }
+    tot[0] = t;
+    tot[1] = q;
+  }
+  __syncthreads();
+  for (int a = threadIdx.x; a < n; a += blockDim.x) {
+    tau_out[a] = a == ref ? 0.0 : (rt[a] + tot[0]) / (double)n;
+    phi_out[a] = a == ref ? wrap_pi(phi0[a]) : wrap_pi(phi0[a] + (rp[a] + tot[1]) / (double)n);
   }
 }
 
@@ -323,8 +303,7 @@ hipError_t launch_solve(const float2* vis, const uint8_t* mask, int64_t n_time, 
     default: return hipErrorInvalidValue;
   }
   if (e != hipSuccess) return e;
-  const int F = n_ant - 1;
-  const size_t lds = sizeof(double) * (2 * F * F + 2 * F + n_ant);
+  const size_t lds = sizeof(double) * 3 * n_ant;
   hipLaunchKernelGGL(solve_antenna_kernel, dim3(1), dim3(64), lds, s, tau_b, phi_b, n_ant, ref, tau, phi);
   return hipGetLastError();
 }
