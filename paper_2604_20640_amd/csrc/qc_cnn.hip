@@ -417,22 +417,43 @@ cnn_mfma_conv_kernel(const _Float16* __restrict__ in, const _Float16* __restrict
   float bco[16];
 #pragma unroll
   for (int r = 0; r < 16; ++r) bco[r] = bias[8 * (r >> 2) + 4 * kh + (r & 3)];
+  // The input tile with its halo (4 16-byte chunks per pixel) is loaded
+  // into registers one tile ahead: the loads of the next tile are in
+  // flight while the matrix cores work on this one.
+  constexpr int CHUNKS = LH * LW * 4;
+  constexpr int NPRE = (CHUNKS + MT_NT - 1) / MT_NT;
+  uint4 pre[NPRE];
+  auto load_tile = [&](int64_t tl) {
+    const int64_t n = tl / tiles_per_img;
+    const int tt = (int)(tl % tiles_per_img);
+    const int y0 = (tt / tiles_x) * MT_H, x0 = (tt % tiles_x) * MT_W;
+#pragma unroll
+    for (int i = 0; i < NPRE; ++i) {
+      const int e = t + i * MT_NT;
+      const int c4 = e & 3, pix = e >> 2;
+      const int r = pix / LW, q = pix % LW;
+      const int y = y0 + r - R, x = x0 + q - R;
+      pre[i] = make_uint4(0u, 0u, 0u, 0u);
+      if (e < CHUNKS && y >= 0 && y < H && x >= 0 && x < W)
+        pre[i] = reinterpret_cast<const uint4*>(in + (((n * H + y) * (int64_t)W + x) * 32))[c4];
+    }
+  };
+  if ((int64_t)blockIdx.x < n_tiles) load_tile(blockIdx.x);
   for (int64_t tl = blockIdx.x; tl < n_tiles; tl += gridDim.x) {
     const int64_t n = tl / tiles_per_img;
     const int tt = (int)(tl % tiles_per_img);
     const int y0 = (tt / tiles_x) * MT_H, x0 = (tt % tiles_x) * MT_W;
     __syncthreads();  // previous tile's reads done (and weights stored)
-    // stage the input tile with its halo: 4 16-byte chunks per pixel
-    for (int e = t; e < LH * LW * 4; e += MT_NT) {
-      const int c4 = e & 3, pix = e >> 2;
-      const int r = pix / LW, q = pix % LW;
-      const int y = y0 + r - R, x = x0 + q - R;
-      uint4 v = make_uint4(0u, 0u, 0u, 0u);
-      if (y >= 0 && y < H && x >= 0 && x < W)
-        v = reinterpret_cast<const uint4*>(in + (((n * H + y) * (int64_t)W + x) * 32))[c4];
-      *reinterpret_cast<uint4*>(st + (r * LW + q) * MT_PS + 8 * c4) = v;
+#pragma unroll
+    for (int i = 0; i < NPRE; ++i) {
+      const int e = t + i * MT_NT;
+      if (e < CHUNKS) {
+        const int c4 = e & 3, pix = e >> 2;
+        *reinterpret_cast<uint4*>(st + pix * MT_PS + 8 * c4) = pre[i];
+      }
     }
     __syncthreads();
+    if (tl + gridDim.x < n_tiles) load_tile(tl + gridDim.x);
     float16_t acc[2];
 #pragma unroll
     for (int u = 0; u < 2; ++u)
