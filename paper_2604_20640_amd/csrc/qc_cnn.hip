@@ -383,7 +383,10 @@ __global__ void cnn_normalize_kernel(const float2* __restrict__ vis, const doubl
 typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
 typedef float float16_t __attribute__((ext_vector_type(16)));
 
-constexpr int MT_H = 16;     // tile rows (8 waves x 2 rows)
+// tile rows: 8 waves x mt_u(D) rows, as many as fit the LDS beside the
+// packed weights (each weight operand read from LDS feeds MT_U products)
+constexpr int mt_u(int D) { return D == 1 ? 4 : 3; }
+constexpr int mt_h(int D) { return 8 * mt_u(D); }
 constexpr int MT_W = 32;     // tile columns (one MFMA column block)
 constexpr int MT_NT = 512;
 constexpr int MT_PS = 40;    // LDS pixel stride in halves (80 B: conflict-free 16-byte reads)
@@ -407,6 +410,7 @@ cnn_mfma_conv_kernel(const _Float16* __restrict__ in, const _Float16* __restrict
                      const float* __restrict__ bias, int H, int W, int tiles_x, int tiles_per_img,
                      int64_t n_tiles, _Float16* __restrict__ out) {
   constexpr int R = 2 * D;  // D*(5-1)/2
+  constexpr int U = mt_u(D), MT_H = mt_h(D);
   constexpr int LH = MT_H + 2 * R, LW = MT_W + 2 * R;
   extern __shared__ uint4 smem[];
   uint4* sw = smem;                                       // [50][64] 16-byte operands
@@ -454,9 +458,9 @@ cnn_mfma_conv_kernel(const _Float16* __restrict__ in, const _Float16* __restrict
     }
     __syncthreads();
     if (tl + gridDim.x < n_tiles) load_tile(tl + gridDim.x);
-    float16_t acc[2];
+    float16_t acc[U];
 #pragma unroll
-    for (int u = 0; u < 2; ++u)
+    for (int u = 0; u < U; ++u)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[u][r] = 0.f;
 #pragma unroll 5
@@ -465,8 +469,8 @@ cnn_mfma_conv_kernel(const _Float16* __restrict__ in, const _Float16* __restrict
       const int ky = tap / 5, kx = tap % 5;
       const half8_t a = __builtin_bit_cast(half8_t, sw[sl * 64 + lane]);
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const int row = 2 * wave + u + ky * D;
+      for (int u = 0; u < U; ++u) {
+        const int row = U * wave + u + ky * D;
         const half8_t b = __builtin_bit_cast(
             half8_t, *reinterpret_cast<const uint4*>(st + (row * LW + px + kx * D) * MT_PS + 16 * h + 8 * kh));
         acc[u] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, acc[u], 0, 0, 0);
@@ -475,8 +479,8 @@ cnn_mfma_conv_kernel(const _Float16* __restrict__ in, const _Float16* __restrict
     // epilogue: bias, ReLU, half; lane holds output channels
     // {8g + 4kh + i} of pixel px for g, i < 4
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int y = y0 + 2 * wave + u, x = x0 + px;
+    for (int u = 0; u < U; ++u) {
+      const int y = y0 + U * wave + u, x = x0 + px;
       if (y < H && x < W) {
         _Float16* o = out + ((n * H + y) * (int64_t)W + x) * 32;
 #pragma unroll
@@ -678,7 +682,7 @@ hipError_t cnn_pack_mfma(const float* w, _Float16* p, hipStream_t s) {
 
 size_t cnn_mfma_lds_bytes(int D) {
   const int R = 2 * D;
-  return sizeof(uint4) * MT_SLICES * 64 + sizeof(_Float16) * (MT_H + 2 * R) * (MT_W + 2 * R) * MT_PS;
+  return sizeof(uint4) * MT_SLICES * 64 + sizeof(_Float16) * (mt_h(D) + 2 * R) * (MT_W + 2 * R) * MT_PS;
 }
 
 // Inference forward with half activations: x [n][H][W] float32 ->
@@ -692,22 +696,26 @@ hipError_t cnn_forward_f16(const float* params, const _Float16* w2p, const _Floa
                      params + CNN_OFF_L1, params + CNN_OFF_L1 + 288, H, W, n_pix, A);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int tx = ceil_div(W, MT_W), ty = ceil_div(H, MT_H);
-  const int64_t n_tiles = n_img * tx * ty;
-  const unsigned grid = (unsigned)(n_tiles < 1024 ? n_tiles : 1024);
+  const int tx = ceil_div(W, MT_W), ty2 = ceil_div(H, mt_h(1)), ty3 = ceil_div(H, mt_h(2));
+  const int64_t n_tiles2 = n_img * tx * ty2, n_tiles3 = n_img * tx * ty3;
+  const unsigned grid2 = (unsigned)(n_tiles2 < 1024 ? n_tiles2 : 1024);
+  const unsigned grid3 = (unsigned)(n_tiles3 < 1024 ? n_tiles3 : 1024);
   const size_t l2 = cnn_mfma_lds_bytes(1), l3 = cnn_mfma_lds_bytes(2);
+  static_assert(sizeof(uint4) * MT_SLICES * 64 + sizeof(_Float16) * (mt_h(2) + 8) * (MT_W + 8) * MT_PS <=
+                    160 * 1024 && sizeof(uint4) * MT_SLICES * 64 + sizeof(_Float16) * (mt_h(1) + 4) * (MT_W + 4) * MT_PS <= 160 * 1024,
+                "half convolution tiles: LDS");
   e = hipFuncSetAttribute(reinterpret_cast<const void*>(cnn_mfma_conv_kernel<1>),
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)l2);
   if (e != hipSuccess) return e;
   e = hipFuncSetAttribute(reinterpret_cast<const void*>(cnn_mfma_conv_kernel<2>),
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)l3);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(cnn_mfma_conv_kernel<1>, dim3(grid), dim3(MT_NT), l2, s, A, w2p, params + CNN_OFF_L2 + 25600,
-                     H, W, tx, tx * ty, n_tiles, B);
+  hipLaunchKernelGGL(cnn_mfma_conv_kernel<1>, dim3(grid2), dim3(MT_NT), l2, s, A, w2p, params + CNN_OFF_L2 + 25600,
+                     H, W, tx, tx * ty2, n_tiles2, B);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(cnn_mfma_conv_kernel<2>, dim3(grid), dim3(MT_NT), l3, s, B, w3p, params + CNN_OFF_L3 + 25600,
-                     H, W, tx, tx * ty, n_tiles, A);
+  hipLaunchKernelGGL(cnn_mfma_conv_kernel<2>, dim3(grid3), dim3(MT_NT), l3, s, B, w3p, params + CNN_OFF_L3 + 25600,
+                     H, W, tx, tx * ty3, n_tiles3, A);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(cnn_head_nhwc_kernel, dim3((unsigned)ceil_div(n_pix, 256)), dim3(256), 0, s, A,
