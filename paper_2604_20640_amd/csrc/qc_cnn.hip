@@ -196,6 +196,161 @@ cnn_wgrad32_kernel(const float* __restrict__ a, const float* __restrict__ g, int
   }
 }
 
+typedef float mf32x16_t __attribute__((ext_vector_type(16)));
+
+// One staged pixel tile's products for a wave's NQ taps: rows of 32 pixels,
+// each two pixels per step (lanes 32..63 the odd one), every tap's operand at
+// the tap's offset from the same pixel.  g points at channel cl's gradient
+// row plus the lane's pixel slot, a at channel cl's input tile likewise.
+template <int NQ, int TG, int LW>
+__device__ __forceinline__ void wgrad_tile_products(const float* __restrict__ g, const float* __restrict__ a,
+                                                    const int (&toff)[TG], mf32x16_t (&acc)[TG]) {
+  // operands of step px + 2 are read before step px's products are issued
+#pragma unroll 1
+  for (int py = 0; py < CT_H; ++py) {
+    const float* gr = g + py * CT_W;
+    const float* ar[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) ar[q] = a + py * LW + toff[q];
+    float gv = gr[0], av[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) av[q] = ar[q][0];
+#pragma unroll
+    for (int px = 0; px < CT_W; px += 2) {
+      float gn = 0.f, an[NQ];
+      if (px + 2 < CT_W) {
+        gn = gr[px + 2];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) an[q] = ar[q][px + 2];
+      }
+      __builtin_amdgcn_sched_barrier(0);   // keep the reads ahead of the products
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(gv, av[q], acc[q], 0, 0, 0);
+      gv = gn;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) av[q] = an[q];
+    }
+  }
+}
+
+// The same weight gradient on the matrix cores: per tap t, dW_t = G A_t^T
+// with G = g [32 outputs x pixels] and A_t = a shifted by the tap's offset
+// [32 inputs x pixels], a 32 x 32 product reduced over pixels two at a time
+// by v_mfma_f32_32x32x2_f32 (lane l: channel l % 32, pixel slot l / 32 of
+// both operands).  All 32 input channels of a pixel tile are staged at once,
+// the next tile's values travelling in registers while this one is reduced.
+// Wave w owns taps w, w + 8, w + 16, w + 24, so that the two waves sharing a
+// SIMD hold 6 or 7 of the 25 taps.  The bias gradient is summed from the
+// staged tile, 16 lanes per output channel.  Workgroups stride over pixel
+// tiles and write their partial sums to part[block][...] in the layout of
+// the vector-ALU kernel.
+template <int K, int D>
+__global__ void __launch_bounds__(512)
+cnn_wgrad32_mfma_kernel(const float* __restrict__ a, const float* __restrict__ g, int H, int W,
+                        int tiles_x, int tiles_per_img, int64_t n_tiles, float* __restrict__ part) {
+  constexpr int C = 32, NTH = 512, NW = NTH / 64;
+  constexpr int R = D * (K - 1) / 2;
+  constexpr int LH = CT_H + 2 * R, LW = CT_W + 2 * R;
+  constexpr int AS = LH * LW + 1;   // odd channel strides: the 32 channels a
+  constexpr int GS = CNT + 1;       // wave reads at one pixel hit distinct banks
+  constexpr int NT = K * K;
+  constexpr int TG = (NT + NW - 1) / NW;
+  constexpr int IG = C * CNT / NTH, IA = C * LH * LW / NTH, ITER = IG + IA;
+  static_assert(IG * NTH == C * CNT && IA * NTH == C * LH * LW && NTH % CNT == 0, "whole staging rounds");
+  static_assert(CNT % 2 == 0 && CNT == 16 * 16, "pixel pairs; 16 lanes x 16 pixels per bias sum");
+  extern __shared__ float sm[];
+  float* sg = sm;                   // [32][GS]
+  float* sa = sm + C * GS;          // [32][AS]
+  const int t = threadIdx.x, lane = t & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int cl = lane & 31, kh = lane >> 5;
+  mf32x16_t acc[TG];
+#pragma unroll
+  for (int q = 0; q < TG; ++q)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[q][r] = 0.f;
+  float sb = 0.f;                   // bias partial: channel t / 16, pixels t % 16 + 16 j
+  int toff[TG];                     // LDS offsets of the wave's taps (uniform)
+#pragma unroll
+  for (int q = 0; q < TG; ++q) {
+    const int tap = wave + NW * q;
+    toff[q] = tap < NT ? (tap / K) * D * LW + (tap % K) * D : 0;
+  }
+  const int nq = wave + NW * (TG - 1) < NT ? TG : TG - 1;
+  static_assert(NW * (TG - 1) < NT, "every wave holds at least TG - 1 taps");
+  float pre[ITER];
+  const int HW = H * W;             // C * H * W < 2^31: 32-bit offsets in an image
+  // Staging: the gradient tile as 16 rounds of 2 channels (thread t: channel
+  // t / 256 + 2 i, pixel t % 256), the input tile with halo as IA rounds over
+  // [channel][row][col].  Padding reads a valid element and discards it, so
+  // the loads are straight-line code.
+  auto load_tile = [&](int64_t tl) {
+    const int64_t n = tl / tiles_per_img;
+    const int tt = (int)(tl % tiles_per_img);
+    const int y0 = (tt / tiles_x) * CT_H, x0 = (tt % tiles_x) * CT_W;
+    const float* gi = g + img_off(n, 0, C, H, W);
+    const float* ai = a + img_off(n, 0, C, H, W);
+    int tv = t, hw = HW;
+    asm volatile("" : "+v"(tv), "+s"(hw));   // offsets are recomputed per tile, not held live
+    {
+      const int p = tv % CNT, y = y0 + p / CT_W, x = x0 + p % CT_W;
+      const bool in = y < H && x < W;
+      int o = in ? (tv / CNT) * hw + y * W + x : 0;
+      const int step = in ? (NTH / CNT) * hw : 0;
+#pragma unroll
+      for (int i = 0; i < IG; ++i, o += step) {
+        const float v = gi[o];
+        pre[i] = in ? v : 0.f;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < IA; ++i) {
+      const int f = tv + NTH * i;
+      const int c = f / (LH * LW), r = (f / LW) % LH, q = f % LW;
+      const int y = y0 + r - R, x = x0 + q - R;
+      const bool in = y >= 0 && y < H && x >= 0 && x < W;
+      const float v = ai[in ? c * HW + y * W + x : 0];
+      pre[IG + i] = in ? v : 0.f;
+    }
+  };
+  if (blockIdx.x < n_tiles) load_tile(blockIdx.x);
+  for (int64_t tl = blockIdx.x; tl < n_tiles; tl += gridDim.x) {
+    __syncthreads();  // the previous tile's reads are done
+    int tv = t;
+    asm volatile("" : "+v"(tv));
+#pragma unroll
+    for (int i = 0; i < IG; ++i) sg[((NTH / CNT) * i + tv / CNT) * GS + tv % CNT] = pre[i];
+#pragma unroll
+    for (int i = 0; i < IA; ++i) {
+      const int f = tv + NTH * i;
+      sa[f + f / (LH * LW)] = pre[IG + i];   // channel stride LH * LW + 1
+    }
+    __syncthreads();
+    if (tl + gridDim.x < n_tiles) load_tile(tl + gridDim.x);
+#pragma unroll
+    for (int j = 0; j < 16; ++j) sb += sg[(t >> 4) * GS + (t & 15) + 16 * j];
+    if (nq == TG)
+      wgrad_tile_products<TG, TG, LW>(sg + cl * GS + kh, sa + cl * AS + kh, toff, acc);
+    else
+      wgrad_tile_products<TG - 1, TG, LW>(sg + cl * GS + kh, sa + cl * AS + kh, toff, acc);
+  }
+  float* out = part + (int64_t)blockIdx.x * (C * C * NT + C);
+#pragma unroll
+  for (int q = 0; q < TG; ++q) {
+    const int tap = wave + NW * q;
+    if (tap < NT) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int o = 8 * (r >> 2) + 4 * kh + (r & 3);   // accumulator row
+        out[(o * C + cl) * NT + tap] = acc[q][r];
+      }
+    }
+  }
+#pragma unroll
+  for (int m = 8; m >= 1; m >>= 1) sb += __shfl_xor(sb, m, 16);
+  if ((t & 15) == 0) out[C * C * NT + (t >> 4)] = sb;
+}
+
 // Weight gradient of a layer with few weights (L1: 1 input channel): one
 // lane per weight, pixel tiles staged in LDS.
 template <int CI, int CO, int K, int D>
@@ -254,13 +409,36 @@ cnn_wgrad_small_kernel(const float* __restrict__ a, const float* __restrict__ g,
     if (t + j * 256 < NW) out[t + j * 256] = s[j];
 }
 
-// dst[e] = sum_b part[b][e], in block order.
-__global__ void cnn_sum_parts_kernel(const float* __restrict__ part, int n_parts, int n, float* __restrict__ dst) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n) return;
+// sum_b part[b][e] for the workgroup's 64 elements e = 64 blockIdx.x + lane,
+// in a fixed order: wave w sums parts w, w + SP_WAVES, ... and wave 0 adds
+// the waves' sums in wave order.  Valid in wave 0 (e < n); all threads call.
+constexpr int SP_WAVES = 16;
+
+__device__ __forceinline__ float sum_parts_block(const float* __restrict__ part, int n_parts, int n) {
+  __shared__ float red[SP_WAVES][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int e = blockIdx.x * 64 + lane;
   float s = 0.f;
-  for (int b = 0; b < n_parts; ++b) s += part[(int64_t)b * n + e];
-  dst[e] = s;
+  if (e < n) {
+#pragma unroll 8
+    for (int b = w; b < n_parts; b += SP_WAVES) s += part[(int64_t)b * n + e];
+  }
+  red[w][lane] = s;
+  __syncthreads();
+  float t = 0.f;
+  if (w == 0) {
+#pragma unroll
+    for (int k = 0; k < SP_WAVES; ++k) t += red[k][lane];
+  }
+  return t;
+}
+
+// dst[e] = sum_b part[b][e]
+__global__ void __launch_bounds__(64 * SP_WAVES)
+cnn_sum_parts_kernel(const float* __restrict__ part, int n_parts, int n, float* __restrict__ dst) {
+  const float s = sum_parts_block(part, n_parts, n);
+  const int e = blockIdx.x * 64 + (threadIdx.x & 63);
+  if (threadIdx.x < 64 && e < n) dst[e] = s;
 }
 
 // L4 forward: logit = b + sum_c w[c] a[c]; optionally the flag decision
@@ -283,16 +461,15 @@ __global__ void cnn_head_kernel(const float* __restrict__ a, const float* __rest
 }
 
 // grad4[0..31] = sum_b part[b][0..31] (dW4), grad4[32] = sum_b part[b][33]
-// (db4), loss = inv_count * sum_b part[b][32] (the mean); in block order.
-__global__ void cnn_head_finish_kernel(const float* __restrict__ part, int n_parts, float inv_count,
-                                       float* __restrict__ grad4, float* __restrict__ loss) {
+// (db4), loss = inv_count * sum_b part[b][32] (the mean); one workgroup.
+__global__ void __launch_bounds__(64 * SP_WAVES)
+cnn_head_finish_kernel(const float* __restrict__ part, int n_parts, float inv_count, float* __restrict__ grad4,
+                       float* __restrict__ loss) {
+  const float s = sum_parts_block(part, n_parts, 34);
   const int t = threadIdx.x;
-  if (t >= 34) return;
-  float s = 0.f;
-  for (int b = 0; b < n_parts; ++b) s += part[(int64_t)b * 34 + t];
   if (t < 32) grad4[t] = s;
   else if (t == 32) *loss = s * inv_count;
-  else grad4[32] = s;
+  else if (t == 33) grad4[32] = s;
 }
 
 __device__ __forceinline__ float softplus_f(float z) { return fmaxf(z, 0.f) + log1pf(expf(-fabsf(z))); }
@@ -592,18 +769,38 @@ hipError_t cnn_conv(int layer, int dir, const float* in, const float* wp, const 
   return hipErrorInvalidValue;
 }
 
+// Weight gradients of the 32 -> 32 layers: matrix cores (default) or the
+// vector-ALU kernel; both sum the same products in float32 per workgroup.
+static bool g_cnn_wgrad_mfma = true;
+
+void set_cnn_wgrad_mfma(bool on) { g_cnn_wgrad_mfma = on; }
+bool get_cnn_wgrad_mfma() { return g_cnn_wgrad_mfma; }
+
 int64_t cnn_wgrad_blocks(int64_t n_img, int H, int W) {
   const int64_t tiles = n_img * ceil_div(W, CT_W) * ceil_div(H, CT_H);
   return tiles < 512 ? tiles : 512;
 }
 
+// blocks: in, the partial-sum slots available; out, the slots written.
 template <int K, int D>
 static hipError_t wgrad32_t(const float* a, const float* g, int64_t n_img, int H, int W, float* part,
-                            int64_t blocks, hipStream_t s) {
+                            int64_t& blocks, hipStream_t s) {
   constexpr int R = D * (K - 1) / 2;
   constexpr int LH = CT_H + 2 * R, LW = CT_W + 2 * R;
-  const size_t lds = sizeof(float) * (32 * (CNT + 1) + 8 * (LH * LW + 1));
   const int tx = ceil_div(W, CT_W), ty = ceil_div(H, CT_H);
+  // the matrix-core kernel addresses an image's 32 channels with 32-bit offsets
+  if (g_cnn_wgrad_mfma && 32LL * H * W < (1LL << 31)) {
+    // one 512-thread workgroup fills a CU's LDS: one per CU
+    if (blocks > 256) blocks = 256;
+    const size_t lds = sizeof(float) * (32 * (CNT + 1) + 32 * (LH * LW + 1));
+    const void* k = reinterpret_cast<const void*>(cnn_wgrad32_mfma_kernel<K, D>);
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((cnn_wgrad32_mfma_kernel<K, D>), dim3((unsigned)blocks), dim3(512), lds, s, a, g, H, W,
+                       tx, tx * ty, n_img * tx * ty, part);
+    return hipGetLastError();
+  }
+  const size_t lds = sizeof(float) * (32 * (CNT + 1) + 8 * (LH * LW + 1));
   hipLaunchKernelGGL((cnn_wgrad32_kernel<K, D>), dim3((unsigned)blocks), dim3(256), lds, s, a, g, H, W, tx,
                      tx * ty, n_img * tx * ty, part);
   return hipGetLastError();
@@ -612,7 +809,7 @@ static hipError_t wgrad32_t(const float* a, const float* g, int64_t n_img, int H
 // Gradient of layer `layer`'s weights and bias (flat, W then b) into dst.
 hipError_t cnn_wgrad(int layer, const float* a, const float* g, int64_t n_img, int H, int W, float* part,
                      float* dst, hipStream_t s) {
-  const int64_t blocks = cnn_wgrad_blocks(n_img, H, W);
+  int64_t blocks = cnn_wgrad_blocks(n_img, H, W);
   if (blocks <= 0) return hipSuccess;
   int nw = 0;
   hipError_t e = hipSuccess;
@@ -632,7 +829,8 @@ hipError_t cnn_wgrad(int layer, const float* a, const float* g, int64_t n_img, i
     return hipErrorInvalidValue;
   }
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(cnn_sum_parts_kernel, dim3(ceil_div(nw, 256)), dim3(256), 0, s, part, (int)blocks, nw, dst);
+  hipLaunchKernelGGL(cnn_sum_parts_kernel, dim3(ceil_div(nw, 64)), dim3(64 * SP_WAVES), 0, s, part, (int)blocks, nw,
+                     dst);
   return hipGetLastError();
 }
 
@@ -661,7 +859,7 @@ hipError_t cnn_head_bwd(const float* logits, const uint8_t* labels, const float*
                      (int64_t)H * W, n_total, pos_weight, (float)(1.0 / (double)n_total), g3, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(cnn_head_finish_kernel, dim3(1), dim3(64), 0, s, part, (int)blocks,
+  hipLaunchKernelGGL(cnn_head_finish_kernel, dim3(1), dim3(64 * SP_WAVES), 0, s, part, (int)blocks,
                      (float)(1.0 / (double)n_total), grad4, loss);
   return hipGetLastError();
 }

@@ -104,6 +104,35 @@ def test_grad_matches_oracle(qc, n, H, W, pw):
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("n,H,W", [(2, 19, 70), (130, 3, 40), (300, 8, 1)])
+def test_grad_variants_match_oracle(qc, variant, n, H, W):
+    # both weight-gradient kernels; 130 x 3 x 40 and 300 x 8 x 1 give more
+    # pixel tiles than workgroups, so workgroups sum several ragged tiles
+    import torch
+    rng = np.random.default_rng(n * H + W)
+    p = _params(n + H + W)
+    x = rng.normal(0, 1.0, (n, H, W)).astype(np.float32)
+    y = (rng.random((n, H, W)) < 0.2).astype(np.uint8)
+    old = qc.cnn_wgrad_variant()
+    try:
+        qc.cnn_wgrad_variant(variant)
+        g, loss = qc.cnn_grad(_t(p), _t(x), _t(y), 3.0)
+        torch.cuda.synchronize()
+    finally:
+        qc.cnn_wgrad_variant(old)
+    g = g.cpu().numpy()
+    loss_ref, g_ref = cnn.loss_and_grad(p.astype(np.float64), x.astype(np.float64), y, 3.0)
+    assert abs(float(loss.cpu().numpy()[0]) - loss_ref) <= 1e-5 * abs(loss_ref)
+    o = 0
+    for s in SHAPES:
+        k = int(np.prod(s))
+        ref = g_ref[o:o + k]
+        assert np.max(np.abs(g[o:o + k] - ref)) <= 1e-4 * np.max(np.abs(ref)) + 1e-12, (s, o)
+        o += k
+
+
+@pytest.mark.gpu
 def test_grad_is_deterministic(qc):
     import torch
     rng = np.random.default_rng(4)
