@@ -384,15 +384,17 @@ qc_status qc_cnn_flag(const float* params, const float* vis, int64_t n_time, int
                       int32_t n_chan, float logit_threshold, int32_t act_prec, uint8_t* mask,
                       void* stream);
 
-/* Weight-gradient kernel of the two 32 -> 32 layers used by qc_cnn_grad and
- * qc_cnn_train_step (process-wide; not thread-safe against concurrent
- * calls): 0 (default) the matrix cores, each 5 x 5 tap's 32 x 32 gradient a
- * product of the output gradient and the shifted input over the pixels
- * (v_mfma_f32_32x32x2_f32); 1 the vector ALU.  Both sum the same float32
- * products per workgroup in a fixed order (deterministic); the choice
- * affects rounding order and speed only. */
-qc_status qc_cnn_set_wgrad_variant(int32_t variant);
-int32_t qc_cnn_get_wgrad_variant(void);
+/* Kernel choice for the float32 work of the two 32 -> 32 layers
+ * (convolutions forward and backward-data, weight gradients), used by
+ * qc_cnn_forward (act_prec 0), qc_cnn_grad, qc_cnn_train_step and qc_cnn_flag
+ * (act_prec 0); process-wide, not thread-safe against concurrent calls.
+ * 0 (default): the matrix cores, v_mfma_f32_32x32x2_f32 (convolution: per
+ * tap, a 32 x 32 weight block times the shifted input; weight gradient: per
+ * tap, the output gradient times the shifted input over the pixels);
+ * 1: the vector ALU.  Both are float32 throughout and deterministic; the
+ * choice affects rounding order and speed only. */
+qc_status qc_cnn_set_variant(int32_t variant);
+int32_t qc_cnn_get_variant(void);
 
 /* Human-readable name of a status code (static storage). */
 const char* qc_status_string(qc_status s);

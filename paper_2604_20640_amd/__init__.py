@@ -17,7 +17,7 @@ __all__ = [
     "QCError", "lib", "pfb_channelize", "xcorrelate", "xcorrelate_chan", "mad_flag",
     "apply_delay_phase", "n_base", "PREC", "timing_enable", "timing_read", "KERNELS", "Stream",
     "solve_delay_phase", "Plan", "cnn_param_count", "cnn_normalize", "cnn_forward", "cnn_grad", "cnn_adam",
-    "cnn_train_step", "cnn_flag", "channelize_variant", "cnn_wgrad_variant",
+    "cnn_train_step", "cnn_flag", "channelize_variant", "cnn_variant",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -142,10 +142,10 @@ def lib() -> ctypes.CDLL:
         L.qc_xengine_set_variant.restype = ctypes.c_int32
         L.qc_xengine_get_variant.argtypes = []
         L.qc_xengine_get_variant.restype = ctypes.c_int32
-        L.qc_cnn_set_wgrad_variant.argtypes = [_I32]
-        L.qc_cnn_set_wgrad_variant.restype = ctypes.c_int32
-        L.qc_cnn_get_wgrad_variant.argtypes = []
-        L.qc_cnn_get_wgrad_variant.restype = ctypes.c_int32
+        L.qc_cnn_set_variant.argtypes = [_I32]
+        L.qc_cnn_set_variant.restype = ctypes.c_int32
+        L.qc_cnn_get_variant.argtypes = []
+        L.qc_cnn_get_variant.restype = ctypes.c_int32
         L.qc_cnn_param_count.argtypes = []
         L.qc_cnn_param_count.restype = ctypes.c_int32
         L.qc_timing_enable.argtypes = [ctypes.c_int32]
@@ -319,12 +319,12 @@ def channelize_variant(v=None):
     return int(lib().qc_channelize_get_variant())
 
 
-def cnn_wgrad_variant(v=None):
-    """Get (and with v, set) the flagger weight-gradient kernel: 0 matrix
-    cores, 1 vector ALU."""
+def cnn_variant(v=None):
+    """Get (and with v, set) the flagger's float32 kernels (convolutions and
+    weight gradients): 0 matrix cores, 1 vector ALU."""
     if v is not None:
-        _check(lib().qc_cnn_set_wgrad_variant(int(v)), "qc_cnn_set_wgrad_variant")
-    return int(lib().qc_cnn_get_wgrad_variant())
+        _check(lib().qc_cnn_set_variant(int(v)), "qc_cnn_set_variant")
+    return int(lib().qc_cnn_get_variant())
 
 
 def xengine_variant(v=None):

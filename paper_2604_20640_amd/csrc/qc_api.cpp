@@ -1396,14 +1396,14 @@ qc_status qc_xengine_set_variant(int32_t variant) {
 
 int32_t qc_xengine_get_variant(void) { return qc::get_xeng_f32_variant(); }
 
-qc_status qc_cnn_set_wgrad_variant(int32_t variant) {
+qc_status qc_cnn_set_variant(int32_t variant) {
   g_err.clear();
   if (variant < 0 || variant > 1) return fail(QC_EINVAL, "variant must be 0 or 1");
-  qc::set_cnn_wgrad_mfma(variant == 0);
+  qc::set_cnn_mfma(variant == 0);
   return QC_OK;
 }
 
-int32_t qc_cnn_get_wgrad_variant(void) { return qc::get_cnn_wgrad_mfma() ? 0 : 1; }
+int32_t qc_cnn_get_variant(void) { return qc::get_cnn_mfma() ? 0 : 1; }
 
 qc_status qc_cnn_normalize(const float* vis, int64_t n_time, int64_t n_base, int32_t n_chan, float* x,
                            void* stream) {

@@ -30,6 +30,8 @@ constexpr int CT_H = 8;   // output tile rows
 constexpr int CT_W = 32;  // output tile columns; 256 threads, one pixel each
 constexpr int CNT = CT_H * CT_W;
 
+typedef float mf32x16_t __attribute__((ext_vector_type(16)));
+
 __device__ __forceinline__ int64_t img_off(int64_t n, int c, int C, int H, int W) {
   return ((n * C + c) * (int64_t)H) * W;
 }
@@ -102,6 +104,140 @@ cnn_conv_kernel(const float* __restrict__ in, const float* __restrict__ wp, cons
       if constexpr (MODE == 1) v = gate[oi] > 0.f ? v : 0.f;
       if constexpr (MODE == 2) v = v + bias[o];
       out[oi] = v;
+    }
+  }
+}
+
+// Float32 5x5 32 -> 32 convolution on the matrix cores, an implicit GEMM:
+// out[co][p] = sum over (tap, ci) of P[ci][tap][co] in[ci][p + tap offset],
+// one v_mfma_f32_32x32x2_f32 per tap and pair of input channels (lane l:
+// output channel = pixel slot l % 32, input channel 2s + l / 32).  P is the
+// [in][tap][out] packing cnn_pack writes for both directions, copied once
+// per workgroup into LDS in operand order.  Tiles of 8 x 32 pixels (wave w:
+// row w) are staged 16 input channels at a time, the next half-tile's values
+// travelling in registers while this one is reduced.  Input-channel pairs
+// rotate over four accumulators, added in the epilogue.  MODE as for
+// cnn_conv_kernel.
+constexpr int CM_NTH = 512, CM_HC = 16;
+
+constexpr int cm_cs(int D) {  // channel stride of the staged half-tile, = 32 mod 64
+  return (CT_H + 4 * D) * (CT_W + 4 * D) + (96 - ((CT_H + 4 * D) * (CT_W + 4 * D)) % 64) % 64;
+}
+constexpr size_t cm_lds(int D) { return sizeof(float) * (25 * 16 * 64 + CM_HC * cm_cs(D)); }
+
+template <int D, int MODE>
+__global__ void __launch_bounds__(CM_NTH)
+cnn_conv32_mfma_kernel(const float* __restrict__ in, const float* __restrict__ wp, const float* __restrict__ bias,
+                       const float* __restrict__ gate, int H, int W, int tiles_x, int tiles_per_img,
+                       int64_t n_tiles, float* __restrict__ out) {
+  constexpr int C = 32, NT = 25, R = 2 * D;
+  constexpr int LH = CT_H + 2 * R, LW = CT_W + 2 * R, PL = LH * LW, CS = cm_cs(D);
+  constexpr int IH = (CM_HC * PL + CM_NTH - 1) / CM_NTH;
+  static_assert(CS % 64 == 32 && CS >= PL, "channel stride");
+  static_assert(cm_lds(D) <= 160 * 1024, "LDS");
+  static_assert(CM_NTH / 64 == CT_H && CT_W == 32, "one tile row per wave, one MFMA column block");
+  extern __shared__ float sm[];
+  float* sw = sm;                   // [tap][s][lane]
+  float* st = sm + NT * 16 * 64;    // [CM_HC][CS]
+  const int t = threadIdx.x, lane = t & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int px = lane & 31, kh = lane >> 5;
+  for (int e = t; e < NT * 16 * 64; e += CM_NTH) {
+    const int l = e & 63, sk = (e >> 6) & 15, tap = e >> 10;
+    sw[e] = wp[((2 * sk + (l >> 5)) * NT + tap) * C + (l & 31)];
+  }
+  float bco[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) bco[r] = MODE != 1 ? bias[8 * (r >> 2) + 4 * kh + (r & 3)] : 0.f;
+  const int HW = H * W;             // C * H * W < 2^31: 32-bit offsets in an image
+  float pre[IH];
+  // half h of tile tl: input channels 16 h .. 16 h + 15 with the halo
+  auto load_half = [&](int64_t tl, int h) {
+    const int64_t n = tl / tiles_per_img;
+    const int tt = (int)(tl % tiles_per_img);
+    const int y0 = (tt / tiles_x) * CT_H, x0 = (tt % tiles_x) * CT_W;
+    const float* ip = in + img_off(n, CM_HC * h, C, H, W);
+    int tv = t;
+    asm volatile("" : "+v"(tv));    // offsets are recomputed per stage, not held live
+#pragma unroll
+    for (int i = 0; i < IH; ++i) {
+      const int f = tv + CM_NTH * i;
+      const int c = f / PL, r = (f / LW) % LH, q = f % LW;
+      const int y = y0 + r - R, x = x0 + q - R;
+      const bool ok = (IH * CM_NTH == CM_HC * PL || f < CM_HC * PL) && y >= 0 && y < H && x >= 0 && x < W;
+      const float v = ip[ok ? c * HW + y * W + x : 0];
+      pre[i] = ok ? v : 0.f;
+    }
+  };
+  if ((int64_t)blockIdx.x < n_tiles) load_half(blockIdx.x, 0);
+  for (int64_t tl = blockIdx.x; tl < n_tiles; tl += gridDim.x) {
+    mf32x16_t acc[4];   // four independent accumulation chains, added at the end
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[j][r] = 0.f;
+#pragma unroll 1
+    for (int h = 0; h < 2; ++h) {
+      __syncthreads();  // the previous stage's reads are done (and the weights stored)
+      {
+        int tv = t;
+        asm volatile("" : "+v"(tv));
+#pragma unroll
+        for (int i = 0; i < IH; ++i) {
+          const int f = tv + CM_NTH * i;
+          if (IH * CM_NTH == CM_HC * PL || f < CM_HC * PL) st[f + (f / PL) * (CS - PL)] = pre[i];
+        }
+      }
+      __syncthreads();
+      if (h == 0)
+        load_half(tl, 1);
+      else if (tl + gridDim.x < n_tiles)
+        load_half(tl + gridDim.x, 0);
+      const float* ab = sw + (8 * h) * 64 + lane;
+      const float* bb = st + kh * CS + wave * LW + px;
+      // operands of tap + 1 are read while tap's products run
+      float av[8], bv[8];
+#pragma unroll
+      for (int sk = 0; sk < 8; ++sk) {
+        av[sk] = ab[sk * 64];
+        bv[sk] = bb[2 * sk * CS];
+      }
+#pragma unroll 1
+      for (int tap = 0; tap < NT; ++tap) {
+        const int tn = tap + 1 < NT ? tap + 1 : tap;
+        const float* a = ab + tn * 16 * 64;
+        const float* b = bb + (tn / 5) * D * LW + (tn % 5) * D;
+        float an[8], bn[8];
+#pragma unroll
+        for (int sk = 0; sk < 8; ++sk) {
+          an[sk] = a[sk * 64];
+          bn[sk] = b[2 * sk * CS];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int sk = 0; sk < 8; ++sk) acc[sk & 3] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[sk], bv[sk], acc[sk & 3], 0, 0, 0);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int sk = 0; sk < 8; ++sk) {
+          av[sk] = an[sk];
+          bv[sk] = bn[sk];
+        }
+      }
+    }
+    const int64_t n = tl / tiles_per_img;
+    const int tt = (int)(tl % tiles_per_img);
+    const int y = (tt / tiles_x) * CT_H + wave, x = (tt % tiles_x) * CT_W + px;
+    if (y < H && x < W) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int o = 8 * (r >> 2) + 4 * kh + (r & 3);   // accumulator row: output channel
+        const int64_t oi = img_off(n, o, C, H, W) + (int64_t)y * W + x;
+        float v = (acc[0][r] + acc[1][r]) + (acc[2][r] + acc[3][r]);
+        if constexpr (MODE == 0) v = fmaxf(v + bco[r], 0.f);
+        if constexpr (MODE == 1) v = gate[oi] > 0.f ? v : 0.f;
+        if constexpr (MODE == 2) v = v + bco[r];
+        out[oi] = v;
+      }
     }
   }
 }
@@ -195,8 +331,6 @@ cnn_wgrad32_kernel(const float* __restrict__ a, const float* __restrict__ g, int
     out[C * C * NT + t] = sb;
   }
 }
-
-typedef float mf32x16_t __attribute__((ext_vector_type(16)));
 
 // One staged pixel tile's products for a wave's NQ taps: rows of 32 pixels,
 // each two pixels per step (lanes 32..63 the odd one), every tap's operand at
@@ -742,12 +876,31 @@ hipError_t cnn_pack(const float* w, int CI, int CO, int K, int flip, float* p, h
   return hipGetLastError();
 }
 
+// Float32 kernels of the flagger: matrix cores (default) or vector ALU.
+static bool g_cnn_mfma = true;
+
+void set_cnn_mfma(bool on) { g_cnn_mfma = on; }
+bool get_cnn_mfma() { return g_cnn_mfma; }
+
 template <int CI, int CO, int K, int D, int MODE>
 static hipError_t conv_t(const float* in, const float* wp, const float* b, const float* gate, int64_t n_img,
                          int H, int W, float* out, hipStream_t s) {
   const int tx = ceil_div(W, CT_W), ty = ceil_div(H, CT_H);
   const int64_t blocks = n_img * tx * ty;
   if (blocks <= 0) return hipSuccess;
+  if constexpr (CI == 32 && CO == 32 && K == 5) {
+    // the matrix-core kernel addresses an image's 32 channels with 32-bit offsets
+    if (g_cnn_mfma && 32LL * H * W < (1LL << 31)) {
+      const size_t lds = cm_lds(D);
+      const void* k = reinterpret_cast<const void*>(cnn_conv32_mfma_kernel<D, MODE>);
+      hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+      const int64_t grid = blocks < 256 ? blocks : 256;   // one workgroup per CU, striding over tiles
+      hipLaunchKernelGGL((cnn_conv32_mfma_kernel<D, MODE>), dim3((unsigned)grid), dim3(CM_NTH), lds, s, in, wp, b,
+                         gate, H, W, tx, tx * ty, blocks, out);
+      return hipGetLastError();
+    }
+  }
   if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
   hipLaunchKernelGGL((cnn_conv_kernel<CI, CO, K, D, MODE>), dim3((unsigned)blocks), dim3(CNT), 0, s, in, wp, b,
                      gate, H, W, tx, tx * ty, out);
@@ -769,12 +922,6 @@ hipError_t cnn_conv(int layer, int dir, const float* in, const float* wp, const 
   return hipErrorInvalidValue;
 }
 
-// Weight gradients of the 32 -> 32 layers: matrix cores (default) or the
-// vector-ALU kernel; both sum the same products in float32 per workgroup.
-static bool g_cnn_wgrad_mfma = true;
-
-void set_cnn_wgrad_mfma(bool on) { g_cnn_wgrad_mfma = on; }
-bool get_cnn_wgrad_mfma() { return g_cnn_wgrad_mfma; }
 
 int64_t cnn_wgrad_blocks(int64_t n_img, int H, int W) {
   const int64_t tiles = n_img * ceil_div(W, CT_W) * ceil_div(H, CT_H);
@@ -789,7 +936,7 @@ static hipError_t wgrad32_t(const float* a, const float* g, int64_t n_img, int H
   constexpr int LH = CT_H + 2 * R, LW = CT_W + 2 * R;
   const int tx = ceil_div(W, CT_W), ty = ceil_div(H, CT_H);
   // the matrix-core kernel addresses an image's 32 channels with 32-bit offsets
-  if (g_cnn_wgrad_mfma && 32LL * H * W < (1LL << 31)) {
+  if (g_cnn_mfma && 32LL * H * W < (1LL << 31)) {
     // one 512-thread workgroup fills a CU's LDS: one per CU
     if (blocks > 256) blocks = 256;
     const size_t lds = sizeof(float) * (32 * (CNT + 1) + 32 * (LH * LW + 1));

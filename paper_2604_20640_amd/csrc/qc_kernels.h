@@ -156,10 +156,10 @@ hipError_t cnn_pack(const float* w, int CI, int CO, int K, int flip, float* p, h
 hipError_t cnn_conv(int layer, int dir, const float* in, const float* wp, const float* b, const float* gate,
                     int64_t n_img, int H, int W, float* out, hipStream_t s);
 int64_t cnn_wgrad_blocks(int64_t n_img, int H, int W);
-// Weight gradients of the 32 -> 32 layers on the matrix cores (default) or
-// the vector ALU (process-wide).
-void set_cnn_wgrad_mfma(bool on);
-bool get_cnn_wgrad_mfma();
+// Float32 convolutions and weight gradients of the 32 -> 32 layers on the
+// matrix cores (default) or the vector ALU (process-wide).
+void set_cnn_mfma(bool on);
+bool get_cnn_mfma();
 // Weight and bias gradient of layer 1..3 into dst (flat W then b); part
 // holds cnn_wgrad_blocks() * (weights + biases) floats.
 hipError_t cnn_wgrad(int layer, const float* a, const float* g, int64_t n_img, int H, int W, float* part,

@@ -136,11 +136,11 @@ def test_kernel_variant_switches():
     finally:
         L.qc_xengine_set_variant(0)
     assert qc.xengine_variant() == 0
-    assert L.qc_cnn_get_wgrad_variant() == 0
+    assert L.qc_cnn_get_variant() == 0
     for bad in (-1, 2):
-        assert L.qc_cnn_set_wgrad_variant(bad) == QC_EINVAL
+        assert L.qc_cnn_set_variant(bad) == QC_EINVAL
     try:
-        assert L.qc_cnn_set_wgrad_variant(1) == 0 and qc.cnn_wgrad_variant() == 1
+        assert L.qc_cnn_set_variant(1) == 0 and qc.cnn_variant() == 1
     finally:
-        L.qc_cnn_set_wgrad_variant(0)
-    assert qc.cnn_wgrad_variant() == 0
+        L.qc_cnn_set_variant(0)
+    assert qc.cnn_variant() == 0

@@ -68,9 +68,20 @@ def test_cnn_entry_points_reject_bad_arguments():
 
 # ---------------------------------------------------------------- GPU parity
 
+@pytest.fixture(params=[0, 1], ids=["mfma", "valu"])
+def cnn_variant(request, qc):
+    """Run the test with the float32 convolutions and weight gradients on the
+    matrix cores (0) and on the vector ALU (1)."""
+    old = qc.cnn_variant()
+    qc.cnn_variant(request.param)
+    yield request.param
+    qc.cnn_variant(old)
+
+
 @pytest.mark.gpu
-@pytest.mark.parametrize("n,H,W", [(2, 13, 37), (1, 8, 32), (3, 5, 70), (1, 1, 1), (2, 21, 9)])
-def test_forward_matches_oracle(qc, n, H, W):
+@pytest.mark.parametrize("n,H,W", [(2, 13, 37), (1, 8, 32), (3, 5, 70), (1, 1, 1), (2, 21, 9), (130, 3, 40)])
+def test_forward_matches_oracle(qc, cnn_variant, n, H, W):
+    # 130 x 3 x 40 gives more pixel tiles than the matrix-core kernel's workgroups
     import torch
     p = _params(n * 100 + H)
     x = np.random.default_rng(H * W).normal(0, 1.0, (n, H, W)).astype(np.float32)
@@ -104,23 +115,17 @@ def test_grad_matches_oracle(qc, n, H, W, pw):
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("variant", [0, 1])
 @pytest.mark.parametrize("n,H,W", [(2, 19, 70), (130, 3, 40), (300, 8, 1)])
-def test_grad_variants_match_oracle(qc, variant, n, H, W):
-    # both weight-gradient kernels; 130 x 3 x 40 and 300 x 8 x 1 give more
-    # pixel tiles than workgroups, so workgroups sum several ragged tiles
+def test_grad_variants_match_oracle(qc, cnn_variant, n, H, W):
+    # both kernel sets; 130 x 3 x 40 and 300 x 8 x 1 give more pixel tiles
+    # than workgroups, so workgroups work through several ragged tiles
     import torch
     rng = np.random.default_rng(n * H + W)
     p = _params(n + H + W)
     x = rng.normal(0, 1.0, (n, H, W)).astype(np.float32)
     y = (rng.random((n, H, W)) < 0.2).astype(np.uint8)
-    old = qc.cnn_wgrad_variant()
-    try:
-        qc.cnn_wgrad_variant(variant)
-        g, loss = qc.cnn_grad(_t(p), _t(x), _t(y), 3.0)
-        torch.cuda.synchronize()
-    finally:
-        qc.cnn_wgrad_variant(old)
+    g, loss = qc.cnn_grad(_t(p), _t(x), _t(y), 3.0)
+    torch.cuda.synchronize()
     g = g.cpu().numpy()
     loss_ref, g_ref = cnn.loss_and_grad(p.astype(np.float64), x.astype(np.float64), y, 3.0)
     assert abs(float(loss.cpu().numpy()[0]) - loss_ref) <= 1e-5 * abs(loss_ref)
@@ -177,7 +182,7 @@ def test_normalize_matches_oracle(qc, n_time, n_base, n_chan):
 
 
 @pytest.mark.gpu
-def test_flag_matches_oracle(qc):
+def test_flag_matches_oracle(qc, cnn_variant):
     import torch
     rng = np.random.default_rng(12)
     n_time, n_base, n_chan = 16, 3, 40
