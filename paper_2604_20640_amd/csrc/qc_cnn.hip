@@ -110,20 +110,22 @@ cnn_conv_kernel(const float* __restrict__ in, const float* __restrict__ wp, cons
 
 // Float32 5x5 32 -> 32 convolution on the matrix cores, an implicit GEMM:
 // out[co][p] = sum over (tap, ci) of P[ci][tap][co] in[ci][p + tap offset],
-// one v_mfma_f32_32x32x2_f32 per tap and pair of input channels (lane l:
-// output channel = pixel slot l % 32, input channel 2s + l / 32).  P is the
-// [in][tap][out] packing cnn_pack writes for both directions, copied once
-// per workgroup into LDS in operand order.  Tiles of 8 x 32 pixels (wave w:
-// row w) are staged 16 input channels at a time, the next half-tile's values
-// travelling in registers while this one is reduced.  Input-channel pairs
-// rotate over four accumulators, added in the epilogue.  MODE as for
+// one v_mfma_f32_32x32x2_f32 per tap and pair of input channels.  P is the
+// [in][tap][out] packing cnn_pack writes for both directions.  A tile is
+// 8 x 32 pixels (wave w: row w), reduced in two halves of 16 input channels
+// h; within a half, product (q, j) pairs channels 16h + 4q + j and
+// 16h + 8 + 4q + j (lane l: output channel = pixel slot l % 32, the pair's
+// member l / 32), so each lane's operands of four products are 16
+// contiguous bytes in LDS: the weights [tap][h][q][lane][4] (copied once
+// per workgroup, 100 KB) and the staged half-tile channel-fastest,
+// [pixel][16 channels] with an 80-byte pixel stride (conflict-free 16-byte
+// reads).  The next half-tile's values travel in registers while this one
+// is reduced; four accumulators take the four j.  MODE as for
 // cnn_conv_kernel.
-constexpr int CM_NTH = 512, CM_HC = 16;
+constexpr int CM_NTH = 512, CM_HC = 16, CM_PS = 20;
 
-constexpr int cm_cs(int D) {  // channel stride of the staged half-tile, = 32 mod 64
-  return (CT_H + 4 * D) * (CT_W + 4 * D) + (96 - ((CT_H + 4 * D) * (CT_W + 4 * D)) % 64) % 64;
-}
-constexpr size_t cm_lds(int D) { return sizeof(float) * (25 * 16 * 64 + CM_HC * cm_cs(D)); }
+constexpr int cm_pl(int D) { return (CT_H + 4 * D) * (CT_W + 4 * D); }
+constexpr size_t cm_lds(int D) { return sizeof(float) * (25 * 16 * 64 + cm_pl(D) * CM_PS); }
 
 template <int D, int MODE>
 __global__ void __launch_bounds__(CM_NTH)
@@ -131,27 +133,29 @@ cnn_conv32_mfma_kernel(const float* __restrict__ in, const float* __restrict__ w
                        const float* __restrict__ gate, int H, int W, int tiles_x, int tiles_per_img,
                        int64_t n_tiles, float* __restrict__ out) {
   constexpr int C = 32, NT = 25, R = 2 * D;
-  constexpr int LH = CT_H + 2 * R, LW = CT_W + 2 * R, PL = LH * LW, CS = cm_cs(D);
+  constexpr int LH = CT_H + 2 * R, LW = CT_W + 2 * R, PL = LH * LW;
   constexpr int IH = (CM_HC * PL + CM_NTH - 1) / CM_NTH;
-  static_assert(CS % 64 == 32 && CS >= PL, "channel stride");
   static_assert(cm_lds(D) <= 160 * 1024, "LDS");
   static_assert(CM_NTH / 64 == CT_H && CT_W == 32, "one tile row per wave, one MFMA column block");
-  extern __shared__ float sm[];
-  float* sw = sm;                   // [tap][s][lane]
-  float* st = sm + NT * 16 * 64;    // [CM_HC][CS]
+  extern __shared__ float4 sm4[];
+  float4* sw = sm4;                                              // [tap][h][q][lane]
+  float* st = reinterpret_cast<float*>(sm4 + NT * 2 * 2 * 64);  // [pixel][CM_PS]
   const int t = threadIdx.x, lane = t & 63;
   const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
   const int px = lane & 31, kh = lane >> 5;
-  for (int e = t; e < NT * 16 * 64; e += CM_NTH) {
-    const int l = e & 63, sk = (e >> 6) & 15, tap = e >> 10;
-    sw[e] = wp[((2 * sk + (l >> 5)) * NT + tap) * C + (l & 31)];
+  for (int e = t; e < NT * 2 * 2 * 64; e += CM_NTH) {
+    const int l = e & 63, q = (e >> 6) & 1, h = (e >> 7) & 1, tap = e >> 8;
+    const int c0 = 16 * h + 8 * (l >> 5) + 4 * q, co = l & 31;
+    sw[e] = make_float4(wp[((c0 + 0) * NT + tap) * C + co], wp[((c0 + 1) * NT + tap) * C + co],
+                        wp[((c0 + 2) * NT + tap) * C + co], wp[((c0 + 3) * NT + tap) * C + co]);
   }
   float bco[16];
 #pragma unroll
   for (int r = 0; r < 16; ++r) bco[r] = MODE != 1 ? bias[8 * (r >> 2) + 4 * kh + (r & 3)] : 0.f;
   const int HW = H * W;             // C * H * W < 2^31: 32-bit offsets in an image
   float pre[IH];
-  // half h of tile tl: input channels 16 h .. 16 h + 15 with the halo
+  // half h of tile tl: input channels 16 h .. 16 h + 15 with the halo,
+  // element f = [channel][row][col] (coalesced global reads)
   auto load_half = [&](int64_t tl, int h) {
     const int64_t n = tl / tiles_per_img;
     const int tt = (int)(tl % tiles_per_img);
@@ -171,7 +175,7 @@ cnn_conv32_mfma_kernel(const float* __restrict__ in, const float* __restrict__ w
   };
   if ((int64_t)blockIdx.x < n_tiles) load_half(blockIdx.x, 0);
   for (int64_t tl = blockIdx.x; tl < n_tiles; tl += gridDim.x) {
-    mf32x16_t acc[4];   // four independent accumulation chains, added at the end
+    mf32x16_t acc[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
@@ -185,7 +189,7 @@ cnn_conv32_mfma_kernel(const float* __restrict__ in, const float* __restrict__ w
 #pragma unroll
         for (int i = 0; i < IH; ++i) {
           const int f = tv + CM_NTH * i;
-          if (IH * CM_NTH == CM_HC * PL || f < CM_HC * PL) st[f + (f / PL) * (CS - PL)] = pre[i];
+          if (IH * CM_NTH == CM_HC * PL || f < CM_HC * PL) st[(f % PL) * CM_PS + f / PL] = pre[i];
         }
       }
       __syncthreads();
@@ -193,35 +197,32 @@ cnn_conv32_mfma_kernel(const float* __restrict__ in, const float* __restrict__ w
         load_half(tl, 1);
       else if (tl + gridDim.x < n_tiles)
         load_half(tl + gridDim.x, 0);
-      const float* ab = sw + (8 * h) * 64 + lane;
-      const float* bb = st + kh * CS + wave * LW + px;
+      const float4* ab = sw + h * 2 * 64 + lane;
+      const float* bb = st + (wave * LW + px) * CM_PS + 8 * kh;
       // operands of tap + 1 are read while tap's products run
-      float av[8], bv[8];
-#pragma unroll
-      for (int sk = 0; sk < 8; ++sk) {
-        av[sk] = ab[sk * 64];
-        bv[sk] = bb[2 * sk * CS];
-      }
-#pragma unroll 1
+      float4 a0 = ab[0], a1 = ab[64];
+      float4 b0 = *reinterpret_cast<const float4*>(bb), b1 = *reinterpret_cast<const float4*>(bb + 4);
+#pragma unroll 5
       for (int tap = 0; tap < NT; ++tap) {
         const int tn = tap + 1 < NT ? tap + 1 : tap;
-        const float* a = ab + tn * 16 * 64;
-        const float* b = bb + (tn / 5) * D * LW + (tn % 5) * D;
-        float an[8], bn[8];
-#pragma unroll
-        for (int sk = 0; sk < 8; ++sk) {
-          an[sk] = a[sk * 64];
-          bn[sk] = b[2 * sk * CS];
-        }
+        const float4* a = ab + tn * 4 * 64;
+        const float* b = bb + ((tn / 5) * D * LW + (tn % 5) * D) * CM_PS;
+        const float4 an0 = a[0], an1 = a[64];
+        const float4 bn0 = *reinterpret_cast<const float4*>(b), bn1 = *reinterpret_cast<const float4*>(b + 4);
         __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int sk = 0; sk < 8; ++sk) acc[sk & 3] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[sk], bv[sk], acc[sk & 3], 0, 0, 0);
+        acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.x, b0.x, acc[0], 0, 0, 0);
+        acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.y, b0.y, acc[1], 0, 0, 0);
+        acc[2] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.z, b0.z, acc[2], 0, 0, 0);
+        acc[3] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.w, b0.w, acc[3], 0, 0, 0);
+        acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1.x, b1.x, acc[0], 0, 0, 0);
+        acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1.y, b1.y, acc[1], 0, 0, 0);
+        acc[2] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1.z, b1.z, acc[2], 0, 0, 0);
+        acc[3] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1.w, b1.w, acc[3], 0, 0, 0);
         __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int sk = 0; sk < 8; ++sk) {
-          av[sk] = an[sk];
-          bv[sk] = bn[sk];
-        }
+        a0 = an0;
+        a1 = an1;
+        b0 = bn0;
+        b1 = bn1;
       }
     }
     const int64_t n = tl / tiles_per_img;
