@@ -775,18 +775,31 @@ cnn_mfma_conv_kernel(const _Float16* __restrict__ in, const _Float16* __restrict
     for (int u = 0; u < U; ++u)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[u][r] = 0.f;
-#pragma unroll 5
-    for (int sl = 0; sl < MT_SLICES; ++sl) {
+    // operands of slice sl + 1 are read while slice sl's products run
+    auto opa = [&](int sl) { return __builtin_bit_cast(half8_t, sw[sl * 64 + lane]); };
+    auto opb = [&](int sl, int u) {
       const int tap = sl >> 1, h = sl & 1;
-      const int ky = tap / 5, kx = tap % 5;
-      const half8_t a = __builtin_bit_cast(half8_t, sw[sl * 64 + lane]);
+      const int row = U * wave + u + (tap / 5) * D;
+      return __builtin_bit_cast(
+          half8_t, *reinterpret_cast<const uint4*>(st + (row * LW + px + (tap % 5) * D) * MT_PS + 16 * h + 8 * kh));
+    };
+    half8_t a = opa(0), b[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int row = U * wave + u + ky * D;
-        const half8_t b = __builtin_bit_cast(
-            half8_t, *reinterpret_cast<const uint4*>(st + (row * LW + px + kx * D) * MT_PS + 16 * h + 8 * kh));
-        acc[u] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, acc[u], 0, 0, 0);
-      }
+    for (int u = 0; u < U; ++u) b[u] = opb(0, u);
+#pragma unroll 10
+    for (int sl = 0; sl < MT_SLICES; ++sl) {
+      const int sn = sl + 1 < MT_SLICES ? sl + 1 : sl;
+      const half8_t an = opa(sn);
+      half8_t bn[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) bn[u] = opb(sn, u);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int u = 0; u < U; ++u) acc[u] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b[u], acc[u], 0, 0, 0);
+      __builtin_amdgcn_sched_barrier(0);
+      a = an;
+#pragma unroll
+      for (int u = 0; u < U; ++u) b[u] = bn[u];
     }
     // epilogue: bias, ReLU, half; lane holds output channels
     // {8g + 4kh + i} of pixel px for g, i < 4
