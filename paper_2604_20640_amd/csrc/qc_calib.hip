@@ -116,6 +116,26 @@ __device__ __forceinline__ void find_digit(const unsigned* hist, int64_t kk, uns
 // gathered and ranked by one wave instead of further histogram passes.
 constexpr int SEL_CAND = 64;
 
+// fn(i, key(i)) for this thread's elements i = threadIdx.x + NT j.  The
+// large-population kernel forms its keys in batches of 8 so that as many
+// loads are in flight per thread (populations read from global memory are
+// latency-bound otherwise); the one-wave kernel reads LDS and keeps one.
+template <int NT, typename K, typename KeyFn, typename Fn>
+__device__ __forceinline__ void for_keys(int64_t count, KeyFn key, Fn fn) {
+  constexpr int B = NT >= 256 ? 8 : 1;
+  int64_t i = threadIdx.x;
+  if constexpr (B > 1) {
+    for (; i + (int64_t)(B - 1) * NT < count; i += (int64_t)B * NT) {
+      K kv[B];
+#pragma unroll
+      for (int u = 0; u < B; ++u) kv[u] = key(i + (int64_t)u * NT);
+#pragma unroll
+      for (int u = 0; u < B; ++u) fn(i + (int64_t)u * NT, kv[u]);
+    }
+  }
+  for (; i < count; i += NT) fn(i, key(i));
+}
+
 struct SelScratch {
   unsigned* hist;            // 2^DB bins
   unsigned* wsum;            // NT / 64
@@ -154,10 +174,9 @@ __device__ K radix_select(int64_t count, int64_t k, K kmin, K kmax, KeyFn key, c
     const K dmask = (K)((1u << width) - 1u);
     for (int i = threadIdx.x; i < NBINS; i += NT) sc.hist[i] = 0;
     __syncthreads();
-    for (int64_t i = threadIdx.x; i < count; i += NT) {
-      const K kv = key(i);
+    for_keys<NT, K>(count, key, [&](int64_t, K kv) {
       if ((kv & mask) == prefix) atomicAdd(&sc.hist[(unsigned)((kv >> shift) & dmask)], 1u);
-    }
+    });
     __syncthreads();
     find_digit<NT, NBINS>(sc.hist, kk, sc.wsum, sc.sh);
     const unsigned digit = (unsigned)sc.sh[0];
@@ -194,12 +213,11 @@ __device__ K radix_select(int64_t count, int64_t k, K kmin, K kmax, KeyFn key, c
       }
       if (threadIdx.x == 0) *sc.ncand = 0;
       __syncthreads();
-      for (int64_t i = threadIdx.x; i < count; i += NT) {
-        const K kv = key(i);
+      for_keys<NT, K>(count, key, [&](int64_t, K kv) {
         const K km = kv & mask;
         if (km == prefix || (c2 > 0 && km == prefix2))
           sc.cand[atomicAdd(sc.ncand, 1u)] = (unsigned long long)kv;
-      }
+      });
       c += c2;
       __syncthreads();
       if (threadIdx.x < 64) {
@@ -236,11 +254,10 @@ __device__ K next_rank(int64_t count, int64_t k, K kk, KeyFn key, unsigned long 
   constexpr int NW = NT / 64;
   unsigned long long le = 0;
   K mn = ~(K)0;
-  for (int64_t i = threadIdx.x; i < count; i += NT) {
-    const K kv = key(i);
+  for_keys<NT, K>(count, key, [&](int64_t, K kv) {
     if (kv <= kk) ++le;
     else if (kv < mn) mn = kv;
-  }
+  });
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) {
     le += __shfl_down(le, d);
@@ -394,7 +411,7 @@ mad_kernel(const float2* __restrict__ vis, int64_t n_time, int64_t n_base, int n
   const double c = (double)sigma * 1.4826;
   const double T = med + c * madv;
   if (mask) {
-    if (pop.inner_n >= NT) {
+    if (cached && pop.inner_n >= NT) {
       // element i = q * inner_n + r; a step of NT carries into q at most once
       int64_t q = 0, r = threadIdx.x;
       for (int64_t i = threadIdx.x; i < n; i += NT) {
@@ -406,7 +423,7 @@ mad_kernel(const float2* __restrict__ vis, int64_t n_time, int64_t n_base, int n
         }
       }
     } else {
-      for (int64_t i = threadIdx.x; i < n; i += NT) mask[pop.off(i)] = (double)amp(i) > T ? 1 : 0;
+      for_keys<NT, float>(n, amp, [&](int64_t i, float a) { mask[pop.off(i)] = (double)a > T ? 1 : 0; });
     }
   }
   if (threadIdx.x == 0) {
