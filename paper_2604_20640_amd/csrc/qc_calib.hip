@@ -315,6 +315,33 @@ __global__ void mad_amp_kernel(const float2* __restrict__ vis, int64_t n_time, i
   amp[e] = amp_f32(vis[make_pop(id, n_time, n_base, n_chan, population).off(i)]);
 }
 
+// The same for per-baseline populations (contiguous runs of n_chan, a
+// multiple of 4) of a 32-byte aligned plane: four amplitudes per thread from
+// two 16-byte loads, written with one 16-byte store.
+__global__ void mad_amp4_kernel(const float4* __restrict__ vis, int64_t n_base, int n_chan, int64_t count,
+                                int64_t total4, float4* __restrict__ amp) {
+  const int64_t e4 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e4 >= total4) return;
+  const int64_t e = 4 * e4;
+  int64_t id, t, k;  // baseline, integration, channel (k % 4 == 0)
+  if (4 * total4 <= 0x7fffffffLL) {  // 32-bit division
+    const uint32_t q = (uint32_t)e / (uint32_t)count, i = (uint32_t)e - q * (uint32_t)count;
+    const uint32_t tq = i / (uint32_t)n_chan;
+    id = q;
+    t = tq;
+    k = i - tq * (uint32_t)n_chan;
+  } else {
+    const int64_t i = e % count;
+    id = e / count;
+    t = i / n_chan;
+    k = i % n_chan;
+  }
+  const int64_t v = ((t * n_base + id) * n_chan + k) / 2;  // float4 = two visibilities
+  const float4 a = vis[v], b = vis[v + 1];
+  amp[e4] = make_float4(amp_f32(make_float2(a.x, a.y)), amp_f32(make_float2(a.z, a.w)),
+                        amp_f32(make_float2(b.x, b.y)), amp_f32(make_float2(b.z, b.w)));
+}
+
 template <int NT, int DB>
 __global__ void __launch_bounds__(NT)
 mad_kernel(const float2* __restrict__ vis, int64_t n_time, int64_t n_base, int n_chan, float sigma,
@@ -465,8 +492,16 @@ hipError_t launch_mad(const float2* vis, int64_t n_time, int64_t n_base, int n_c
       // element instead of forming a float64 square root each, and
       // populations beyond the LDS cache read 4 bytes per pass
       const int64_t total = npop * count;
-      hipLaunchKernelGGL(mad_amp_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, vis, n_time,
-                         n_base, n_chan, population, count, total, amp_scratch);
+      if (population == 0 && n_chan % 4 == 0 && (reinterpret_cast<uintptr_t>(vis) & 31u) == 0 &&
+          (reinterpret_cast<uintptr_t>(amp_scratch) & 15u) == 0) {
+        const int64_t total4 = total / 4;
+        hipLaunchKernelGGL(mad_amp4_kernel, dim3((unsigned)((total4 + 255) / 256)), dim3(256), 0, s,
+                           reinterpret_cast<const float4*>(vis), n_base, n_chan, count, total4,
+                           reinterpret_cast<float4*>(amp_scratch));
+      } else {
+        hipLaunchKernelGGL(mad_amp_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, vis, n_time,
+                           n_base, n_chan, population, count, total, amp_scratch);
+      }
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
       gamp = amp_scratch;

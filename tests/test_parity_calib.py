@@ -41,6 +41,23 @@ def test_mad_bit_exact(qc, shape, pop):
         assert np.array_equal(T.cpu().numpy(), T_ref)
 
 
+def test_mad_offset_plane(qc):
+    # a plane that starts one visibility past an aligned address takes the
+    # scalar amplitude pass, an aligned one the 16-byte pass: both bit-exact
+    import torch
+    shape = (8, 3, 4096)
+    v = _vis(shape, seed=77)
+    m_ref, T_ref = mad.mad_flag(v, 5.0, 0)
+    buf = torch.zeros(v.size + 1, dtype=torch.complex64, device="cuda")
+    for off in (0, 1):
+        d = buf[off:off + v.size].view(shape)
+        d.copy_(torch.from_numpy(v).cuda())
+        assert (d.data_ptr() % 32 == 0) == (off == 0)
+        m, T = qc.mad_flag(d, 5.0, 0)
+        assert np.array_equal(m.cpu().numpy(), m_ref), off
+        assert np.array_equal(T.cpu().numpy(), T_ref), off
+
+
 def _tie_plane(shape, pop, pattern, rng):
     """Real-valued visibilities (amplitude exactly |v|) with a tie structure
     inside every population:
