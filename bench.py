@@ -15,7 +15,10 @@ injected lags and the oracle's solve, timed beside it), the 32-antenna
 X-engine comparison (float32 vs FP16/BF16/E4M3 on the matrix cores, with
 visibility errors against the FP64 oracle), five uneven arrays as one
 plan, and the learned flagger; then the FP64 oracle timed on the host
-cores on a bounded sample.
+cores on a bounded sample.  The `achievable` section times the library's
+microbenchmark kernels (HBM read and copy, scalar FP32 FMA, FP32 and FP16
+matrix-core instructions): what this GPU sustains, beside the published
+peaks that the roofline fractions use.
 """
 
 from __future__ import annotations
@@ -50,6 +53,8 @@ def parse():
     ap.add_argument("--no-flagger", action="store_true", help="skip the learned-flagger section")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 256 MiB device copy kernel (counter calibration)")
+    ap.add_argument("--no-achievable", action="store_true",
+                    help="skip the microbenchmarks of what this GPU sustains (HBM, vector ALU, matrix cores)")
     return ap.parse_args()
 
 
@@ -347,6 +352,31 @@ def cpu_baseline(x, N, P, spd, sigma, tau, phi, df, gpu_vis, n_dumps=8):
             "seconds": round(dt, 2), "gpu_vs_oracle_err_on_sample": float(f"{err:.3e}")}
 
 
+def achievable_section(torch, qc):
+    """What this GPU sustains, measured by the library's microbenchmark
+    kernels (streaming read and copy of 4 GiB; independent scalar float32
+    FMAs; the float32 and float16 matrix-core instructions), beside the
+    published peaks used as roofline denominators."""
+    buf = torch.empty(4 << 30, dtype=torch.uint8, device="cuda")
+    r = {
+        "hbm_read_GBps": qc.measure_peak("hbm_read", buf, reps=10),
+        "hbm_copy_GBps": qc.measure_peak("hbm_copy", buf, reps=10),
+        "valu_f32_TFLOPs": qc.measure_peak("valu_f32", buf, reps=3),
+        "mfma_f32_TFLOPs": qc.measure_peak("mfma_f32", buf, reps=3),
+        "mfma_f16_TFLOPs": qc.measure_peak("mfma_f16", buf, reps=3),
+    }
+    del buf
+    torch.cuda.empty_cache()
+    r = {k: round(v, 1) for k, v in r.items()}
+    r["published"] = {"hbm_GBps": PEAK_HBM_GBS, "valu_f32_TFLOPs": PEAK_FP32_TFLOPS,
+                      "valu_f32_unpacked_TFLOPs": PEAK_FP32_TFLOPS / 2, "mfma_f32_TFLOPs": 157.3,
+                      "mfma_f16_TFLOPs": 2500.0}
+    log(f"[bench] achievable: read {r['hbm_read_GBps']} GB/s, copy {r['hbm_copy_GBps']} GB/s, "
+        f"FP32 FMA {r['valu_f32_TFLOPs']} TFLOP/s, FP32 MFMA {r['mfma_f32_TFLOPs']}, "
+        f"FP16 MFMA {r['mfma_f16_TFLOPs']} TFLOP/s")
+    return r
+
+
 def solve_section(torch, qc, vis, n_ant, df, fs, sigma, reps):
     """Delay/phase solve (Sec. 7): the real-time visibilities flagged by MAD
     -> per-antenna delays and phases against antenna 0, checked against the
@@ -496,6 +526,10 @@ def main():
         "fused_tile": {"chosen": best_tile, "ms_per_tile": [round(v, 4) for v in tile_ms]},
         "wall_s_timed_region": round(t_wall, 4),
     }
+    if not args.no_achievable:
+        ach = achievable_section(torch, qc)
+        out["achievable"] = ach
+        out["roofline"]["frac_of_achievable"] = round(achieved / ach["valu_f32_TFLOPs"], 4)
     if not args.no_stream:
         out["stream"] = stream_section(torch, qc, x, N, P, spd, vis_check)
     out["solve"] = solve_section(torch, qc, vis_check, n_ant, df, fs, sigma, max(3, args.steps // 10))

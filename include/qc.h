@@ -396,6 +396,33 @@ qc_status qc_cnn_flag(const float* params, const float* vis, int64_t n_time, int
 qc_status qc_cnn_set_variant(int32_t variant);
 int32_t qc_cnn_get_variant(void);
 
+/* Measurement helper, not part of the method: the rate that one kernel of
+ * the given kind sustains on this GPU, so that the library's kernels can be
+ * read against what the hardware delivers as well as against its published
+ * peaks.  One warm-up launch, then `reps` back-to-back launches timed with
+ * HIP events on `stream`; synchronous.
+ *   QC_PEAK_HBM_READ: streaming read of `bytes` of scratch, GB/s;
+ *   QC_PEAK_HBM_COPY: copy of the first half of scratch into the second,
+ *     GB/s of bytes read plus written;
+ *   QC_PEAK_VALU_F32: independent float32 FMAs, scalar instructions (the
+ *     library is built without packed FP32), TFLOP/s;
+ *   QC_PEAK_MFMA_F32: v_mfma_f32_32x32x2_f32, TFLOP/s;
+ *   QC_PEAK_MFMA_F16: v_mfma_f32_32x32x16_f16, TFLOP/s.
+ * scratch: device memory, 16-byte aligned, `bytes` long: at least 64 MiB
+ * for the two memory kinds (larger reads the steady state better), at
+ * least 64 KiB for the others (written only in a case that cannot occur,
+ * which keeps the results live).  QC_EINVAL on a bad kind, pointer, size or
+ * reps, before any GPU work. */
+enum {
+  QC_PEAK_HBM_READ = 0,
+  QC_PEAK_HBM_COPY = 1,
+  QC_PEAK_VALU_F32 = 2,
+  QC_PEAK_MFMA_F32 = 3,
+  QC_PEAK_MFMA_F16 = 4
+};
+qc_status qc_measure_peak(int32_t kind, void* scratch, int64_t bytes, int32_t reps, double* rate,
+                          void* stream);
+
 /* Human-readable name of a status code (static storage). */
 const char* qc_status_string(qc_status s);
 /* Thread-local detail of the last failure in this thread ("" if none). */

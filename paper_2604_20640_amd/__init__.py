@@ -17,7 +17,7 @@ __all__ = [
     "QCError", "lib", "pfb_channelize", "xcorrelate", "xcorrelate_chan", "mad_flag",
     "apply_delay_phase", "n_base", "PREC", "timing_enable", "timing_read", "KERNELS", "Stream",
     "solve_delay_phase", "Plan", "cnn_param_count", "cnn_normalize", "cnn_forward", "cnn_grad", "cnn_adam",
-    "cnn_train_step", "cnn_flag", "channelize_variant", "cnn_variant",
+    "cnn_train_step", "cnn_flag", "channelize_variant", "cnn_variant", "measure_peak",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -142,6 +142,9 @@ def lib() -> ctypes.CDLL:
         L.qc_xengine_set_variant.restype = ctypes.c_int32
         L.qc_xengine_get_variant.argtypes = []
         L.qc_xengine_get_variant.restype = ctypes.c_int32
+        L.qc_measure_peak.argtypes = [_I32, ctypes.c_void_p, ctypes.c_int64, _I32,
+                                      ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]
+        L.qc_measure_peak.restype = ctypes.c_int32
         L.qc_cnn_set_variant.argtypes = [_I32]
         L.qc_cnn_set_variant.restype = ctypes.c_int32
         L.qc_cnn_get_variant.argtypes = []
@@ -317,6 +320,23 @@ def channelize_variant(v=None):
     if v is not None:
         _check(lib().qc_channelize_set_variant(int(v)), "qc_channelize_set_variant")
     return int(lib().qc_channelize_get_variant())
+
+
+PEAK_KINDS = {"hbm_read": 0, "hbm_copy": 1, "valu_f32": 2, "mfma_f32": 3, "mfma_f16": 4}
+
+
+def measure_peak(kind, scratch, reps=10):
+    """Rate (GB/s or TFLOP/s) one measurement kernel of `kind` sustains on
+    the current GPU; scratch: a CUDA tensor (its bytes are overwritten by
+    the copy kind).  Not part of the method: a denominator for roofline
+    fractions."""
+    assert scratch.is_cuda and scratch.is_contiguous()
+    rate = ctypes.c_double(0.0)
+    st = lib().qc_measure_peak(PEAK_KINDS[kind], ctypes.c_void_p(scratch.data_ptr()),
+                               scratch.numel() * scratch.element_size(), int(reps), ctypes.byref(rate),
+                               _stream())
+    _check(st, "qc_measure_peak")
+    return rate.value
 
 
 def cnn_variant(v=None):

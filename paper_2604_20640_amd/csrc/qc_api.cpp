@@ -1396,6 +1396,20 @@ qc_status qc_xengine_set_variant(int32_t variant) {
 
 int32_t qc_xengine_get_variant(void) { return qc::get_xeng_f32_variant(); }
 
+qc_status qc_measure_peak(int32_t kind, void* scratch, int64_t bytes, int32_t reps, double* rate,
+                          void* stream) {
+  g_err.clear();
+  if (kind < QC_PEAK_HBM_READ || kind > QC_PEAK_MFMA_F16) return fail(QC_EINVAL, "unknown kind %d", kind);
+  if (!scratch || !rate) return fail(QC_EINVAL, "scratch and rate must be non-null");
+  if (reps < 1) return fail(QC_EINVAL, "reps must be >= 1");
+  if (reinterpret_cast<uintptr_t>(scratch) & 15u) return fail(QC_EINVAL, "scratch must be 16-byte aligned");
+  const int64_t need = kind <= QC_PEAK_HBM_COPY ? (int64_t)64 << 20 : (int64_t)64 << 10;
+  if (bytes < need) return fail(QC_EINVAL, "scratch of %lld bytes is below the %lld this kind needs",
+                                (long long)bytes, (long long)need);
+  QC_HIP(qc::measure_peak(kind, scratch, bytes, reps, rate, (hipStream_t)stream), "measure_peak");
+  return QC_OK;
+}
+
 qc_status qc_cnn_set_variant(int32_t variant) {
   g_err.clear();
   if (variant < 0 || variant > 1) return fail(QC_EINVAL, "variant must be 0 or 1");

@@ -183,4 +183,7 @@ hipError_t cnn_forward_f16(const float* params, const _Float16* w2p, const _Floa
                            int64_t n_img, int H, int W, _Float16* A, _Float16* B, float* logits, float thr,
                            int64_t img0, int64_t n_base, uint8_t* mask, hipStream_t s);
 
+// Rate one measurement kernel of the given kind sustains (see qc_measure_peak).
+hipError_t measure_peak(int kind, void* scratch, int64_t bytes, int reps, double* rate, hipStream_t s);
+
 }  // namespace qc

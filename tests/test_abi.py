@@ -144,3 +144,19 @@ def test_kernel_variant_switches():
     finally:
         L.qc_cnn_set_variant(0)
     assert qc.cnn_variant() == 0
+
+
+def test_measure_peak_rejects_bad_arguments():
+    # host-side validation only: no GPU work is started
+    L = qc.lib()
+    r = ctypes.c_double(0.0)
+    p = ctypes.c_void_p(0x100000)
+    assert L.qc_measure_peak(5, p, 1 << 30, 1, ctypes.byref(r), None) == QC_EINVAL    # unknown kind
+    assert L.qc_measure_peak(-1, p, 1 << 30, 1, ctypes.byref(r), None) == QC_EINVAL
+    assert L.qc_measure_peak(0, None, 1 << 30, 1, ctypes.byref(r), None) == QC_EINVAL  # null scratch
+    assert L.qc_measure_peak(0, p, 1 << 30, 1, None, None) == QC_EINVAL                # null rate
+    assert L.qc_measure_peak(0, p, 1 << 30, 0, ctypes.byref(r), None) == QC_EINVAL     # reps < 1
+    assert L.qc_measure_peak(0, ctypes.c_void_p(0x100008), 1 << 30, 1, ctypes.byref(r), None) == QC_EINVAL
+    assert L.qc_measure_peak(1, p, (64 << 20) - 32, 1, ctypes.byref(r), None) == QC_EINVAL  # too small
+    assert L.qc_measure_peak(3, p, (64 << 10) - 16, 1, ctypes.byref(r), None) == QC_EINVAL
+
