@@ -716,11 +716,26 @@ __global__ void cnn_pack_mfma_kernel(const float* __restrict__ w, _Float16* __re
   p[e] = (_Float16)w[(co * 32 + ci) * 25 + tap];
 }
 
-template <int D>
+// The output layer fused into the last convolution's epilogue: logits
+// and/or the flag mask in the [time][baseline][chan] layout.
+struct HeadArgs {
+  const float* w4;  // 32 weights, then the bias
+  float* logits;    // [n_img][H][W] or null
+  float thr;
+  int64_t img0, n_base;
+  uint8_t* mask;    // or null
+};
+
+// HEAD: instead of storing the activations, apply L4 to them: the partner
+// lane (l ^ 32) passes its 16 channels of the pixel over, and lane l < 32
+// sums all 32 in channel order from the bias, each activation rounded to
+// half first, which is exactly what the separate output-layer kernel
+// computes from stored half activations.
+template <int D, bool HEAD>
 __global__ void __launch_bounds__(MT_NT)
 cnn_mfma_conv_kernel(const _Float16* __restrict__ in, const _Float16* __restrict__ wp,
                      const float* __restrict__ bias, int H, int W, int tiles_x, int tiles_per_img,
-                     int64_t n_tiles, _Float16* __restrict__ out) {
+                     int64_t n_tiles, _Float16* __restrict__ out, HeadArgs hd) {
   constexpr int R = 2 * D;  // D*(5-1)/2
   constexpr int U = mt_u(D), MT_H = mt_h(D);
   constexpr int LH = MT_H + 2 * R, LW = MT_W + 2 * R;
@@ -806,7 +821,25 @@ cnn_mfma_conv_kernel(const _Float16* __restrict__ in, const _Float16* __restrict
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int y = y0 + U * wave + u, x = x0 + px;
-      if (y < H && x < W) {
+      if constexpr (HEAD) {
+        float v[16], o[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) v[r] = (float)(_Float16)fmaxf(acc[u][r] + bco[r], 0.f);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) o[r] = __shfl_xor(v[r], 32);
+        if (kh == 0 && y < H && x < W) {
+          float z = hd.w4[32];
+#pragma unroll
+          for (int g = 0; g < 4; ++g) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) z = fmaf(hd.w4[8 * g + i], v[4 * g + i], z);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) z = fmaf(hd.w4[8 * g + 4 + i], o[4 * g + i], z);
+          }
+          if (hd.logits) hd.logits[(n * H + y) * (int64_t)W + x] = z;
+          if (hd.mask) hd.mask[((int64_t)y * hd.n_base + (hd.img0 + n)) * W + x] = z > hd.thr ? 1 : 0;
+        }
+      } else if (y < H && x < W) {
         _Float16* o = out + ((n * H + y) * (int64_t)W + x) * 32;
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
@@ -851,29 +884,6 @@ cnn_l1_nhwc_kernel(const float* __restrict__ x, const float* __restrict__ w1, co
       o[i] = (_Float16)fmaxf(a, 0.f);
     }
     *reinterpret_cast<half8v*>(out + e * 32 + 8 * c8) = o;
-  }
-}
-
-// L4 (1x1, 32 -> 1) from NHWC half: logits and/or the flag mask.
-__global__ void cnn_head_nhwc_kernel(const _Float16* __restrict__ a, const float* __restrict__ w4, int H, int W,
-                                     int64_t n_pix, float* __restrict__ logits, float thr, int64_t img0,
-                                     int64_t n_base, uint8_t* __restrict__ mask) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n_pix) return;
-  typedef _Float16 half8v __attribute__((ext_vector_type(8)));
-  float z = w4[32];
-#pragma unroll
-  for (int c8 = 0; c8 < 4; ++c8) {
-    const half8v v = reinterpret_cast<const half8v*>(a + e * 32)[c8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) z = fmaf(w4[8 * c8 + i], (float)v[i], z);
-  }
-  if (logits) logits[e] = z;
-  if (mask) {
-    const int64_t hw = (int64_t)H * W;
-    const int64_t n = e / hw, p = e % hw;
-    const int64_t tt = p / W, f = p % W;
-    mask[(tt * n_base + (img0 + n)) * W + f] = z > thr ? 1 : 0;
   }
 }
 
@@ -1063,22 +1073,20 @@ hipError_t cnn_forward_f16(const float* params, const _Float16* w2p, const _Floa
   static_assert(sizeof(uint4) * MT_SLICES * 64 + sizeof(_Float16) * (mt_h(2) + 8) * (MT_W + 8) * MT_PS <=
                     160 * 1024 && sizeof(uint4) * MT_SLICES * 64 + sizeof(_Float16) * (mt_h(1) + 4) * (MT_W + 4) * MT_PS <= 160 * 1024,
                 "half convolution tiles: LDS");
-  e = hipFuncSetAttribute(reinterpret_cast<const void*>(cnn_mfma_conv_kernel<1>),
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(cnn_mfma_conv_kernel<1, false>),
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)l2);
   if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute(reinterpret_cast<const void*>(cnn_mfma_conv_kernel<2>),
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(cnn_mfma_conv_kernel<2, true>),
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)l3);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(cnn_mfma_conv_kernel<1>, dim3(grid2), dim3(MT_NT), l2, s, A, w2p, params + CNN_OFF_L2 + 25600,
-                     H, W, tx, tx * ty2, n_tiles2, B);
+  hipLaunchKernelGGL((cnn_mfma_conv_kernel<1, false>), dim3(grid2), dim3(MT_NT), l2, s, A, w2p,
+                     params + CNN_OFF_L2 + 25600, H, W, tx, tx * ty2, n_tiles2, B, HeadArgs{});
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(cnn_mfma_conv_kernel<2>, dim3(grid3), dim3(MT_NT), l3, s, B, w3p, params + CNN_OFF_L3 + 25600,
-                     H, W, tx, tx * ty3, n_tiles3, A);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(cnn_head_nhwc_kernel, dim3((unsigned)ceil_div(n_pix, 256)), dim3(256), 0, s, A,
-                     params + CNN_OFF_L4, H, W, n_pix, logits, thr, img0, n_base, mask);
+  // L3 with the output layer in its epilogue (its activations are not stored)
+  const HeadArgs hd{params + CNN_OFF_L4, logits, thr, img0, n_base, mask};
+  hipLaunchKernelGGL((cnn_mfma_conv_kernel<2, true>), dim3(grid3), dim3(MT_NT), l3, s, B, w3p,
+                     params + CNN_OFF_L3 + 25600, H, W, tx, tx * ty3, n_tiles3, nullptr, hd);
   return hipGetLastError();
 }
 
