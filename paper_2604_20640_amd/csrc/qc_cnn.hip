@@ -486,6 +486,84 @@ cnn_wgrad32_mfma_kernel(const float* __restrict__ a, const float* __restrict__ g
   if ((t & 15) == 0) out[C * C * NT + (t >> 4)] = sb;
 }
 
+// L1's weight gradient (3 x 3, 1 -> 32) on the matrix cores: per pair of
+// pixels one v_mfma_f32_32x32x2_f32 forms dW[o][tap] for all 32 outputs
+// (rows, A = the output gradient) and the 9 taps (columns, B = the input at
+// the tap's offset), with column 9 holding 1 so that the bias gradient is
+// the same sum; columns 10..31 are zero.  Wave w takes tile rows 2w, 2w+1;
+// the four waves' sums are added in wave order at the end and written to
+// part[block][...] in the layout of the vector-ALU kernel.
+constexpr int L1M_NT = 256;
+
+__global__ void __launch_bounds__(L1M_NT)
+cnn_wgrad_l1_mfma_kernel(const float* __restrict__ a, const float* __restrict__ g, int H, int W, int tiles_x,
+                         int tiles_per_img, int64_t n_tiles, float* __restrict__ part) {
+  constexpr int C = 32, NTAP = 9, LH = CT_H + 2, LW = CT_W + 2, GS = CNT + 1, NWV = L1M_NT / 64;
+  static_assert(CT_H == 2 * NWV, "two tile rows per wave");
+  __shared__ float sg[C * GS];
+  __shared__ float sa[LH * LW];
+  __shared__ float red[NWV][16][64];
+  const int t = threadIdx.x, lane = t & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int j = lane & 31, kh = lane >> 5;        // column (tap) and pixel slot
+  const int ky = j / 3, kx = j % 3;
+  mf32x16_t acc;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+  for (int64_t tl = blockIdx.x; tl < n_tiles; tl += gridDim.x) {
+    const int64_t n = tl / tiles_per_img;
+    const int tt = (int)(tl % tiles_per_img);
+    const int y0 = (tt / tiles_x) * CT_H, x0 = (tt % tiles_x) * CT_W;
+    static_assert(L1M_NT == CNT, "thread t stages pixel t of every channel");
+    // all 32 channels of this thread's pixel: independent loads, in flight together
+    float gv[C];
+    {
+      const int y = y0 + t / CT_W, x = x0 + t % CT_W;
+      const bool in = y < H && x < W;
+      const float* gp = g + img_off(n, 0, C, H, W) + (in ? (int64_t)y * W + x : 0);
+#pragma unroll
+      for (int o = 0; o < C; ++o) {
+        const float v = gp[(int64_t)o * H * W];
+        gv[o] = in ? v : 0.f;
+      }
+    }
+    __syncthreads();  // the previous tile's reads are done
+#pragma unroll
+    for (int o = 0; o < C; ++o) sg[o * GS + t] = gv[o];
+    for (int e = t; e < LH * LW; e += L1M_NT) {
+      const int y = y0 + e / LW - 1, x = x0 + e % LW - 1;
+      sa[e] = (y >= 0 && y < H && x >= 0 && x < W) ? a[img_off(n, 0, 1, H, W) + (int64_t)y * W + x] : 0.f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int rr = 0; rr < 2; ++rr) {
+      const int py = 2 * wave + rr;
+#pragma unroll 4
+      for (int px = 0; px < CT_W; px += 2) {
+        const float av = sg[j * GS + py * CT_W + px + kh];   // A: row = output channel j
+        float bv = 0.f;
+        if (j < NTAP) bv = sa[(py + ky) * LW + px + kh + kx];
+        else if (j == NTAP) bv = 1.f;
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 16; ++r) red[wave][r][lane] = acc[r];
+  __syncthreads();
+  float* out = part + (int64_t)blockIdx.x * (C * NTAP + C);
+  for (int e = t; e < C * (NTAP + 1); e += L1M_NT) {
+    const int o = e / (NTAP + 1), col = e % (NTAP + 1);
+    // accumulator row o lives in register 4 (o / 8) + o % 4 of lanes with kh = (o / 4) % 2
+    const int r = 4 * (o >> 3) + (o & 3), ln = col + 32 * ((o >> 2) & 1);
+    float sum = 0.f;
+#pragma unroll
+    for (int w = 0; w < NWV; ++w) sum += red[w][r][ln];
+    if (col < NTAP) out[o * NTAP + col] = sum;
+    else out[C * NTAP + o] = sum;
+  }
+}
+
 // Weight gradient of a layer with few weights (L1: 1 input channel): one
 // lane per weight, pixel tiles staged in LDS.
 template <int CI, int CO, int K, int D>
@@ -987,8 +1065,12 @@ hipError_t cnn_wgrad(int layer, const float* a, const float* g, int64_t n_img, i
   const int tx = ceil_div(W, CT_W), ty = ceil_div(H, CT_H);
   if (layer == 1) {
     nw = 32 * 9 + 32;
-    hipLaunchKernelGGL((cnn_wgrad_small_kernel<1, 32, 3, 1>), dim3((unsigned)blocks), dim3(256), 0, s, a, g, H,
-                       W, tx, tx * ty, n_img * tx * ty, part);
+    if (g_cnn_mfma)
+      hipLaunchKernelGGL(cnn_wgrad_l1_mfma_kernel, dim3((unsigned)blocks), dim3(L1M_NT), 0, s, a, g, H, W, tx,
+                         tx * ty, n_img * tx * ty, part);
+    else
+      hipLaunchKernelGGL((cnn_wgrad_small_kernel<1, 32, 3, 1>), dim3((unsigned)blocks), dim3(256), 0, s, a, g, H,
+                         W, tx, tx * ty, n_img * tx * ty, part);
     e = hipGetLastError();
   } else if (layer == 2) {
     nw = 32 * 32 * 25 + 32;
