@@ -384,13 +384,15 @@ qc_status qc_cnn_flag(const float* params, const float* vis, int64_t n_time, int
                       int32_t n_chan, float logit_threshold, int32_t act_prec, uint8_t* mask,
                       void* stream);
 
-/* Kernel choice for the float32 work of the two 32 -> 32 layers
- * (convolutions forward and backward-data, weight gradients), used by
+/* Kernel choice for the flagger's float32 work (the two 32 -> 32 layers'
+ * convolutions forward and backward-data, and the weight gradients of L1,
+ * L2 and L3), used by
  * qc_cnn_forward (act_prec 0), qc_cnn_grad, qc_cnn_train_step and qc_cnn_flag
  * (act_prec 0); process-wide, not thread-safe against concurrent calls.
  * 0 (default): the matrix cores, v_mfma_f32_32x32x2_f32 (convolution: per
  * tap, a 32 x 32 weight block times the shifted input; weight gradient: per
- * tap, the output gradient times the shifted input over the pixels);
+ * tap, the output gradient times the shifted input over the pixels, for L1
+ * all 9 taps and the bias in one product);
  * 1: the vector ALU.  Both are float32 throughout and deterministic; the
  * choice affects rounding order and speed only. */
 qc_status qc_cnn_set_variant(int32_t variant);
