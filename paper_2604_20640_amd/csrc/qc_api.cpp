@@ -1336,8 +1336,9 @@ qc_status cnn_forward_chunk(const float* p, const CnnPacked& pk, const float* x,
                             uint8_t* mask, hipStream_t s) {
   QC_HIP(qc::cnn_conv(1, 0, x, pk.w1, p + qc::CNN_OFF_L1 + 288, nullptr, n, H, W, A, s), "conv L1");
   QC_HIP(qc::cnn_conv(2, 0, A, pk.w2, p + qc::CNN_OFF_L2 + 25600, nullptr, n, H, W, B, s), "conv L2");
-  QC_HIP(qc::cnn_conv(3, 0, B, pk.w3, p + qc::CNN_OFF_L3 + 25600, nullptr, n, H, W, A, s), "conv L3");
-  QC_HIP(qc::cnn_head(A, p + qc::CNN_OFF_L4, n, H, W, logits, thr, img0, n_base, mask, s), "head");
+  QC_HIP(qc::cnn_conv3_head(B, pk.w3, p + qc::CNN_OFF_L3 + 25600, p + qc::CNN_OFF_L4, n, H, W, A, logits, thr,
+                            img0, n_base, mask, s),
+         "conv L3 + head");
   return QC_OK;
 }
 

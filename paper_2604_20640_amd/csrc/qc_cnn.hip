@@ -36,6 +36,16 @@ __device__ __forceinline__ int64_t img_off(int64_t n, int c, int C, int H, int W
   return ((n * C + c) * (int64_t)H) * W;
 }
 
+// The output layer fused into the last convolution's epilogue: logits
+// and/or the flag mask in the [time][baseline][chan] layout.
+struct HeadArgs {
+  const float* w4;  // 32 weights, then the bias
+  float* logits;    // [n_img][H][W] or null
+  float thr;
+  int64_t img0, n_base;
+  uint8_t* mask;    // or null
+};
+
 // Repack W[o][i][ky][kx] -> P[i][ky][kx][o]; with flip, the backward-data
 // kernel P[o][K-1-ky][K-1-kx][i] (inputs and outputs exchanged).
 __global__ void cnn_pack_kernel(const float* __restrict__ w, int CI, int CO, int K, int flip,
@@ -121,7 +131,8 @@ cnn_conv_kernel(const float* __restrict__ in, const float* __restrict__ wp, cons
 // [pixel][16 channels] with an 80-byte pixel stride (conflict-free 16-byte
 // reads).  The next half-tile's values travel in registers while this one
 // is reduced; four accumulators take the four j.  MODE as for
-// cnn_conv_kernel.
+// cnn_conv_kernel, and 3: forward with ReLU followed by the output layer,
+// writing logits and/or flags instead of the activations.
 constexpr int CM_NTH = 512, CM_HC = 16, CM_PS = 20;
 
 constexpr int cm_pl(int D) { return (CT_H + 4 * D) * (CT_W + 4 * D); }
@@ -131,7 +142,7 @@ template <int D, int MODE>
 __global__ void __launch_bounds__(CM_NTH)
 cnn_conv32_mfma_kernel(const float* __restrict__ in, const float* __restrict__ wp, const float* __restrict__ bias,
                        const float* __restrict__ gate, int H, int W, int tiles_x, int tiles_per_img,
-                       int64_t n_tiles, float* __restrict__ out) {
+                       int64_t n_tiles, float* __restrict__ out, HeadArgs hd) {
   constexpr int C = 32, NT = 25, R = 2 * D;
   constexpr int LH = CT_H + 2 * R, LW = CT_W + 2 * R, PL = LH * LW;
   constexpr int IH = (CM_HC * PL + CM_NTH - 1) / CM_NTH;
@@ -228,7 +239,28 @@ cnn_conv32_mfma_kernel(const float* __restrict__ in, const float* __restrict__ w
     const int64_t n = tl / tiles_per_img;
     const int tt = (int)(tl % tiles_per_img);
     const int y = (tt / tiles_x) * CT_H + wave, x = (tt % tiles_x) * CT_W + px;
-    if (y < H && x < W) {
+    if constexpr (MODE == 3) {
+      // the output layer on this pixel's 32 activations: the partner lane
+      // (l ^ 32) passes its 16 channels over, lane l < 32 sums all 32 in
+      // channel order from the bias (as the separate output-layer kernel)
+      float v[16], o[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) v[r] = fmaxf((acc[0][r] + acc[1][r]) + (acc[2][r] + acc[3][r]) + bco[r], 0.f);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) o[r] = __shfl_xor(v[r], 32);
+      if (kh == 0 && y < H && x < W) {
+        float z = hd.w4[32];
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) z = fmaf(hd.w4[8 * g + i], v[4 * g + i], z);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) z = fmaf(hd.w4[8 * g + 4 + i], o[4 * g + i], z);
+        }
+        if (hd.logits) hd.logits[(n * H + y) * (int64_t)W + x] = z;
+        if (hd.mask) hd.mask[((int64_t)y * hd.n_base + (hd.img0 + n)) * W + x] = z > hd.thr ? 1 : 0;
+      }
+    } else if (y < H && x < W) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int o = 8 * (r >> 2) + 4 * kh + (r & 3);   // accumulator row: output channel
@@ -794,15 +826,6 @@ __global__ void cnn_pack_mfma_kernel(const float* __restrict__ w, _Float16* __re
   p[e] = (_Float16)w[(co * 32 + ci) * 25 + tap];
 }
 
-// The output layer fused into the last convolution's epilogue: logits
-// and/or the flag mask in the [time][baseline][chan] layout.
-struct HeadArgs {
-  const float* w4;  // 32 weights, then the bias
-  float* logits;    // [n_img][H][W] or null
-  float thr;
-  int64_t img0, n_base;
-  uint8_t* mask;    // or null
-};
 
 // HEAD: instead of storing the activations, apply L4 to them: the partner
 // lane (l ^ 32) passes its 16 channels of the pixel over, and lane l < 32
@@ -999,7 +1022,7 @@ static hipError_t conv_t(const float* in, const float* wp, const float* b, const
       if (e != hipSuccess) return e;
       const int64_t grid = blocks < 256 ? blocks : 256;   // one workgroup per CU, striding over tiles
       hipLaunchKernelGGL((cnn_conv32_mfma_kernel<D, MODE>), dim3((unsigned)grid), dim3(CM_NTH), lds, s, in, wp, b,
-                         gate, H, W, tx, tx * ty, blocks, out);
+                         gate, H, W, tx, tx * ty, blocks, out, HeadArgs{});
       return hipGetLastError();
     }
   }
@@ -1085,6 +1108,27 @@ hipError_t cnn_wgrad(int layer, const float* a, const float* g, int64_t n_img, i
   hipLaunchKernelGGL(cnn_sum_parts_kernel, dim3(ceil_div(nw, 64)), dim3(64 * SP_WAVES), 0, s, part, (int)blocks, nw,
                      dst);
   return hipGetLastError();
+}
+
+hipError_t cnn_conv3_head(const float* a2, const float* w3p, const float* b3, const float* w4, int64_t n_img,
+                          int H, int W, float* a3, float* logits, float thr, int64_t img0, int64_t n_base,
+                          uint8_t* mask, hipStream_t s) {
+  const int tx = ceil_div(W, CT_W), ty = ceil_div(H, CT_H);
+  const int64_t blocks = n_img * tx * ty;
+  if (blocks <= 0) return hipSuccess;
+  if (g_cnn_mfma && 32LL * H * W < (1LL << 31)) {
+    const size_t lds = cm_lds(2);
+    const void* k = reinterpret_cast<const void*>(cnn_conv32_mfma_kernel<2, 3>);
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    const int64_t grid = blocks < 256 ? blocks : 256;
+    hipLaunchKernelGGL((cnn_conv32_mfma_kernel<2, 3>), dim3((unsigned)grid), dim3(CM_NTH), lds, s, a2, w3p, b3,
+                       nullptr, H, W, tx, tx * ty, blocks, nullptr, HeadArgs{w4, logits, thr, img0, n_base, mask});
+    return hipGetLastError();
+  }
+  hipError_t e = cnn_conv(3, 0, a2, w3p, b3, nullptr, n_img, H, W, a3, s);
+  if (e != hipSuccess) return e;
+  return cnn_head(a3, w4, n_img, H, W, logits, thr, img0, n_base, mask, s);
 }
 
 hipError_t cnn_head(const float* a3, const float* w4, int64_t n_img, int H, int W, float* logits, float thr,

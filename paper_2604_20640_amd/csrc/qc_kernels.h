@@ -167,6 +167,12 @@ hipError_t cnn_wgrad(int layer, const float* a, const float* g, int64_t n_img, i
 // Output layer: logits and/or a flag mask in [time][baseline][chan] layout.
 hipError_t cnn_head(const float* a3, const float* w4, int64_t n_img, int H, int W, float* logits, float thr,
                     int64_t img0, int64_t n_base, uint8_t* mask, hipStream_t s);
+// L3 forward followed by the output layer (inference): on the matrix cores
+// the logits/flags come from L3's epilogue and a3 is not written; otherwise
+// L3 into a3, then cnn_head.
+hipError_t cnn_conv3_head(const float* a2, const float* w3p, const float* b3, const float* w4, int64_t n_img,
+                          int H, int W, float* a3, float* logits, float thr, int64_t img0, int64_t n_base,
+                          uint8_t* mask, hipStream_t s);
 int64_t cnn_head_bwd_blocks(int64_t n_total);
 // Loss, dW4/db4 (grad4[33]) and g3; part holds cnn_head_bwd_blocks() * 34 floats.
 hipError_t cnn_head_bwd(const float* logits, const uint8_t* labels, const float* a3, const float* w4,
