@@ -11,11 +11,13 @@ Prints one JSON line: input GB/s (10^9 B/s) with a roofline record of the
 dominant kernel (fused F+X, timed by HIP events around its own launches on
 its own stream), and sections for the other steps: the same stream pushed
 from pinned host memory, the delay/phase solve (checked against the
-injected lags and the oracle's solve, timed beside it), the 32-antenna
-X-engine comparison (float32 vs FP16/BF16/E4M3 on the matrix cores, with
-visibility errors against the FP64 oracle), five uneven arrays as one
-plan, and the learned flagger; then the FP64 oracle timed on the host
-cores on a bounded sample.  The `achievable` section times the library's
+injected lags), the 32-antenna X-engine comparison (float32 vs
+FP16/BF16/E4M3 on the matrix cores), five uneven arrays as one plan, and
+the learned flagger.  The CPU-baseline leg comes last: the FP64 oracle
+timed on the host cores on a bounded sample, then the oracle's side of the
+other comparisons (the solve of the same visibilities, timed beside the
+GPU's; the 32-antenna visibility errors against FP64), written back into
+their sections.  With --no-cpu-baseline the oracle is not run at all.  The `achievable` section times the library's
 microbenchmark kernels (HBM read and copy, scalar FP32 FMA, FP32 and FP16
 matrix-core instructions): what this GPU sustains, beside the published
 peaks that the roofline fractions use.
@@ -139,9 +141,10 @@ def oracle_vis_subset(x, N, P, spd, chans, dumps, block=256):
     return np.stack(out)
 
 
-def precision_section(torch, qc, steps):
-    """32 antennas x 2^24 samples, N=4096: FP32 two-pass vs matrix cores."""
-    from tests.util import vis_err as vis_err_local
+def precision_section(torch, qc, steps, checks):
+    """32 antennas x 2^24 samples, N=4096: FP32 two-pass vs matrix cores.
+    With `checks` (a list), the visibilities of 8 sampled channels are kept
+    for the oracle comparison that the CPU-baseline leg makes."""
     n_ant, N, P = 32, 4096, 4
     S = 1 << 24
     spd = S // N
@@ -153,9 +156,7 @@ def precision_section(torch, qc, steps):
            "spec_per_dump": spd}
     rng = np.random.default_rng(3)
     chans = np.sort(rng.choice(N // 2, 8, replace=False))
-    t0 = time.time()
-    V_ref = oracle_vis_subset(x, N, P, spd, chans, [0], block=128)
-    log(f"[bench] 32-antenna oracle subset in {time.time() - t0:.1f}s")
+    sampled = {}
     reps = max(3, steps // 10)
     for prec in ["f32", "f16", "bf16", "fp8"]:
         vis = torch.empty((1, n_ant * (n_ant + 1) // 2, N // 2), dtype=torch.complex64, device="cuda")
@@ -167,14 +168,14 @@ def precision_section(torch, qc, steps):
         k_ch, n_ch = qc.timing_read("channelize")
         kname = "xeng_f32" if prec == "f32" else "xeng_mfma"
         k_x, n_x = qc.timing_read(kname)
-        V = vis.cpu().numpy()[:, :, chans]
-        err = vis_err_local(V, V_ref, n_ant)
+        sampled[prec] = vis.cpu().numpy()[:, :, chans]
         res[prec] = {"ms": round(ms, 4), "input_GBps": round(x.nbytes / ms / 1e6, 2),
                      "f_engine_ms": round(k_ch / max(n_ch, 1), 4),
-                     "x_engine_ms": round(k_x / max(n_x, 1), 4),
-                     "vis_err_vs_fp64": float(f"{err:.3e}")}
-        log(f"[bench] 32-ant {prec}: {ms:.3f} ms, err {err:.2e}")
+                     "x_engine_ms": round(k_x / max(n_x, 1), 4)}
+        log(f"[bench] 32-ant {prec}: {ms:.3f} ms")
     del xd
+    if checks is not None:
+        checks.append(("precision", res, x, N, P, spd, chans, sampled))
     return res
 
 
@@ -352,6 +353,30 @@ def cpu_baseline(x, N, P, spd, sigma, tau, phi, df, gpu_vis, n_dumps=8):
             "seconds": round(dt, 2), "gpu_vs_oracle_err_on_sample": float(f"{err:.3e}")}
 
 
+def oracle_checks(checks):
+    """The rest of the oracle's part in the CPU-baseline leg: each section's
+    kept GPU results against the FP64 oracle on the same input, the figures
+    written back into that section."""
+    from oracle import calib
+    from tests.util import vis_err as vis_err_local
+    for item in checks:
+        if item[0] == "precision":
+            _, res, x, N, P, spd, chans, sampled = item
+            t0 = time.time()
+            V_ref = oracle_vis_subset(x, N, P, spd, chans, [0], block=128)
+            log(f"[bench] 32-antenna oracle subset in {time.time() - t0:.1f}s")
+            for prec, V in sampled.items():
+                res[prec]["vis_err_vs_fp64"] = float(f"{vis_err_local(V, V_ref, x.shape[0]):.3e}")
+        elif item[0] == "solve":
+            _, res, V, M, n_ant, df, fs, lo, hi, tau, phi = item
+            t0 = time.perf_counter()
+            tau_o, phi_o = calib.solve_delay_phase(V, M, n_ant, 0.0, df, 0, lo, hi)
+            res["oracle_ms"] = round((time.perf_counter() - t0) * 1e3, 2)
+            res["max_tau_diff_vs_oracle_samples"] = float(f"{np.max(np.abs(tau - tau_o)) * fs:.3e}")
+            res["max_phi_diff_vs_oracle_rad"] = float(f"{np.max(np.abs(calib.wrap(phi - phi_o))):.3e}")
+            log(f"[bench] solve oracle {res['oracle_ms']:.1f} ms (4 ant)")
+
+
 def achievable_section(torch, qc):
     """What this GPU sustains, measured by the library's microbenchmark
     kernels (streaming read and copy of 4 GiB; independent scalar float32
@@ -377,15 +402,15 @@ def achievable_section(torch, qc):
     return r
 
 
-def solve_section(torch, qc, vis, n_ant, df, fs, sigma, reps):
+def solve_section(torch, qc, vis, n_ant, df, fs, sigma, reps, checks):
     """Delay/phase solve (Sec. 7): the real-time visibilities flagged by MAD
-    -> per-antenna delays and phases against antenna 0, checked against the
-    oracle's solve of the same input (timed beside it).  Then the 32-antenna
-    precision plane (496 cross baselines, no RFI), checked against its
-    injected lags.  The real-time stream's RFI is common to all antennas
-    (zero lag), and the lines MAD leaves unflagged pull its delays towards
-    zero, so lag recovery is judged on the clean stream."""
-    from oracle import calib
+    -> per-antenna delays and phases against antenna 0 (with `checks`, kept
+    for the CPU-baseline leg, which solves the same input with the oracle,
+    timed beside it, and compares).  Then the 32-antenna precision plane
+    (496 cross baselines, no RFI), checked against its injected lags.  The
+    real-time stream's RFI is common to all antennas (zero lag), and the
+    lines MAD leaves unflagged pull its delays towards zero, so lag recovery
+    is judged on the clean stream."""
     n_chan = vis.shape[2]
     lo, hi = 16, n_chan - 16
     mask, _ = qc.mad_flag(vis, sigma, 0)
@@ -396,13 +421,10 @@ def solve_section(torch, qc, vis, n_ant, df, fs, sigma, reps):
         tau, phi = qc.solve_delay_phase(vis, n_ant, 0.0, df, 0, lo, hi, mask=mask)
     gpu_ms = (time.perf_counter() - t0) / reps * 1e3
     V, M = vis.cpu().numpy(), mask.cpu().numpy()
-    t0 = time.perf_counter()
-    tau_o, phi_o = calib.solve_delay_phase(V, M, n_ant, 0.0, df, 0, lo, hi)
-    oracle_ms = (time.perf_counter() - t0) * 1e3
     res = {"workload": f"realtime_{n_ant}ant: {V.shape[0]} dumps x {V.shape[1]} baselines x {n_chan} ch",
-           "gpu_ms_synchronous": round(gpu_ms, 4), "oracle_ms": round(oracle_ms, 2),
-           "max_tau_diff_vs_oracle_samples": float(f"{np.max(np.abs(tau - tau_o)) * fs:.3e}"),
-           "max_phi_diff_vs_oracle_rad": float(f"{np.max(np.abs(calib.wrap(phi - phi_o))):.3e}")}
+           "gpu_ms_synchronous": round(gpu_ms, 4)}
+    if checks is not None:
+        checks.append(("solve", res, V, M, n_ant, df, fs, lo, hi, np.asarray(tau), np.asarray(phi)))
     # 32 antennas: the precision workload's float32 visibilities
     spec32 = synth.array_spec(32, 1 << 24, 3000)
     x32 = synth.generate(spec32)
@@ -417,8 +439,7 @@ def solve_section(torch, qc, vis, n_ant, df, fs, sigma, reps):
     res["gpu_ms_synchronous_32ant"] = round((time.perf_counter() - t0) / reps * 1e3, 4)
     inj = np.array(spec32.lags, np.float64) - spec32.lags[0]
     res["max_tau_err_vs_injected_samples_32ant"] = float(f"{np.max(np.abs(tau32 * fs - inj)):.3e}")
-    log(f"[bench] solve: {gpu_ms:.3f} ms (4 ant), {res['gpu_ms_synchronous_32ant']:.3f} ms (32 ant); "
-        f"oracle {oracle_ms:.1f} ms (4 ant)")
+    log(f"[bench] solve: {gpu_ms:.3f} ms (4 ant), {res['gpu_ms_synchronous_32ant']:.3f} ms (32 ant)")
     return res
 
 
@@ -532,16 +553,19 @@ def main():
         out["roofline"]["frac_of_achievable"] = round(achieved / ach["valu_f32_TFLOPs"], 4)
     if not args.no_stream:
         out["stream"] = stream_section(torch, qc, x, N, P, spd, vis_check)
-    out["solve"] = solve_section(torch, qc, vis_check, n_ant, df, fs, sigma, max(3, args.steps // 10))
+    # comparisons with the oracle are made in the CPU-baseline leg at the end
+    checks = None if args.no_cpu_baseline else []
+    out["solve"] = solve_section(torch, qc, vis_check, n_ant, df, fs, sigma, max(3, args.steps // 10), checks)
     if not args.no_precision:
         del vis_check
-        out["precision_32ant"] = precision_section(torch, qc, args.steps)
+        out["precision_32ant"] = precision_section(torch, qc, args.steps, checks)
     if not args.no_batched:
         out["batched"] = batched_section(torch, qc, args.steps)
     if not args.no_flagger:
         out["flagger"] = flagger_section(torch, qc, args.steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(x, N, P, spd, sigma, tau, phi, df, gpu_vis)
+        oracle_checks(checks)
     print(json.dumps(out), flush=True)
 
 
