@@ -29,7 +29,11 @@ lag_pad * n_chan, at most 8192 (and at least n_chan); fit weights are the
 amplitudes of the time-integrated, flag-zeroed visibilities; the phase is
 unwrapped as numpy.unwrap does (a step of magnitude above pi gets a 2 pi
 correction of the opposite sign).
-Status: pinned on noiseless synthetic phases (tests/test_oracle.py).
+Status: pinned (tests/test_oracle.py): the delay spectrum by numpy's
+inverse FFT of the zero-padded spectrum; the coarse delay by exact recovery
+of on-grid delays of both signs and nearest-lag recovery off the grid; the
+whole solve by noiseless recovery and by steep, noisy phases that only the
+coarse step lets the fine fit unwrap.
 """
 
 from __future__ import annotations
@@ -77,6 +81,20 @@ def lag_grid(n_chan: int, lag_pad: int = 4) -> int:
     return n
 
 
+def coarse_delay(Vb, df, n_lag: int) -> float:
+    """Step 1 of Sec. 7: the delay at the peak of |delay spectrum|.
+
+    Lag l of the n_lag-point grid is the delay l / (n_lag df) for
+    l < n_lag/2 and (l - n_lag) / (n_lag df) above (the grid spans one
+    period 1/df of the spectrum's delay response, centred on zero).  Ties go
+    to the smallest l (numpy.argmax).
+    """
+    D = np.abs(delay_spectrum(Vb, n_lag))
+    l = int(np.argmax(D))
+    ls = l if l < n_lag // 2 else l - n_lag
+    return ls / (n_lag * df)
+
+
 def solve_baseline(Vb, f0, df, chan_lo, chan_hi, lag_pad: int = 4):
     """(tau, phi) for one baseline's time-integrated spectrum Vb[k].
 
@@ -87,10 +105,7 @@ def solve_baseline(Vb, f0, df, chan_lo, chan_hi, lag_pad: int = 4):
     n_lag = lag_grid(n_chan, lag_pad)
     f = f0 + np.arange(n_chan, dtype=np.float64) * df
     # step 1: coarse delay from the delay-spectrum peak
-    D = np.abs(delay_spectrum(Vb, n_lag))
-    l = int(np.argmax(D))
-    ls = l if l < n_lag // 2 else l - n_lag
-    tau_c = ls / (n_lag * df)
+    tau_c = coarse_delay(Vb, df, n_lag)
     # step 2: weighted LS of unwrapped phase vs frequency in the clean band
     W = Vb * np.exp(2j * np.pi * f * tau_c)
     band = slice(chan_lo, chan_hi)

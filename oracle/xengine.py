@@ -11,8 +11,11 @@ Readings:
     (the paper says "accumulated"), full dumps only;
   * autos carry an imaginary part of exactly zero.
 
-The multiply-accumulate is written out per baseline.  Status: pinned (see
-tests/test_oracle.py).
+The multiply-accumulate is written out per baseline.  Status: pinned.
+correlate() by the Gram-matrix route, Hermitian/PSD/Cauchy-Schwarz
+identities and noise and delay statistics; correlate_fast() by exact
+agreement with correlate() on ragged dumps from 1 to 32 antennas, with a
+check of which operand carries the conjugate (tests/test_oracle.py).
 """
 
 from __future__ import annotations

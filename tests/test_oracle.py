@@ -155,6 +155,27 @@ def test_xengine_matches_gram_matrix_route():
                 assert abs(V[d, b, k] - G[i, j]) < 1e-10
 
 
+@pytest.mark.parametrize("n_ant,M,C,D", [(1, 7, 5, 3), (4, 11, 9, 4), (32, 5, 3, 2), (3, 9, 4, 9),
+                                         (2, 4, 6, 5)])
+def test_correlate_fast_equals_explicit_mac(n_ant, M, C, D):
+    """The vectorised sum over a dump is the explicit per-spectrum MAC of
+    correlate(): same pairs, same conjugated operand, same dropped tail
+    (ragged M), autos exactly real.  correlate() is pinned by the Gram,
+    Hermitian and PSD tests, so correlate_fast inherits those pins."""
+    X = _random_X(n_ant, M, C) * 37.0
+    Vf = xengine.correlate_fast(X, D)
+    V = xengine.correlate(X, D)
+    assert Vf.shape == V.shape == (M // D, n_ant * (n_ant + 1) // 2, C)
+    assert np.allclose(Vf, V, rtol=0, atol=1e-12 * np.abs(V).max() if V.size else 0)
+    for a in range(n_ant):
+        assert np.all(Vf[:, xengine.baseline_index(a, a, n_ant)].imag == 0)
+    # the conjugate falls on the second antenna: V_01 = sum X_0 conj(X_1)
+    if n_ant >= 2 and M >= D:
+        ref = np.sum(X[0, :D] * np.conj(X[1, :D]), axis=0)
+        assert np.allclose(Vf[0, 1], ref, rtol=0, atol=1e-9)
+        assert not np.allclose(Vf[0, 1], np.conj(ref), rtol=0, atol=1e-9)
+
+
 def test_xengine_hermitian_autos_cauchy_schwarz_psd():
     n_ant = 6
     X = _random_X(n_ant, 20, 9)
@@ -335,6 +356,80 @@ def test_solve_recovers_noiseless_delay_and_phase():
     # and applying the solution flattens every cross baseline
     W = calib.apply_delay_phase(V, n_ant, f0, df, t, p)
     assert np.allclose(np.angle(W), 0, atol=1e-7)
+
+
+def test_delay_spectrum_is_scaled_inverse_fft_of_padded_spectrum():
+    """D[l] = sum_k V[k] e^{+2 pi i k l / L} is L * ifft of V zero-padded to L
+    (numpy's inverse FFT carries the + sign and a 1/L factor)."""
+    for C, L in [(7, 16), (64, 256), (100, 128)]:
+        Vb = RNG.normal(size=C) + 1j * RNG.normal(size=C)
+        ref = L * np.fft.ifft(np.concatenate([Vb, np.zeros(L - C)]))
+        assert np.allclose(calib.delay_spectrum(Vb, L), ref, rtol=0, atol=1e-9 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("lag", [0, 1, 5, -3, -500, 511, -512, 300])
+def test_coarse_delay_recovers_on_grid_delays_both_signs(lag):
+    """A noiseless V[k] = exp(-2 pi i f_k tau) with tau = lag / (L df) on the
+    delay grid peaks exactly at that lag (|D| = C there, < C elsewhere);
+    the grid covers lags -L/2 .. L/2 - 1."""
+    C = 256
+    L = calib.lag_grid(C)
+    f0, df = 1.3e9, 1e9 / 4096
+    tau = lag / (L * df)
+    Vb = np.exp(-2j * np.pi * (f0 + df * np.arange(C)) * tau + 0.7j)
+    assert calib.coarse_delay(Vb, df, L) == pytest.approx(tau, abs=1e-6 / (L * df))
+
+
+def test_coarse_delay_off_grid_is_nearest_lag():
+    C, f0, df = 512, 0.2e9, 1e9 / 1024
+    L = calib.lag_grid(C)
+    for frac in [-0.49, -0.3, -0.01, 0.2, 0.37, 0.48]:
+        tau = frac / df
+        Vb = np.exp(-2j * np.pi * (f0 + df * np.arange(C)) * tau)
+        tc = calib.coarse_delay(Vb, df, L)
+        assert abs(tc - tau) <= 0.5 / (L * df) + 1e-18
+
+
+def _steep_noisy(n_ant, C, f0, df, tau, phi, seed, amp=0.35 * np.pi):
+    """Cross phases with a slope of up to 0.94 pi per channel plus bounded
+    phase noise: unwrapping without the coarse step mistracks."""
+    rng = np.random.default_rng(seed)
+    pairs = xengine.baseline_pairs(n_ant)
+    f = f0 + df * np.arange(C)
+    V = np.zeros((2, len(pairs), C), complex)
+    for b, (i, j) in enumerate(pairs):
+        eps = rng.uniform(-amp, amp, C) if i != j else 0.0
+        V[:, b] = np.exp(-1j * (2 * np.pi * f * (tau[i] - tau[j]) + (phi[i] - phi[j])) + 1j * eps)
+    return V
+
+
+def test_solve_needs_the_coarse_step_on_steep_noisy_phases():
+    """Sec. 7 step 1 matters once the per-channel phase step plus noise
+    passes pi: baseline (1, 2) steps 0.92 pi per channel (every baseline
+    stays inside the delay grid, |dtau df| < 1/2) and the noise moves each
+    step by up to 0.7 pi.  The coarse step removes the slope to within one
+    lag cell first, so the fine fit unwraps correctly; without it (or with
+    its transform's sign flipped) the unwrap mistracks and tau is off by
+    microseconds."""
+    n_ant, C = 4, 512
+    f0, df = 1.3e9, 1e9 / 4096
+    tau = np.array([0.0, 0.22, -0.24, 0.1]) / df
+    phi = np.array([0.0, 1.1, -2.5, 0.3])
+    V = _steep_noisy(n_ant, C, f0, df, tau, phi, seed=7)
+    # the raw phase steps of baseline (1, 2) do pass pi
+    b12 = xengine.baseline_index(1, 2, n_ant)
+    assert np.any(np.abs(np.diff(np.angle(V[0, b12, 40:480]))) > np.pi)
+    t, p = calib.solve_delay_phase(V, None, n_ant, f0, df, 0, 40, 480)
+    assert np.max(np.abs(t - tau)) < 0.5e-9
+    # each baseline's own (tau, phi) flattens its band (the per-antenna fit
+    # spreads the baselines' tau scatter, which 2 pi f0 turns into phase)
+    f = f0 + df * np.arange(C)
+    for b, (i, j) in enumerate(xengine.baseline_pairs(n_ant)):
+        if i != j:
+            tb, pb = calib.solve_baseline(V.sum(axis=0)[b], f0, df, 40, 480)
+            assert abs(tb - (tau[i] - tau[j])) < 0.5e-9
+            W = V[0, b, 40:480] * np.exp(1j * (2 * np.pi * f[40:480] * tb + pb))
+            assert abs(np.angle(W.sum())) < 0.05
 
 
 # -------------------------------------------------------------- quant ----

@@ -38,6 +38,32 @@ def test_solve_recovers_noiseless(qc, n_ant, C):
     assert np.max(np.abs(calib.wrap(p - po))) < 1e-4
 
 
+@pytest.mark.parametrize("seed,sign", [(7, 1.0), (8, -1.0)])
+def test_solve_steep_noisy_phases_need_the_coarse_step(qc, seed, sign):
+    """Cross phases stepping up to 0.92 pi per channel (both signs), with
+    bounded phase noise that moves each step by up to 0.7 pi: unwrapping
+    without the coarse delay (Sec. 7 step 1) mistracks, so agreement with
+    the oracle and with the injected delays checks the GPU's coarse argmax."""
+    import torch
+    n_ant, C = 4, 512
+    f0, df = 0.3e9, 1e9 / 4096
+    tau = sign * np.array([0.0, 0.22, -0.24, 0.1]) / df
+    phi = np.array([0.0, 1.1, -2.5, 0.3])
+    rng = np.random.default_rng(seed)
+    pairs = [(i, j) for i in range(n_ant) for j in range(i, n_ant)]
+    f = f0 + df * np.arange(C)
+    V = np.zeros((2, len(pairs), C), np.complex64)
+    for b, (i, j) in enumerate(pairs):
+        eps = rng.uniform(-0.35 * np.pi, 0.35 * np.pi, C) if i != j else 0.0
+        V[:, b] = 1e3 * np.exp(-1j * (2 * np.pi * f * (tau[i] - tau[j]) + (phi[i] - phi[j])) + 1j * eps)
+    lo, hi = 40, 480
+    t, p = qc.solve_delay_phase(torch.from_numpy(V).cuda(), n_ant, f0, df, 0, lo, hi)
+    to, po = calib.solve_delay_phase(V, None, n_ant, f0, df, 0, lo, hi)
+    assert np.max(np.abs(t - to)) < 1e-3 / 1e9, np.max(np.abs(t - to))
+    assert np.max(np.abs(calib.wrap(p - po))) < 1e-4
+    assert np.max(np.abs(t - tau)) < 0.5e-9
+
+
 def test_solve_matches_oracle_on_pipeline_output(qc):
     """Correlated stream with injected lags -> visibilities -> MAD flags ->
     solve: GPU and oracle agree, and the solution matches the lags."""
