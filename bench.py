@@ -107,6 +107,45 @@ def measured_traffic():
     return int(fields["hbm_bytes_per_launch"])
 
 
+def _auto_scale(V_ref, n_ant):
+    """sqrt(V_ii V_jj) per (dump, baseline, channel) from the reference autos."""
+    pairs = [(i, j) for i in range(n_ant) for j in range(i, n_ant)]
+    idx = {p: b for b, p in enumerate(pairs)}
+    autos = np.stack([V_ref[:, idx[(a, a)], :].real for a in range(n_ant)], axis=1)
+    sc = np.empty(V_ref.shape, np.float64)
+    for b, (i, j) in enumerate(pairs):
+        sc[:, b, :] = np.sqrt(np.maximum(autos[:, i, :] * autos[:, j, :], 0.0))
+    return sc
+
+
+def vis_err(V, V_ref, n_ant):
+    """max |V - V_ref| / sqrt(V_ii V_jj), the autos taken from the reference."""
+    d = np.abs(np.asarray(V, np.complex128) - np.asarray(V_ref, np.complex128))
+    return float(np.max(d / np.maximum(_auto_scale(V_ref, n_ant), 1e-300)))
+
+
+def per_baseline_errors(V, V_ref, n_ant):
+    """Per baseline (max over dumps and channels): amplitude error
+    ||V| - |V_ref|| / |V_ref|, phase error |arg(V conj V_ref)| in degrees, and
+    the auto-normalised error."""
+    V = np.asarray(V, np.complex128)
+    V_ref = np.asarray(V_ref, np.complex128)
+    amp = np.abs(np.abs(V) - np.abs(V_ref)) / np.maximum(np.abs(V_ref), 1e-300)
+    ph = np.degrees(np.abs(np.angle(V * np.conj(V_ref))))
+    nerr = np.abs(V - V_ref) / np.maximum(_auto_scale(V_ref, n_ant), 1e-300)
+    return amp.max(axis=(0, 2)), ph.max(axis=(0, 2)), nerr.max(axis=(0, 2))
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def timed(torch, fn, reps):
     s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -214,8 +253,7 @@ def stream_section(torch, qc, x, N, P, spd, vis_ref, reps=3):
         run_ms.append((time.perf_counter() - t0) * 1e3)
         seq += 1          # a gap: the next pass starts a fresh stream (zero history)
     st.close()
-    from tests.util import vis_err as vis_err_local
-    err = vis_err_local(vis.cpu().numpy(), vis_ref.cpu().numpy(), n_ant)
+    err = vis_err(vis.cpu().numpy(), vis_ref.cpu().numpy(), n_ant)
     ms, cms = min(run_ms), min(copy_ms)
     log(f"[bench] streamed from pinned host: {ms:.2f} ms ({x.nbytes / ms / 1e6:.1f} GB/s); "
         f"plain H2D copy {cms:.2f} ms")
@@ -273,7 +311,6 @@ def batched_section(torch, qc, steps):
     """Five uneven arrays (4..32 antennas, 512..4096 channels, 2^22 samples
     each) as one plan: eager, replay of its captured graph, and the same work
     as separate per-array calls."""
-    from tests.util import vis_err as vis_err_local
     n_samp = 1 << 22
     t0 = time.time()
     ws = synth.batched(n_samp, 4000)
@@ -313,7 +350,7 @@ def batched_section(torch, qc, steps):
     plan.check()
     sep = plan.empty_vis()
     s_ms = on_side(lambda: plan.execute_separate(xs, sep))
-    err = max(vis_err_local(a.cpu().numpy(), b.cpu().numpy(), d["n_ant"])
+    err = max(vis_err(a.cpu().numpy(), b.cpu().numpy(), d["n_ant"])
               for a, b, d in zip(vis, sep, descs))
     log(f"[bench] batched: graph {g_ms:.3f} ms, eager plan {e_ms:.3f} ms, separate {s_ms:.3f} ms")
     plan.close()
@@ -333,7 +370,6 @@ def cpu_baseline(x, N, P, spd, sigma, tau, phi, df, gpu_vis, n_dumps=8):
     n_dumps dumps (64 MiB of input each) on a 64-channel subset, F+X then MAD
     then apply."""
     from oracle import calib, mad
-    from tests.util import vis_err as vis_err_local
     cores = len(os.sched_getaffinity(0))
     rng = np.random.default_rng(0)
     chans = np.sort(rng.choice(N // 2, 64, replace=False))
@@ -346,11 +382,42 @@ def cpu_baseline(x, N, P, spd, sigma, tau, phi, df, gpu_vis, n_dumps=8):
     full[:, :, chans] = V
     W = calib.apply_delay_phase(full, n_ant, 0.0, df, tau, phi)[:, :, chans]
     dt = time.perf_counter() - t0
-    err = vis_err_local(gpu_vis[:n_dumps][:, :, chans], V, n_ant)
-    return {"value": round(xs.nbytes / dt / 1e9, 5), "unit": "GB/s", "cores": cores, "kind": "oracle",
-            "sample": f"first {n_dumps} dumps (4 ant x {n_dumps * spd * N} samples = {xs.nbytes >> 20} MiB), "
-                      f"{len(chans)} of {N // 2} channels, F+X + MAD + apply, float64",
-            "seconds": round(dt, 2), "gpu_vs_oracle_err_on_sample": float(f"{err:.3e}")}
+    err = vis_err(gpu_vis[:n_dumps][:, :, chans], V, n_ant)
+    out = {"value": round(xs.nbytes / dt / 1e9, 5), "unit": "GB/s", "cores": cores, "kind": "oracle",
+           "sample": f"first {n_dumps} dumps (4 ant x {n_dumps * spd * N} samples = {xs.nbytes >> 20} MiB), "
+                     f"{len(chans)} of {N // 2} channels, F+X + MAD + apply, float64",
+           "seconds": round(dt, 2), "gpu_vs_oracle_err_on_sample": float(f"{err:.3e}"),
+           "cpu_model": cpu_model()}
+    out["other_workloads"] = other_oracle_rates()
+    return out
+
+
+def other_oracle_rates():
+    """The oracle's input rate on the other bounded samples: the plain
+    4-antenna correlator in full (N = 1024, all 512 channels, one dump), and
+    the 32-antenna stream's first 512 spectra (2^21 samples per antenna) on
+    64 of its 2048 channels.  Each is the rate of exactly what was computed."""
+    from oracle import pfb, xengine
+    res = {}
+    w = synth.plain_fx()
+    t0 = time.perf_counter()
+    xengine.correlate_fast(pfb.channelize(w.x, w.n_fft, w.n_taps), w.spec_per_dump)
+    dt = time.perf_counter() - t0
+    res["plain_fx_4ant_n1024"] = {"GBps": round(w.x.nbytes / dt / 1e9, 5), "seconds": round(dt, 3),
+                                  "sample": "whole workload: 4 ant x 2^20 samples, 512 of 512 channels"}
+    x32 = synth.generate(synth.array_spec(32, 1 << 24, 3000))
+    xs = np.ascontiguousarray(x32[:, :1 << 21])
+    del x32
+    chans = np.arange(0, 2048, 32)
+    t0 = time.perf_counter()
+    X = pfb.channelize(xs, 4096, 4, chans=chans)
+    xengine.correlate_fast(X, X.shape[1])
+    dt = time.perf_counter() - t0
+    res["precision_32ant_n4096"] = {"GBps": round(xs.nbytes / dt / 1e9, 5), "seconds": round(dt, 3),
+                                    "sample": "32 ant x first 2^21 samples (512 spectra), 64 of 2048 channels"}
+    log(f"[bench] oracle: plain FX {res['plain_fx_4ant_n1024']['GBps']} GB/s, "
+        f"32 ant subset {res['precision_32ant_n4096']['GBps']} GB/s")
+    return res
 
 
 def oracle_checks(checks):
@@ -358,15 +425,27 @@ def oracle_checks(checks):
     kept GPU results against the FP64 oracle on the same input, the figures
     written back into that section."""
     from oracle import calib
-    from tests.util import vis_err as vis_err_local
     for item in checks:
         if item[0] == "precision":
             _, res, x, N, P, spd, chans, sampled = item
             t0 = time.time()
             V_ref = oracle_vis_subset(x, N, P, spd, chans, [0], block=128)
             log(f"[bench] 32-antenna oracle subset in {time.time() - t0:.1f}s")
+            n_ant = x.shape[0]
+            cross = np.array([i != j for i in range(n_ant) for j in range(i, n_ant)])
             for prec, V in sampled.items():
-                res[prec]["vis_err_vs_fp64"] = float(f"{vis_err_local(V, V_ref, x.shape[0]):.3e}")
+                res[prec]["vis_err_vs_fp64"] = float(f"{vis_err(V, V_ref, n_ant):.3e}")
+                amp, ph, nerr = per_baseline_errors(V, V_ref, n_ant)
+                # over the 528 baselines (phase over the 496 cross baselines:
+                # autos are real on both sides)
+                res[prec]["per_baseline"] = {
+                    "amp_err_max": float(f"{amp.max():.3e}"),
+                    "amp_err_median": float(f"{np.median(amp):.3e}"),
+                    "phase_err_deg_max": float(f"{ph[cross].max():.3e}"),
+                    "phase_err_deg_median": float(f"{np.median(ph[cross]):.3e}"),
+                    "norm_err_max": float(f"{nerr.max():.3e}"),
+                    "norm_err_median": float(f"{np.median(nerr):.3e}"),
+                    "channels": [int(c) for c in chans]}
         elif item[0] == "solve":
             _, res, V, M, n_ant, df, fs, lo, hi, tau, phi = item
             t0 = time.perf_counter()

@@ -19,7 +19,7 @@ import pytest
 
 import synth
 from oracle import cnn, mad, pfb, xengine
-from tests.util import vis_err
+from tests.util import quant_bar, vis_err
 
 pytestmark = pytest.mark.gpu
 
@@ -44,6 +44,40 @@ def _oracle_vis(x, N, P, spd, chans, dumps, block=512):
             acc = V if acc is None else acc + V
         out.append(acc)
     return np.stack(out)
+
+
+def test_plain_fx_config_all_channels(qc):
+    """The plain correlator as specified: 4 antennas x 2^20 samples, sigma 16
+    noise, 30 % correlated power at lags {0, 3, 5, 7}, a tone of amplitude 16
+    centred on channel 137; N = 1024, P = 4, one dump of 1024 spectra.  All
+    512 channels against the oracle; the injected lags' phase slopes; and
+    the tone alone (no noise) in channel 137 with >= 44 dB to its
+    neighbours (the prototype's response one channel off is -44.4 dB)."""
+    import torch
+    w = synth.plain_fx()
+    assert w.x.shape == (4, 1 << 20) and w.params["lags"] == (0, 3, 5, 7)
+    V = qc.xcorrelate(torch.from_numpy(w.x).cuda(), 1024, 4, 1024).cpu().numpy()
+    assert V.shape == (1, 10, 512)
+    V_ref = xengine.correlate_fast(pfb.channelize(w.x, 1024, 4), 1024)
+    err = vis_err(V, V_ref, 4)
+    print(f"plain FX: err {err:.3e} over all 512 channels")
+    assert err <= 1e-5
+    lags = w.params["lags"]
+    k = np.array([c for c in range(10, 502) if abs(c - 137) > 2])
+    for b, (i, j) in enumerate(xengine.baseline_pairs(4)):
+        if i != j:
+            ph = np.angle(V[0, b, k] * np.exp(2j * np.pi * k * (lags[i] - lags[j]) / 1024))
+            assert np.abs(ph).max() < 0.6 and abs(ph.mean()) < 0.03, (i, j)
+    tone = synth.StreamSpec(2, 1 << 16, 1000, sigma=0.0, corr=0.0, tone_amp=16.0,
+                            tone_cycles_per_sample=137 / 1024, period=1024)
+    xt = synth.generate(tone)
+    X = qc.pfb_channelize(torch.from_numpy(xt).cuda(), 1024, 4)[0].cpu().numpy()[:, 3:]
+    X_ref = pfb.channelize(xt, 1024, 4)[:, 3:]
+    assert np.abs(X - X_ref).max() <= 1e-6 * np.abs(X_ref).max()
+    p = np.abs(X.astype(np.complex128)) ** 2
+    iso = 10 * np.log10(p[:, :, 137] / np.maximum(p[:, :, 136], p[:, :, 138]))
+    print(f"tone isolation {iso.min():.2f} dB")
+    assert iso.min() >= 44.0
 
 
 def test_realtime_full_size(qc):
@@ -74,10 +108,13 @@ def test_precision_32ant_full_size(qc):
     xd = torch.from_numpy(x).cuda()
     chans = np.array([0, 777, 2047])
     V_ref = _oracle_vis(x, N, P, spd, chans, [0], block=256)
-    for prec, tol in (("f32", 1e-5), ("f16", 1e-3)):
+    for prec in ("f32", "f16", "bf16", "fp8"):
+        tol = 1e-5 if prec == "f32" else quant_bar(prec, spd)
         V = qc.xcorrelate(xd, N, P, spd, x_prec=prec)
         torch.cuda.synchronize()
-        assert vis_err(V.cpu().numpy()[:, :, chans], V_ref, 32) <= tol, prec
+        err = vis_err(V.cpu().numpy()[:, :, chans], V_ref, 32)
+        print(f"32 antennas {prec}: err {err:.3e} (bar {tol:.2e})")
+        assert err <= tol, (prec, err)
 
 
 def test_batched_full_size(qc):

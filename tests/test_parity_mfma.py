@@ -8,8 +8,8 @@
   matches the oracle's float64 multiply-accumulate of those codes to float32
   accumulation error (products of the formats are exact in FP32);
 * end to end (F-engine -> requantise -> matrix cores) against the plain FP64
-  oracle: FP16 within 1e-3 and BF16 within 5e-3 of the auto scale at these
-  short dumps; E4M3 is reported.
+  oracle: every format within the bar its significand width sets for the
+  dump length (tests.util.quant_bar: z * 2^(1-p) / sqrt(3 M), z = 5).
 """
 
 import numpy as np
@@ -17,7 +17,7 @@ import pytest
 
 import synth
 from oracle import pfb, quant, xengine
-from tests.util import per_baseline_errors, vis_err
+from tests.util import per_baseline_errors, quant_bar, vis_err
 
 pytestmark = pytest.mark.gpu
 
@@ -115,11 +115,9 @@ def test_mfma_end_to_end_accuracy(qc, prec):
     V_ref = xengine.correlate_fast(pfb.channelize(x, N, 4), spd)
     err = vis_err(V, V_ref, n_ant)
     amp, ph, nerr = per_baseline_errors(V, V_ref, n_ant)
-    print(f"{prec}: err vs fp64 {err:.2e}; median per-baseline err {np.median(nerr):.2e}")
-    if prec == "f16":
-        assert err <= 1e-3, err
-    elif prec == "bf16":
-        assert err <= 5e-3, err
+    print(f"{prec}: err vs fp64 {err:.2e}; median per-baseline err {np.median(nerr):.2e}; "
+          f"bar {quant_bar(prec, spd):.2e}")
+    assert err <= quant_bar(prec, spd), err
 
 
 def test_mfma_hermitian_structure(qc):
@@ -148,9 +146,8 @@ def test_xcorrelate_reduced_precision_two_pass(qc, prec):
     V = qc.xcorrelate(torch.from_numpy(x).cuda(), N, 4, 16, x_prec=prec).cpu().numpy()
     V_ref = xengine.correlate_fast(pfb.channelize(x, N, 4), 16)
     err = vis_err(V, V_ref, n_ant)
-    print(f"two-pass {prec}: err vs fp64 {err:.2e}")
-    bar = {"fp8": 0.2, "bf16": 5e-3, "f16": 1e-3}[prec]
-    assert err <= bar
+    print(f"two-pass {prec}: err vs fp64 {err:.2e}; bar {quant_bar(prec, 16):.2e}")
+    assert err <= quant_bar(prec, 16), err
 
 
 def test_mfma_rejects_unsupported(qc):

@@ -43,3 +43,23 @@ def per_baseline_errors(V, V_ref, n_ant):
     ph = np.degrees(np.abs(np.angle(V * np.conj(V_ref))))
     nerr = np.abs(V - V_ref) / np.maximum(sc, 1e-300)
     return amp.max(axis=(0, 2)), ph.max(axis=(0, 2)), nerr.max(axis=(0, 2))
+
+
+SIG_BITS = {"f16": 11, "fp16": 11, "bf16": 8, "fp8": 4, "e4m3": 4}
+
+
+def quant_bar(prec, M, z=5.0):
+    """Bar on the auto-normalised visibility error of a requantised X-engine.
+
+    Rounding each component of X to a p-bit significand (round to nearest)
+    leaves an error e with E|e|^2 <= delta^2 |X|^2, delta = 2^(1-p)/sqrt(12)
+    (uniform error over one unit in the last place, whose size relative to
+    the value is at most 2^(1-p)).  To first order a dump of M spectra then
+    carries sum_m (X_i e_j* + e_i X_j*), whose rms over sqrt(V_ii V_jj) is
+    sqrt(2/M) delta for a cross baseline and sqrt(4/M) delta for an auto.
+    The bar is z times the larger, z * 2^(1-p) / sqrt(3 M); z = 5 covers the
+    maximum over ~10^6 visibilities.  FP32 accumulation (~1e-7) is below
+    it for every format here.
+    """
+    p = SIG_BITS[prec]
+    return z * 2.0 ** (1 - p) / np.sqrt(3.0 * M)
