@@ -17,8 +17,8 @@ magnitude saturate to it):
 
 Per-antenna scale (reading): s_a = 2^round(log2(target / rms_a)), where
 rms_a is the expected channel rms from the input power,
-rms_a = sqrt(mean(x_a^2) * sum_q h[q]^2), the mean taken over the first
-min(S, 2^20) samples of antenna a.  Targets: E4M3 32, FP16 256, BF16 1.
+rms_a = sqrt(mean(|x_a|^2) * sum_q h[q]^2), the mean taken over the first
+min(S, 2^20) samples of antenna a (|x|^2 = I^2 + Q^2 for complex samples).  Targets: E4M3 32, FP16 256, BF16 1.
 round() here is round-half-to-even on the float64 log2.
 Status: pinned (tests/test_oracle.py: grids, ties, saturation).
 """
@@ -72,7 +72,13 @@ def pow2_scales(x, taps, prec: str) -> np.ndarray:
     """Per-antenna power-of-two scale s_a (float64) from the input power."""
     x = np.asarray(x)
     n = min(x.shape[1], SCALE_PREFIX)
-    p = (x[:, :n].astype(np.int64) ** 2).sum(axis=1).astype(np.float64) / n
+    if np.iscomplexobj(x):
+        # complex I/Q samples: the power is |x|^2 = I^2 + Q^2
+        re = x[:, :n].real.astype(np.int64)
+        im = x[:, :n].imag.astype(np.int64)
+        p = (re * re + im * im).sum(axis=1).astype(np.float64) / n
+    else:
+        p = (x[:, :n].astype(np.int64) ** 2).sum(axis=1).astype(np.float64) / n
     h2 = float(np.sum(np.asarray(taps, np.float64) ** 2))
     rms = np.sqrt(p * h2)
     e = np.zeros(x.shape[0])

@@ -119,6 +119,104 @@ def test_int8_tone_rounding_bound():
     assert np.max(np.abs(d)) <= 0.5 * np.sum(np.abs(h)) + 1e-9
 
 
+def test_kaiser_taps_match_scipy_kaiser_times_sinc():
+    for N, P, beta in [(16, 8, 8.0), (1024, 8, 8.0), (64, 3, 5.0)]:
+        L = N * P
+        h = pfb.kaiser_sinc_taps(N, P, beta)
+        w = scipy.signal.windows.kaiser(L, beta, sym=True)
+        ref = w * np.sinc((np.arange(L) - (L - 1) / 2) / N)
+        assert np.allclose(h, ref, rtol=0, atol=1e-14)
+        assert np.allclose(h, h[::-1], atol=1e-15)
+
+
+def test_complex_p1_rectangular_is_numpy_fft():
+    N = 64
+    x = RNG.integers(-128, 128, (2, 10 * N)) + 1j * RNG.integers(-128, 128, (2, 10 * N))
+    X = pfb.channelize_complex(x, N, 1, taps=np.ones(N))
+    ref = np.fft.fft(x.reshape(2, 10, N), axis=2)
+    assert np.allclose(X, ref, rtol=1e-12, atol=1e-9)
+
+
+@pytest.mark.parametrize("N,P", [(16, 4), (32, 8)])
+def test_complex_pfb_equals_decimated_long_fft(N, P):
+    M = 7
+    x = RNG.integers(-9000, 9000, (2, M * N)) + 1j * RNG.integers(-9000, 9000, (2, M * N))
+    h = pfb.kaiser_sinc_taps(N, P, 8.0)
+    X = pfb.channelize_complex(x, N, P, taps=h)
+    xp = np.concatenate([np.zeros((2, (P - 1) * N)), x], axis=1)
+    for m in range(M):
+        F = np.fft.fft(xp[:, m * N:m * N + P * N] * h[None, :], axis=1)
+        assert np.allclose(X[:, m], F[:, ::P], rtol=1e-12, atol=1e-6)
+
+
+def test_complex_is_linear_in_i_and_q_and_real_input_is_hermitian():
+    N, P = 32, 4
+    xi = RNG.integers(-128, 128, (3, 6 * N))
+    xq = RNG.integers(-128, 128, (3, 6 * N))
+    allk = np.arange(N)
+    Xc = pfb.channelize_complex(xi + 1j * xq, N, P)
+    Xi = pfb.channelize(xi, N, P, chans=allk)
+    Xq = pfb.channelize(xq, N, P, chans=allk)
+    assert np.allclose(Xc, Xi + 1j * Xq, rtol=1e-12, atol=1e-8)
+    # real input: X[N-k] = conj X[k]; the first N/2 channels are the real path's
+    Xr = pfb.channelize_complex(xi + 0j, N, P)
+    assert np.allclose(Xr[..., 1:][..., ::-1], np.conj(Xr[..., 1:]), atol=1e-8)
+    assert np.allclose(Xr[..., :N // 2], pfb.channelize(xi, N, P), atol=1e-8)
+
+
+@pytest.mark.parametrize("k0", [37, -37])
+def test_complex_tone_lands_in_its_signed_channel(k0):
+    """exp(2 pi i k0 n / N) lands in channel k0 mod N: negative frequencies
+    occupy k >= N/2, with >= 44 dB to the neighbours (Hann-sinc, P = 4)."""
+    N, P = 256, 4
+    n = np.arange(8 * N)
+    x = np.rint(8000 * np.exp(2j * np.pi * k0 * n / N).real) + 1j * np.rint(8000 * np.exp(2j * np.pi * k0 * n / N).imag)
+    X = pfb.channelize_complex(x[None], N, P)[0, P - 1:]
+    k = k0 % N
+    p = np.abs(X) ** 2
+    assert np.all(np.argmax(p, axis=1) == k)
+    assert np.all(10 * np.log10(p[:, k] / p[:, (k + 1) % N]) > 44)
+    assert np.all(10 * np.log10(p[:, k] / p[:, (k - 1) % N]) > 44)
+
+
+def test_int16_exact_integer_n4_by_hand():
+    """16-bit padded samples enter as the integers they are."""
+    x = np.array([[8191, -8192, 4000, 1, -7000, 9, 2, -6]], np.int16)
+    X = pfb.channelize(x, 4, 2, taps=np.ones(8), keep_nyquist=True)
+    b = [[0, 0, 0, 0], [8191, -8192, 4000, 1], [-7000, 9, 2, -6]]
+    for m in range(2):
+        y = [b[m][n] + b[m + 1][n] for n in range(4)]
+        want = [sum(y), complex(y[0] - y[2], -(y[1] - y[3])), y[0] - y[1] + y[2] - y[3]]
+        assert np.allclose(X[0, m], want, atol=1e-9)
+
+
+def test_rectangular_half_bin_leakage_is_the_dirichlet_kernel():
+    """A complex tone half a bin above channel k0 through the plain FFT: the
+    power at channel k0 + d relative to channel k0 is
+    |D(d - 1/2)|^2 / |D(-1/2)|^2 with D(v) = sin(pi v) / sin(pi v / N)."""
+    N, k0 = 128, 40
+    n = np.arange(4 * N)
+    x = np.exp(2j * np.pi * (k0 + 0.5) * n / N)
+    X = pfb.channelize_complex(x[None], N, 1, taps=pfb.rect_taps(N))[0]
+    p = np.mean(np.abs(X) ** 2, axis=0)
+
+    def D(v):
+        return np.sin(np.pi * v) / np.sin(np.pi * v / N)
+
+    for d in list(range(-10, 0)) + list(range(1, 11)):
+        want = (D(d - 0.5) / D(-0.5)) ** 2
+        assert p[k0 + d] / p[k0] == pytest.approx(want, rel=1e-9)
+
+
+def test_pow2_scale_complex_reduces_to_real():
+    x = RNG.integers(-300, 300, (2, 1 << 12))
+    h = pfb.hann_sinc_taps(64, 4)
+    assert np.array_equal(quant.pow2_scales(x + 0j, h, "fp16"), quant.pow2_scales(x, h, "fp16"))
+    # doubling |x| halves the scale
+    assert np.array_equal(quant.pow2_scales(2 * x + 2j * x, h, "fp8"),
+                          quant.pow2_scales(x + 1j * x, h, "fp8") / 2)
+
+
 def test_history_carry_equals_one_shot():
     N, P = 32, 4
     x = RNG.integers(-128, 128, (3, 20 * N))
