@@ -118,6 +118,28 @@ qc_status qc_xcorrelate(const int8_t* x, int64_t ld_x, int32_t n_ant, int64_t n_
                         int64_t spec_per_dump, qc_prec x_prec, float* vis, int32_t accumulate,
                         int64_t* n_dumps_out, void* stream);
 
+/* qc_xcorrelate without device allocation, for callers that cannot
+ * allocate: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Arguments, layouts, accumulate, n_dumps_out and
+ * results as qc_xcorrelate with x_prec = QC_F32 (within the ordering of the
+ * float32 partial sums), restricted to the shapes with a fused F+X kernel:
+ * n_fft 512, 1024, 2048 or 4096 with 4 antennas, 1024 or 2048 with 8,
+ * 1024 or 4096 with 2 (else QC_EUNSUPPORTED; nothing is launched).
+ * Work memory is one device array of QC_NOALLOC_SCRATCH_BYTES inside the
+ * library, per GPU, held until the process ends: FFT twiddles and the
+ * built-in taps are rebuilt in it at every call, and dumps are correlated in
+ * batches whose partial sums fit it (a batch inside the stream takes its
+ * filter history from the stream).  No call allocates or frees device or
+ * host memory.  Calls that overlap on one GPU (other streams or threads)
+ * share that array and race: serialise them.  Sizes whose single dump does
+ * not fit the array are rejected with QC_EUNSUPPORTED (none of the shapes
+ * above reaches it). */
+#define QC_NOALLOC_SCRATCH_BYTES (64ll << 20)
+qc_status qc_xcorrelate_noalloc(const int8_t* x, int64_t ld_x, int32_t n_ant, int64_t n_samp,
+                                const qc_pfb_params* p, const int8_t* hist, int8_t* hist_out,
+                                int64_t spec_per_dump, float* vis, int32_t accumulate,
+                                int64_t* n_dumps_out, void* stream);
+
 /* X-engine alone from channelised voltages as written by qc_pfb_channelize
  * (Sec. 4.1 eq. 1; Sec. 4.2 X-engine and integration).
  *   v      : device [n_ant][n_spec][n_chan] (re, im) pairs of type prec.

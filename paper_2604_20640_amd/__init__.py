@@ -14,7 +14,7 @@ import os
 import torch
 
 __all__ = [
-    "QCError", "lib", "pfb_channelize", "xcorrelate", "xcorrelate_chan", "mad_flag",
+    "QCError", "lib", "pfb_channelize", "xcorrelate", "xcorrelate_noalloc", "xcorrelate_chan", "mad_flag",
     "apply_delay_phase", "n_base", "PREC", "timing_enable", "timing_read", "KERNELS", "Stream",
     "solve_delay_phase", "Plan", "cnn_param_count", "cnn_normalize", "cnn_forward", "cnn_grad", "cnn_adam",
     "cnn_train_step", "cnn_flag", "channelize_variant", "cnn_variant", "measure_peak",
@@ -52,6 +52,8 @@ _SIGS = {
     "qc_pfb_channelize": [_P, _I64, _I32, _I64, ctypes.POINTER(PfbParams), _P, _P, _I32, _P, _P, _P],
     "qc_xcorrelate": [_P, _I64, _I32, _I64, ctypes.POINTER(PfbParams), _P, _P, _I64, _I32, _P, _I32,
                       ctypes.POINTER(_I64), _P],
+    "qc_xcorrelate_noalloc": [_P, _I64, _I32, _I64, ctypes.POINTER(PfbParams), _P, _P, _I64, _P, _I32,
+                              ctypes.POINTER(_I64), _P],
     "qc_xcorrelate_chan": [_P, _I32, _P, _I32, _I64, _I32, _I64, _P, _I32, _P],
     "qc_mad_flag": [_P, _I64, _I64, _I32, ctypes.c_float, _I32, _P, _P, _P],
     "qc_apply_delay_phase": [_P, _I64, _I32, _I32, ctypes.c_double, ctypes.c_double,
@@ -543,6 +545,25 @@ def xcorrelate(x, n_fft, n_taps, spec_per_dump, taps=None, hist=None, hist_out=N
                              _ptr(hist_out), spec_per_dump, PREC[x_prec], _ptr(vis),
                              1 if accumulate else 0, ctypes.byref(nd), _stream())
     _check(st, "qc_xcorrelate")
+    assert nd.value == n_dump
+    return vis
+
+
+def xcorrelate_noalloc(x, n_fft, n_taps, spec_per_dump, vis, taps=None, hist=None, hist_out=None,
+                       accumulate=False):
+    """qc_xcorrelate_noalloc: the fused float32 F+X into a caller-supplied
+    vis [n_dump, n_base, n_chan] (complex64); the library allocates nothing."""
+    _check_x(x)
+    n_ant, n_samp = x.shape
+    n_dump = (n_samp // n_fft) // spec_per_dump
+    assert vis.dtype == torch.complex64 and vis.is_contiguous()
+    assert tuple(vis.shape) == (n_dump, n_base(n_ant), n_fft // 2)
+    p = _pfb(n_fft, n_taps, taps)
+    nd = _I64(0)
+    st = lib().qc_xcorrelate_noalloc(_ptr(x), x.stride(0), n_ant, n_samp, ctypes.byref(p), _ptr(hist),
+                                     _ptr(hist_out), spec_per_dump, _ptr(vis), 1 if accumulate else 0,
+                                     ctypes.byref(nd), _stream())
+    _check(st, "qc_xcorrelate_noalloc")
     assert nd.value == n_dump
     return vis
 

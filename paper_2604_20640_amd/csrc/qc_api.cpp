@@ -18,6 +18,7 @@
 #include <tuple>
 #include <vector>
 
+#include "qc_internal.h"
 #include "qc_kernels.h"
 
 #include <new>
@@ -312,6 +313,27 @@ qc_status channelize_impl(const Resolved& r, qc_prec out_prec, void* out, float*
 }
 
 }  // namespace
+
+namespace qc {
+
+void api_clear_error() { g_err.clear(); }
+
+qc_status api_fail(qc_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+qc_status api_check_stream_args(const int8_t* x, int64_t ld_x, int32_t n_ant, int64_t n_samp,
+                                const qc_pfb_params* p, const int8_t* hist, const int8_t* hist_out) {
+  return check_stream_args(x, ld_x, n_ant, n_samp, p, hist, hist_out);
+}
+
+}  // namespace qc
 
 extern "C" {
 
