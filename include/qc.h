@@ -118,6 +118,55 @@ qc_status qc_xcorrelate(const int8_t* x, int64_t ld_x, int32_t n_ant, int64_t n_
                         int64_t spec_per_dump, qc_prec x_prec, float* vis, int32_t accumulate,
                         int64_t* n_dumps_out, void* stream);
 
+/* Input words of the acquisition chain (Sec. 3.3 quantisation modes; Sec.
+ * 4.2: raw samples are unpacked into complex voltage streams).
+ *   QC_SAMPLE_I8  : real int8 (the 8-bit truncated mode).
+ *   QC_SAMPLE_I16 : real int16 (the default 16-bit padded mode: the 14-bit
+ *                   ADC value stored in 16 bits, used as the integer it is).
+ *   QC_SAMPLE_CI8 : complex int8, I and Q interleaved (2 bytes per sample).
+ *   QC_SAMPLE_CI16: complex int16, I and Q interleaved (4 bytes per sample).
+ * Real words give n_chan = N/2 channels k = 0..N/2-1; complex words an
+ * N-point complex DFT with all n_chan = N channels k = 0..N-1 in natural
+ * order (k >= N/2 are the negative frequencies).  The same real prototype
+ * filters I and Q. */
+typedef enum { QC_SAMPLE_I8 = 0, QC_SAMPLE_I16 = 1, QC_SAMPLE_CI8 = 2, QC_SAMPLE_CI16 = 3 } qc_sample;
+
+/* F-engine of any input word (Sec. 4.2 "F-engine"; Sec. 3.3).  As
+ * qc_pfb_channelize, except:
+ *   x, hist, hist_out: device buffers of the word `sample`; ld_x and n_samp
+ *     count samples (an I/Q pair is one sample); x and hist aligned to 4
+ *     samples; hist / hist_out hold (P-1)*N samples per antenna.
+ *   out: [n_ant][n_spec][n_chan] with n_chan as above.  Scales for reduced
+ *     precision use mean |x|^2 (I^2 + Q^2 for complex words).
+ *   QC_SAMPLE_I8 gives exactly qc_pfb_channelize's result. */
+qc_status qc_pfb_channelize_ex(const void* x, int32_t sample, int64_t ld_x, int32_t n_ant, int64_t n_samp,
+                               const qc_pfb_params* p, const void* hist, void* hist_out, qc_prec out_prec,
+                               void* out, float* scale_out, void* stream);
+
+/* F+X of any input word (Sec. 4.1 eq. 1; Sec. 4.2; Sec. 3.3).  As
+ * qc_xcorrelate with the word conventions of qc_pfb_channelize_ex; vis is
+ * [n_dump][n_base][n_chan].  QC_SAMPLE_I8 calls qc_xcorrelate; other words
+ * run the F-engine of the full dumps' spectra into a stream-ordered pool
+ * buffer, then qc_xcorrelate_chan.  Reduced x_prec needs n_ant <= 32 and
+ * n_chan % 32 == 0 (else QC_EUNSUPPORTED). */
+qc_status qc_xcorrelate_ex(const void* x, int32_t sample, int64_t ld_x, int32_t n_ant, int64_t n_samp,
+                           const qc_pfb_params* p, const void* hist, void* hist_out, int64_t spec_per_dump,
+                           qc_prec x_prec, float* vis, int32_t accumulate, int64_t* n_dumps_out,
+                           void* stream);
+
+/* Prototype filters (Fig. pfb_fft compares an 8-tap Kaiser PFB, beta = 8,
+ * with a plain rectangular-window FFT).  Writes P*N float taps, designed in
+ * float64 and rounded once, to device memory `taps` (16-byte aligned) for
+ * use as qc_pfb_params.taps; synchronises `stream`.
+ *   QC_WINDOW_HANN  : the built-in Hann-windowed sinc (beta ignored).
+ *   QC_WINDOW_KAISER: w[q] = I0(beta sqrt(1 - (2q/(L-1) - 1)^2)) / I0(beta),
+ *                     h[q] = w[q] sinc((q - (L-1)/2)/N), unnormalised;
+ *                     beta in [0, 100].
+ *   QC_WINDOW_RECT  : h[q] = 1 (with P = 1, the plain FFT). */
+typedef enum { QC_WINDOW_HANN = 0, QC_WINDOW_KAISER = 1, QC_WINDOW_RECT = 2 } qc_window;
+qc_status qc_pfb_design_taps(int32_t n_fft, int32_t n_taps, int32_t window, double beta, float* taps,
+                             void* stream);
+
 /* qc_xcorrelate without device allocation, for callers that cannot
  * allocate: code under HIP graph capture, tight serving loops, harnesses
  * that forbid hipMalloc.  Arguments, layouts, accumulate, n_dumps_out and

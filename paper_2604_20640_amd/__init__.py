@@ -14,7 +14,8 @@ import os
 import torch
 
 __all__ = [
-    "QCError", "lib", "pfb_channelize", "xcorrelate", "xcorrelate_noalloc", "xcorrelate_chan", "mad_flag",
+    "QCError", "lib", "pfb_channelize", "xcorrelate", "xcorrelate_noalloc", "xcorrelate_chan",
+    "pfb_channelize_ex", "xcorrelate_ex", "design_taps", "SAMPLE", "WINDOW", "mad_flag",
     "apply_delay_phase", "n_base", "PREC", "timing_enable", "timing_read", "KERNELS", "Stream",
     "solve_delay_phase", "Plan", "cnn_param_count", "cnn_normalize", "cnn_forward", "cnn_grad", "cnn_adam",
     "cnn_train_step", "cnn_flag", "channelize_variant", "cnn_variant", "measure_peak",
@@ -24,6 +25,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libqc.so")
 
 PREC = {"f32": 0, "f16": 1, "bf16": 2, "fp8": 3}
+SAMPLE = {"i8": 0, "i16": 1, "ci8": 2, "ci16": 3}
+WINDOW = {"hann": 0, "kaiser": 1, "rect": 2}
 _PAIR_BYTES = {0: 8, 1: 4, 2: 4, 3: 2}
 
 
@@ -55,6 +58,11 @@ _SIGS = {
     "qc_xcorrelate_noalloc": [_P, _I64, _I32, _I64, ctypes.POINTER(PfbParams), _P, _P, _I64, _P, _I32,
                               ctypes.POINTER(_I64), _P],
     "qc_xcorrelate_chan": [_P, _I32, _P, _I32, _I64, _I32, _I64, _P, _I32, _P],
+    "qc_pfb_channelize_ex": [_P, _I32, _I64, _I32, _I64, ctypes.POINTER(PfbParams), _P, _P, _I32, _P, _P,
+                             _P],
+    "qc_xcorrelate_ex": [_P, _I32, _I64, _I32, _I64, ctypes.POINTER(PfbParams), _P, _P, _I64, _I32, _P,
+                         _I32, ctypes.POINTER(_I64), _P],
+    "qc_pfb_design_taps": [_I32, _I32, _I32, ctypes.c_double, _P, _P],
     "qc_mad_flag": [_P, _I64, _I64, _I32, ctypes.c_float, _I32, _P, _P, _P],
     "qc_apply_delay_phase": [_P, _I64, _I32, _I32, ctypes.c_double, ctypes.c_double,
                              ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), _P],
@@ -506,6 +514,67 @@ def _pfb(n_fft, n_taps, taps):
 def _check_x(x):
     assert x.dtype == torch.int8 and x.is_cuda and x.dim() == 2 and x.stride(1) == 1, \
         "x must be a CUDA int8 [n_ant, n_samp] tensor with unit sample stride"
+
+
+def _sample_word(x):
+    """Input word of x: int8 / int16 [n_ant, n_samp] real, or int8 / int16
+    [n_ant, n_samp, 2] complex (I, Q interleaved); returns (code, n_ant, n_samp, ld_x)."""
+    assert x.is_cuda and x.dtype in (torch.int8, torch.int16), "x must be a CUDA int8 or int16 tensor"
+    if x.dim() == 2:
+        assert x.stride(1) == 1, "unit sample stride"
+        return (0 if x.dtype == torch.int8 else 1), x.shape[0], x.shape[1], x.stride(0)
+    assert x.dim() == 3 and x.shape[2] == 2 and x.stride(2) == 1 and x.stride(1) == 2, \
+        "complex samples: [n_ant, n_samp, 2] with I, Q adjacent"
+    assert x.stride(0) % 2 == 0
+    return (2 if x.dtype == torch.int8 else 3), x.shape[0], x.shape[1], x.stride(0) // 2
+
+
+def pfb_channelize_ex(x, n_fft, n_taps, taps=None, hist=None, hist_out=None, out_prec="f32",
+                      out=None, scale_out=None):
+    """F-engine of any input word (see _sample_word): (out, scale); out is
+    complex64 [n_ant, n_spec, n_chan] for f32 (n_chan = N/2 real, N complex),
+    else uint8 pairs of the format."""
+    code, n_ant, n_samp, ld = _sample_word(x)
+    prec = PREC[out_prec]
+    n_spec = n_samp // n_fft
+    n_chan = n_fft if code >= 2 else n_fft // 2
+    if out is None:
+        if prec == 0:
+            out = torch.empty((n_ant, n_spec, n_chan), dtype=torch.complex64, device=x.device)
+        else:
+            out = torch.empty((n_ant, n_spec, n_chan * _PAIR_BYTES[prec]), dtype=torch.uint8, device=x.device)
+    if prec != 0 and scale_out is None:
+        scale_out = torch.empty(n_ant, dtype=torch.float32, device=x.device)
+    p = _pfb(n_fft, n_taps, taps)
+    _check(lib().qc_pfb_channelize_ex(_ptr(x), code, ld, n_ant, n_samp, ctypes.byref(p), _ptr(hist),
+                                      _ptr(hist_out), prec, _ptr(out), _ptr(scale_out), _stream()),
+           "qc_pfb_channelize_ex")
+    return out, scale_out
+
+
+def xcorrelate_ex(x, n_fft, n_taps, spec_per_dump, taps=None, hist=None, hist_out=None, vis=None,
+                  accumulate=False, x_prec="f32"):
+    """F+X of any input word: complex64 [n_dump, n_base, n_chan]."""
+    code, n_ant, n_samp, ld = _sample_word(x)
+    n_chan = n_fft if code >= 2 else n_fft // 2
+    n_dump = (n_samp // n_fft) // spec_per_dump
+    if vis is None:
+        vis = torch.empty((n_dump, n_base(n_ant), n_chan), dtype=torch.complex64, device=x.device)
+    p = _pfb(n_fft, n_taps, taps)
+    nd = _I64(0)
+    _check(lib().qc_xcorrelate_ex(_ptr(x), code, ld, n_ant, n_samp, ctypes.byref(p), _ptr(hist),
+                                  _ptr(hist_out), spec_per_dump, PREC[x_prec], _ptr(vis),
+                                  1 if accumulate else 0, ctypes.byref(nd), _stream()), "qc_xcorrelate_ex")
+    assert nd.value == n_dump
+    return vis
+
+
+def design_taps(n_fft, n_taps, window="hann", beta=0.0, device="cuda"):
+    """Prototype filter taps (float32 [P*N] on the device) from the library."""
+    taps = torch.empty(n_fft * n_taps, dtype=torch.float32, device=device)
+    _check(lib().qc_pfb_design_taps(n_fft, n_taps, WINDOW[window], float(beta), _ptr(taps), _stream()),
+           "qc_pfb_design_taps")
+    return taps
 
 
 def pfb_channelize(x, n_fft, n_taps, taps=None, hist=None, hist_out=None, out_prec="f32",

@@ -65,6 +65,47 @@ std::vector<double> hann_sinc(int N, int P) {
   return h;
 }
 
+// Modified Bessel function of the first kind, order 0, by its power series
+// sum_k ((x/2)^k / k!)^2 (all terms positive; stops once a term no longer
+// changes the float64 sum).
+double bessel_i0(double x) {
+  const double q = 0.25 * x * x;
+  double term = 1.0, sum = 1.0;
+  for (int k = 1; k < 500; ++k) {
+    term *= q / ((double)k * (double)k);
+    const double next = sum + term;
+    if (next == sum) break;
+    sum = next;
+  }
+  return sum;
+}
+
+// Prototype filters for qc_pfb_design_taps, float64: window 0 Hann-sinc
+// (the built-in prototype), 1 Kaiser(beta)-sinc, 2 all ones (no filter).
+std::vector<double> design_taps(int N, int P, int window, double beta) {
+  if (window == 0) return hann_sinc(N, P);
+  const int L = N * P;
+  std::vector<double> h(L, 1.0);
+  if (window == 2) return h;
+  const double pi = 3.14159265358979323846;
+  const double i0b = bessel_i0(beta);
+  for (int q = 0; q < L; ++q) {
+    double w = 1.0;
+    if (L > 1) {
+      const double r = 2.0 * q / (L - 1) - 1.0;
+      const double t = 1.0 - r * r;
+      w = bessel_i0(beta * std::sqrt(t > 0.0 ? t : 0.0)) / i0b;
+    }
+    const double u = (q - (L - 1) / 2.0) / N;
+    const double sn = (u == 0.0) ? 1.0 : std::sin(pi * u) / (pi * u);
+    h[q] = w * sn;
+  }
+  return h;
+}
+
+int sample_bytes(int sample) { return sample == 0 ? 1 : sample == 3 ? 4 : 2; }
+bool sample_complex(int sample) { return sample >= 2; }
+
 struct TapsEntry {
   float* dev = nullptr;
   double sum_h2 = 0.0;
@@ -312,6 +353,70 @@ qc_status channelize_impl(const Resolved& r, qc_prec out_prec, void* out, float*
   return QC_OK;
 }
 
+qc_status check_any_args(const void* x, int32_t sample, int64_t ld_x, int32_t n_ant, int64_t n_samp,
+                         const qc_pfb_params* p, const void* hist, const void* hist_out) {
+  qc_status st = check_pfb(p);
+  if (st != QC_OK) return st;
+  if (sample < QC_SAMPLE_I8 || sample > QC_SAMPLE_CI16) return fail(QC_EINVAL, "bad sample word %d", sample);
+  if (n_ant < 1 || n_ant > 4096) return fail(QC_EINVAL, "n_ant must be in [1, 4096] (got %d)", n_ant);
+  if (n_samp < 0 || n_samp % p->n_fft)
+    return fail(QC_EINVAL, "n_samp (%lld) must be a non-negative multiple of n_fft (%d)",
+                (long long)n_samp, p->n_fft);
+  if (n_samp > 0x7fffffffLL) return fail(QC_EINVAL, "n_samp must be below 2^31 per antenna");
+  if (n_samp > 0 && !x) return fail(QC_EINVAL, "x is NULL");
+  if (ld_x < n_samp || (ld_x & 3)) return fail(QC_EINVAL, "ld_x must be >= n_samp and a multiple of 4");
+  const uintptr_t al = 4u * (uintptr_t)sample_bytes(sample) - 1u;
+  if (reinterpret_cast<uintptr_t>(x) & al)
+    return fail(QC_EINVAL, "x must be aligned to 4 samples (%d bytes)", (int)(al + 1));
+  if (hist && (reinterpret_cast<uintptr_t>(hist) & al))
+    return fail(QC_EINVAL, "hist must be aligned to 4 samples (%d bytes)", (int)(al + 1));
+  if (hist && hist == hist_out) return fail(QC_EINVAL, "hist_out may not alias hist");
+  return QC_OK;
+}
+
+// The F-engine of any word into `out` (n_samp samples, caller-validated).
+qc_status channelize_any_impl(const void* x, int32_t sample, int64_t ld_x, int32_t n_ant, int64_t n_samp,
+                              const qc_pfb_params* p, const void* hist, qc_prec out_prec, void* out,
+                              float* scale_out, hipStream_t s) {
+  Resolved r;
+  qc_status st = resolve(nullptr, ld_x, n_ant, n_samp, p, nullptr, &r);
+  if (st != QC_OK) return st;
+  const qc::ChanxArgs a{x, ld_x, n_ant, n_samp, p->n_fft, p->n_taps, r.args.taps, r.args.tw, hist};
+  if (out_prec != QC_F32) {
+    double s2 = r.sum_h2;
+    if (p->taps != nullptr) {
+      st = user_sum_h2(p->taps, p->n_fft * p->n_taps, &s2);
+      if (st != QC_OK) return st;
+    }
+    const int64_t n_use = n_samp < (1 << 20) ? n_samp : (1 << 20);
+    if (n_use > 0) {
+      AsyncBuf sp;
+      st = alloc_async(sp, (size_t)n_ant * qc::SC_BLOCKS * sizeof(unsigned long long), s);
+      if (st != QC_OK) return st;
+      QC_HIP(qc::launch_scales_any(x, sample, ld_x, n_ant, n_use, s2, prec_target(out_prec),
+                                   (unsigned long long*)sp.p, scale_out, s),
+             "scales kernel");
+    }
+  }
+  if (n_samp > 0) {
+    KTimer t(QC_KERNEL_CHANNELIZE, s);
+    QC_HIP(qc::launch_channelize_any(a, sample, (int)out_prec, out, scale_out, s), "channelize kernel");
+  }
+  return QC_OK;
+}
+
+qc_status hist_copy_any(const void* x, int32_t sample, int64_t ld_x, int32_t n_ant, int64_t n_samp,
+                        const qc_pfb_params* p, const void* hist, void* hist_out, hipStream_t s) {
+  if (!hist_out || p->n_taps <= 1) return QC_OK;
+  const int b = sample_bytes(sample);
+  const int64_t keep = (int64_t)(p->n_taps - 1) * p->n_fft;
+  // byte-wise copy of the last keep samples of (hist ++ x)
+  QC_HIP(qc::launch_hist_copy(static_cast<const int8_t*>(x), ld_x * b, n_ant, n_samp * b,
+                              static_cast<const int8_t*>(hist), keep * b, static_cast<int8_t*>(hist_out), s),
+         "history copy");
+  return QC_OK;
+}
+
 }  // namespace
 
 namespace qc {
@@ -435,6 +540,82 @@ qc_status qc_xcorrelate(const int8_t* x, int64_t ld_x, int32_t n_ant, int64_t n_
     QC_HIP(qc::launch_hist_copy(x, ld_x, n_ant, n_samp, hist, (int64_t)(p->n_taps - 1) * N, hist_out, s),
            "history copy");
   return QC_OK;
+}
+
+qc_status qc_pfb_design_taps(int32_t n_fft, int32_t n_taps, int32_t window, double beta, float* taps,
+                             void* stream) {
+  g_err.clear();
+  if (!is_pow2(n_fft) || n_fft < 4 || n_fft > 8192)
+    return fail(QC_EINVAL, "n_fft must be a power of two in [4, 8192] (got %d)", n_fft);
+  if (n_taps < 1 || n_taps > 16) return fail(QC_EINVAL, "n_taps must be in [1, 16] (got %d)", n_taps);
+  if (window < QC_WINDOW_HANN || window > QC_WINDOW_RECT) return fail(QC_EINVAL, "bad window %d", window);
+  if (window == QC_WINDOW_KAISER && !(beta >= 0.0 && beta <= 100.0))
+    return fail(QC_EINVAL, "Kaiser beta must be in [0, 100]");
+  if (!taps) return fail(QC_EINVAL, "taps is NULL");
+  if (reinterpret_cast<uintptr_t>(taps) & 15u) return fail(QC_EINVAL, "taps must be 16-byte aligned");
+  const std::vector<double> h = design_taps(n_fft, n_taps, window, beta);
+  std::vector<float> hf(h.begin(), h.end());
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  QC_HIP(hipMemcpyAsync(taps, hf.data(), hf.size() * sizeof(float), hipMemcpyHostToDevice, s),
+         "hipMemcpyAsync(taps)");
+  QC_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+  return QC_OK;
+}
+
+qc_status qc_pfb_channelize_ex(const void* x, int32_t sample, int64_t ld_x, int32_t n_ant, int64_t n_samp,
+                               const qc_pfb_params* p, const void* hist, void* hist_out, qc_prec out_prec,
+                               void* out, float* scale_out, void* stream) {
+  g_err.clear();
+  qc_status st = check_any_args(x, sample, ld_x, n_ant, n_samp, p, hist, hist_out);
+  if (st != QC_OK) return st;
+  if (out_prec < QC_F32 || out_prec > QC_FP8_E4M3) return fail(QC_EINVAL, "bad out_prec %d", (int)out_prec);
+  if (n_samp > 0 && !out) return fail(QC_EINVAL, "out is NULL");
+  if (out_prec != QC_F32 && !scale_out) return fail(QC_EINVAL, "scale_out is NULL for reduced precision");
+  if (reinterpret_cast<uintptr_t>(out) % prec_pair_bytes(out_prec))
+    return fail(QC_EINVAL, "out is misaligned for its precision");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  st = channelize_any_impl(x, sample, ld_x, n_ant, n_samp, p, hist, out_prec, out, scale_out, s);
+  if (st != QC_OK) return st;
+  return hist_copy_any(x, sample, ld_x, n_ant, n_samp, p, hist, hist_out, s);
+}
+
+qc_status qc_xcorrelate_ex(const void* x, int32_t sample, int64_t ld_x, int32_t n_ant, int64_t n_samp,
+                           const qc_pfb_params* p, const void* hist, void* hist_out, int64_t spec_per_dump,
+                           qc_prec x_prec, float* vis, int32_t accumulate, int64_t* n_dumps_out,
+                           void* stream) {
+  g_err.clear();
+  qc_status st = check_any_args(x, sample, ld_x, n_ant, n_samp, p, hist, hist_out);
+  if (st != QC_OK) return st;
+  if (sample == QC_SAMPLE_I8)
+    return qc_xcorrelate(static_cast<const int8_t*>(x), ld_x, n_ant, n_samp, p,
+                         static_cast<const int8_t*>(hist), static_cast<int8_t*>(hist_out), spec_per_dump,
+                         x_prec, vis, accumulate, n_dumps_out, stream);
+  if (spec_per_dump < 1) return fail(QC_EINVAL, "spec_per_dump must be >= 1");
+  if (x_prec < QC_F32 || x_prec > QC_FP8_E4M3) return fail(QC_EINVAL, "bad x_prec %d", (int)x_prec);
+  const int N = p->n_fft;
+  const int n_chan = sample_complex(sample) ? N : N / 2;
+  const int64_t n_dump = (n_samp / N) / spec_per_dump;
+  if (n_dump > 0 && !vis) return fail(QC_EINVAL, "vis is NULL");
+  if (reinterpret_cast<uintptr_t>(vis) & 7u) return fail(QC_EINVAL, "vis must be 8-byte aligned");
+  if (x_prec != QC_F32 && (n_ant > 32 || n_chan % 32))
+    return fail(QC_EUNSUPPORTED, "matrix-core X-engine needs n_ant <= 32 and n_chan %% 32 == 0");
+  if (n_dumps_out) *n_dumps_out = n_dump;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (n_dump > 0) {
+    // two passes: the F-engine of the full dumps' spectra to HBM, then the X-engine
+    const int64_t ns = n_dump * spec_per_dump;
+    AsyncBuf v, scale;
+    st = alloc_async(v, (size_t)n_ant * ns * n_chan * prec_pair_bytes(x_prec), s);
+    if (st != QC_OK) return st;
+    st = alloc_async(scale, (size_t)n_ant * sizeof(float), s);
+    if (st != QC_OK) return st;
+    st = channelize_any_impl(x, sample, ld_x, n_ant, ns * N, p, hist, x_prec, v.p, (float*)scale.p, s);
+    if (st != QC_OK) return st;
+    st = qc_xcorrelate_chan(v.p, x_prec, (const float*)scale.p, n_ant, ns, n_chan, spec_per_dump, vis,
+                            accumulate, stream);
+    if (st != QC_OK) return st;
+  }
+  return hist_copy_any(x, sample, ld_x, n_ant, n_samp, p, hist, hist_out, s);
 }
 
 qc_status qc_xcorrelate_chan(const void* v, qc_prec prec, const float* scale, int32_t n_ant,

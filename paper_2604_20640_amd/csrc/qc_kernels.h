@@ -43,6 +43,28 @@ int get_channelize_variant();
 hipError_t launch_channelize(const FxArgs& a, int prec, void* out, const float* scale,
                              hipStream_t s);
 
+// F-engine over any input word (sample: 0 real int8, 1 real int16, 2 complex
+// int8, 3 complex int16; I and Q interleaved).  ld_x and n_samp count
+// samples; hist holds (P-1)N samples per antenna of the same word.  Output
+// [n_ant][n_spec][n_chan] with n_chan = N/2 (real words) or N (complex).
+struct ChanxArgs {
+  const void* x;
+  int64_t ld_x;
+  int32_t n_ant;
+  int64_t n_samp;
+  int32_t n_fft;
+  int32_t n_taps;
+  const float* taps;  // device [P*N]
+  const float2* tw;   // device [N], exp(-2 pi i e/N)
+  const void* hist;   // device [n_ant][(P-1)N] samples or null
+};
+hipError_t launch_channelize_any(const ChanxArgs& a, int sample, int prec, void* out, const float* scale,
+                                 hipStream_t s);
+// Scales as launch_scales, from |x|^2 of any input word.
+hipError_t launch_scales_any(const void* x, int sample, int64_t ld_x, int n_ant, int64_t n_use,
+                             double sum_h2, double target, unsigned long long* part, float* scale_out,
+                             hipStream_t s);
+
 // Per-antenna power-of-two scales for requantised output from the first
 // n_use samples; part holds n_ant * SC_BLOCKS partial sums (scratch).
 constexpr int SC_BLOCKS = 64;

@@ -50,6 +50,10 @@ class StreamSpec:
     # linear chirps [(start_sample, length, f0, f1, amp, phase)]: frequency
     # f0 -> f1 (cycles per sample) over the length, common to all antennas
     chirps: list = field(default_factory=list)
+    # sample word: 8 -> int8 in [-128, 127]; 14 or 16 -> int16 clipped to
+    # [-2^(bits-1), 2^(bits-1) - 1] (14 bits: the ADC range of the 16-bit
+    # padded mode)
+    bits: int = 8
 
 
 def _common_component(spec: StreamSpec, lo: int, hi: int, max_lag: int) -> np.ndarray:
@@ -115,17 +119,19 @@ def _fill_chunk(spec: StreamSpec, x: np.ndarray, lo: int, lags, max_lag, periodi
             v += k_corr * cpre[max_lag - d:max_lag - d + L]
         v += common
         np.rint(v, out=v)
-        np.clip(v, -128, 127, out=v)
-        x[a_, lo:hi] = v.astype(np.int8)
+        top = float(2 ** (spec.bits - 1))
+        np.clip(v, -top, top - 1, out=v)
+        x[a_, lo:hi] = v.astype(x.dtype)
 
 
 def generate(spec: StreamSpec, out: np.ndarray | None = None, threads: int | None = None) -> np.ndarray:
-    """int8 [n_ant, n_samp] stream for ``spec`` (deterministic in spec.seed)."""
+    """int8 (or int16 for bits > 8) [n_ant, n_samp] stream for ``spec``
+    (deterministic in spec.seed)."""
     n_ant, S = spec.n_ant, spec.n_samp
     lags = tuple(spec.lags) if spec.lags else (0,) * n_ant
     assert len(lags) == n_ant
     max_lag = max(lags) if lags else 0
-    x = np.empty((n_ant, S), np.int8) if out is None else out
+    x = np.empty((n_ant, S), np.int8 if spec.bits <= 8 else np.int16) if out is None else out
     periodic = _periodic_component(spec)
     starts = list(range(0, S, CHUNK))
     if threads is None:
@@ -137,6 +143,24 @@ def generate(spec: StreamSpec, out: np.ndarray | None = None, threads: int | Non
         with cf.ThreadPoolExecutor(threads) as ex:
             list(ex.map(lambda lo: _fill_chunk(spec, x, lo, lags, max_lag, periodic), starts))
     return x
+
+
+def generate_iq(spec: StreamSpec, threads: int | None = None) -> np.ndarray:
+    """Complex I/Q stream [n_ant, n_samp, 2] (I, Q interleaved; int8 or int16).
+
+    I is generate(spec); Q is an independent stream of the same shape with
+    seed + 1 (its own noise and its own common component, so the common
+    component is complex Gaussian with the same lags), and the tone and
+    lines phase-shifted by -pi/2, so a tone becomes exp(+2 pi i f n).
+    """
+    import dataclasses
+    q_lines = [(f, a, ph - math.pi / 2) for (f, a, ph) in spec.lines]
+    if spec.tone_amp:
+        q_lines.append((spec.tone_cycles_per_sample, spec.tone_amp, -math.pi / 2))
+    qspec = dataclasses.replace(spec, seed=spec.seed + 1, tone_amp=0.0, lines=q_lines)
+    xi = generate(spec, threads=threads)
+    xq = generate(qspec, threads=threads)
+    return np.stack([xi, xq], axis=-1)
 
 
 # ---- the workloads (seed = 1000 * config number + realisation) -------------
