@@ -192,6 +192,45 @@ qc_status get_twiddles(int N, float2** out) {
   return QC_OK;
 }
 
+std::map<std::pair<int, int>, float2*> g_twp;  // (device, N): per-pass radix-16 twiddles
+
+// Per-pass twiddles of the radix-16 Stockham FFT (radix 16 while it divides
+// what is left, then the remainder): the pass of stride NS and radix R holds
+// W_{NS R}^{jm r} = exp(-2 pi i jm r / (NS R)) at (NS-1) + (r-1) NS + jm,
+// r = 1..R-1, jm = 0..NS-1; N-1 entries over all passes.  The angle comes
+// from the exact integers, in float64, rounded once to float32.
+qc_status get_pass_twiddles(int N, float2** out) {
+  int dev = 0;
+  QC_HIP(hipGetDevice(&dev), "hipGetDevice");
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto key = std::make_pair(dev, N);
+  auto it = g_twp.find(key);
+  if (it != g_twp.end()) {
+    *out = it->second;
+    return QC_OK;
+  }
+  std::vector<float2> t(N > 1 ? N - 1 : 1, make_float2(0.f, 0.f));
+  const double pi = 3.14159265358979323846;
+  int ns = 1, off = 0;
+  while (N / ns > 1) {
+    const int R = (N / ns) >= 16 ? 16 : N / ns;
+    for (int r = 1; r < R; ++r)
+      for (int jm = 0; jm < ns; ++jm) {
+        const long long e = (long long)jm * r;  // exponent of W_{ns R}
+        const double a = -2.0 * pi * (double)(e % (ns * R)) / (double)(ns * R);
+        t[off + (r - 1) * ns + jm] = make_float2((float)std::cos(a), (float)std::sin(a));
+      }
+    off += (R - 1) * ns;
+    ns *= R;
+  }
+  float2* d = nullptr;
+  QC_HIP(hipMalloc(&d, t.size() * sizeof(float2)), "hipMalloc(pass twiddles)");
+  QC_HIP(hipMemcpy(d, t.data(), t.size() * sizeof(float2), hipMemcpyHostToDevice), "hipMemcpy(pass twiddles)");
+  g_twp[key] = d;
+  *out = d;
+  return QC_OK;
+}
+
 qc_status check_pfb(const qc_pfb_params* p) {
   if (!p) return fail(QC_EINVAL, "pfb params is NULL");
   if (!is_pow2(p->n_fft) || p->n_fft < 4 || p->n_fft > 8192)
@@ -240,7 +279,10 @@ qc_status resolve(const int8_t* x, int64_t ld_x, int32_t n_ant, int64_t n_samp,
     taps = e.dev;
     s2 = e.sum_h2;
   }
-  r->args = qc::FxArgs{x, ld_x, n_ant, n_samp, p->n_fft, p->n_taps, taps, tw, hist, p->taps == nullptr};
+  float2* twp = nullptr;
+  st = get_pass_twiddles(p->n_fft, &twp);
+  if (st != QC_OK) return st;
+  r->args = qc::FxArgs{x, ld_x, n_ant, n_samp, p->n_fft, p->n_taps, taps, tw, hist, p->taps == nullptr, twp};
   r->sum_h2 = s2;
   return QC_OK;
 }

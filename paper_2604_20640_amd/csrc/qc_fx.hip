@@ -422,6 +422,237 @@ fx_fused_ring_kernel(const int8_t* __restrict__ x, int64_t ld_x, const int8_t* _
   }
 }
 
+// Ping-pong ring variant.  Same sums as the ring variant; the transform
+// passes alternate between two LDS buffers, so each pass ends with one
+// barrier instead of two: four per spectrum (after the FIR and after each of
+// the three passes; the next spectrum's FIR writes the buffer the last pass
+// read, and its first pass writes the buffer the X step read, each behind a
+// barrier).  Beside the two buffers, LDS holds the per-pass twiddle table up
+// to the last pass's r = 8 (a prefix of the per-pass layout); the last
+// pass forms W^{jm (8+q)} = W^{jm q} W^{8 jm} for q = 1..7 (seven complex
+// products per spectrum, which keeps the whole working set within 160 KiB).
+// The taps of a thread's chunk positions are read from global memory into
+// registers once (any P = 4 prototype).
+template <int N, int V>
+struct PpTw {
+  static constexpr int PASSES = fft_pass_count(N, V);
+  static constexpr int last_ns() {
+    int ns = 1;
+    while (N / ns > fft_radix(N / ns, V)) ns *= fft_radix(N / ns, V);
+    return ns;
+  }
+  static constexpr int NSL = last_ns();
+  static constexpr int RLAST = N / NSL;
+  static_assert(RLAST == 16, "the last pass has radix 16");
+  // per-pass entries before the last pass, then the last pass's r = 1..8
+  static constexpr int EARLY = (N - 1) - (RLAST - 1) * NSL;
+  static constexpr int LDS_TW = EARLY + 8 * NSL;
+};
+
+// Last pass (stride NS, radix 16, one butterfly per thread) with the
+// twiddles of r = 1..8 from the LDS table and r = 9..15 from products.
+template <int N, int NS, int NT>
+__device__ __forceinline__ void stockham_last_pass_half(const float2* src, float2* dst, const float2* twl,
+                                                        int tid) {
+  constexpr int R = 16;
+  constexpr int NB = N / R;
+  const int f = tid / NB, j = tid % NB;
+  const int jm = j % NS;
+  float2 v[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) v[r] = src[lds_pad(f * N + j + r * NB)];
+  float2 w[R];
+#pragma unroll
+  for (int r = 1; r <= 8; ++r) w[r] = twl[(NS - 1) + (r - 1) * NS + jm];
+#pragma unroll
+  for (int q = 1; q < 8; ++q) w[8 + q] = cmul(w[q], w[8]);
+#pragma unroll
+  for (int r = 1; r < R; ++r) v[r] = cmul(v[r], w[r]);
+  dft_r<R>(v);
+  const int k = (j / NS) * NS * R + jm;
+#pragma unroll
+  for (int r = 0; r < R; ++r) dst[lds_pad(f * N + k + r * NS)] = v[r];
+  __syncthreads();
+}
+
+template <int N, int NS, int NT, int V, int PASS>
+__device__ __forceinline__ void fft_pp_passes(float2* b0, float2* b1, const float2* twl, int tid) {
+  constexpr int REM = N / NS;
+  if constexpr (REM > 1) {
+    constexpr int R = fft_radix(REM, V);
+    float2* src = (PASS % 2 == 0) ? b0 : b1;
+    float2* dst = (PASS % 2 == 0) ? b1 : b0;
+    if constexpr (NS * R == N)
+      stockham_last_pass_half<N, NS, NT>(src, dst, twl, tid);
+    else
+      stockham_pass<N, R, NS, NT, V, false, false, true>(src, dst, twl, tid);
+    fft_pp_passes<N, NS * R, NT, V, PASS + 1>(b0, b1, twl, tid);
+  }
+}
+
+template <int N, int NA, int V, int P>
+struct RingPpCfg {
+  using C = FusedCfg<N, NA, 1, V, false, 0>;
+  static constexpr int BUF = C::BUF;  // padded buffer
+  static constexpr size_t LDS_BYTES = sizeof(float2) * (2 * (size_t)BUF + PpTw<N, V>::LDS_TW);
+};
+
+template <int N, int NA, int V, int P>
+__global__ void __launch_bounds__((FusedCfg<N, NA, 1, V, false, 0>::NT))
+fx_fused_ring_pp_kernel(const int8_t* __restrict__ x, int64_t ld_x, const int8_t* __restrict__ hist,
+                        const float* __restrict__ taps, const float2* __restrict__ twp,
+                        int64_t spec_per_dump, int64_t cpd, float2* __restrict__ part) {
+  using C = FusedCfg<N, NA, 1, V, false, 0>;
+  using RC = RingPpCfg<N, NA, V, P>;
+  static_assert(fft_pass_count(N, V) % 2 == 1, "odd pass count: the output lands in the second buffer");
+  constexpr int G = C::CHUNKS;
+  extern __shared__ float2 buf[];
+  float2* b0 = buf;
+  float2* b1 = buf + RC::BUF;
+  float2* twl = buf + 2 * RC::BUF;  // per-pass twiddles up to the last pass's r = 8
+  const int tid = threadIdx.x;
+  const int64_t w = blockIdx.x;
+  const int64_t d = w / cpd, c = w % cpd;
+  const int64_t m_lo = d * spec_per_dump + (c * spec_per_dump) / cpd;
+  const int64_t m_hi = d * spec_per_dump + ((c + 1) * spec_per_dump) / cpd;
+
+  for (int i = tid; i < PpTw<N, V>::LDS_TW; i += C::NT) twl[i] = twp[i];
+
+  constexpr int GP = G / C::NP;
+  static_assert(GP * C::NP == G && GP * C::NT * 4 == N, "ring chunk mapping");
+  int cn0[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) cn0[g] = 4 * (tid + (g % GP) * C::NT);
+  auto row = [&](int a) -> const int8_t* { return x + (int64_t)a * ld_x; };
+  auto hrow = [&](int a) -> const int8_t* {
+    return hist ? hist + (int64_t)a * (P - 1) * N : nullptr;
+  };
+  auto load_blk = [&](int g, int which, int64_t blk) -> uint32_t {
+    const int a = 2 * (g / GP) + which;
+    if (a >= NA) return 0u;
+    if (blk >= 0) return *reinterpret_cast<const uint32_t*>(row(a) + (int)blk * N + cn0[g]);
+    const int8_t* h = hrow(a);
+    if (!h) return 0u;
+    return *reinterpret_cast<const uint32_t*>(h + (int)(blk + P - 1) * N + cn0[g]);
+  };
+  uint32_t ring[P][G][2];
+#pragma unroll
+  for (int q = 0; q < P; ++q)
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int64_t blk = m_lo - P + 1 + q;
+      ring[q][g][0] = load_blk(g, 0, blk);
+      ring[q][g][1] = load_blk(g, 1, blk);
+    }
+  float4 hr[GP][P];
+#pragma unroll
+  for (int g = 0; g < GP; ++g)
+#pragma unroll
+    for (int q = 0; q < P; ++q) hr[g][q] = *reinterpret_cast<const float4*>(taps + q * N + cn0[g]);
+
+  float2 acc[C::CPT][C::NB];
+#pragma unroll
+  for (int cc = 0; cc < C::CPT; ++cc)
+#pragma unroll
+    for (int b = 0; b < C::NB; ++b) acc[cc][b] = make_float2(0.f, 0.f);
+  __syncthreads();  // twiddles in LDS
+
+  for (int64_t m = m_lo; m < m_hi; ++m) {
+    // prefetch block m+1 (consumed at the end of this iteration)
+    uint32_t nxt[G][2];
+    const bool more = m + 1 < m_hi;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      nxt[g][0] = more ? load_blk(g, 0, m + 1) : 0u;
+      nxt[g][1] = more ? load_blk(g, 1, m + 1) : 0u;
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      float y0[4] = {0.f, 0.f, 0.f, 0.f}, y1[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int q = 0; q < P; ++q) {
+        const float4 h = hr[g % GP][q];
+        const uint32_t w0 = ring[q][g][0], w1 = ring[q][g][1];
+        y0[0] += h.x * sbyte(w0, 0);
+        y0[1] += h.y * sbyte(w0, 1);
+        y0[2] += h.z * sbyte(w0, 2);
+        y0[3] += h.w * sbyte(w0, 3);
+        y1[0] += h.x * sbyte(w1, 0);
+        y1[1] += h.y * sbyte(w1, 1);
+        y1[2] += h.z * sbyte(w1, 2);
+        y1[3] += h.w * sbyte(w1, 3);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) b0[lds_pad((g / GP) * N + cn0[g] + i)] = make_float2(y0[i], y1[i]);
+    }
+    __syncthreads();
+    fft_pp_passes<N, 1, C::NT, V, 0>(b0, b1, twl, tid);
+#pragma unroll
+    for (int cc = 0; cc < C::CPT; ++cc) {
+      const int k = tid + cc * C::NT;
+      if (C::NCH % C::NT == 0 || k < C::NCH) {
+        const int kn = (N - k) & (N - 1);
+        float2 X[2 * C::NP];
+#pragma unroll
+        for (int p = 0; p < C::NP; ++p) {
+          const float2 zk = b1[lds_pad(p * N + k)];
+          const float2 zn = b1[lds_pad(p * N + kn)];
+          separate(zk, zn, X[2 * p], X[2 * p + 1]);
+        }
+        int b = 0;
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+          acc[cc][b].x += X[i].x * X[i].x + X[i].y * X[i].y;
+          ++b;
+#pragma unroll
+          for (int j = i + 1; j < NA; ++j) {
+            acc[cc][b].x += X[i].x * X[j].x + X[i].y * X[j].y;
+            acc[cc][b].y += X[i].y * X[j].x - X[i].x * X[j].y;
+            ++b;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q + 1 < P; ++q)
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        ring[q][g][0] = ring[q + 1][g][0];
+        ring[q][g][1] = ring[q + 1][g][1];
+      }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      ring[P - 1][g][0] = nxt[g][0];
+      ring[P - 1][g][1] = nxt[g][1];
+    }
+  }
+  float2* out = part + w * (int64_t)C::NB * C::NCH;
+#pragma unroll
+  for (int cc = 0; cc < C::CPT; ++cc) {
+    const int k = tid + cc * C::NT;
+    if (C::NCH % C::NT == 0 || k < C::NCH) {
+#pragma unroll
+      for (int b = 0; b < C::NB; ++b) out[(int64_t)b * C::NCH + k] = acc[cc][b];
+    }
+  }
+}
+
+template <int N, int NA, int V>
+static hipError_t launch_fused_ring_pp(const FxArgs& a, int64_t n_dump, int64_t spd, int64_t cpd,
+                                       float2* part, hipStream_t s) {
+  using RC = RingPpCfg<N, NA, V, 4>;
+  static_assert(RC::LDS_BYTES <= 160 * 1024, "ping-pong ring tile: LDS");
+  if (a.n_taps != 4) return hipErrorInvalidValue;
+  auto kern = fx_fused_ring_pp_kernel<N, NA, V, 4>;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)RC::LDS_BYTES);
+  if (e != hipSuccess) return e;
+  if (!a.twp) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(kern, dim3((unsigned)(n_dump * cpd)), dim3(RC::C::NT), RC::LDS_BYTES, s, a.x,
+                     a.ld_x, a.hist, a.taps, a.twp, spd, cpd, part);
+  return hipGetLastError();
+}
+
 template <int N, int NA, int V>
 static hipError_t launch_fused_ring(const FxArgs& a, int64_t n_dump, int64_t spd, int64_t cpd,
                                     float2* part, hipStream_t s) {
@@ -482,7 +713,7 @@ struct TileList {
     static constexpr int count = (int)(sizeof(tiles) / sizeof(tiles[0]));       \
   };
 QC_TILES(4096, 4, {0, 16, false, 0}, {1, 16, false, 0}, {1, 16, true, 0}, {2, 16, false, 0},
-         {1, 8, true, 0}, {1, 16, false, 4})
+         {1, 8, true, 0}, {1, 16, false, 4}, {0, 16, true, 0})
 QC_TILES(1024, 4, {2, 16, true, 0}, {2, 16, false, 0}, {4, 16, false, 0}, {2, 8, true, 0},
          {1, 16, true, 4}, {2, 16, false, 4}, {0, 16, false, 0})
 QC_TILES(2048, 4, {0, 16, false, 0}, {1, 16, true, 0}, {1, 16, false, 0}, {1, 16, false, 4},
@@ -491,7 +722,7 @@ QC_TILES(512, 4, {4, 16, true, 0}, {4, 16, false, 0}, {2, 16, true, 4})
 QC_TILES(1024, 8, {1, 16, true, 0}, {1, 8, true, 0})
 QC_TILES(2048, 8, {1, 8, true, 0}, {1, 8, false, 0})
 QC_TILES(1024, 2, {4, 16, true, 0}, {4, 16, false, 0}, {2, 16, true, 4})
-QC_TILES(4096, 2, {0, 16, false, 0}, {1, 16, true, 0}, {1, 16, false, 0}, {1, 16, false, 4})
+QC_TILES(4096, 2, {0, 16, false, 0}, {1, 16, true, 0}, {1, 16, false, 0}, {1, 16, false, 4}, {0, 16, true, 0})
 #undef QC_TILES
 
 template <int N, int NA, int I>
@@ -502,7 +733,11 @@ static hipError_t dispatch_tile(int tile, const FxArgs& a, int64_t n_dump, int64
   } else {
     if (tile == I) {
       constexpr FusedTile t = TileList<N, NA>::tiles[I];
-      if constexpr (t.S == 0) {
+      if constexpr (t.S == 0 && t.PP) {
+        // ping-pong ring variant (one spectrum in flight): needs P = 4, any taps
+        if (a.n_taps == 4) return launch_fused_ring_pp<N, NA, t.V>(a, n_dump, spd, cpd, part, s);
+        return launch_fused_p<N, NA, 1, t.V, false, 0>(a, n_dump, spd, cpd, part, s);
+      } else if constexpr (t.S == 0) {
         // ring variant (one spectrum in flight): needs P = 4 and the built-in
         // (symmetric) prototype
         if (a.n_taps == 4 && a.taps_symmetric)

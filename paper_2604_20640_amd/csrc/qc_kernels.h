@@ -16,6 +16,9 @@ struct FxArgs {
   const float2* tw;    // device [N], exp(-2 pi i e/N)
   const int8_t* hist;  // device [n_ant][(P-1)N] or null
   bool taps_symmetric; // h[q] == h[P*N-1-q] (the built-in prototype)
+  // device [N-1]: per-pass twiddles of the radix-16 Stockham FFT, the pass
+  // of stride NS holding W_{NS R}^{jm r} at (NS-1) + (r-1) NS + jm
+  const float2* twp = nullptr;
 };
 
 // Fused F+X for small arrays.  Returns false if no fused kernel exists for

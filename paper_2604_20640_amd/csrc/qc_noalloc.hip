@@ -34,7 +34,8 @@ constexpr int64_t kScratchBytes = QC_NOALLOC_SCRATCH_BYTES;
 constexpr int64_t kTwBytes = 8192 * 8;        // float2 [n_fft], n_fft <= 8192
 constexpr int64_t kTapsBytes = 16 * 8192 * 4; // float [P * n_fft], P <= 16
 constexpr int64_t kHistBytes = 1 << 20;       // int8 [n_ant][(P-1) n_fft]
-constexpr int64_t kPartOff = kTwBytes + kTapsBytes + kHistBytes;
+constexpr int64_t kTwpBytes = 8192 * 8;       // float2 [n_fft - 1], per-pass twiddles
+constexpr int64_t kPartOff = kTwBytes + kTapsBytes + kHistBytes + kTwpBytes;
 static_assert(kPartOff % 256 == 0, "scratch regions stay 256-byte aligned");
 
 static __device__ __align__(256) unsigned char scratch[kScratchBytes];
@@ -61,14 +62,31 @@ qc_status scratch_ptr(void** out) {
   return QC_OK;
 }
 
+// twp: the per-pass twiddles of the radix-16 Stockham FFT (pass of stride NS
+// and radix R: W_{NS R}^{jm r} at (NS-1) + (r-1) NS + jm), entry i < N-1;
 // tw[e] = exp(-2 pi i e / N) from the exact integer e (float64, rounded once);
 // h[q] = Hann-windowed sinc of L = P N taps, centre (L-1)/2, sinc zeros every
 // N, unnormalised (the built-in prototype).  Same definitions as the cached
 // host-built tables of qc_xcorrelate.
 __global__ void noalloc_tables_kernel(int N, int P, int build_taps, float2* __restrict__ tw,
-                                      float* __restrict__ taps) {
+                                      float* __restrict__ taps, float2* __restrict__ twp) {
   const int L = N * P;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N + L; i += gridDim.x * blockDim.x) {
+    if (i < N - 1) {
+      int ns = 1, off = 0;
+      while (true) {
+        const int R = (N / ns) >= 16 ? 16 : N / ns;
+        if (i < off + (R - 1) * ns) {
+          const int q = i - off, r = 1 + q / ns, jm = q % ns;
+          double sv, cv;
+          sincospi(-2.0 * (double)((jm * r) % (ns * R)) / (double)(ns * R), &sv, &cv);
+          twp[i] = make_float2((float)cv, (float)sv);
+          break;
+        }
+        off += (R - 1) * ns;
+        ns *= R;
+      }
+    }
     if (i < N) {
       double sv, cv;
       sincospi(-2.0 * (double)i / (double)N, &sv, &cv);
@@ -120,14 +138,15 @@ extern "C" qc_status qc_xcorrelate_noalloc(const int8_t* x, int64_t ld_x, int32_
     float2* tw = reinterpret_cast<float2*>(b);
     float* taps_dev = reinterpret_cast<float*>(b + kTwBytes);
     int8_t* bhist = reinterpret_cast<int8_t*>(b + kTwBytes + kTapsBytes);
+    float2* twp = reinterpret_cast<float2*>(b + kTwBytes + kTapsBytes + kHistBytes);
     float2* part = reinterpret_cast<float2*>(b + kPartOff);
     const int build_taps = p->taps == nullptr;
     const int n_tab = N + (build_taps ? N * P : 0);
     hipLaunchKernelGGL(noalloc_tables_kernel, dim3((unsigned)((n_tab + 255) / 256)), dim3(256), 0, s, N, P,
-                       build_taps, tw, taps_dev);
+                       build_taps, tw, taps_dev, twp);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return qc::api_fail(QC_EHIP, "tables kernel: %s", hipGetErrorString(e));
-    qc::FxArgs a{x, ld_x, n_ant, 0, N, P, build_taps ? taps_dev : p->taps, tw, hist, build_taps != 0};
+    qc::FxArgs a{x, ld_x, n_ant, 0, N, P, build_taps ? taps_dev : p->taps, tw, hist, build_taps != 0, twp};
     const int tile = qc_fx_get_tile(N, n_ant);
     const int64_t nd_max = cap < n_dump ? cap : n_dump;
     for (int64_t d0 = 0; d0 < n_dump; d0 += nd_max) {
