@@ -18,11 +18,13 @@ Each module states the passage of the paper it follows:
   quantisation-aware reference for the MFMA X-engine.
 * :mod:`oracle.cnn`    -- the learned RFI flagger beside MAD (Sec. 5 RFI
   structure, Sec. 7 MAD): forward, backpropagation, loss, Adam.
+* :mod:`oracle.imaging` -- synthesis imaging of Sec. 8.1: gridding, dirty
+  image and beam, Hogbom CLEAN.
 
 Everything is float64 (complex128) unless a function says otherwise.  Where
 the paper is silent the reading taken is stated in the function docstring.
 """
 
-from . import pfb, xengine, mad, calib, quant, cnn  # noqa: F401
+from . import pfb, xengine, mad, calib, quant, cnn, imaging  # noqa: F401
 
-__all__ = ["pfb", "xengine", "mad", "calib", "quant", "cnn"]
+__all__ = ["pfb", "xengine", "mad", "calib", "quant", "cnn", "imaging"]
