@@ -154,6 +154,46 @@ qc_status qc_xcorrelate_ex(const void* x, int32_t sample, int64_t ld_x, int32_t 
                            qc_prec x_prec, float* vis, int32_t accumulate, int64_t* n_dumps_out,
                            void* stream);
 
+/* Synthesis imaging of calibrated visibilities (Sec. 8.1: gridding,
+ * Fourier inversion to the dirty image and synthesized beam, CLEAN).
+ * n: image and grid size, a power of two; cell_rad: image pixel (radians);
+ * the uv cell is du = 1 / (n cell_rad) wavelengths; grid cell (iu, iv) is
+ * at u = (iu - n/2) du, v = (iv - n/2) du, image pixel (il, im) at
+ * l = (il - n/2) cell, m = (im - n/2) cell.  All calls are asynchronous on
+ * `stream` and allocate nothing.
+ *
+ * qc_image_grid: nearest-cell gridding.  u, v: device float [n_vis]
+ *   (wavelengths); vis: device cfloat [n_vis]; weight: device float
+ *   [n_vis] or NULL (1).  Cell iu = floor(u * n cell_rad + 1/2) + n/2
+ *   (float64), likewise iv; the weighted visibility is added at (iu, iv)
+ *   and its conjugate at (n - iu, n - iv); samples with a cell outside
+ *   [0, n) are dropped.  grid: device cfloat [n][n] (indexed [iu][iv]),
+ *   overwritten; wsum: device double[1] receives the total gridded weight
+ *   (both copies).  64 <= n <= 4096.  Float32 atomic sums: the grid's
+ *   rounding depends on the order of arrival.
+ * qc_image_invert: image[il][im] = Re sum_{iu,iv} grid[iu][iv]
+ *   exp(+2 pi i ((iu-n/2)(il-n/2) + (iv-n/2)(im-n/2)) / n) / wsum, so a unit
+ *   point source at the phase centre peaks at 1 (with unit visibilities the
+ *   result is the synthesized beam, peak at (n/2, n/2)).  work: device
+ *   cfloat [2 n n] scratch; image: device float [n][n].  64 <= n <= 4096.
+ * qc_image_clean: Hogbom CLEAN in place on residual (device float [n][n],
+ *   the dirty image on entry) with the beam psf (device float [n][n], peak
+ *   at (n/2, n/2)).  Each iteration takes the pixel of largest |residual|
+ *   (ties: smallest flat index il*n + im), stops if that magnitude is below
+ *   threshold or max_iter components are found, records flux
+ *   g = gain * peak and the flat index in comp_flux / comp_pix (device
+ *   [max_iter]), and subtracts g * psf[((p - peak + (n/2, n/2)) mod n] from
+ *   every pixel p (the dirty image of gridded data is periodic over the
+ *   field), product and difference each rounded to float32.  n_comp:
+ *   device int32[1] receives the number of components.  One workgroup;
+ *   2 <= n <= 8192, 0 < gain <= 1. */
+qc_status qc_image_grid(const float* u, const float* v, const float* vis, const float* weight, int64_t n_vis,
+                        int32_t n, double cell_rad, float* grid, double* wsum, void* stream);
+qc_status qc_image_invert(const float* grid, const double* wsum, int32_t n, float* work, float* image,
+                          void* stream);
+qc_status qc_image_clean(float* residual, const float* psf, int32_t n, float gain, float threshold,
+                         int32_t max_iter, int32_t* comp_pix, float* comp_flux, int32_t* n_comp, void* stream);
+
 /* Prototype filters (Fig. pfb_fft compares an 8-tap Kaiser PFB, beta = 8,
  * with a plain rectangular-window FFT).  Writes P*N float taps, designed in
  * float64 and rounded once, to device memory `taps` (16-byte aligned) for

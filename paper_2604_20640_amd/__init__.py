@@ -15,7 +15,8 @@ import torch
 
 __all__ = [
     "QCError", "lib", "pfb_channelize", "xcorrelate", "xcorrelate_noalloc", "xcorrelate_chan",
-    "pfb_channelize_ex", "xcorrelate_ex", "design_taps", "SAMPLE", "WINDOW", "mad_flag",
+    "pfb_channelize_ex", "xcorrelate_ex", "design_taps", "SAMPLE", "WINDOW", "image_grid", "image_invert",
+    "image_clean", "image_dirty_and_psf", "mad_flag",
     "apply_delay_phase", "n_base", "PREC", "timing_enable", "timing_read", "KERNELS", "Stream",
     "solve_delay_phase", "Plan", "cnn_param_count", "cnn_normalize", "cnn_forward", "cnn_grad", "cnn_adam",
     "cnn_train_step", "cnn_flag", "channelize_variant", "cnn_variant", "measure_peak",
@@ -63,6 +64,9 @@ _SIGS = {
     "qc_xcorrelate_ex": [_P, _I32, _I64, _I32, _I64, ctypes.POINTER(PfbParams), _P, _P, _I64, _I32, _P,
                          _I32, ctypes.POINTER(_I64), _P],
     "qc_pfb_design_taps": [_I32, _I32, _I32, ctypes.c_double, _P, _P],
+    "qc_image_grid": [_P, _P, _P, _P, _I64, _I32, ctypes.c_double, _P, _P, _P],
+    "qc_image_invert": [_P, _P, _I32, _P, _P, _P],
+    "qc_image_clean": [_P, _P, _I32, ctypes.c_float, ctypes.c_float, _I32, _P, _P, _P, _P],
     "qc_mad_flag": [_P, _I64, _I64, _I32, ctypes.c_float, _I32, _P, _P, _P],
     "qc_apply_delay_phase": [_P, _I64, _I32, _I32, ctypes.c_double, ctypes.c_double,
                              ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), _P],
@@ -575,6 +579,55 @@ def design_taps(n_fft, n_taps, window="hann", beta=0.0, device="cuda"):
     _check(lib().qc_pfb_design_taps(n_fft, n_taps, WINDOW[window], float(beta), _ptr(taps), _stream()),
            "qc_pfb_design_taps")
     return taps
+
+
+def image_grid(u, v, vis, n, cell_rad, weight=None, grid=None, wsum=None):
+    """Nearest-cell gridding (qc_image_grid): returns (grid complex64 [n, n],
+    wsum float64 [1]) on the device."""
+    assert u.dtype == torch.float32 and v.dtype == torch.float32 and vis.dtype == torch.complex64
+    n_vis = vis.numel()
+    if grid is None:
+        grid = torch.empty((n, n), dtype=torch.complex64, device=vis.device)
+    if wsum is None:
+        wsum = torch.empty(1, dtype=torch.float64, device=vis.device)
+    _check(lib().qc_image_grid(_ptr(u), _ptr(v), _ptr(vis), _ptr(weight), n_vis, n, float(cell_rad),
+                               _ptr(grid), _ptr(wsum), _stream()), "qc_image_grid")
+    return grid, wsum
+
+
+def image_invert(grid, wsum, image=None, work=None):
+    """Dirty image (or beam) float32 [n, n] from a grid (qc_image_invert)."""
+    n = grid.shape[0]
+    if image is None:
+        image = torch.empty((n, n), dtype=torch.float32, device=grid.device)
+    if work is None:
+        work = torch.empty((2, n, n), dtype=torch.complex64, device=grid.device)
+    _check(lib().qc_image_invert(_ptr(grid), _ptr(wsum), n, _ptr(work), _ptr(image), _stream()),
+           "qc_image_invert")
+    return image
+
+
+def image_dirty_and_psf(u, v, vis, n, cell_rad, weight=None):
+    """(dirty image, synthesized beam), both float32 [n, n] on the device."""
+    g, w = image_grid(u, v, vis, n, cell_rad, weight)
+    dirty = image_invert(g, w)
+    ones = torch.ones_like(vis)
+    gp, wp = image_grid(u, v, ones, n, cell_rad, weight)
+    return dirty, image_invert(gp, wp)
+
+
+def image_clean(residual, psf, gain, threshold, max_iter):
+    """Hogbom CLEAN in place on residual (qc_image_clean): returns
+    (flat pixel indices int32 [k], fluxes float32 [k]) on the device."""
+    n = residual.shape[0]
+    assert residual.dtype == torch.float32 and psf.dtype == torch.float32 and residual.is_contiguous()
+    pix = torch.empty(max(max_iter, 1), dtype=torch.int32, device=residual.device)
+    flux = torch.empty(max(max_iter, 1), dtype=torch.float32, device=residual.device)
+    nc = torch.empty(1, dtype=torch.int32, device=residual.device)
+    _check(lib().qc_image_clean(_ptr(residual), _ptr(psf), n, float(gain), float(threshold), max_iter,
+                                _ptr(pix), _ptr(flux), _ptr(nc), _stream()), "qc_image_clean")
+    k = int(nc.item())
+    return pix[:k], flux[:k]
 
 
 def pfb_channelize(x, n_fft, n_taps, taps=None, hist=None, hist_out=None, out_prec="f32",

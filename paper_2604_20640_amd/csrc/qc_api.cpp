@@ -480,6 +480,8 @@ qc_status api_check_stream_args(const int8_t* x, int64_t ld_x, int32_t n_ant, in
   return check_stream_args(x, ld_x, n_ant, n_samp, p, hist, hist_out);
 }
 
+qc_status api_twiddles(int n, float2** out) { return get_twiddles(n, out); }
+
 }  // namespace qc
 
 extern "C" {

@@ -342,3 +342,61 @@ def rfi_realisation(seed, n_ant=32, n_samp=1 << 24, n_fft=4096, spec_per_dump=16
               "n_int": n_int, "n_chan": nch, "spec_per_dump": spec_per_dump, "n_fft": n_fft,
               "n_taps": n_taps}
     return spec, truth, params
+
+
+# ---- synthetic interferometer observations for imaging --------------------
+
+C_LIGHT = 299792458.0
+
+
+@dataclass
+class ImagingObs:
+    u: np.ndarray        # float32 [n_vis], wavelengths
+    v: np.ndarray        # float32 [n_vis]
+    vis: np.ndarray      # complex64 [n_vis]
+    sources: list        # [(flux, l, m)]
+    n: int               # image size
+    cell_rad: float      # image pixel
+
+
+def imaging_obs(n_ant=4, n_chan=256, n_time=64, seed=5000, n=256, noise=0.0, sources=None,
+                radius_m=60.0, f0_hz=1.30e9, bw_hz=1.0e8, lat_deg=36.7, dec_deg=58.8,
+                ha_span_h=4.0):
+    """Point sources observed by n_ant antennas at random positions within
+    radius_m (east, north), over n_chan channels in [f0, f0 + bw) and n_time
+    hour angles across ha_span_h hours (earth-rotation synthesis), at a
+    source declination dec_deg from latitude lat_deg.  (u, v) per cross
+    baseline i < j from the standard east-north to equatorial rotation.
+    Visibilities V = sum_s F_s exp(-2 pi i (u l_s + v m_s)) plus complex
+    Gaussian noise of rms `noise`.  The pixel size puts the longest
+    projected baseline at n/4 cells (every cell and its mirror stay on the
+    grid); the default sources sit on pixel centres."""
+    rng = _rng(seed, 11, 0)
+    rad = radius_m * np.sqrt(rng.uniform(0, 1, n_ant))
+    ang = rng.uniform(0, 2 * np.pi, n_ant)
+    east, north = rad * np.cos(ang), rad * np.sin(ang)
+    lat, dec = np.radians(lat_deg), np.radians(dec_deg)
+    ha = np.radians(15.0 * np.linspace(-ha_span_h / 2, ha_span_h / 2, n_time))
+    freqs = f0_hz + (np.arange(n_chan) + 0.5) * (bw_hz / n_chan)
+    us, vs = [], []
+    for i in range(n_ant):
+        for j in range(i + 1, n_ant):
+            dE, dN = east[j] - east[i], north[j] - north[i]
+            X, Y, Z = -np.sin(lat) * dN, dE, np.cos(lat) * dN
+            u_m = np.sin(ha) * X + np.cos(ha) * Y
+            v_m = -np.sin(dec) * np.cos(ha) * X + np.sin(dec) * np.sin(ha) * Y + np.cos(dec) * Z
+            us.append(np.outer(u_m, freqs / C_LIGHT).ravel())
+            vs.append(np.outer(v_m, freqs / C_LIGHT).ravel())
+    u = np.concatenate(us).astype(np.float32)
+    v = np.concatenate(vs).astype(np.float32)
+    umax = float(max(np.abs(u).max(), np.abs(v).max()))
+    cell = 1.0 / (4.0 * umax)          # |u| <= n/4 cells: every cell and mirror in range
+    if sources is None:
+        sources = [(1.0, 0.0, 0.0), (0.5, 12 * cell, -7 * cell), (0.3, -20 * cell, 15 * cell)]
+    ud, vd = u.astype(np.float64), v.astype(np.float64)
+    V = np.zeros(u.shape, np.complex128)
+    for (F, l, m) in sources:
+        V += F * np.exp(-2j * np.pi * np.mod(ud * l + vd * m, 1.0))
+    if noise:
+        V += noise * (rng.standard_normal(u.size) + 1j * rng.standard_normal(u.size)) / np.sqrt(2)
+    return ImagingObs(u, v, V.astype(np.complex64), sources, n, cell)
