@@ -154,6 +154,50 @@ qc_status qc_xcorrelate_ex(const void* x, int32_t sample, int64_t ld_x, int32_t 
                            qc_prec x_prec, float* vis, int32_t accumulate, int64_t* n_dumps_out,
                            void* stream);
 
+/* File ingest (Alg. 1 with its reader threads, pinned buffers and bounded
+ * DataQueue; Sec. 4.2 "Asynchronous I/O"; the batch-packets / queue-max
+ * operating point of Sec. 6).
+ *   paths: n_ant files, each the raw samples of one antenna (words of type
+ *     `sample`, as qc_pfb_channelize_ex; no header).
+ *   packet_samp: samples per antenna per packet; batch_packets: packets per
+ *     GPU batch; queue_max: page-locked batch buffers the readers may fill
+ *     ahead of the GPU (the bounded queue); n_readers: reader threads
+ *     (antennas split round-robin); depth: device batch slots (1..16).
+ *   A batch (packet_samp * batch_packets samples per antenna, a multiple of
+ *   n_fft) either holds whole dumps or a whole number of batches make one
+ *   dump.  Reader threads fill buffers in batch order; the calling thread
+ *   copies each complete batch to the device on a copy stream and
+ *   correlates it (F-engine, X-engine, integration, the filter history
+ *   carried across batches) on a compute stream, overlapping reads, copies
+ *   and compute.  vis: device cfloat [max_dumps][n_base][n_chan] receives
+ *   the whole dumps found in every file (at most max_dumps; max_dumps < 0:
+ *   no limit, then vis must hold every dump); n_chan as qc_pfb_channelize_ex.
+ *   Synchronous: returns when the last dump is on the device.  Allocates its
+ *   pinned buffers, device slots and streams per call (default priority). */
+typedef struct {
+  int32_t n_ant;
+  int32_t sample;          /* qc_sample */
+  int64_t packet_samp;
+  int32_t batch_packets;
+  int32_t queue_max;
+  int32_t n_readers;
+  int32_t depth;
+  qc_pfb_params pfb;
+  int64_t spec_per_dump;
+} qc_ingest_config;
+typedef struct {
+  int64_t bytes;       /* input bytes correlated */
+  int64_t batches;
+  int64_t dumps;
+  double wall_s;       /* first read to the end of the last computation */
+  double read_s;       /* reader threads' time inside file reads (summed) */
+  double h2d_s;        /* host-to-device copies (HIP events, summed) */
+  double compute_s;    /* F+X per batch (HIP events, summed) */
+  double wait_s;       /* consumer waiting for a complete buffer */
+} qc_ingest_stats;
+qc_status qc_ingest_run(const char* const* paths, const qc_ingest_config* cfg, float* vis, int64_t max_dumps,
+                        qc_ingest_stats* stats);
+
 /* Synthesis imaging of calibrated visibilities (Sec. 8.1: gridding,
  * Fourier inversion to the dirty image and synthesized beam, CLEAN).
  * n: image and grid size, a power of two; cell_rad: image pixel (radians);

@@ -16,7 +16,7 @@ import torch
 __all__ = [
     "QCError", "lib", "pfb_channelize", "xcorrelate", "xcorrelate_noalloc", "xcorrelate_chan",
     "pfb_channelize_ex", "xcorrelate_ex", "design_taps", "SAMPLE", "WINDOW", "image_grid", "image_invert",
-    "image_clean", "image_dirty_and_psf", "mad_flag",
+    "image_clean", "image_dirty_and_psf", "ingest_run", "IngestConfig", "IngestStats", "mad_flag",
     "apply_delay_phase", "n_base", "PREC", "timing_enable", "timing_read", "KERNELS", "Stream",
     "solve_delay_phase", "Plan", "cnn_param_count", "cnn_normalize", "cnn_forward", "cnn_grad", "cnn_adam",
     "cnn_train_step", "cnn_flag", "channelize_variant", "cnn_variant", "measure_peak",
@@ -42,6 +42,18 @@ class PfbParams(ctypes.Structure):
                 ("taps", ctypes.c_void_p), ("keep_nyquist", ctypes.c_int32)]
 
 
+class IngestConfig(ctypes.Structure):
+    _fields_ = [("n_ant", ctypes.c_int32), ("sample", ctypes.c_int32), ("packet_samp", ctypes.c_int64),
+                ("batch_packets", ctypes.c_int32), ("queue_max", ctypes.c_int32), ("n_readers", ctypes.c_int32),
+                ("depth", ctypes.c_int32), ("pfb", PfbParams), ("spec_per_dump", ctypes.c_int64)]
+
+
+class IngestStats(ctypes.Structure):
+    _fields_ = [("bytes", ctypes.c_int64), ("batches", ctypes.c_int64), ("dumps", ctypes.c_int64),
+                ("wall_s", ctypes.c_double), ("read_s", ctypes.c_double), ("h2d_s", ctypes.c_double),
+                ("compute_s", ctypes.c_double), ("wait_s", ctypes.c_double)]
+
+
 class ArrayDesc(ctypes.Structure):
     _fields_ = [("n_ant", ctypes.c_int32), ("n_samp", ctypes.c_int64), ("n_fft", ctypes.c_int32),
                 ("n_taps", ctypes.c_int32), ("spec_per_dump", ctypes.c_int64)]
@@ -65,6 +77,8 @@ _SIGS = {
                          _I32, ctypes.POINTER(_I64), _P],
     "qc_pfb_design_taps": [_I32, _I32, _I32, ctypes.c_double, _P, _P],
     "qc_image_grid": [_P, _P, _P, _P, _I64, _I32, ctypes.c_double, _P, _P, _P],
+    "qc_ingest_run": [ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(IngestConfig), _P, _I64,
+                      ctypes.POINTER(IngestStats)],
     "qc_image_invert": [_P, _P, _I32, _P, _P, _P],
     "qc_image_clean": [_P, _P, _I32, ctypes.c_float, ctypes.c_float, _I32, _P, _P, _P, _P],
     "qc_mad_flag": [_P, _I64, _I64, _I32, ctypes.c_float, _I32, _P, _P, _P],
@@ -579,6 +593,34 @@ def design_taps(n_fft, n_taps, window="hann", beta=0.0, device="cuda"):
     _check(lib().qc_pfb_design_taps(n_fft, n_taps, WINDOW[window], float(beta), _ptr(taps), _stream()),
            "qc_pfb_design_taps")
     return taps
+
+
+def ingest_run(paths, n_fft, n_taps, spec_per_dump, packet_samp, batch_packets, queue_max, n_readers=None,
+               depth=4, sample="i8", taps=None, vis=None, max_dumps=-1):
+    """File ingest (qc_ingest_run): one raw sample file per antenna, read by
+    reader threads into queue_max pinned batch buffers, copied and
+    correlated on the device.  Returns (vis complex64 [n_dump, n_base,
+    n_chan], stats dict).  vis, if given, must hold max_dumps dumps."""
+    n_ant = len(paths)
+    code = SAMPLE[sample]
+    wb = {0: 1, 1: 2, 2: 2, 3: 4}[code]
+    n_chan = n_fft if code >= 2 else n_fft // 2
+    batch_samp = packet_samp * batch_packets
+    bspec = batch_samp // n_fft
+    if vis is None:
+        n_batch = min(os.path.getsize(p) for p in paths) // (batch_samp * wb)
+        nd = (n_batch // (spec_per_dump // bspec)) if spec_per_dump >= bspec else n_batch * (bspec // spec_per_dump)
+        if max_dumps >= 0:
+            nd = min(nd, max_dumps)
+        max_dumps = nd
+        vis = torch.empty((max(nd, 1), n_base(n_ant), n_chan), dtype=torch.complex64, device="cuda")
+    cfg = IngestConfig(n_ant, code, packet_samp, batch_packets, queue_max, n_readers or n_ant, depth,
+                       _pfb(n_fft, n_taps, taps), spec_per_dump)
+    arr = (ctypes.c_char_p * n_ant)(*[os.fsencode(p) for p in paths])
+    st = IngestStats()
+    _check(lib().qc_ingest_run(arr, ctypes.byref(cfg), _ptr(vis), max_dumps, ctypes.byref(st)), "qc_ingest_run")
+    stats = {k: getattr(st, k) for k, _ in IngestStats._fields_}
+    return vis[:st.dumps], stats
 
 
 def image_grid(u, v, vis, n, cell_rad, weight=None, grid=None, wsum=None):
