@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the uneven-arrays section")
     ap.add_argument("--no-stream", action="store_true", help="skip the host-streaming section")
     ap.add_argument("--no-flagger", action="store_true", help="skip the learned-flagger section")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the sidelobe, input-word, file-ingest and imaging sections")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 256 MiB device copy kernel (counter calibration)")
     ap.add_argument("--no-achievable", action="store_true",
@@ -365,6 +367,159 @@ def batched_section(torch, qc, steps):
             "autotune_s": round(tune_s, 2), "vis_err_vs_separate": float(f"{err:.3e}")}
 
 
+LEAK_OFFSETS = list(range(-10, 0)) + list(range(1, 11))
+
+
+def leakage_db(X, k0):
+    """Mean power at channels k0 + d (d = +-1..+-10) over the strongest
+    channel's, in dB, floored at -300 dB (exact zeros: a bin-centred tone
+    through the plain FFT)."""
+    p = np.mean(np.abs(np.asarray(X, np.complex128)) ** 2, axis=0)
+    pk = p.max()
+    return [round(float(max(10 * np.log10(max(p[(k0 + d) % p.size], 1e-300) / pk), -300.0)), 2)
+            for d in LEAK_OFFSETS]
+
+
+def sidelobe_section(torch, qc, checks):
+    """Fig. pfb_fft as numbers: a complex 16-bit tone at channel 100 + frac
+    (N = 1024) through the 8-tap Kaiser (beta = 8) PFB and the plain
+    rectangular FFT; leakage at +-1..+-10 channels relative to the peak
+    channel, on the GPU (the oracle's values on the same samples are added
+    by the CPU-baseline leg)."""
+    N, k0, M = 1024, 100, 24
+    res = {"workload": "complex int16 tone, N = 1024, channel 100 + frac, 24 spectra",
+           "offsets": LEAK_OFFSETS, "pfb": "8 taps, Kaiser beta = 8", "fft": "1 tap, rectangular"}
+    kaiser = qc.design_taps(N, 8, "kaiser", 8.0)
+    rect = qc.design_taps(N, 1, "rect")
+    for frac in (0.0, 0.25, 0.5):
+        spec = synth.StreamSpec(1, N * M, 21, sigma=0.0, corr=0.0, bits=16, tone_amp=30000.0,
+                                tone_cycles_per_sample=(k0 + frac) / N, period=4 * N)
+        x = synth.generate_iq(spec)
+        xd = torch.from_numpy(x).cuda()
+        row = {}
+        for name, P, taps in (("pfb", 8, kaiser), ("fft", 1, rect)):
+            X = qc.pfb_channelize_ex(xd, N, P, taps=taps)[0].cpu().numpy()[0, P - 1:]
+            row[name] = leakage_db(X, k0)
+        res[f"frac_{frac}"] = row
+        if checks is not None:
+            checks.append(("sidelobes", res, frac, x, N, k0, kaiser.cpu().numpy(), rect.cpu().numpy()))
+    log(f"[bench] sidelobes: off-bin (0.5) PFB {res['frac_0.5']['pfb'][9]} dB vs FFT "
+        f"{res['frac_0.5']['fft'][9]} dB at -1; at +-10: {res['frac_0.5']['pfb'][0]} vs {res['frac_0.5']['fft'][0]}")
+    return res
+
+
+def input_words_section(torch, qc, steps):
+    """F+X over the input words of Sec. 3.3 / Sec. 4.2 at the real-time
+    shape (4 antennas, N = 4096, P = 4, 4096 spectra per dump), 2^26 samples
+    per antenna: real int8 (fused kernel), real int16 (the default 16-bit
+    padded mode) and complex int8 / int16 I/Q (4096 channels), the last three
+    through the F-engine of any word and the X-engine."""
+    N, P, spd, S = 4096, 4, 4096, 1 << 26
+    reps = max(3, steps // 10)
+    out = {"workload": "4 ant x 2^26 samples, N = 4096, P = 4, 4096 spectra per dump"}
+    for word in ("i8", "i16", "ci8", "ci16"):
+        bits = 14 if word.endswith("16") else 8
+        spec = synth.StreamSpec(4, S, 7000, sigma=1200.0 if bits == 14 else 16.0, corr=0.3,
+                                lags=(0, 3, 5, 7), bits=bits)
+        x = synth.generate_iq(spec) if word.startswith("c") else synth.generate(spec)
+        xd = torch.from_numpy(x).cuda()
+        del x
+        fn = (lambda: qc.xcorrelate(xd, N, P, spd)) if word == "i8" else (lambda: qc.xcorrelate_ex(xd, N, P, spd))
+        fn()
+        ms = timed(torch, fn, reps)
+        nbytes = xd.numel() * xd.element_size()
+        out[word] = {"ms": round(ms, 4), "input_GBps": round(nbytes / ms / 1e6, 2),
+                     "samples_per_s": round(4 * S / (ms * 1e-3), 1)}
+        log(f"[bench] word {word}: {ms:.3f} ms, {nbytes / ms / 1e6:.1f} GB/s")
+        del xd
+    return out
+
+
+def ingest_section(torch, qc, x, N, P, spd, vis_ref):
+    """Sec. 6's operating-point scan on the real-time stream written to local
+    files (one raw int8 file per antenna, 256 MiB each): packets of 8192
+    samples, batch-packets x queue-max, four reader threads.  The files were
+    just written, so reads come from the page cache (no NFS or disk), and
+    the scan measures the read/copy/compute overlap of the pipeline."""
+    import shutil
+    import tempfile
+    d = tempfile.mkdtemp(prefix="qc_ingest_")
+    try:
+        paths = []
+        for a in range(x.shape[0]):
+            pth = os.path.join(d, f"ant{a}.raw")
+            x[a].tofile(pth)
+            paths.append(pth)
+        packet = 8192
+        grid = []
+        best = None
+        vis = torch.empty_like(vis_ref)
+        for bp in (16, 64, 256, 1024):
+            for qm in (2, 4, 12):
+                if qm * x.shape[0] * packet * bp > (3 << 30):
+                    continue
+                _, st = qc.ingest_run(paths, N, P, spd, packet, bp, qm, n_readers=4, vis=vis,
+                                      max_dumps=vis.shape[0])
+                gbps = st["bytes"] / st["wall_s"] / 1e9
+                row = {"batch_packets": bp, "queue_max": qm, "GBps": round(gbps, 2),
+                       "wall_ms": round(st["wall_s"] * 1e3, 2), "read_ms": round(st["read_s"] * 1e3, 2),
+                       "h2d_ms": round(st["h2d_s"] * 1e3, 2), "compute_ms": round(st["compute_s"] * 1e3, 2),
+                       "wait_ms": round(st["wait_s"] * 1e3, 2)}
+                grid.append(row)
+                if best is None or gbps > best["GBps"]:
+                    best = row
+                log(f"[bench] ingest bp={bp} qm={qm}: {gbps:.1f} GB/s")
+        err = vis_err(vis.cpu().numpy(), vis_ref.cpu().numpy(), x.shape[0])
+    finally:
+        shutil.rmtree(d, ignore_errors=True)
+    return {"workload": "realtime_4ant_n4096 from 4 local files (page cache)", "packet_samp": packet,
+            "readers": 4, "scan": grid, "best": best, "vis_err_vs_resident": float(f"{err:.3e}")}
+
+
+def imaging_section(torch, qc, steps):
+    """Sec. 8.1 on synthetic observations: gridding, dirty image and beam,
+    Hogbom CLEAN (gain 0.1, 1000 components at most, threshold 1 % of the
+    peak).  The paper's 4-antenna array (98,304 visibilities, 256 x 256)
+    and a 32-antenna one (8.1 M visibilities, 1024 x 1024)."""
+    out = {}
+    reps = max(3, steps // 10)
+    for name, na, n in (("4ant_256px", 4, 256), ("32ant_1024px", 32, 1024)):
+        o = synth.imaging_obs(n_ant=na, n=n)
+        u, v, vis = (torch.from_numpy(a).cuda() for a in (o.u, o.v, o.vis))
+        g, w = qc.image_grid(u, v, vis, n, o.cell_rad)
+        work = torch.empty((2, n, n), dtype=torch.complex64, device="cuda")
+        img = torch.empty((n, n), dtype=torch.float32, device="cuda")
+        t_grid = timed(torch, lambda: qc.image_grid(u, v, vis, n, o.cell_rad, grid=g, wsum=w), reps)
+        t_inv = timed(torch, lambda: qc.image_invert(g, w, image=img, work=work), reps)
+        dirty, psf = qc.image_dirty_and_psf(u, v, vis, n, o.cell_rad)
+        peak = float(dirty.max())
+        res = dirty.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pix, flux = qc.image_clean(res, psf, 0.1, 0.01 * peak, 1000)
+        torch.cuda.synchronize()
+        t_clean = (time.perf_counter() - t0) * 1e3
+        model = np.zeros(n * n)
+        np.add.at(model, pix.cpu().numpy(), flux.cpu().numpy())
+        model = model.reshape(n, n)
+        rec = []
+        for (F, l, m) in o.sources:
+            il, im = int(round(l / o.cell_rad)) + n // 2, int(round(m / o.cell_rad)) + n // 2
+            rec.append([F, round(float(model[il - 1:il + 2, im - 1:im + 2].sum()), 4)])
+        out[name] = {"n_vis": int(o.u.size), "image": n, "grid_ms": round(t_grid, 4),
+                     "grid_Mvis_per_s": round(o.u.size / (t_grid * 1e-3) / 1e6, 1),
+                     "invert_ms": round(t_inv, 4), "clean_ms": round(t_clean, 2),
+                     "components": int(pix.numel()),
+                     "clean_ms_per_component": round(t_clean / max(int(pix.numel()), 1), 4),
+                     "dynamic_range_dirty": round(peak / float(dirty.abs().flatten()[
+                         dirty.abs().flatten() < 0.5 * peak].std()), 1),
+                     "residual_peak_frac": round(float(res.abs().max()) / peak, 4),
+                     "flux_true_vs_clean": rec}
+        log(f"[bench] imaging {name}: grid {t_grid:.3f} ms, invert {t_inv:.3f} ms, CLEAN {t_clean:.1f} ms "
+            f"({pix.numel()} components)")
+    return out
+
+
 def cpu_baseline(x, N, P, spd, sigma, tau, phi, df, gpu_vis, n_dumps=8):
     """The FP64 oracle on the host cores over a bounded sample: the first
     n_dumps dumps (64 MiB of input each) on a 64-channel subset, F+X then MAD
@@ -446,6 +601,18 @@ def oracle_checks(checks):
                     "norm_err_max": float(f"{nerr.max():.3e}"),
                     "norm_err_median": float(f"{np.median(nerr):.3e}"),
                     "channels": [int(c) for c in chans]}
+        elif item[0] == "sidelobes":
+            from oracle import pfb
+            _, res, frac, x, N, k0, kaiser, rect = item
+            xc = x[..., 0].astype(np.int64) + 1j * x[..., 1].astype(np.int64)
+            row = res[f"frac_{frac}"]
+            for name, P, taps in (("pfb", 8, kaiser), ("fft", 1, rect)):
+                Xo = pfb.channelize_complex(xc, N, P, taps=taps.astype(np.float64))[0, P - 1:]
+                o = leakage_db(Xo, k0)
+                row[name + "_oracle"] = o
+                g = np.array(row[name])
+                row[name + "_max_amp_diff_vs_oracle"] = float(
+                    f"{np.max(np.abs(10 ** (g / 20) - 10 ** (np.array(o) / 20))):.2e}")
         elif item[0] == "solve":
             _, res, V, M, n_ant, df, fs, lo, hi, tau, phi = item
             t0 = time.perf_counter()
@@ -642,6 +809,11 @@ def main():
         out["batched"] = batched_section(torch, qc, args.steps)
     if not args.no_flagger:
         out["flagger"] = flagger_section(torch, qc, args.steps)
+    if not args.no_extras:
+        out["sidelobes"] = sidelobe_section(torch, qc, checks)
+        out["input_words"] = input_words_section(torch, qc, args.steps)
+        out["ingest"] = ingest_section(torch, qc, x, N, P, spd, torch.from_numpy(gpu_vis).cuda())
+        out["imaging"] = imaging_section(torch, qc, args.steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(x, N, P, spd, sigma, tau, phi, df, gpu_vis)
         oracle_checks(checks)

@@ -9,6 +9,8 @@ the fallback flagger.  Every numerical step runs in the library's kernels
 module only draws training tiles and counts agreements.
 
     python -m paper_2604_20640_amd.flagger --out weights.npy --metrics m.json
+    python -m paper_2604_20640_amd.flagger --train-seeds 200 --train-ant 32 \
+        --test-seeds 50 --test-ant 32 --tiles-per-set 64 --steps 1500
 """
 
 from __future__ import annotations
@@ -80,6 +82,54 @@ class TileSampler:
         return torch.stack(xs).contiguous(), torch.stack(ys).contiguous()
 
 
+class TilePool:
+    """A fixed pool of training tiles: each realisation contributes
+    `per_set` random (time x channel) tiles of random baselines of its
+    normalised plane, and the plane is then freed, so many realisations fit
+    in device memory.  Batches are drawn from the pool with replacement."""
+
+    def __init__(self, per_set, tile=(64, 256), seed=0):
+        self.per_set, self.tile = per_set, tile
+        self.g = torch.Generator(device="cpu").manual_seed(seed)
+        self.xs, self.ys = [], []
+        self.X = self.Y = None
+
+    def add(self, vis, truth):
+        img = qc.cnn_normalize(vis)          # [n_base, n_int, n_chan]
+        th, tw = self.tile
+        nb, T, F = img.shape
+        for _ in range(self.per_set):
+            b = int(torch.randint(nb, (1,), generator=self.g))
+            t0 = int(torch.randint(T - th + 1, (1,), generator=self.g))
+            f0 = int(torch.randint(F - tw + 1, (1,), generator=self.g))
+            self.xs.append(img[b, t0:t0 + th, f0:f0 + tw].clone())
+            self.ys.append(truth[t0:t0 + th, f0:f0 + tw].clone())
+        del img
+
+    def finalize(self):
+        self.X = torch.stack(self.xs).contiguous()
+        self.Y = torch.stack(self.ys).contiguous()
+        self.xs, self.ys = [], []
+        self.pos_frac = float(self.Y.float().mean())
+
+    def batch(self, n):
+        idx = torch.randint(self.X.shape[0], (n,), generator=self.g).to(self.X.device)
+        return self.X[idx].contiguous(), self.Y[idx].contiguous()
+
+
+def summarise(results):
+    """Mean, standard deviation, minimum and maximum of every rate over the
+    held-out realisations."""
+    out = {}
+    for group in results[0]:
+        out[group] = {}
+        for key in results[0][group]:
+            v = np.array([r[group][key] for r in results], np.float64)
+            out[group][key] = {"mean": round(float(v.mean()), 4), "std": round(float(v.std()), 4),
+                               "min": round(float(v.min()), 4), "max": round(float(v.max()), 4)}
+    return out
+
+
 def train(sampler, steps=400, batch=32, lr=1e-3, seed=0, log_every=50, log=print):
     params = init_params(seed)
     m = torch.zeros_like(params)
@@ -134,24 +184,43 @@ def main(argv=None):
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--out", type=str, default=None)
     ap.add_argument("--metrics", type=str, default=None)
+    ap.add_argument("--tiles-per-set", type=int, default=0,
+                    help="keep this many random tiles per training realisation (0: whole planes)")
+    ap.add_argument("--act", type=str, default="f32", help="inference activations for the test set")
     a = ap.parse_args(argv)
     t0 = time.time()
-    sets = [realise(s, a.train_ant) for s in range(a.train_seeds)]
-    print(f"[flagger] {len(sets)} training realisations in {time.time() - t0:.1f}s", flush=True)
-    sampler = TileSampler(sets, seed=1)
-    del sets
+    if a.tiles_per_set > 0:
+        sampler = TilePool(a.tiles_per_set, seed=1)
+        for s in range(a.train_seeds):
+            vis, truth, _ = realise(s, a.train_ant)
+            sampler.add(vis, truth)
+            del vis, truth
+            if (s + 1) % 10 == 0:
+                print(f"[flagger] {s + 1} training realisations in {time.time() - t0:.1f}s", flush=True)
+        sampler.finalize()
+    else:
+        sets = [realise(s, a.train_ant) for s in range(a.train_seeds)]
+        sampler = TileSampler(sets, seed=1)
+        del sets
+    print(f"[flagger] {a.train_seeds} training realisations in {time.time() - t0:.1f}s", flush=True)
     t0 = time.time()
     params, info = train(sampler, a.steps, a.batch, a.lr, log=lambda s: print(s, flush=True))
     torch.cuda.synchronize()
     info["train_s"] = round(time.time() - t0, 2)
     del sampler
     results = []
+    t0 = time.time()
     for s in range(200, 200 + a.test_seeds):
         vis, truth, _ = realise(s, a.test_ant)
-        results.append(evaluate(params, vis, truth))
+        results.append(evaluate(params, vis, truth, act=a.act))
         print(f"[flagger] test seed {s}: {results[-1]}", flush=True)
         del vis
+    info["test_s"] = round(time.time() - t0, 2)
+    info["config"] = {"train_seeds": a.train_seeds, "train_ant": a.train_ant, "test_seeds": a.test_seeds,
+                      "test_ant": a.test_ant, "steps": a.steps, "batch": a.batch, "lr": a.lr,
+                      "tiles_per_set": a.tiles_per_set, "act": a.act}
     info["test"] = results
+    info["test_summary"] = summarise(results)
     if a.out:
         np.save(a.out, params.cpu().numpy())
     if a.metrics:
