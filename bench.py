@@ -355,6 +355,19 @@ def batched_section(torch, qc, steps):
     err = max(vis_err(a.cpu().numpy(), b.cpu().numpy(), d["n_ant"])
               for a, b, d in zip(vis, sep, descs))
     log(f"[bench] batched: graph {g_ms:.3f} ms, eager plan {e_ms:.3f} ms, separate {s_ms:.3f} ms")
+    # the same arrays in one persistent launch (its own knobs, not tuned)
+    plan.set_mode("persistent")
+    pvis = plan.empty_vis()
+    p_ms = on_side(lambda: plan.execute(xs, pvis))
+    plan.check()
+    with torch.cuda.stream(side):
+        plan.capture_graph(xs, pvis)
+    torch.cuda.synchronize()
+    pg_ms = on_side(plan.replay)
+    plan.check()
+    perr = max(vis_err(a.cpu().numpy(), b.cpu().numpy(), d["n_ant"])
+               for a, b, d in zip(pvis, sep, descs))
+    log(f"[bench] batched persistent: eager {p_ms:.3f} ms, graph {pg_ms:.3f} ms")
     plan.close()
     del xs
     return {"workload": "batched_5arrays", "arrays_ant_chan": [list(a) for a in synth.BATCH_ARRAYS],
@@ -364,7 +377,11 @@ def batched_section(torch, qc, steps):
             "speedup_vs_separate": round(s_ms / g_ms, 3), "plan_mode": "graph",
             "launches_per_execution": n_launch,
             "knobs": {"concurrent": conc, "fused_tile": tiles, "split": splits},
-            "autotune_s": round(tune_s, 2), "vis_err_vs_separate": float(f"{err:.3e}")}
+            "autotune_s": round(tune_s, 2), "vis_err_vs_separate": float(f"{err:.3e}"),
+            "persistent": {"eager_ms": round(p_ms, 4), "graph_ms": round(pg_ms, 4),
+                           "input_GBps": round(nbytes / min(p_ms, pg_ms) / 1e6, 2),
+                           "launches_per_execution": 2,
+                           "vis_err_vs_separate": float(f"{perr:.3e}")}}
 
 
 LEAK_OFFSETS = list(range(-10, 0)) + list(range(1, 11))

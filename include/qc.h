@@ -347,9 +347,16 @@ qc_status qc_solve_delay_phase(const float* vis, const uint8_t* mask, int64_t n_
  *     plan-owned buffers.  With `concurrent` set, every array runs on a
  *     stream of its own between a fork and a join event on the caller's
  *     stream, so a captured graph holds the arrays as independent branches.
- *   QC_PLAN_PERSISTENT: one persistent launch claiming work items from an
- *     ordered queue with bounded waits between dependent items.  Switched
- *     off in this build: selecting it returns QC_EUNSUPPORTED.
+ *   QC_PLAN_PERSISTENT: every array's work in one persistent launch (256
+ *     workgroups of 512 threads) that claims work items from one ordered
+ *     queue: fused F+X items, F-engine items, FP32 X-engine items and
+ *     reductions.  An item that needs others (X-engine after its array's
+ *     F-engine, reduction after its partials) waits for their done counter,
+ *     bounded in time (qc_plan_set_wait_timeout); on expiry the item is
+ *     skipped, an error flag is set that qc_plan_check reports, and every
+ *     later wait gives up at once, so the launch always drains.  Reductions
+ *     scale like qc_xcorrelate's, so both modes give the same float32 sums
+ *     up to the grouping of partial sums.
  *
  *   qc_plan_create: n_arrays in [1, 8]; each array 1..64 antennas, n_fft a
  *     power of two in [16, 8192], n_samp a multiple of n_fft (< 2^31), at
@@ -366,7 +373,8 @@ qc_status qc_solve_delay_phase(const float* vis, const uint8_t* mask, int64_t n_
  *     (time limit of one dependency wait in microseconds, default 2 s; test
  *     hook that makes every wait target unreachable).
  *   qc_plan_capture_graph: captures one execution (fixed x / vis pointers)
- *     on a non-default stream into a hipGraph; qc_plan_replay launches it.
+ *     on a non-default stream into a hipGraph; qc_plan_replay launches it,
+ *     also on a non-default stream (QC_EINVAL on the legacy default stream).
  *     Changing the mode or re-tuning drops the graph.
  *   qc_plan_autotune: graph mode; times executions over the knobs
  *     (concurrency; per array the fused tile and the split: chunks per dump

@@ -256,8 +256,8 @@ class Stream:
 
 class Plan:
     """Several arrays correlated together (qc_plan_*): per-array kernels on
-    streams of their own, capturable as one hipGraph; the persistent
-    single-launch mode is switched off in the library."""
+    streams of their own, capturable as one hipGraph ("graph"), or every
+    array's work in one persistent launch ("persistent")."""
 
     MODES = {"graph": 0, "persistent": 1}
 

@@ -900,11 +900,10 @@ qc_status qc_timing_read(int32_t kernel, double* total_ms, int64_t* launches) {
 // array on a stream of its own between a fork and a join event, so that one
 // captured graph holds every array as an independent branch.  The second
 // (QC_PLAN_PERSISTENT: one persistent launch claiming work items from a
-// queue, with bounded waits between dependent items) is compiled but
-// switched off: it did not complete on gfx950.
+// queue, with bounded waits between dependent items) does every array's
+// work in one launch.
 namespace {
 constexpr int PLAN_SLOTS = 16;  // descriptor slots for executions in flight (+1 for a graph)
-constexpr bool kPersistentPlanEnabled = false;
 
 struct PlanArr {
   bool fused = false;
@@ -1372,10 +1371,6 @@ qc_status qc_plan_set_mode(qc_plan* P, int32_t mode) {
     return QC_OK;
   }
   if (mode != QC_PLAN_PERSISTENT) return fail(QC_EINVAL, "unknown plan mode %d", mode);
-  if (!kPersistentPlanEnabled)
-    return fail(QC_EUNSUPPORTED,
-                "the single persistent launch is switched off: on gfx950 it did not complete "
-                "and the cause is not yet identified");
   if (P->mode != mode) {
     plan_drop_graph(P);
     qc_status st = P->d_ctr ? persist_build(P) : persist_setup(P);
@@ -1472,6 +1467,10 @@ qc_status qc_plan_capture_graph(qc_plan* P, const int8_t* const* x, float* const
 qc_status qc_plan_replay(qc_plan* P, void* stream) {
   g_err.clear();
   if (!P || !P->gexec) return fail(QC_ESTATE, "no captured graph");
+  // created streams only: a multi-branch graph replayed on the legacy default
+  // stream (which synchronises implicitly with every blocking stream) once
+  // left a later device-wide synchronisation waiting
+  if (stream == nullptr) return fail(QC_EINVAL, "graph replay needs a non-default stream");
   QC_HIP(hipGraphLaunch(P->gexec, reinterpret_cast<hipStream_t>(stream)), "hipGraphLaunch");
   return QC_OK;
 }

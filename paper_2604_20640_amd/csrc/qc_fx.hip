@@ -1437,8 +1437,55 @@ __global__ void plan_reset_kernel(unsigned* ctr, int n) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) ctr[i] = 0u;
 }
 
-__device__ __noinline__ void reduce_item(const PlArray* __restrict__ Ap, int64_t index) {
-  const PlArray& A = *Ap;
+// The item functions below are not inlined, so their arguments reach them in
+// vector registers and the compiler takes every value derived from them for
+// a per-lane one: loops whose bounds come from the descriptor would be
+// compiled as lane-divergent loops around the bodies' barriers.  All of them
+// are in fact the same for the whole block; readfirstlane says so, and the
+// loops become scalar.
+__device__ __forceinline__ int32_t uni(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uni(int64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+template <class T>
+__device__ __forceinline__ T* uni(T* p) {
+  return reinterpret_cast<T*>(uni((int64_t)reinterpret_cast<uintptr_t>(p)));
+}
+__device__ __forceinline__ float uni(float v) { return __int_as_float(uni((int32_t)__float_as_int(v))); }
+
+static_assert(sizeof(PlArray) == 128, "load_uniform copies every field of PlArray");
+__device__ __forceinline__ PlArray load_uniform(const PlArray* Ap) {
+  const PlArray* p = uni(Ap);
+  PlArray A;
+  A.x = uni(p->x);
+  A.vis = uni(p->vis);
+  A.part = uni(p->part);
+  A.chan = uni(p->chan);
+  A.taps = uni(p->taps);
+  A.tw = uni(p->tw);
+  A.n_samp = uni(p->n_samp);
+  A.spd = uni(p->spd);
+  A.n_dump = uni(p->n_dump);
+  A.n_split = uni(p->n_split);
+  A.spec_per_item = uni(p->spec_per_item);
+  A.n_ant = uni(p->n_ant);
+  A.n_fft = uni(p->n_fft);
+  A.n_taps = uni(p->n_taps);
+  A.mode = uni(p->mode);
+  A.n_chan_items = uni(p->n_chan_items);
+  A.n_part_items = uni(p->n_part_items);
+  A.n_cgrp = uni(p->n_cgrp);
+  A.n_bp = uni(p->n_bp);
+  A.n_red_blocks = uni(p->n_red_blocks);
+  A.scale = uni(p->scale);
+  return A;
+}
+
+__device__ __noinline__ void reduce_item(const PlArray* __restrict__ Ap, int64_t index_in) {
+  const PlArray A = load_uniform(Ap);
+  const int64_t index = uni(index_in);
   const int64_t nb = (int64_t)A.n_ant * (A.n_ant + 1) / 2;
   const int64_t elems = nb * (A.n_fft / 2);
   const int64_t d = index / A.n_red_blocks, eb = index % A.n_red_blocks;
@@ -1456,8 +1503,10 @@ __device__ __noinline__ void reduce_item(const PlArray* __restrict__ Ap, int64_t
 }
 
 template <int N, int NA>
-__device__ __noinline__ void plan_fused(const PlArray* __restrict__ Ap, int64_t w, float2* buf) {
-  const PlArray& A = *Ap;
+__device__ __noinline__ void plan_fused(const PlArray* __restrict__ Ap, int64_t w_in, float2* buf_in) {
+  const PlArray A = load_uniform(Ap);
+  const int64_t w = uni(w_in);
+  float2* buf = uni(buf_in);
   constexpr int S = 8192 / (((NA + 1) / 2) * N);
   static_assert(FusedCfg<N, NA, S, 16, false, 0>::NT == PL_NT, "plan fused tile");
   if (A.n_taps == 4)
@@ -1469,8 +1518,10 @@ __device__ __noinline__ void plan_fused(const PlArray* __restrict__ Ap, int64_t 
 }
 
 template <int N>
-__device__ __noinline__ void plan_chan(const PlArray* __restrict__ Ap, int64_t index, float2* buf) {
-  const PlArray& A = *Ap;
+__device__ __noinline__ void plan_chan(const PlArray* __restrict__ Ap, int64_t index_in, float2* buf_in) {
+  const PlArray A = load_uniform(Ap);
+  const int64_t index = uni(index_in);
+  float2* buf = uni(buf_in);
   constexpr int S = 8192 / N;
   static_assert(ChanCfg<N, S>::NT == PL_NT, "plan F-engine tile");
   const int n_pair = (A.n_ant + 1) / 2;
@@ -1481,8 +1532,9 @@ __device__ __noinline__ void plan_chan(const PlArray* __restrict__ Ap, int64_t i
                      A.spec_per_item, nullptr, A.chan, bx, p, buf);
 }
 
-__device__ __noinline__ void xeng_item(const PlArray* __restrict__ Ap, int64_t index) {
-  const PlArray& A = *Ap;
+__device__ __noinline__ void xeng_item(const PlArray* __restrict__ Ap, int64_t index_in) {
+  const PlArray A = load_uniform(Ap);
+  const int64_t index = uni(index_in);
   // index -> (run dz, block pair bp, channel group cg)
   const int64_t per_dz = (int64_t)A.n_bp * A.n_cgrp;
   const int64_t dz = index / per_dz;
@@ -1491,32 +1543,56 @@ __device__ __noinline__ void xeng_item(const PlArray* __restrict__ Ap, int64_t i
                        rem % A.n_cgrp, rem / A.n_cgrp, dz, A.part);
 }
 
-// Bounded dependency wait, run by the whole block.  Thread 0 polls the
+// Every branch of the persistent loop below is wave-uniform.  The claim, the
+// polls and the publish are done by all 64 lanes of wave 0, selected by a
+// readfirstlane'd wave index (a scalar branch), never by a `threadIdx.x == 0`
+// test: a lane-divergent branch at the loop's head or latch lets the
+// optimizer thread the two `thread 0` tests into a shortcut for the other
+// lanes, and the structurizer then nests the loop so that lane 0 leaves an
+// inner loop after publishing while its wave's other lanes (and the other
+// waves) go round through the barriers again, read the stale item index and
+// redo the same item for ever.  With only scalar branches every lane of a
+// wave takes the same path, so each wave meets the barriers in program
+// order.
+
+// Value of one lane-0-only atomic add done by the whole wave: lane 0 adds
+// `v`, the other lanes add 0, and lane 0's old value (the count before the
+// add, whatever order the lanes' adds take) is returned to every lane.
+__device__ __forceinline__ unsigned wave_fetch_add(unsigned* p, unsigned v) {
+  const unsigned mine = (threadIdx.x & 63u) == 0u ? v : 0u;
+  return (unsigned)__builtin_amdgcn_readfirstlane((int)atomicAdd(p, mine));
+}
+
+__device__ __forceinline__ unsigned wave_load(const unsigned* p) {
+  return (unsigned)__builtin_amdgcn_readfirstlane(
+      (int)__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+
+// Bounded dependency wait, run by the whole block.  Wave 0 polls the
 // counter with relaxed agent-scope loads (a coherent read, no cache
 // maintenance per poll) until it reaches `target`, the time limit (in ticks
 // of the constant-rate wall clock) passes, or another block has already
 // given up (error flag set).  After the barrier every wave issues one
 // agent-scope acquire fence, so the producers' results are read fresh.
 __device__ __forceinline__ bool plan_wait(const unsigned* ctr, unsigned target, unsigned* err,
-                                          int64_t limit_ticks, int* sflag) {
-  if (threadIdx.x == 0) {
+                                          int64_t limit_ticks, int wave, int* sflag) {
+  if (wave == 0) {
     int ok = 1;
-    if (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    if (wave_load(ctr) < target) {
       const int64_t t0 = wall_clock64();
-      while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-        if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
-            wall_clock64() - t0 > limit_ticks) {
+      while (wave_load(ctr) < target) {
+        if (wave_load(err) != 0u || wall_clock64() - t0 > limit_ticks) {
           ok = 0;
-          atomicOr(err, 1u);
+          (void)wave_fetch_add(err, 1u);
           break;
         }
         __builtin_amdgcn_s_sleep(16);
       }
     }
-    *sflag = ok;
+    *sflag = ok;  // the same value from every lane
   }
   __syncthreads();
-  const bool ok = *sflag != 0;
+  const bool ok = __builtin_amdgcn_readfirstlane(*sflag) != 0;
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   __syncthreads();
   return ok;
@@ -1526,10 +1602,11 @@ __global__ void __launch_bounds__(PL_NT) plan_kernel(PlArgs a) {
   extern __shared__ float2 buf[];
   __shared__ int s_item, s_flag;
   unsigned* err = a.ctr + 1;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   for (;;) {
-    if (threadIdx.x == 0) s_item = (int)atomicAdd(a.ctr, 1u);
+    if (wave == 0) s_item = (int)wave_fetch_add(a.ctr, 1u);
     __syncthreads();
-    const int it = s_item;
+    const int it = __builtin_amdgcn_readfirstlane(s_item);
     __syncthreads();
     if (it >= a.n_items) break;
     const PlItem item = a.items[it];
@@ -1538,9 +1615,11 @@ __global__ void __launch_bounds__(PL_NT) plan_kernel(PlArgs a) {
     unsigned* done_chan = a.ctr + 3 + 2 * item.array;
     bool ok = true;
     if (item.kind == PL_XENG)
-      ok = plan_wait(done_chan, (unsigned)(Ap->n_chan_items + a.wait_bias), err, a.wait_ticks, &s_flag);
+      ok = plan_wait(done_chan, (unsigned)(Ap->n_chan_items + a.wait_bias), err, a.wait_ticks, wave,
+                     &s_flag);
     else if (item.kind == PL_REDUCE)
-      ok = plan_wait(done_part, (unsigned)(Ap->n_part_items + a.wait_bias), err, a.wait_ticks, &s_flag);
+      ok = plan_wait(done_part, (unsigned)(Ap->n_part_items + a.wait_bias), err, a.wait_ticks, wave,
+                     &s_flag);
     if (ok) {
       const int N = Ap->n_fft, NA = Ap->n_ant;
       if (item.kind == PL_FUSED) {
@@ -1573,8 +1652,9 @@ __global__ void __launch_bounds__(PL_NT) plan_kernel(PlArgs a) {
       // release increment counts the item done (skipped items count too)
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       __syncthreads();
-      if (threadIdx.x == 0)
-        __hip_atomic_fetch_add(item.kind == PL_CHAN ? done_chan : done_part, 1u, __ATOMIC_RELEASE,
+      if (wave == 0)
+        __hip_atomic_fetch_add(item.kind == PL_CHAN ? done_chan : done_part,
+                               (threadIdx.x & 63u) == 0u ? 1u : 0u, __ATOMIC_RELEASE,
                                __HIP_MEMORY_SCOPE_AGENT);
     } else {
       __syncthreads();  // LDS and s_item reuse

@@ -1,15 +1,21 @@
 """Batched plans: uneven arrays correlated together, hipGraph replay,
 autotuner, and (persistent mode) the bounded-wait error path.
 
-Parity bar: the plan computes the same float32 sums as qc_xcorrelate, so
-against it max |V - V_ref| / sqrt(V_ii V_jj) <= 1e-6 (only the grouping of
-partial sums may differ), and against the FP64 oracle on sampled channels
-<= 1e-5 like every FP32 path.
+Parity bar: the graph mode runs qc_xcorrelate's own kernels, so against it
+max |V - V_ref| / sqrt(V_ii V_jj) <= 1e-6 (only the grouping of partial
+sums may differ).  The persistent mode runs other float32 kernels (the
+plain F-engine, the non-ring fused body and the vector-ALU X-engine, where
+qc_xcorrelate may take the ring F-engine, the ring fused tile and the
+matrix-core X-engine), so the two round differently; each is held to the
+FP32 bar of 1e-5 against the FP64 oracle, and between them the bar is the
+sum of the two, 2e-5.  A lost or doubled work item would show as an error
+of order 1 / spec_per_dump, far above either bar.
 
 The persistent mode (one launch, work-item queue, waits between dependent
-items) did not complete on the GPU in either of two runs (> 120 s, the
-second with time-bounded waits); its cause is not identified, the library
-rejects the mode, and its cases below are skipped."""
+items) runs every case the graph mode runs.  Its kernel's loop once
+compiled into a lane-divergent nest in which the lanes other than lane 0
+re-ran their first item for ever; tests/test_isa_loops.py checks the built
+code objects for barriers inside lane-divergent loops."""
 
 import ctypes
 
@@ -22,9 +28,12 @@ from tests.util import vis_err
 
 TOL = 1e-5
 
-PERSISTENT_OFF = ("persistent plan mode switched off: its kernel did not complete on gfx950 "
-                  "(two runs, > 120 s); cause not identified")
-MODES = ["graph", pytest.param("persistent", marks=pytest.mark.skip(reason=PERSISTENT_OFF))]
+
+def _cross_bar(mode):
+    """Bar between a plan's result and qc_xcorrelate's (see the module)."""
+    return 1e-6 if mode == "graph" else 2 * TOL
+
+MODES = ["graph", "persistent"]
 
 # (n_ant, n_fft, n_spec, spec_per_dump): fused (4 ant N=1024/4096, 8 ant
 # N=2048) and two-pass (odd and larger antenna counts) arrays, ragged dumps.
@@ -106,7 +115,10 @@ def test_plan_matches_xcorrelate_and_oracle(qc, mode):
     hx, xs = _inputs(arrays)
     plan = qc.Plan(arrays, mode)
     n_launch, conc, tiles, splits = plan.info()
-    assert n_launch >= 2 * len(arrays) and conc in (0, 1) and min(splits) >= 1
+    if mode == "graph":
+        assert n_launch >= 2 * len(arrays) and conc in (0, 1) and min(splits) >= 1
+    else:
+        assert n_launch == 2                      # counter reset + the persistent kernel
     assert [t >= 0 for t in tiles] == [qc.fx_tile_count(a["n_fft"], a["n_ant"]) > 0 for a in arrays]
     vis = plan.empty_vis()
     plan.execute(xs, vis)
@@ -117,7 +129,7 @@ def test_plan_matches_xcorrelate_and_oracle(qc, mode):
         torch.cuda.synchronize()
         got = v.cpu().numpy()
         assert got.shape == ref.shape
-        assert vis_err(got, ref.cpu().numpy(), na) <= 1e-6, i
+        assert vis_err(got, ref.cpu().numpy(), na) <= _cross_bar(mode), i
         ch = _chans(N, i)
         V_ref = xengine.correlate_fast(pfb.channelize(h, N, a["n_taps"], chans=ch), spd)
         assert vis_err(got[:, :, ch], V_ref, na) <= TOL, i
@@ -143,7 +155,7 @@ def test_plan_batch_workload_shapes(qc, mode):
     plan.execute_separate(xs, sep)
     torch.cuda.synchronize()
     for i, a in enumerate(arrays):
-        assert vis_err(vis[i].cpu().numpy(), sep[i].cpu().numpy(), a["n_ant"]) <= 1e-6
+        assert vis_err(vis[i].cpu().numpy(), sep[i].cpu().numpy(), a["n_ant"]) <= _cross_bar(mode), i
     # oracle on one sampled channel set of the largest array
     a, h = arrays[-1], hx[-1]
     ch = _chans(a["n_fft"], 9)
@@ -203,6 +215,7 @@ def test_plan_graph_replays(qc, mode):
 
 @pytest.mark.gpu
 def test_plan_capture_needs_side_stream(qc):
+    import torch
     arrays = [_desc(*SMALL[0])]
     _, xs = _inputs(arrays)
     plan = qc.Plan(arrays)
@@ -210,10 +223,17 @@ def test_plan_capture_needs_side_stream(qc):
         plan.capture_graph(xs, plan.empty_vis())   # the legacy default stream cannot capture
     with pytest.raises(qc.QCError):
         plan.replay()                              # nothing captured
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        plan.capture_graph(xs, plan.empty_vis())
+    with pytest.raises(qc.QCError):
+        plan.replay()                              # replays need a created stream too
+    with torch.cuda.stream(s):
+        plan.replay()
+    s.synchronize()
 
 
 @pytest.mark.gpu
-@pytest.mark.skip(reason=PERSISTENT_OFF)
 def test_plan_wait_timeout_reports_error(qc):
     """Dependencies made unsatisfiable from the host: every bounded wait
     expires, the kernel still drains, check() reports it, and the next
@@ -298,9 +318,21 @@ def test_plan_serial_equals_concurrent(qc):
 
 
 @pytest.mark.gpu
-def test_plan_persistent_mode_rejected(qc):
-    plan = qc.Plan([_desc(*SMALL[0])])
-    with pytest.raises(qc.QCError) as ei:
-        plan.set_mode("persistent")
-    assert ei.value.status == -2                      # QC_EUNSUPPORTED
-    assert plan.info()[0] == 2                        # still the graph mode
+def test_plan_mode_switch(qc):
+    """graph -> persistent -> graph -> persistent on one plan: each mode
+    repeats itself bit for bit, and the two agree to the cross bar."""
+    arrays = [_desc(*s) for s in SMALL[:6]]
+    _, xs = _inputs(arrays, seed=17)
+    plan = qc.Plan(arrays)
+    runs = []
+    for mode in ("graph", "persistent", "graph", "persistent"):
+        plan.set_mode(mode)
+        if mode == "persistent":
+            assert plan.info()[0] == 2
+        v = plan.empty_vis()
+        plan.execute(xs, v)
+        plan.check()
+        runs.append([t.cpu().numpy() for t in v])
+    for i, a in enumerate(arrays):
+        assert np.array_equal(runs[0][i], runs[2][i]) and np.array_equal(runs[1][i], runs[3][i])
+        assert vis_err(runs[1][i], runs[0][i], a["n_ant"]) <= _cross_bar("persistent"), i
