@@ -75,7 +75,7 @@ def fx_flops(n_ant, n_samp, n_fft, n_taps, n_spec_used):
     return f + x
 
 
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "fx_fused_ring_realtime_4ant_n4096.md")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "fx_fused_ring_pp_realtime_4ant_n4096.md")
 # The fused kernels' source: their section of qc_fx.hip and the FFT header.
 FUSED_SECTION = ("paper_2604_20640_amd/csrc/qc_fx.hip", "// ==== fused F+X kernels ====",
                  "// ==== end of fused F+X kernels ====")

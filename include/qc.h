@@ -423,8 +423,17 @@ void qc_plan_destroy(qc_plan* plan);
  *     memory; it must stay unchanged until qc_stream_wait_copied(st, seq) or
  *     qc_stream_sync returns.  seq must increase; a gap (seq != previous + 1)
  *     marks dropped chunks and restarts the filter history from zeros.
- *     vis_out: device cfloat [chunk dumps][n_base][n_chan], written on the
- *     compute stream.  n_dumps_out: host, or NULL.  Asynchronous.
+ *     host_chunk NULL pushes chunk seq as dropped: its samples count as
+ *     zeros, vis_out is zero-filled and the next chunk starts from a zero
+ *     history.  vis_out: device cfloat [chunk dumps][n_base][n_chan],
+ *     written on the compute stream.  n_dumps_out: host, or NULL.
+ *     Asynchronous.
+ *   qc_stream_valid_spectra: host int64 n_valid[n] receives, per dump of the
+ *     last pushed chunk, the spectra whose whole FIR window (their block and
+ *     the P-1 before it) holds received samples: spec_per_dump, less the
+ *     first P-1 spectra after a zero-filled history (stream start, a gap, a
+ *     dropped chunk), and 0 for a dropped chunk.  A weight for averaging
+ *     dumps; the visibilities themselves are not rescaled.
  *   qc_stream_wait_copied: blocks until chunk seq has reached the device.
  *   qc_stream_sync: blocks until all pushed work is done.
  *   qc_stream_compute_stream: the hipStream_t (as void*) results are written on.
@@ -434,6 +443,7 @@ qc_status qc_stream_create(int32_t n_ant, int64_t chunk_samp, const qc_pfb_param
                            int64_t spec_per_dump, int32_t depth, qc_stream** out);
 qc_status qc_stream_push(qc_stream* st, const int8_t* host_chunk, int64_t seq, float* vis_out,
                          int64_t* n_dumps_out);
+qc_status qc_stream_valid_spectra(const qc_stream* st, int64_t* n_valid, int64_t n);
 qc_status qc_stream_wait_copied(qc_stream* st, int64_t seq);
 qc_status qc_stream_sync(qc_stream* st);
 void* qc_stream_compute_stream(qc_stream* st);

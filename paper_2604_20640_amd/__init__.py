@@ -108,6 +108,8 @@ def lib() -> ctypes.CDLL:
         L.qc_stream_create.restype = ctypes.c_int32
         L.qc_stream_push.argtypes = [_P, _P, _I64, _P, ctypes.POINTER(_I64)]
         L.qc_stream_push.restype = ctypes.c_int32
+        L.qc_stream_valid_spectra.argtypes = [_P, ctypes.POINTER(_I64), _I64]
+        L.qc_stream_valid_spectra.restype = ctypes.c_int32
         L.qc_stream_wait_copied.argtypes = [_P, _I64]
         L.qc_stream_wait_copied.restype = ctypes.c_int32
         L.qc_stream_sync.argtypes = [_P]
@@ -222,15 +224,26 @@ class Stream:
         return (self.chunk_samp // self.n_fft) // self.spec_per_dump
 
     def push(self, host_chunk, seq, vis_out):
-        """host_chunk: pinned int8 CPU tensor [n_ant, chunk_samp]; vis_out: device complex64."""
-        assert host_chunk.dtype == torch.int8 and not host_chunk.is_cuda and host_chunk.is_contiguous()
+        """host_chunk: pinned int8 CPU tensor [n_ant, chunk_samp], or None for
+        a dropped chunk (zero-filled); vis_out: device complex64."""
+        if host_chunk is not None:
+            assert host_chunk.dtype == torch.int8 and not host_chunk.is_cuda and host_chunk.is_contiguous()
         assert vis_out.is_cuda and vis_out.dtype == torch.complex64
         nd = _I64(0)
-        st = lib().qc_stream_push(self._h, ctypes.c_void_p(host_chunk.data_ptr()), seq,
-                                  ctypes.c_void_p(vis_out.data_ptr()), ctypes.byref(nd))
+        ptr = None if host_chunk is None else ctypes.c_void_p(host_chunk.data_ptr())
+        st = lib().qc_stream_push(self._h, ptr, seq, ctypes.c_void_p(vis_out.data_ptr()), ctypes.byref(nd))
         if st != 0:
             raise QCError(st, "qc_stream_push", lib().qc_stream_last_error().decode())
         return nd.value
+
+    def valid_spectra(self):
+        """Valid spectra per dump of the last pushed chunk (a list of ints)."""
+        n = self.n_dump_per_chunk
+        out = (_I64 * max(n, 1))()
+        st = lib().qc_stream_valid_spectra(self._h, out, n)
+        if st != 0:
+            raise QCError(st, "qc_stream_valid_spectra", lib().qc_stream_last_error().decode())
+        return list(out)[:n]
 
     def wait_copied(self, seq):
         st = lib().qc_stream_wait_copied(self._h, seq)

@@ -32,6 +32,10 @@ struct qc_stream {
   int64_t pushed = 0;
   int64_t last_seq = -1;
   std::vector<int64_t> slot_seq;
+  // the next chunk's filter history is zero-filled (stream start, a gap in
+  // the sequence, or a dropped chunk before it)
+  bool fresh = true;
+  std::vector<int64_t> valid;  // valid spectra per dump of the last chunk
 };
 
 namespace {
@@ -59,6 +63,43 @@ void release(qc_stream* st) {
   if (st->copy) (void)hipStreamDestroy(st->copy);
   if (st->compute) (void)hipStreamDestroy(st->compute);
   delete st;
+}
+}  // namespace
+
+namespace {
+// Valid spectra per dump: a spectrum counts when its whole FIR window (its
+// block and the P-1 before it) holds received samples.  After a zero-filled
+// history the chunk's first P-1 spectra do not.
+void count_valid(qc_stream* st, bool fresh, bool dropped) {
+  const int64_t spd = st->spec_per_dump;
+  const int64_t n_dump = (st->chunk_samp / st->pfb.n_fft) / spd;
+  st->valid.assign((size_t)n_dump, dropped ? 0 : spd);
+  if (dropped || !fresh) return;
+  int64_t bad = st->pfb.n_taps - 1;
+  for (int64_t d = 0; d < n_dump && bad > 0; ++d) {
+    const int64_t k = bad < spd ? bad : spd;
+    st->valid[(size_t)d] -= k;
+    bad -= k;
+  }
+}
+
+// A dropped chunk: its samples count as zeros.  Its dumps are written as
+// zero visibilities with no valid spectrum, and the history the next chunk
+// starts from is zeros.
+qc_status push_dropped(qc_stream* st, int64_t seq, float* vis_out, int64_t* n_dumps_out) {
+  const int64_t N = st->pfb.n_fft, spd = st->spec_per_dump;
+  const int64_t n_dump = (st->chunk_samp / N) / spd;
+  const size_t vbytes = sizeof(float) * 2 * (size_t)n_dump * ((size_t)st->n_ant * (st->n_ant + 1) / 2) *
+                        (size_t)(N / 2);
+  const size_t hbytes = (size_t)st->n_ant * (size_t)(st->pfb.n_taps - 1) * N;
+  hipError_t e = hipMemsetAsync(vis_out, 0, vbytes, st->compute);
+  if (e == hipSuccess && hbytes) e = hipMemsetAsync(st->hist[st->cur], 0, hbytes, st->compute);
+  if (e != hipSuccess) return sfail(QC_EHIP, "zero fill", e);
+  count_valid(st, true, true);
+  if (n_dumps_out) *n_dumps_out = n_dump;
+  st->fresh = true;
+  st->last_seq = seq;
+  return QC_OK;
 }
 }  // namespace
 
@@ -125,14 +166,17 @@ qc_status qc_stream_create(int32_t n_ant, int64_t chunk_samp, const qc_pfb_param
   return QC_OK;
 }
 
+
 qc_status qc_stream_push(qc_stream* st, const int8_t* host_chunk, int64_t seq, float* vis_out,
                          int64_t* n_dumps_out) {
   g_serr.clear();
-  if (!st || !host_chunk || !vis_out) return sfail(QC_EINVAL, "NULL argument");
+  if (!st || !vis_out) return sfail(QC_EINVAL, "NULL argument");
   if (seq <= st->last_seq) return sfail(QC_ESTATE, "sequence numbers must increase");
+  if (!host_chunk) return push_dropped(st, seq, vis_out, n_dumps_out);
   const int s = (int)(st->pushed % st->depth);
   const size_t bytes = (size_t)st->n_ant * (size_t)st->chunk_samp;
   const size_t hbytes = (size_t)st->n_ant * (size_t)(st->pfb.n_taps - 1) * st->pfb.n_fft;
+  const bool gap = st->last_seq >= 0 && seq != st->last_seq + 1;
   hipError_t e;
   // the copy into slot s may start once the compute that last read it is done
   if (st->slot_seq[s] >= 0) {
@@ -147,7 +191,7 @@ qc_status qc_stream_push(qc_stream* st, const int8_t* host_chunk, int64_t seq, f
   if (e != hipSuccess) return sfail(QC_EHIP, "wait", e);
   // a gap in the sequence: the samples before this chunk are unknown, so the
   // filter history restarts from zero (as at the start of a stream)
-  if (st->last_seq >= 0 && seq != st->last_seq + 1 && hbytes) {
+  if (gap && hbytes) {
     e = hipMemsetAsync(st->hist[st->cur], 0, hbytes, st->compute);
     if (e != hipSuccess) return sfail(QC_EHIP, "history reset", e);
   }
@@ -158,10 +202,20 @@ qc_status qc_stream_push(qc_stream* st, const int8_t* host_chunk, int64_t seq, f
   if (q != QC_OK) return sfail(q, qc_last_error());
   e = hipEventRecord(st->computed[s], st->compute);
   if (e != hipSuccess) return sfail(QC_EHIP, "event", e);
+  count_valid(st, st->fresh || gap, false);
+  st->fresh = false;
   st->cur = nxt;
   st->slot_seq[s] = seq;
   st->last_seq = seq;
   ++st->pushed;
+  return QC_OK;
+}
+
+qc_status qc_stream_valid_spectra(const qc_stream* st, int64_t* n_valid, int64_t n) {
+  g_serr.clear();
+  if (!st || !n_valid || n < 0) return sfail(QC_EINVAL, "NULL argument or negative count");
+  if (st->last_seq < 0) return sfail(QC_ESTATE, "no chunk pushed yet");
+  for (int64_t d = 0; d < n && d < (int64_t)st->valid.size(); ++d) n_valid[d] = st->valid[(size_t)d];
   return QC_OK;
 }
 
