@@ -11,7 +11,9 @@
 // the wanted rank contains at most SEL_CAND keys, one pass gathers them and
 // one wave ranks them.  Even counts average the two middle order
 // statistics; the upper one is read off the same candidates when it lies
-// among them (else one counting pass finds it).  One workgroup handles one
+// among them (else one counting pass finds it).  Once the digit holding the
+// wanted rank has few enough keys for the LDS left over, their values are
+// compacted into LDS and the remaining passes scan only them.  One workgroup handles one
 // population (1024 threads and 11-bit digits for large populations, one
 // wave and 8-bit digits for small ones); large populations get their
 // amplitudes formed once by a whole-GPU pass and cached in LDS when they
@@ -143,17 +145,34 @@ struct SelScratch {
   unsigned long long* red;   // 2 * NT / 64
   unsigned long long* cand;  // SEL_CAND
   unsigned* ncand;           // 1
+  float* comp;               // compacted values still in play (LDS), comp_cap of them
+  int64_t comp_cap;          // 0: no compaction
 };
 
+// Appends v to sc.comp where hit, one LDS atomic per wave: the lanes that
+// hit take consecutive slots after the count so far.
+__device__ __forceinline__ void append_wave(const SelScratch& sc, bool hit, float v) {
+  const unsigned long long bal = __ballot(hit);
+  if (bal == 0ull) return;
+  const int lane = (int)(threadIdx.x & 63u);
+  const int leader = __ffsll((long long)bal) - 1;
+  unsigned base = 0u;
+  if (lane == leader) base = atomicAdd(sc.ncand, (unsigned)__popcll(bal));
+  base = __shfl(base, leader);
+  if (hit) sc.comp[base + (unsigned)__popcll(bal & ((1ull << lane) - 1ull))] = v;
+}
+
 // k-th smallest (0-based) key of the population, most significant digit
-// first, for keys known to lie in [kmin, kmax].  KEY(i) returns the unsigned
-// key of element i.  Bits that every key in the range shares need no pass.
-// When the digit that holds rank k contains at most SEL_CAND keys, one pass
+// first, for keys known to lie in [kmin, kmax].  Element i has the value
+// VAL(i) and the unsigned key KEYOF(value).  Bits that every key in the
+// range shares need no pass.  Once the digit that holds rank k has at most
+// comp_cap keys, one pass copies their values into sc.comp and every later
+// pass scans only those.  When it has at most SEL_CAND keys, one pass
 // gathers them and one wave ranks them.  With want2, the key of rank k+1 is
 // also returned (has2) when it lies among the same candidates.
-template <int NT, int DB, typename K, typename KeyFn>
-__device__ K radix_select(int64_t count, int64_t k, K kmin, K kmax, KeyFn key, const SelScratch& sc,
-                          bool want2, K& v2, bool& has2) {
+template <int NT, int DB, typename K, typename ValFn, typename KeyOf>
+__device__ K radix_select(int64_t count, int64_t k, K kmin, K kmax, ValFn val, KeyOf keyof,
+                          const SelScratch& sc, bool want2, K& v2, bool& has2) {
   constexpr int W = (int)sizeof(K) * 8;
   constexpr int NBINS = 1 << DB;
   has2 = false;
@@ -168,13 +187,17 @@ __device__ K radix_select(int64_t count, int64_t k, K kmin, K kmax, KeyFn key, c
   const K low = (top + 1 >= W) ? ~(K)0 : (((K)1 << (top + 1)) - 1);
   K prefix = kmin & ~low, mask = ~low;
   int64_t kk = k;
+  // keys scanned per pass: the whole population, or its compacted part
+  bool compact = false;
+  int64_t n_in = count;
+  auto key = [&](int64_t i) -> K { return compact ? keyof(sc.comp[i]) : keyof(val(i)); };
   for (int hi = top + 1; hi > 0; hi -= DB) {
     const int width = hi >= DB ? DB : hi;
     const int shift = hi - width;
     const K dmask = (K)((1u << width) - 1u);
     for (int i = threadIdx.x; i < NBINS; i += NT) sc.hist[i] = 0;
     __syncthreads();
-    for_keys<NT, K>(count, key, [&](int64_t, K kv) {
+    for_keys<NT, K>(n_in, key, [&](int64_t, K kv) {
       if ((kv & mask) == prefix) atomicAdd(&sc.hist[(unsigned)((kv >> shift) & dmask)], 1u);
     });
     __syncthreads();
@@ -213,7 +236,7 @@ __device__ K radix_select(int64_t count, int64_t k, K kmin, K kmax, KeyFn key, c
       }
       if (threadIdx.x == 0) *sc.ncand = 0;
       __syncthreads();
-      for_keys<NT, K>(count, key, [&](int64_t, K kv) {
+      for_keys<NT, K>(n_in, key, [&](int64_t, K kv) {
         const K km = kv & mask;
         if (km == prefix || (c2 > 0 && km == prefix2))
           sc.cand[atomicAdd(sc.ncand, 1u)] = (unsigned long long)kv;
@@ -241,6 +264,18 @@ __device__ K radix_select(int64_t count, int64_t k, K kmin, K kmax, KeyFn key, c
       }
       __syncthreads();
       return v1;
+    }
+    if (!compact && c <= sc.comp_cap) {
+      // the c keys sharing the prefix: their values into sc.comp (in any
+      // order; only counts and values matter from here on)
+      if (threadIdx.x == 0) *sc.ncand = 0;
+      __syncthreads();
+      for_keys<NT, float>(n_in, val, [&](int64_t, float v) {
+        append_wave(sc, (keyof(v) & mask) == prefix, v);
+      });
+      __syncthreads();
+      compact = true;
+      n_in = c;
     }
   }
   return prefix;  // not reached: the last pass has shift == 0
@@ -345,20 +380,20 @@ __global__ void mad_amp4_kernel(const float4* __restrict__ vis, int64_t n_base, 
 template <int NT, int DB>
 __global__ void __launch_bounds__(NT)
 mad_kernel(const float2* __restrict__ vis, int64_t n_time, int64_t n_base, int n_chan, float sigma,
-           int population, int64_t cap, const float* __restrict__ gamp, uint8_t* __restrict__ mask,
-           double* __restrict__ thresh, double* __restrict__ stats) {
+           int population, int64_t cap, int64_t comp_cap, const float* __restrict__ gamp,
+           uint8_t* __restrict__ mask, double* __restrict__ thresh, double* __restrict__ stats) {
   __shared__ unsigned hist[1 << DB];
   __shared__ unsigned wsum[NT / 64];
   __shared__ unsigned long long sh[4];
   __shared__ unsigned long long red[2 * (NT / 64)];
   __shared__ unsigned long long cand[SEL_CAND];
   __shared__ unsigned ncand;
-  extern __shared__ float acache[];
-  const SelScratch sc{hist, wsum, sh, red, cand, &ncand};
+  extern __shared__ float acache[];  // [cap] amplitude cache, then [comp_cap] compaction buffer
   const int64_t id = blockIdx.x;
   const Pop pop = make_pop(id, n_time, n_base, n_chan, population);
   const int64_t n = pop.count;
   const bool cached = n <= cap;
+  const SelScratch sc{hist, wsum, sh, red, cand, &ncand, acache + (cached ? n : 0), comp_cap};
   const AmpSrc amp{vis, pop, cached ? acache : (gamp ? gamp + id * n : nullptr)};
   // one pass: the amplitudes into the LDS cache (when they fit) and the
   // range of their keys
@@ -415,22 +450,24 @@ mad_kernel(const float2* __restrict__ vis, int64_t n_time, int64_t n_base, int n
   }
   __syncthreads();
   const int64_t k1 = (n - 1) / 2, k2 = n / 2;
-  auto akey = [&](int64_t i) -> uint32_t { return __float_as_uint(amp(i)); };
+  auto akeyof = [](float a) -> uint32_t { return __float_as_uint(a); };
+  auto akey = [&](int64_t i) -> uint32_t { return akeyof(amp(i)); };
   uint32_t a2;
   bool has2;
-  const uint32_t a1 = radix_select<NT, DB, uint32_t>(n, k1, amin, amax, akey, sc, k2 != k1, a2, has2);
+  const uint32_t a1 =
+      radix_select<NT, DB, uint32_t>(n, k1, amin, amax, amp, akeyof, sc, k2 != k1, a2, has2);
   if (k2 == k1) a2 = a1;
   else if (!has2) a2 = next_rank<NT, uint32_t>(n, k1, a1, akey, red);
   const double med = ((double)__uint_as_float(a1) + (double)__uint_as_float(a2)) / 2.0;
-  auto dkey = [&](int64_t i) -> uint64_t {
-    return (uint64_t)__double_as_longlong(fabs((double)amp(i) - med));
-  };
+  auto dkeyof = [&](float a) -> uint64_t { return (uint64_t)__double_as_longlong(fabs((double)a - med)); };
+  auto dkey = [&](int64_t i) -> uint64_t { return dkeyof(amp(i)); };
   // deviations lie in [0, the larger deviation of the two extreme amplitudes]
   const double dlo = fabs((double)__uint_as_float(amin) - med);
   const double dhi = fabs((double)__uint_as_float(amax) - med);
   const uint64_t dmax = (uint64_t)__double_as_longlong(dlo > dhi ? dlo : dhi);
   uint64_t d2;
-  const uint64_t d1 = radix_select<NT, DB, uint64_t>(n, k1, 0ull, dmax, dkey, sc, k2 != k1, d2, has2);
+  const uint64_t d1 =
+      radix_select<NT, DB, uint64_t>(n, k1, 0ull, dmax, amp, dkeyof, sc, k2 != k1, d2, has2);
   if (k2 == k1) d2 = d1;
   else if (!has2) d2 = next_rank<NT, uint64_t>(n, k1, d1, dkey, red);
   const double madv =
@@ -466,6 +503,8 @@ mad_kernel(const float2* __restrict__ vis, int64_t n_time, int64_t n_base, int n
 
 constexpr int64_t MAD_CAP_BIG = 36864;   // floats cached in LDS (144 KiB)
 constexpr int64_t MAD_CAP_SMALL = 2048;
+constexpr int64_t MAD_LDS_FLOATS = 38400;  // dynamic LDS of the 1024-thread kernel: cache + compaction
+constexpr int64_t MAD_COMP_MAX = 32768;
 
 int64_t mad_scratch_floats(int64_t n_time, int64_t n_base, int n_chan, int population) {
   const int64_t npop = population == 0 ? n_base : population == 1 ? n_base * n_chan : n_time * n_base;
@@ -482,7 +521,8 @@ hipError_t launch_mad(const float2* vis, int64_t n_time, int64_t n_base, int n_c
   if (count <= MAD_CAP_SMALL) {
     const size_t lds = (size_t)count * sizeof(float);
     hipLaunchKernelGGL((mad_kernel<64, 8>), dim3((unsigned)npop), dim3(64), lds, s, vis, n_time,
-                       n_base, n_chan, sigma, population, MAD_CAP_SMALL, nullptr, mask, thresh, stats);
+                       n_base, n_chan, sigma, population, MAD_CAP_SMALL, (int64_t)0, nullptr, mask, thresh,
+                       stats);
   } else {
     const int64_t cap = count <= MAD_CAP_BIG ? count : 0;
     const float* gamp = nullptr;
@@ -506,12 +546,16 @@ hipError_t launch_mad(const float2* vis, int64_t n_time, int64_t n_base, int n_c
       if (e != hipSuccess) return e;
       gamp = amp_scratch;
     }
-    const size_t lds = (size_t)cap * sizeof(float);
+    // what LDS the cache leaves holds the compaction buffer
+    int64_t comp_cap = MAD_LDS_FLOATS - cap;
+    comp_cap = comp_cap < MAD_COMP_MAX ? comp_cap : MAD_COMP_MAX;
+    if (comp_cap < 256) comp_cap = 0;
+    const size_t lds = (size_t)(cap + comp_cap) * sizeof(float);
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(mad_kernel<1024, 11>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((mad_kernel<1024, 11>), dim3((unsigned)npop), dim3(1024), lds, s, vis, n_time,
-                       n_base, n_chan, sigma, population, cap, gamp, mask, thresh, stats);
+                       n_base, n_chan, sigma, population, cap, comp_cap, gamp, mask, thresh, stats);
   }
   return hipGetLastError();
 }
