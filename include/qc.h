@@ -349,8 +349,10 @@ qc_status qc_solve_delay_phase(const float* vis, const uint8_t* mask, int64_t n_
  *     stream, so a captured graph holds the arrays as independent branches.
  *   QC_PLAN_PERSISTENT: every array's work in one persistent launch (256
  *     workgroups of 512 threads) that claims work items from one ordered
- *     queue: fused F+X items, F-engine items, FP32 X-engine items and
- *     reductions.  An item that needs others (X-engine after its array's
+ *     queue: fused F+X items (2, 4 or 8 antennas at their fused sizes),
+ *     F-engine items (the ring F-engine at n_fft 4096 / 8192 with 4 taps,
+ *     else the plain one), FP32 X-engine items (matrix cores for 5..32
+ *     antennas, else the vector ALU) and reductions.  An item that needs others (X-engine after its array's
  *     F-engine, reduction after its partials) waits for their done counter,
  *     bounded in time (qc_plan_set_wait_timeout); on expiry the item is
  *     skipped, an error flag is set that qc_plan_check reports, and every

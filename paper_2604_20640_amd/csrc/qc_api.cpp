@@ -932,7 +932,7 @@ struct qc_plan {
   std::vector<void*> gbufs;
   // persistent mode
   qc::PlArray arr[qc::PL_MAX_ARRAYS];
-  int64_t fused_items = 512;  // target fused items per array
+  int64_t fused_items = 128;  // target fused items per array (each at least 32 spectra)
   int64_t chan_mult = 4;      // F-engine item = spectra-in-flight * chan_mult spectra
   int64_t x_split = 2;        // X-engine k-split
   int grid = 256;             // persistent blocks
@@ -1001,34 +1001,61 @@ qc_status persist_build(qc_plan* P) {
     if (qc::plan_fused_supported(N, NA)) {
       A.mode = 0;
       const int S = 8192 / (((NA + 1) / 2) * N);
+      // items of at least 32 spectra: each writes a whole partial tile
+      // (baselines x channels), which must stay small beside its input
       int64_t cpd = (P->fused_items + A.n_dump - 1) / A.n_dump;
-      cpd = std::max<int64_t>(1, std::min<int64_t>(cpd, A.spd / S > 0 ? A.spd / S : 1));
+      const int64_t per = std::max<int64_t>(S, 32);
+      cpd = std::max<int64_t>(1, std::min<int64_t>(cpd, A.spd / per > 0 ? A.spd / per : 1));
       A.n_split = cpd;
       A.n_part_items = (int32_t)(A.n_dump * cpd);
       A.scale = 0.25f;
       for (int64_t w = 0; w < A.n_dump * cpd; ++w) first.push_back({qc::PL_FUSED, (uint16_t)i, (uint32_t)w});
     } else {
       A.mode = 1;
-      const int S = 8192 / N;
       const int64_t ns = A.n_dump * A.spd;
-      A.spec_per_item = std::min<int64_t>(ns, (int64_t)S * P->chan_mult);
-      const int64_t nbx = (ns + A.spec_per_item - 1) / A.spec_per_item;
-      const int n_pair = (NA + 1) / 2;
-      A.n_chan_items = (int32_t)(nbx * n_pair);
-      const int64_t ks = std::max<int64_t>(1, std::min<int64_t>(P->x_split, A.spd / 16 > 0 ? A.spd / 16 : 1));
-      A.n_split = ks;
-      A.n_cgrp = (NCH + qc::PL_NT - 1) / qc::PL_NT;
-      const int nblk = (NA + 3) / 4;
-      A.n_bp = nblk * (nblk + 1) / 2;
-      A.n_part_items = (int32_t)(A.n_dump * ks * A.n_bp * A.n_cgrp);
+      // F-engine items: the ring body (groups of 4 antennas at N = 4096, 2
+      // at 8192, the built-in P = 4 prototype) or the plain body
+      const bool ring = (N == 4096 || N == 8192) && D.n_taps == 4;
+      if (ring) {
+        const int na_g = N == 8192 ? 2 : 4;
+        const int64_t groups = (NA + na_g - 1) / na_g;
+        int64_t spb = (ns * groups + 511) / 512;  // about 512 items, runs of >= 16 spectra
+        spb = std::max<int64_t>(16, spb);
+        A.spb = spb;
+        A.n_chunks = (int32_t)((ns + spb - 1) / spb);
+        A.n_chan_items = (int32_t)(groups * A.n_chunks);
+      } else {
+        const int S = 8192 / N;
+        A.spec_per_item = std::min<int64_t>(ns, (int64_t)S * P->chan_mult);
+        const int64_t nbx = (ns + A.spec_per_item - 1) / A.spec_per_item;
+        A.n_chan_items = (int32_t)(nbx * ((NA + 1) / 2));
+      }
+      // X-engine items: matrix cores for 5..32 antennas (16 x 16 tiles up to
+      // 16), the vector ALU otherwise
+      if (NA >= 5 && NA <= 32 && NCH % 16 == 0) {
+        A.x_kind = NA <= 16 ? 2 : 1;
+        A.n_cb = NCH / 16;
+        A.tile = 16;
+        A.n_split = std::max<int64_t>(1, qc::xeng_f32_mfma_ksplit(NA, A.spd, NCH, A.n_dump));
+        A.n_part_items = (int32_t)(A.n_dump * A.n_split * A.n_cb);
+      } else {
+        const int64_t ks = std::max<int64_t>(1, std::min<int64_t>(P->x_split, A.spd / 16 > 0 ? A.spd / 16 : 1));
+        A.n_split = ks;
+        A.n_cgrp = (NCH + qc::PL_NT - 1) / qc::PL_NT;
+        const int nblk = (NA + 3) / 4;
+        A.n_bp = nblk * (nblk + 1) / 2;
+        A.n_part_items = (int32_t)(A.n_dump * ks * A.n_bp * A.n_cgrp);
+      }
       A.scale = 1.0f;
       void* chan = nullptr;
       hipError_t e = hipMalloc(&chan, sizeof(float2) * (size_t)NA * ns * NCH);
       if (e != hipSuccess) return fail(QC_ENOMEM, "plan spectra buffer: %s", hipGetErrorString(e));
       P->bufs.push_back(chan);
       A.chan = (float2*)chan;
-      for (int64_t q = 0; q < A.n_chan_items; ++q) first.push_back({qc::PL_CHAN, (uint16_t)i, (uint32_t)q});
-      for (int64_t q = 0; q < A.n_part_items; ++q) xeng.push_back({qc::PL_XENG, (uint16_t)i, (uint32_t)q});
+      const uint16_t fk = A.n_chunks > 0 ? qc::PL_CHAN_RING : qc::PL_CHAN;
+      const uint16_t xk = A.x_kind > 0 ? qc::PL_XMFMA : qc::PL_XENG;
+      for (int64_t q = 0; q < A.n_chan_items; ++q) first.push_back({fk, (uint16_t)i, (uint32_t)q});
+      for (int64_t q = 0; q < A.n_part_items; ++q) xeng.push_back({xk, (uint16_t)i, (uint32_t)q});
     }
     hipError_t e = hipMalloc(&part, sizeof(float2) * (size_t)A.n_dump * A.n_split * elems);
     if (e != hipSuccess) return fail(QC_ENOMEM, "plan partial buffer: %s", hipGetErrorString(e));
@@ -1052,9 +1079,11 @@ qc_status persist_build(qc_plan* P) {
       const qc::PlItem& it = P->items[q];
       if (it.array != i) continue;
       const int64_t pos = (int64_t)q;
-      if (it.kind == qc::PL_CHAN) { ++n_chan; last_chan = pos; }
-      if (it.kind == qc::PL_FUSED || it.kind == qc::PL_XENG) { ++n_part; last_part = pos; }
-      if (it.kind == qc::PL_XENG) first_x = std::min(first_x, pos);
+      const bool chan = it.kind == qc::PL_CHAN || it.kind == qc::PL_CHAN_RING;
+      const bool xk = it.kind == qc::PL_XENG || it.kind == qc::PL_XMFMA;
+      if (chan) { ++n_chan; last_chan = pos; }
+      if (it.kind == qc::PL_FUSED || xk) { ++n_part; last_part = pos; }
+      if (xk) first_x = std::min(first_x, pos);
       if (it.kind == qc::PL_REDUCE) first_red = std::min(first_red, pos);
     }
     const qc::PlArray& A = P->arr[i];

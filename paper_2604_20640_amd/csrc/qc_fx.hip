@@ -21,6 +21,7 @@
 
 #include "qc_fft.h"
 #include "qc_kernels.h"
+#include "qc_xmfma_body.h"
 
 namespace qc {
 
@@ -974,23 +975,24 @@ struct ChanRingCfg {
   static constexpr size_t LDS_BYTES = sizeof(float2) * (C::LDS + N);  // transforms, twiddles
 };
 
+// Body of the ring F-engine for antenna group grp and run chk of spb
+// spectra, by all threads of a block, on an LDS region of
+// ChanRingCfg<N, NA, V, P>::LDS_BYTES.
 template <int N, int NA, int V, int P, int PREC>
-__global__ void __launch_bounds__((FusedCfg<N, NA, 1, V, false, 0>::NT))
-chan_ring_kernel(const int8_t* __restrict__ x, int64_t ld_x, int n_ant, const int8_t* __restrict__ hist,
-                 const float* __restrict__ taps, const float2* __restrict__ tw, int64_t n_spec,
-                 int64_t spb, int64_t chunks, const float* __restrict__ scale, void* __restrict__ out) {
+__device__ __forceinline__ void chan_ring_body(const int8_t* __restrict__ x, int64_t ld_x, int n_ant,
+                                               const int8_t* __restrict__ hist, const float* __restrict__ taps,
+                                               const float2* __restrict__ tw, int64_t n_spec, int64_t spb,
+                                               int grp, int64_t chk, const float* __restrict__ scale,
+                                               void* __restrict__ out, float2* buf) {
   using C = FusedCfg<N, NA, 1, V, false, 0>;
   using F = Fft<N, C::NT, V, false, false, true>;
   constexpr int G = C::CHUNKS;
   constexpr int L = P * N;
   constexpr int NCH = N / 2;
-  extern __shared__ float2 buf[];
   float2* b0 = buf;
   float2* twl = buf + C::LDS;
   float4* tl = reinterpret_cast<float4*>(b0);  // taps, until they are in registers
   const int tid = threadIdx.x;
-  const int grp = (int)(blockIdx.x / chunks);
-  const int64_t chk = blockIdx.x % chunks;
   const int a_base = NA * grp;
   const int64_t m_lo = chk * spb;
   const int64_t m_hi = m_lo + spb < n_spec ? m_lo + spb : n_spec;
@@ -1113,6 +1115,16 @@ chan_ring_kernel(const int8_t* __restrict__ x, int64_t ld_x, int n_ant, const in
       ring[P - 1][g][1] = nxt[g][1];
     }
   }
+}
+
+template <int N, int NA, int V, int P, int PREC>
+__global__ void __launch_bounds__((FusedCfg<N, NA, 1, V, false, 0>::NT))
+chan_ring_kernel(const int8_t* __restrict__ x, int64_t ld_x, int n_ant, const int8_t* __restrict__ hist,
+                 const float* __restrict__ taps, const float2* __restrict__ tw, int64_t n_spec,
+                 int64_t spb, int64_t chunks, const float* __restrict__ scale, void* __restrict__ out) {
+  extern __shared__ float2 buf[];
+  chan_ring_body<N, NA, V, P, PREC>(x, ld_x, n_ant, hist, taps, tw, n_spec, spb, (int)(blockIdx.x / chunks),
+                                    (int64_t)(blockIdx.x % chunks), scale, out, buf);
 }
 
 template <int N, int NA, int PREC>
@@ -1426,12 +1438,23 @@ hipError_t launch_xeng_f32(const float2* v, int n_ant, int64_t n_spec, int n_cha
 // skipped and still counted, and every later wait gives up at once, so
 // every block reaches the queue's end and exits.
 // ---------------------------------------------------------------------------
+// Fused items for 4 antennas.  At 8 antennas the fused body's accumulators
+// (36 baselines per channel) do not fit the 248 registers an item function
+// gets inside the persistent kernel and spill; those arrays take the
+// two-pass items (F-engine, then the matrix-core X-engine).
 bool plan_fused_supported(int n_fft, int n_ant) {
-  return (n_ant == 4 && (n_fft == 1024 || n_fft == 2048 || n_fft == 4096)) ||
-         (n_ant == 8 && (n_fft == 1024 || n_fft == 2048));
+  return n_ant == 4 && (n_fft == 1024 || n_fft == 2048 || n_fft == 4096);
 }
 
 bool plan_chan_supported(int n_fft) { return n_fft >= 16 && n_fft <= 8192; }
+
+// LDS frame of the persistent kernel: its largest item body, the
+// matrix-core X-engine's two stages (or the ring F-engine at N = 8192:
+// transform buffer and twiddles); the plain bodies' buffer fits inside.
+constexpr size_t PLAN_LDS = ChanRingCfg<8192, 2, 16, 4>::LDS_BYTES > (size_t)(2 * XM_STAGE)
+                                ? ChanRingCfg<8192, 2, 16, 4>::LDS_BYTES
+                                : (size_t)(2 * XM_STAGE);
+static_assert(PLAN_LDS >= sizeof(float2) * lds_padded_size(8192), "plain bodies' buffer");
 
 __global__ void plan_reset_kernel(unsigned* ctr, int n) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) ctr[i] = 0u;
@@ -1455,7 +1478,7 @@ __device__ __forceinline__ T* uni(T* p) {
 }
 __device__ __forceinline__ float uni(float v) { return __int_as_float(uni((int32_t)__float_as_int(v))); }
 
-static_assert(sizeof(PlArray) == 128, "load_uniform copies every field of PlArray");
+static_assert(sizeof(PlArray) == 160, "load_uniform copies every field of PlArray");
 __device__ __forceinline__ PlArray load_uniform(const PlArray* Ap) {
   const PlArray* p = uni(Ap);
   PlArray A;
@@ -1480,6 +1503,12 @@ __device__ __forceinline__ PlArray load_uniform(const PlArray* Ap) {
   A.n_bp = uni(p->n_bp);
   A.n_red_blocks = uni(p->n_red_blocks);
   A.scale = uni(p->scale);
+  A.spb = uni(p->spb);
+  A.n_chunks = uni(p->n_chunks);
+  A.x_kind = uni(p->x_kind);
+  A.n_cb = uni(p->n_cb);
+  A.tile = uni(p->tile);
+  A.pad0 = A.pad1 = 0;
   return A;
 }
 
@@ -1498,7 +1527,13 @@ __device__ __noinline__ void reduce_item(const PlArray* __restrict__ Ap, int64_t
       acc.x += v.x;
       acc.y += v.y;
     }
-    A.vis[d * elems + e] = make_float2(acc.x * A.scale, acc.y * A.scale);
+    int64_t oe = e;
+    if (A.tile > 0) {  // tile-major partials of the matrix-core X-engine
+      const int64_t t = e / A.tile, col = e - t * A.tile;
+      const int64_t cb = t / nb, b = t - cb * nb;
+      oe = b * (A.n_fft / 2) + cb * A.tile + col;
+    }
+    A.vis[d * elems + oe] = make_float2(acc.x * A.scale, acc.y * A.scale);
   }
 }
 
@@ -1541,6 +1576,32 @@ __device__ __noinline__ void xeng_item(const PlArray* __restrict__ Ap, int64_t i
   const int rem = (int)(index % per_dz);
   xeng_f32_body<PL_NT>(A.chan, A.n_ant, A.n_dump * A.spd, A.n_fft / 2, A.spd, A.n_split,
                        rem % A.n_cgrp, rem / A.n_cgrp, dz, A.part);
+}
+
+template <int N, int NA>
+__device__ __noinline__ void plan_chan_ring(const PlArray* __restrict__ Ap, int64_t index_in, float2* buf_in) {
+  const PlArray A = load_uniform(Ap);
+  const int64_t index = uni(index_in);
+  float2* buf = uni(buf_in);
+  static_assert(FusedCfg<N, NA, 1, 16, false, 0>::NT == PL_NT, "plan ring F-engine tile");
+  static_assert(ChanRingCfg<N, NA, 16, 4>::LDS_BYTES <= PLAN_LDS, "plan ring F-engine LDS");
+  chan_ring_body<N, NA, 16, 4, 0>(A.x, A.n_samp, A.n_ant, nullptr, A.taps, A.tw, A.n_dump * A.spd, A.spb,
+                                  (int)(index / A.n_chunks), index % A.n_chunks, nullptr, A.chan, buf);
+}
+
+__device__ __noinline__ void plan_xmfma(const PlArray* __restrict__ Ap, int64_t index_in, float2* buf_in) {
+  const PlArray A = load_uniform(Ap);
+  const int64_t index = uni(index_in);
+  uint8_t* st0 = reinterpret_cast<uint8_t*>(uni(buf_in));
+  uint8_t* st1 = st0 + XM_STAGE;
+  static_assert(XM_NT == PL_NT && 2 * XM_STAGE <= PLAN_LDS, "plan matrix-core X-engine frame");
+  const int cb = (int)(index % A.n_cb);
+  const int64_t dz = index / A.n_cb;
+  const int64_t n_spec = A.n_dump * A.spd;
+  if (A.x_kind == 1)
+    xeng_mfma_body<0>(A.chan, nullptr, A.n_ant, n_spec, A.n_fft / 2, A.spd, A.n_split, cb, dz, A.part, st0, st1);
+  else
+    xeng_mfma_body<4>(A.chan, nullptr, A.n_ant, n_spec, A.n_fft / 2, A.spd, A.n_split, cb, dz, A.part, st0, st1);
 }
 
 // Every branch of the persistent loop below is wave-uniform.  The claim, the
@@ -1614,7 +1675,7 @@ __global__ void __launch_bounds__(PL_NT) plan_kernel(PlArgs a) {
     unsigned* done_part = a.ctr + 2 + 2 * item.array;
     unsigned* done_chan = a.ctr + 3 + 2 * item.array;
     bool ok = true;
-    if (item.kind == PL_XENG)
+    if (item.kind == PL_XENG || item.kind == PL_XMFMA)
       ok = plan_wait(done_chan, (unsigned)(Ap->n_chan_items + a.wait_bias), err, a.wait_ticks, wave,
                      &s_flag);
     else if (item.kind == PL_REDUCE)
@@ -1623,11 +1684,9 @@ __global__ void __launch_bounds__(PL_NT) plan_kernel(PlArgs a) {
     if (ok) {
       const int N = Ap->n_fft, NA = Ap->n_ant;
       if (item.kind == PL_FUSED) {
-        if (NA == 4 && N == 1024) plan_fused<1024, 4>(Ap, item.index, buf);
-        else if (NA == 4 && N == 2048) plan_fused<2048, 4>(Ap, item.index, buf);
-        else if (NA == 4 && N == 4096) plan_fused<4096, 4>(Ap, item.index, buf);
-        else if (NA == 8 && N == 1024) plan_fused<1024, 8>(Ap, item.index, buf);
-        else if (NA == 8 && N == 2048) plan_fused<2048, 8>(Ap, item.index, buf);
+        if (N == 1024) plan_fused<1024, 4>(Ap, item.index, buf);
+        else if (N == 2048) plan_fused<2048, 4>(Ap, item.index, buf);
+        else plan_fused<4096, 4>(Ap, item.index, buf);
       } else if (item.kind == PL_CHAN) {
         switch (N) {
           case 16: plan_chan<16>(Ap, item.index, buf); break;
@@ -1641,8 +1700,13 @@ __global__ void __launch_bounds__(PL_NT) plan_kernel(PlArgs a) {
           case 4096: plan_chan<4096>(Ap, item.index, buf); break;
           case 8192: plan_chan<8192>(Ap, item.index, buf); break;
         }
+      } else if (item.kind == PL_CHAN_RING) {
+        if (N == 4096) plan_chan_ring<4096, 4>(Ap, item.index, buf);
+        else plan_chan_ring<8192, 2>(Ap, item.index, buf);
       } else if (item.kind == PL_XENG) {
         xeng_item(Ap, item.index);
+      } else if (item.kind == PL_XMFMA) {
+        plan_xmfma(Ap, item.index, buf);
       } else {
         reduce_item(Ap, item.index);
       }
@@ -1653,7 +1717,7 @@ __global__ void __launch_bounds__(PL_NT) plan_kernel(PlArgs a) {
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       __syncthreads();
       if (wave == 0)
-        __hip_atomic_fetch_add(item.kind == PL_CHAN ? done_chan : done_part,
+        __hip_atomic_fetch_add((item.kind == PL_CHAN || item.kind == PL_CHAN_RING) ? done_chan : done_part,
                                (threadIdx.x & 63u) == 0u ? 1u : 0u, __ATOMIC_RELEASE,
                                __HIP_MEMORY_SCOPE_AGENT);
     } else {
@@ -1662,7 +1726,6 @@ __global__ void __launch_bounds__(PL_NT) plan_kernel(PlArgs a) {
   }
 }
 
-constexpr size_t PLAN_LDS = sizeof(float2) * lds_padded_size(8192);
 
 hipError_t prepare_plan() {
   return hipFuncSetAttribute(reinterpret_cast<const void*>(plan_kernel),

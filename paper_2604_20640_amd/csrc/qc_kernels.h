@@ -134,7 +134,10 @@ constexpr int PL_NT = 512;          // threads per block of the persistent kerne
 constexpr int PL_MAX_ARRAYS = 8;
 constexpr int PL_RED_BLOCK = 2048;  // visibilities per reduction item
 
-enum { PL_FUSED = 0, PL_CHAN = 1, PL_XENG = 2, PL_REDUCE = 3 };
+// Work-item kinds: fused F+X; F-engine (plain body, or the ring body at
+// N = 4096 / 8192); X-engine (vector ALU, or matrix cores for 5..32
+// antennas); reduction of partials.
+enum { PL_FUSED = 0, PL_CHAN = 1, PL_XENG = 2, PL_REDUCE = 3, PL_CHAN_RING = 4, PL_XMFMA = 5 };
 
 struct PlArray {
   const int8_t* x;       // [n_ant][n_samp] (set per execution)
@@ -148,6 +151,12 @@ struct PlArray {
   int32_t n_ant, n_fft, n_taps, mode;    // mode 0 fused, 1 two-pass
   int32_t n_chan_items, n_part_items, n_cgrp, n_bp, n_red_blocks;
   float scale;                           // reduction scale (1/4 for two-for-one spectra)
+  int64_t spb;                           // ring F-engine items: spectra per item
+  int32_t n_chunks;                      // ring F-engine items: runs of spb per antenna group
+  int32_t x_kind;                        // 0 vector ALU, 1 matrix cores 32 x 32, 2 matrix cores 16 x 16
+  int32_t n_cb;                          // matrix-core X items: channel blocks of 16
+  int32_t tile;                          // partials: 0 [baseline][chan], else tile-major of this width
+  int32_t pad0, pad1;
 };
 
 struct PlItem {

@@ -6,9 +6,10 @@ bundle) is unbundled and disassembled with the ROCm LLVM tools; each
 function's instructions are split into basic blocks and natural loops are
 found from the CFG (back-edge u -> h with h dominating u).  A loop is
 lane-divergent when one of its latches takes lanes out of exec
-(`s_andn2_b64 exec, exec, m`) or branches back on exec
-(`s_cbranch_execnz`): the wave keeps running it while any lane is left in
-it.  A barrier in such a loop can be met by part of a wave while another
+(`s_andn2_b64 exec, exec, m`, how the compiler lowers a loop exit that
+differs between lanes): the wave keeps running it while any lane is left
+in it.  A branch on exec alone (`s_cbranch_execz/nz`) changes no lane's
+exec and does not make a loop divergent.  A barrier in such a loop can be met by part of a wave while another
 part of the same wave is parked outside the loop, so the block's barriers
 no longer line up with the program's, which is how a claim-and-publish
 loop that tests `threadIdx.x == 0` at its head and latch can compile into
@@ -162,7 +163,7 @@ def divergent_loops_with_barriers(ins):
                     stack.extend(pred[x])
     problems = []
     for h, b in body.items():
-        divergent = any((op == "s_andn2_b64" and args.startswith("exec,exec,")) or op == "s_cbranch_execnz"
+        divergent = any(op == "s_andn2_b64" and args.startswith("exec,exec,")
                         for u in latches[h] for (_, op, args, _) in blocks[u])
         bars = [a for x in b for (a, op, _, _) in blocks[x] if op == "s_barrier"]
         if divergent and bars:
