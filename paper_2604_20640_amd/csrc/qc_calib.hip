@@ -84,19 +84,16 @@ __device__ __forceinline__ void find_digit(const unsigned* hist, int64_t kk, uns
     const unsigned n = __shfl_up(v, d);
     if (lane >= d) v += n;
   }
+  // each thread adds the totals of the waves before its own (independent
+  // broadcast reads instead of one thread's serial prefix and a barrier)
+  unsigned before = 0u;
   if (NW > 1) {
     if (lane == 63) wsum[wave] = v;
     __syncthreads();
-    if (t == 0) {
-      unsigned acc = 0;
-      for (int w = 0; w < NW; ++w) {
-        acc += wsum[w];
-        wsum[w] = acc;
-      }
-    }
-    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < NW; ++w) before += w < wave ? wsum[w] : 0u;
   }
-  const int64_t incl = (int64_t)v + ((NW > 1 && wave > 0) ? wsum[wave - 1] : 0u);
+  const int64_t incl = (int64_t)v + before;
   const int64_t excl = incl - loc;
   if (excl <= kk && kk < incl) {
     int64_t c = excl;
