@@ -67,6 +67,14 @@ struct AmpSrc {
   }
 };
 
+// A block-uniform 64-bit value read back from LDS, made wave-uniform for
+// the compiler (branches on it hold barriers).
+__device__ __forceinline__ int64_t rfl64(int64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 // Block-wide search of the digit that holds rank kk in hist[0..NBINS):
 // returns (digit, rank within the digit) through sh[].
 template <int NT, int NBINS>
@@ -168,11 +176,22 @@ __device__ __forceinline__ void append_wave(const SelScratch& sc, bool hit, floa
 // gathers them and one wave ranks them.  With want2, the key of rank k+1 is
 // also returned (has2) when it lies among the same candidates.
 template <int NT, int DB, typename K, typename ValFn, typename KeyOf>
-__device__ K radix_select(int64_t count, int64_t k, K kmin, K kmax, ValFn val, KeyOf keyof,
+__device__ __forceinline__ K radix_select(int64_t count, int64_t k, K kmin, K kmax, ValFn val, KeyOf keyof,
                           const SelScratch& sc, bool want2, K& v2, bool& has2) {
   constexpr int W = (int)sizeof(K) * 8;
   constexpr int NBINS = 1 << DB;
   has2 = false;
+  // the range and counts are block-uniform; say so to the compiler, so the
+  // pass loop below (barriers inside) is a scalar loop
+  if constexpr (sizeof(K) == 8) {
+    kmin = (K)rfl64((int64_t)kmin);
+    kmax = (K)rfl64((int64_t)kmax);
+  } else {
+    kmin = (K)__builtin_amdgcn_readfirstlane((int)kmin);
+    kmax = (K)__builtin_amdgcn_readfirstlane((int)kmax);
+  }
+  count = rfl64(count);
+  k = rfl64(k);
   const K diff = kmin ^ kmax;
   if (diff == 0) {  // every key equals kmin
     v2 = kmin;
@@ -181,6 +200,7 @@ __device__ K radix_select(int64_t count, int64_t k, K kmin, K kmax, ValFn val, K
   }
   int top = W - 1;  // highest differing bit
   while (!((diff >> top) & (K)1)) --top;
+  top = __builtin_amdgcn_readfirstlane(top);
   const K low = (top + 1 >= W) ? ~(K)0 : (((K)1 << (top + 1)) - 1);
   K prefix = kmin & ~low, mask = ~low;
   int64_t kk = k;
@@ -199,11 +219,13 @@ __device__ K radix_select(int64_t count, int64_t k, K kmin, K kmax, ValFn val, K
     });
     __syncthreads();
     find_digit<NT, NBINS>(sc.hist, kk, sc.wsum, sc.sh);
-    const unsigned digit = (unsigned)sc.sh[0];
-    int64_t c = sc.hist[digit];  // keys sharing the extended prefix
+    // block-uniform values read back from LDS: made wave-uniform, so that
+    // the branches and loop exits that depend on them are scalar
+    const unsigned digit = (unsigned)__builtin_amdgcn_readfirstlane((int)sc.sh[0]);
+    int64_t c = (int64_t)(unsigned)__builtin_amdgcn_readfirstlane((int)sc.hist[digit]);  // keys sharing the extended prefix
     prefix |= (K)digit << shift;
     mask |= dmask << shift;
-    kk = (int64_t)sc.sh[1];
+    kk = rfl64((int64_t)sc.sh[1]);
     __syncthreads();
     if (shift == 0) {  // all bits resolved: the key is the prefix, repeated c times
       if (want2 && kk + 1 < c) {
@@ -224,7 +246,7 @@ __device__ K radix_select(int64_t count, int64_t k, K kmin, K kmax, ValFn val, K
         for (int b = (int)digit + 1 + threadIdx.x; b < NBINS; b += NT)
           if (sc.hist[b] != 0u) atomicMin(sc.ncand, (unsigned)b);
         __syncthreads();
-        const unsigned d2 = *sc.ncand;
+        const unsigned d2 = (unsigned)__builtin_amdgcn_readfirstlane((int)*sc.ncand);
         if (d2 < (unsigned)NBINS && c + (int64_t)sc.hist[d2] <= SEL_CAND) {
           prefix2 = (prefix & ~(dmask << shift)) | ((K)d2 << shift);
           c2 = sc.hist[d2];
@@ -278,11 +300,159 @@ __device__ K radix_select(int64_t count, int64_t k, K kmin, K kmax, ValFn val, K
   return prefix;  // not reached: the last pass has shift == 0
 }
 
+// Ascending bitonic sort of one key per lane across a wave (64 keys), by
+// cross-lane exchanges: no LDS, no block barrier.
+template <typename K>
+__device__ __forceinline__ K wave_sort64(K v) {
+  const int lane = (int)(threadIdx.x & 63u);
+#pragma unroll
+  for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      K o;
+      if constexpr (sizeof(K) == 8) {
+        o = (K)__shfl_xor((unsigned long long)v, j);
+      } else {
+        o = (K)__shfl_xor((unsigned)v, j);
+      }
+      const bool lower = (lane & j) == 0;        // keeps the smaller of the pair
+      const bool up = (lane & k) == 0;           // ascending run
+      const K mn = o < v ? o : v, mx = o < v ? v : o;
+      v = (lower == up) ? mn : mx;
+    }
+  }
+  return v;
+}
+
+// Exact k-th smallest key (and the (k+1)-th when it sits in the same or
+// the next non-empty bin, has2) with bins fitted to the data.  The range
+// [kmin, kmax] that the radix passes split is set by the extreme keys, and
+// when a few outliers stretch it, the first digit puts the bulk of the keys
+// into a handful of bins, whose LDS atomics then serialise.  Here wave 0
+// sorts a 64-key sample (odd stride) in registers and takes the window
+// [lo, hi] between its ranks 8 and 56; one pass histograms every key into
+// NBINS - 2 equal bins of 2^s keys across the window plus an underflow and
+// an overflow bin, and when the bin holding rank k has at most SEL_CAND
+// keys, one pass gathers them and one wave ranks them.  Returns false with
+// nothing selected when rank k falls outside the window or its bin holds
+// more keys (the caller then runs the radix selection).
+template <int NT, int NBINS, typename K, typename ValFn, typename KeyOf>
+__device__ __forceinline__ bool window_select(int64_t n, int64_t k, bool want2, ValFn val, KeyOf keyof,
+                                              const SelScratch& sc, K& v1, K& v2, bool& has2) {
+  const int lane = (int)(threadIdx.x & 63u);
+  auto key = [&](int64_t i) -> K { return keyof(val(i)); };
+  has2 = false;
+  if (threadIdx.x < 64) {
+    int64_t stride = n / 64;
+    if (stride % 2 == 0) --stride;
+    const K srt = wave_sort64<K>(key((int64_t)lane * stride));
+    K lo, hi;
+    if constexpr (sizeof(K) == 8) {
+      lo = (K)__shfl((unsigned long long)srt, 8);
+      hi = (K)__shfl((unsigned long long)srt, 56);
+    } else {
+      lo = (K)__shfl((unsigned)srt, 8);
+      hi = (K)__shfl((unsigned)srt, 56);
+    }
+    int sh = 0;
+    while (sh < (int)(8 * sizeof(K)) - 1 && ((hi - lo) >> sh) >= (K)(NBINS - 2)) ++sh;
+    if (lane == 0) {
+      sc.sh[0] = (unsigned long long)lo;
+      sc.sh[1] = (unsigned long long)sh;
+    }
+  }
+  for (int i = threadIdx.x; i < NBINS; i += NT) sc.hist[i] = 0;
+  __syncthreads();
+  const K lo = (K)rfl64((int64_t)sc.sh[0]);
+  const int sh = __builtin_amdgcn_readfirstlane((int)sc.sh[1]);
+  auto bin = [&](K kv) -> unsigned {
+    if (kv < lo) return 0u;
+    const K q = (kv - lo) >> sh;
+    return q >= (K)(NBINS - 2) ? (unsigned)(NBINS - 1) : (unsigned)q + 1u;
+  };
+  __syncthreads();  // lo and sh read before sh[] is reused
+  for_keys<NT, K>(n, key, [&](int64_t, K kv) { atomicAdd(&sc.hist[bin(kv)], 1u); });
+  __syncthreads();
+  find_digit<NT, NBINS>(sc.hist, k, sc.wsum, sc.sh);
+  const unsigned b = (unsigned)__builtin_amdgcn_readfirstlane((int)sc.sh[0]);
+  const int64_t kk = rfl64((int64_t)sc.sh[1]);
+  int64_t c = (int64_t)(unsigned)__builtin_amdgcn_readfirstlane((int)sc.hist[b]);
+  __syncthreads();
+  if (b == 0u || b == (unsigned)(NBINS - 1) || (c > SEL_CAND && c > sc.comp_cap)) return false;
+  if (c > SEL_CAND) {
+    // a fuller bin: its values into the compaction buffer, then the radix
+    // selection among them, within the bin's key range
+    if (threadIdx.x == 0) *sc.ncand = 0;
+    __syncthreads();
+    for_keys<NT, float>(n, val, [&](int64_t, float v) { append_wave(sc, bin(keyof(v)) == b, v); });
+    __syncthreads();
+    const K base = (K)(b - 1u) << sh;
+    const K kmin = lo + base;
+    const K span = (K)1 << sh;
+    const K kmax = kmin + (span - 1) < kmin ? ~(K)0 : kmin + (span - 1);
+    SelScratch in = sc;
+    in.comp_cap = 0;
+    const float* cv = sc.comp;
+    auto cval = [&](int64_t i) -> float { return cv[i]; };
+    v1 = radix_select<NT, NBINS == 2048 ? 11 : 8, K>(c, kk, kmin, kmax, cval, keyof, in, want2, v2, has2);
+    return true;
+  }
+  // with rank k the last key of its bin, rank k+1 is the smallest key of the
+  // next non-empty bin: gather that bin too when it is an interior one and fits
+  unsigned b2 = (unsigned)NBINS;
+  if (want2 && kk + 1 == c) {
+    if (threadIdx.x == 0) *sc.ncand = (unsigned)NBINS;
+    __syncthreads();
+    for (int q = (int)b + 1 + threadIdx.x; q < NBINS; q += NT)
+      if (sc.hist[q] != 0u) atomicMin(sc.ncand, (unsigned)q);
+    __syncthreads();
+    const unsigned d2 = (unsigned)__builtin_amdgcn_readfirstlane((int)*sc.ncand);
+    if (d2 < (unsigned)(NBINS - 1) && c + (int64_t)sc.hist[d2] <= SEL_CAND) b2 = d2;
+    __syncthreads();
+  }
+  const int64_t c2 = b2 < (unsigned)NBINS ? (int64_t)sc.hist[b2] : 0;
+  if (threadIdx.x == 0) *sc.ncand = 0;
+  __syncthreads();
+  for_keys<NT, K>(n, key, [&](int64_t, K kv) {
+    const unsigned q = bin(kv);
+    if (q == b || q == b2) sc.cand[atomicAdd(sc.ncand, 1u)] = (unsigned long long)kv;
+  });
+  c += c2;
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    // rank every candidate against the others, held one per lane
+    const K mine = lane < c ? (K)sc.cand[lane] : ~(K)0;
+    int64_t less = 0, same = 0;
+    for (int t = 0; t < (int)c; ++t) {
+      K o;
+      if constexpr (sizeof(K) == 8) {
+        const uint32_t olo = __builtin_amdgcn_readlane((uint32_t)mine, t);
+        const uint32_t ohi = __builtin_amdgcn_readlane((uint32_t)(mine >> 32), t);
+        o = (K)(((uint64_t)ohi << 32) | olo);
+      } else {
+        o = (K)__builtin_amdgcn_readlane((uint32_t)mine, t);
+      }
+      less += o < mine;
+      same += o == mine;
+    }
+    if (lane < c && less <= kk && kk < less + same) sc.sh[2] = (unsigned long long)mine;
+    if (lane < c && less <= kk + 1 && kk + 1 < less + same) sc.sh[3] = (unsigned long long)mine;
+  }
+  __syncthreads();
+  v1 = (K)sc.sh[2];
+  if (want2 && kk + 1 < c) {
+    v2 = (K)sc.sh[3];
+    has2 = true;
+  }
+  __syncthreads();
+  return true;
+}
+
 // The order statistic of rank k+1 given the one of rank k (key kk): kk
 // itself if more than k+1 keys are <= kk, else the smallest key above kk.
 // One pass: a count and a minimum, reduced over the block.
 template <int NT, typename K, typename KeyFn>
-__device__ K next_rank(int64_t count, int64_t k, K kk, KeyFn key, unsigned long long* red) {
+__device__ __forceinline__ K next_rank(int64_t count, int64_t k, K kk, KeyFn key, unsigned long long* red) {
   constexpr int NW = NT / 64;
   unsigned long long le = 0;
   K mn = ~(K)0;
@@ -445,16 +615,27 @@ mad_kernel(const float2* __restrict__ vis, int64_t n_time, int64_t n_base, int n
     amin = (uint32_t)red[2 * w] < amin ? (uint32_t)red[2 * w] : amin;
     amax = (uint32_t)red[2 * w + 1] > amax ? (uint32_t)red[2 * w + 1] : amax;
   }
+  // block-uniform values from LDS, and every value derived from them below
+  // (the medians, the key ranges): wave-uniform for the compiler, so the
+  // selection loops that depend on them are scalar loops
+  amin = (uint32_t)__builtin_amdgcn_readfirstlane((int)amin);
+  amax = (uint32_t)__builtin_amdgcn_readfirstlane((int)amax);
   __syncthreads();
   const int64_t k1 = (n - 1) / 2, k2 = n / 2;
   auto akeyof = [](float a) -> uint32_t { return __float_as_uint(a); };
   auto akey = [&](int64_t i) -> uint32_t { return akeyof(amp(i)); };
   uint32_t a2;
   bool has2;
-  const uint32_t a1 =
-      radix_select<NT, DB, uint32_t>(n, k1, amin, amax, amp, akeyof, sc, k2 != k1, a2, has2);
+  // windowed first pass for the large populations, radix passes otherwise
+  // (or when the window misses)
+  constexpr bool WIN = NT >= 1024;
+  uint32_t a1 = 0u;
+  if (!(WIN && window_select<NT, (1 << DB), uint32_t>(n, k1, k2 != k1, amp, akeyof, sc, a1, a2, has2)))
+    a1 = radix_select<NT, DB, uint32_t>(n, k1, amin, amax, amp, akeyof, sc, k2 != k1, a2, has2);
   if (k2 == k1) a2 = a1;
   else if (!has2) a2 = next_rank<NT, uint32_t>(n, k1, a1, akey, red);
+  a1 = (uint32_t)__builtin_amdgcn_readfirstlane((int)a1);
+  a2 = (uint32_t)__builtin_amdgcn_readfirstlane((int)a2);
   const double med = ((double)__uint_as_float(a1) + (double)__uint_as_float(a2)) / 2.0;
   auto dkeyof = [&](float a) -> uint64_t { return (uint64_t)__double_as_longlong(fabs((double)a - med)); };
   auto dkey = [&](int64_t i) -> uint64_t { return dkeyof(amp(i)); };
@@ -463,10 +644,13 @@ mad_kernel(const float2* __restrict__ vis, int64_t n_time, int64_t n_base, int n
   const double dhi = fabs((double)__uint_as_float(amax) - med);
   const uint64_t dmax = (uint64_t)__double_as_longlong(dlo > dhi ? dlo : dhi);
   uint64_t d2;
-  const uint64_t d1 =
-      radix_select<NT, DB, uint64_t>(n, k1, 0ull, dmax, amp, dkeyof, sc, k2 != k1, d2, has2);
+  uint64_t d1 = 0ull;
+  if (!(WIN && window_select<NT, (1 << DB), uint64_t>(n, k1, k2 != k1, amp, dkeyof, sc, d1, d2, has2)))
+    d1 = radix_select<NT, DB, uint64_t>(n, k1, 0ull, dmax, amp, dkeyof, sc, k2 != k1, d2, has2);
   if (k2 == k1) d2 = d1;
   else if (!has2) d2 = next_rank<NT, uint64_t>(n, k1, d1, dkey, red);
+  d1 = (uint64_t)rfl64((int64_t)d1);
+  d2 = (uint64_t)rfl64((int64_t)d2);
   const double madv =
       (__longlong_as_double((long long)d1) + __longlong_as_double((long long)d2)) / 2.0;
   const double c = (double)sigma * 1.4826;
