@@ -47,6 +47,17 @@ __device__ __forceinline__ float sbyte(uint32_t w, int i) {
   return (float)(int8_t)((w >> (8 * i)) & 0xffu);
 }
 
+// An empty asm that reads and writes the K 32-bit words: loads into them
+// complete here.  Used on a register ring before its loop, so that the loop holds
+// no wait for loads issued before it (the compiler otherwise places such a
+// wait inside the loop, where it also waits for the loop's own memory
+// operations).
+template <int K, typename T>
+__device__ __forceinline__ void settle_words(T* w) {
+#pragma unroll
+  for (int i = 0; i < K; ++i) asm volatile("" : "+v"(w[i]));
+}
+
 // FIR for 4 consecutive samples n0..n0+3 of spectrum m, antennas a0 (real
 // part) and a1 (imaginary part; a1 < 0 means none).
 __device__ __forceinline__ void fir4(const int8_t* __restrict__ x, int64_t ld_x,
@@ -310,6 +321,14 @@ fx_fused_ring_kernel(const int8_t* __restrict__ x, int64_t ld_x, const int8_t* _
     if (!h) return 0u;
     return *reinterpret_cast<const uint32_t*>(h + (int)(blk + P - 1) * N + cn0[g]);
   };
+  // Prefetch of stream block nb >= 0 for the next spectrum (block m again
+  // on the last one, its value then unused).  The load is unconditional so
+  // the loop body stays one basic block and the wait for it falls at the
+  // end of the iteration, not inside the FIR.
+  auto load_next = [&](int g, int which, int nb) -> uint32_t {
+    const int a = 2 * (g / GP) + which;
+    return a < NA ? *reinterpret_cast<const uint32_t*>(row(a) + nb * N + cn0[g]) : 0u;
+  };
   uint32_t ring[P][G][2];
 #pragma unroll
   for (int q = 0; q < P; ++q)
@@ -341,14 +360,15 @@ fx_fused_ring_kernel(const int8_t* __restrict__ x, int64_t ld_x, const int8_t* _
       }
     }
 
+  settle_words<P * G * 2>(&ring[0][0][0]);
   for (int64_t m = m_lo; m < m_hi; ++m) {
     // prefetch block m+1 (consumed at the end of this iteration)
     uint32_t nxt[G][2];
-    const bool more = m + 1 < m_hi;
+    const int nb = (int)(m + 1 < m_hi ? m + 1 : m);
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-      nxt[g][0] = more ? load_blk(g, 0, m + 1) : 0u;
-      nxt[g][1] = more ? load_blk(g, 1, m + 1) : 0u;
+      nxt[g][0] = load_next(g, 0, nb);
+      nxt[g][1] = load_next(g, 1, nb);
     }
     // polyphase FIR from the ring
 #pragma unroll
@@ -536,6 +556,14 @@ fx_fused_ring_pp_kernel(const int8_t* __restrict__ x, int64_t ld_x, const int8_t
     if (!h) return 0u;
     return *reinterpret_cast<const uint32_t*>(h + (int)(blk + P - 1) * N + cn0[g]);
   };
+  // Prefetch of stream block nb >= 0 for the next spectrum (block m again
+  // on the last one, its value then unused).  The load is unconditional so
+  // the loop body stays one basic block and the wait for it falls at the
+  // end of the iteration, not inside the FIR.
+  auto load_next = [&](int g, int which, int nb) -> uint32_t {
+    const int a = 2 * (g / GP) + which;
+    return a < NA ? *reinterpret_cast<const uint32_t*>(row(a) + nb * N + cn0[g]) : 0u;
+  };
   uint32_t ring[P][G][2];
 #pragma unroll
   for (int q = 0; q < P; ++q)
@@ -558,14 +586,16 @@ fx_fused_ring_pp_kernel(const int8_t* __restrict__ x, int64_t ld_x, const int8_t
     for (int b = 0; b < C::NB; ++b) acc[cc][b] = make_float2(0.f, 0.f);
   __syncthreads();  // twiddles in LDS
 
+  settle_words<P * G * 2>(&ring[0][0][0]);
+  settle_words<GP * P * 4>(&hr[0][0].x);
   for (int64_t m = m_lo; m < m_hi; ++m) {
     // prefetch block m+1 (consumed at the end of this iteration)
     uint32_t nxt[G][2];
-    const bool more = m + 1 < m_hi;
+    const int nb = (int)(m + 1 < m_hi ? m + 1 : m);
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-      nxt[g][0] = more ? load_blk(g, 0, m + 1) : 0u;
-      nxt[g][1] = more ? load_blk(g, 1, m + 1) : 0u;
+      nxt[g][0] = load_next(g, 0, nb);
+      nxt[g][1] = load_next(g, 1, nb);
     }
 #pragma unroll
     for (int g = 0; g < G; ++g) {
@@ -1012,6 +1042,14 @@ __device__ __forceinline__ void chan_ring_body(const int8_t* __restrict__ x, int
     if (!hist) return 0u;
     return *reinterpret_cast<const uint32_t*>(hist + (int64_t)a * (P - 1) * N + (int)(blk + P - 1) * N + cn0[g]);
   };
+  // Prefetch of stream block nb >= 0 (see the fused ring tile): one
+  // unconditional load per chunk, from the last antenna for a slot past it
+  // (zeroed when it enters the ring).
+  auto load_next = [&](int g, int which, int nb) -> uint32_t {
+    int a = a_base + 2 * (g / GP) + which;
+    a = a < n_ant ? a : n_ant - 1;
+    return *reinterpret_cast<const uint32_t*>(x + (int64_t)a * ld_x + nb * N + cn0[g]);
+  };
   uint32_t ring[P][G][2];
 #pragma unroll
   for (int q = 0; q < P; ++q)
@@ -1042,13 +1080,14 @@ __device__ __forceinline__ void chan_ring_body(const int8_t* __restrict__ x, int
     }
   __syncthreads();  // the transform buffer is free for the FIR output
 
+  settle_words<P * G * 2>(&ring[0][0][0]);
   for (int64_t m = m_lo; m < m_hi; ++m) {
     uint32_t nxt[G][2];
-    const bool more = m + 1 < m_hi;
+    const int nb = (int)(m + 1 < m_hi ? m + 1 : m);
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-      nxt[g][0] = more ? load_blk(g, 0, m + 1) : 0u;
-      nxt[g][1] = more ? load_blk(g, 1, m + 1) : 0u;
+      nxt[g][0] = load_next(g, 0, nb);
+      nxt[g][1] = load_next(g, 1, nb);
     }
 #pragma unroll
     for (int g = 0; g < G; ++g) {
@@ -1071,6 +1110,23 @@ __device__ __forceinline__ void chan_ring_body(const int8_t* __restrict__ x, int
     }
     __syncthreads();
     F::run(b0, b0, twl, tid);
+    // The FIR of spectrum m is done: shift the ring here, before the
+    // stores, so the wait for the prefetch does not also wait for them.
+#pragma unroll
+    for (int q = 0; q + 1 < P; ++q)
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        ring[q][g][0] = ring[q + 1][g][0];
+        ring[q][g][1] = ring[q + 1][g][1];
+      }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int a = a_base + 2 * (g / GP);
+      ring[P - 1][g][0] = a < n_ant ? nxt[g][0] : 0u;
+      ring[P - 1][g][1] = a + 1 < n_ant ? nxt[g][1] : 0u;
+      // pin the update here (it would otherwise sink past the stores)
+      asm volatile("" : "+v"(ring[P - 1][g][0]), "+v"(ring[P - 1][g][1]));
+    }
 #pragma unroll
     for (int cc = 0; cc < C::CPT; ++cc) {
       const int k = tid + cc * C::NT;
@@ -1102,20 +1158,9 @@ __device__ __forceinline__ void chan_ring_body(const int8_t* __restrict__ x, int
       }
     }
     __syncthreads();
-#pragma unroll
-    for (int q = 0; q + 1 < P; ++q)
-#pragma unroll
-      for (int g = 0; g < G; ++g) {
-        ring[q][g][0] = ring[q + 1][g][0];
-        ring[q][g][1] = ring[q + 1][g][1];
-      }
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-      ring[P - 1][g][0] = nxt[g][0];
-      ring[P - 1][g][1] = nxt[g][1];
-    }
   }
 }
+
 
 template <int N, int NA, int V, int P, int PREC>
 __global__ void __launch_bounds__((FusedCfg<N, NA, 1, V, false, 0>::NT))
