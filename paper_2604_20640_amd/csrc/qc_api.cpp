@@ -913,6 +913,7 @@ struct PlanArr {
   int64_t n_dump = 0;
   const float* taps = nullptr;
   float2* tw = nullptr;
+  float2* twp = nullptr;  // per-pass twiddles (ping-pong tiles)
   float2* part = nullptr;
   float2* chan = nullptr;
 };
@@ -1168,6 +1169,8 @@ qc_status graph_setup(qc_plan* P) {
     G.taps = te.dev;
     st = get_twiddles(N, &G.tw);
     if (st != QC_OK) return st;
+    st = get_pass_twiddles(N, &G.twp);
+    if (st != QC_OK) return st;
     G.fused = qc::fused_supported(N, NA);
     if (G.fused) {
       G.tile = 0;
@@ -1202,7 +1205,7 @@ qc_status graph_array(qc_plan* P, int i, const int8_t* x, float* vis, hipStream_
   const int N = D.n_fft, NA = D.n_ant, nch = N / 2;
   const int64_t nb = (int64_t)NA * (NA + 1) / 2, elems = nb * nch;
   const int64_t ns = G.n_dump * D.spec_per_dump;
-  const qc::FxArgs a{x, D.n_samp, NA, ns * N, N, D.n_taps, G.taps, G.tw, nullptr, true};
+  const qc::FxArgs a{x, D.n_samp, NA, ns * N, N, D.n_taps, G.taps, G.tw, nullptr, true, G.twp};
   float2* v = reinterpret_cast<float2*>(vis);
   if (G.fused) {
     QC_HIP(qc::launch_fused(a, G.n_dump, D.spec_per_dump, G.split, G.part, s, G.tile), "fused F+X kernel");

@@ -618,18 +618,26 @@ fx_fused_ring_pp_kernel(const int8_t* __restrict__ x, int64_t ld_x, const int8_t
     }
     __syncthreads();
     fft_pp_passes<N, 1, C::NT, V, 0>(b0, b1, twl, tid);
+    static_assert(C::NCH % C::NT == 0, "every thread has CPT channels");
+    // all of the thread's transform outputs are read before any is used, so
+    // the reads overlap instead of each waiting for the one before
+    float2 zk[C::CPT][C::NP], zn[C::CPT][C::NP];
 #pragma unroll
     for (int cc = 0; cc < C::CPT; ++cc) {
       const int k = tid + cc * C::NT;
-      if (C::NCH % C::NT == 0 || k < C::NCH) {
-        const int kn = (N - k) & (N - 1);
+      const int kn = (N - k) & (N - 1);
+#pragma unroll
+      for (int p = 0; p < C::NP; ++p) {
+        zk[cc][p] = b1[lds_pad(p * N + k)];
+        zn[cc][p] = b1[lds_pad(p * N + kn)];
+      }
+    }
+#pragma unroll
+    for (int cc = 0; cc < C::CPT; ++cc) {
+      {
         float2 X[2 * C::NP];
 #pragma unroll
-        for (int p = 0; p < C::NP; ++p) {
-          const float2 zk = b1[lds_pad(p * N + k)];
-          const float2 zn = b1[lds_pad(p * N + kn)];
-          separate(zk, zn, X[2 * p], X[2 * p + 1]);
-        }
+        for (int p = 0; p < C::NP; ++p) separate(zk[cc][p], zn[cc][p], X[2 * p], X[2 * p + 1]);
         int b = 0;
 #pragma unroll
         for (int i = 0; i < NA; ++i) {
@@ -996,31 +1004,42 @@ channelize_kernel(const int8_t* __restrict__ x, int64_t ld_x, int n_ant, int64_t
 // writing the separated spectra out instead of correlating them.
 // Block = (antenna group, run of spectra).  The half of the symmetric
 // prototype the threads pick their taps from is staged once through the
-// transform buffer, so LDS holds only the buffer and the twiddles.
-template <int N, int NA, int V, int P>
+// transform buffer, so LDS holds only the buffer(s) and the twiddles.
+// With PP the transform ping-pongs between two buffers as in the fused
+// ping-pong tile (one barrier per radix pass, none after the stores);
+// without it the transform runs in place.
+template <int N, int NA, int V, int P, bool PP = false>
 struct ChanRingCfg {
   using C = FusedCfg<N, NA, 1, V, false, 0>;
   static constexpr int TAPS = P * N / 2;  // floats: half of a symmetric prototype
   static_assert(sizeof(float) * TAPS <= sizeof(float2) * C::LDS, "taps staged in the transform buffer");
-  static constexpr size_t LDS_BYTES = sizeof(float2) * (C::LDS + N);  // transforms, twiddles
+  static constexpr size_t lds_bytes() {
+    if constexpr (PP) return RingPpCfg<N, NA, V, P>::LDS_BYTES;
+    else return sizeof(float2) * (C::LDS + N);  // transform, twiddles
+  }
+  static constexpr size_t LDS_BYTES = lds_bytes();
 };
 
 // Body of the ring F-engine for antenna group grp and run chk of spb
 // spectra, by all threads of a block, on an LDS region of
-// ChanRingCfg<N, NA, V, P>::LDS_BYTES.
-template <int N, int NA, int V, int P, int PREC>
+// ChanRingCfg<N, NA, V, P, PP>::LDS_BYTES.  twp: the per-pass twiddle
+// table (read with PP only).
+template <int N, int NA, int V, int P, int PREC, bool PP = false>
 __device__ __forceinline__ void chan_ring_body(const int8_t* __restrict__ x, int64_t ld_x, int n_ant,
                                                const int8_t* __restrict__ hist, const float* __restrict__ taps,
                                                const float2* __restrict__ tw, int64_t n_spec, int64_t spb,
                                                int grp, int64_t chk, const float* __restrict__ scale,
-                                               void* __restrict__ out, float2* buf) {
+                                               void* __restrict__ out, float2* buf,
+                                               const float2* __restrict__ twp = nullptr) {
   using C = FusedCfg<N, NA, 1, V, false, 0>;
   using F = Fft<N, C::NT, V, false, false, true>;
   constexpr int G = C::CHUNKS;
   constexpr int L = P * N;
   constexpr int NCH = N / 2;
+  static_assert(!PP || fft_pass_count(N, V) % 2 == 1, "odd pass count: the output lands in the second buffer");
   float2* b0 = buf;
-  float2* twl = buf + C::LDS;
+  float2* b1 = PP ? buf + C::BUF : buf;      // where the transform's output lands
+  float2* twl = PP ? buf + 2 * C::BUF : buf + C::LDS;
   float4* tl = reinterpret_cast<float4*>(b0);  // taps, until they are in registers
   const int tid = threadIdx.x;
   const int a_base = NA * grp;
@@ -1028,7 +1047,11 @@ __device__ __forceinline__ void chan_ring_body(const int8_t* __restrict__ x, int
   const int64_t m_hi = m_lo + spb < n_spec ? m_lo + spb : n_spec;
 
   for (int i = tid; i < L / 8; i += C::NT) tl[i] = reinterpret_cast<const float4*>(taps)[i];
-  build_pass_twiddles<N, V>(twl, tw, tid, C::NT);
+  if constexpr (PP) {
+    for (int i = tid; i < PpTw<N, V>::LDS_TW; i += C::NT) twl[i] = twp[i];
+  } else {
+    build_pass_twiddles<N, V>(twl, tw, tid, C::NT);
+  }
 
   constexpr int GP = G / C::NP;
   static_assert(GP * C::NP == G && GP * C::NT * 4 == N, "ring chunk mapping");
@@ -1109,7 +1132,8 @@ __device__ __forceinline__ void chan_ring_body(const int8_t* __restrict__ x, int
       for (int i = 0; i < 4; ++i) b0[lds_pad((g / GP) * N + cn0[g] + i)] = make_float2(y0[i], y1[i]);
     }
     __syncthreads();
-    F::run(b0, b0, twl, tid);
+    if constexpr (PP) fft_pp_passes<N, 1, C::NT, V, 0>(b0, b1, twl, tid);
+    else F::run(b0, b0, twl, tid);
     // The FIR of spectrum m is done: shift the ring here, before the
     // stores, so the wait for the prefetch does not also wait for them.
 #pragma unroll
@@ -1127,15 +1151,27 @@ __device__ __forceinline__ void chan_ring_body(const int8_t* __restrict__ x, int
       // pin the update here (it would otherwise sink past the stores)
       asm volatile("" : "+v"(ring[P - 1][g][0]), "+v"(ring[P - 1][g][1]));
     }
+    static_assert(NCH % C::NT == 0, "every thread has CPT channels");
+    // the thread's transform outputs, all read before any is used
+    float2 zk[C::CPT][C::NP], zn[C::CPT][C::NP];
 #pragma unroll
     for (int cc = 0; cc < C::CPT; ++cc) {
       const int k = tid + cc * C::NT;
-      if (NCH % C::NT == 0 || k < NCH) {
-        const int kn = (N - k) & (N - 1);
+      const int kn = (N - k) & (N - 1);
+#pragma unroll
+      for (int p = 0; p < C::NP; ++p) {
+        zk[cc][p] = b1[lds_pad(p * N + k)];
+        zn[cc][p] = b1[lds_pad(p * N + kn)];
+      }
+    }
+#pragma unroll
+    for (int cc = 0; cc < C::CPT; ++cc) {
+      const int k = tid + cc * C::NT;
+      {
 #pragma unroll
         for (int p = 0; p < C::NP; ++p) {
           float2 ya, yb;
-          separate(b0[lds_pad(p * N + k)], b0[lds_pad(p * N + kn)], ya, yb);
+          separate(zk[cc][p], zn[cc][p], ya, yb);
 #pragma unroll
           for (int u = 0; u < 2; ++u) {
             const int a = a_base + 2 * p + u;
@@ -1157,25 +1193,32 @@ __device__ __forceinline__ void chan_ring_body(const int8_t* __restrict__ x, int
         }
       }
     }
-    __syncthreads();
+    // the next FIR overwrites b0: without PP every thread must be done
+    // reading it; with PP the separation read b1, which the next FIR's
+    // barrier protects
+    if constexpr (!PP) __syncthreads();
   }
 }
 
 
-template <int N, int NA, int V, int P, int PREC>
+template <int N, int NA, int V, int P, int PREC, bool PP>
 __global__ void __launch_bounds__((FusedCfg<N, NA, 1, V, false, 0>::NT))
 chan_ring_kernel(const int8_t* __restrict__ x, int64_t ld_x, int n_ant, const int8_t* __restrict__ hist,
-                 const float* __restrict__ taps, const float2* __restrict__ tw, int64_t n_spec,
-                 int64_t spb, int64_t chunks, const float* __restrict__ scale, void* __restrict__ out) {
+                 const float* __restrict__ taps, const float2* __restrict__ tw, const float2* __restrict__ twp,
+                 int64_t n_spec, int64_t spb, int64_t chunks, const float* __restrict__ scale,
+                 void* __restrict__ out) {
   extern __shared__ float2 buf[];
-  chan_ring_body<N, NA, V, P, PREC>(x, ld_x, n_ant, hist, taps, tw, n_spec, spb, (int)(blockIdx.x / chunks),
-                                    (int64_t)(blockIdx.x % chunks), scale, out, buf);
+  chan_ring_body<N, NA, V, P, PREC, PP>(x, ld_x, n_ant, hist, taps, tw, n_spec, spb, (int)(blockIdx.x / chunks),
+                                        (int64_t)(blockIdx.x % chunks), scale, out, buf, twp);
 }
 
+// Ping-pong transform buffers at N = 4096 (four antennas, 154 KiB of LDS).
 template <int N, int NA, int PREC>
 static hipError_t launch_chan_ring_p(const FxArgs& a, void* out, const float* scale, hipStream_t s) {
   constexpr int V = 16;
-  using RC = ChanRingCfg<N, NA, V, 4>;
+  constexpr bool PP = N == 4096;
+  using RC = ChanRingCfg<N, NA, V, 4, PP>;
+  if (PP && !a.twp) return hipErrorInvalidValue;
   using C = FusedCfg<N, NA, 1, V, false, 0>;
   static_assert(RC::LDS_BYTES <= 160 * 1024, "channelize ring: LDS");
   const int64_t n_spec = a.n_samp / N;
@@ -1187,12 +1230,12 @@ static hipError_t launch_chan_ring_p(const FxArgs& a, void* out, const float* sc
   if (spb < 16) spb = 16;
   const int64_t chunks = (n_spec + spb - 1) / spb;
   if ((int64_t)groups * chunks > 0x7fffffffLL) return hipErrorInvalidValue;
-  const void* k = reinterpret_cast<const void*>(chan_ring_kernel<N, NA, V, 4, PREC>);
+  const void* k = reinterpret_cast<const void*>(chan_ring_kernel<N, NA, V, 4, PREC, PP>);
   hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)RC::LDS_BYTES);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((chan_ring_kernel<N, NA, V, 4, PREC>), dim3((unsigned)(groups * chunks)), dim3(C::NT),
-                     RC::LDS_BYTES, s, a.x, a.ld_x, a.n_ant, a.hist, a.taps, a.tw, n_spec, spb, chunks, scale,
-                     out);
+  hipLaunchKernelGGL((chan_ring_kernel<N, NA, V, 4, PREC, PP>), dim3((unsigned)(groups * chunks)), dim3(C::NT),
+                     RC::LDS_BYTES, s, a.x, a.ld_x, a.n_ant, a.hist, a.taps, a.tw, a.twp, n_spec, spb, chunks,
+                     scale, out);
   return hipGetLastError();
 }
 
