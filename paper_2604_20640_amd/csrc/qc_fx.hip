@@ -1564,18 +1564,27 @@ template <class T>
 __device__ __forceinline__ T* uni(T* p) {
   return reinterpret_cast<T*>(uni((int64_t)reinterpret_cast<uintptr_t>(p)));
 }
+// uni() for a pointer known to address global memory (a plan's arrays):
+// the value passes through a global-address-space pointer, so accesses
+// through it compile to global rather than flat instructions (flat ones
+// also count against the LDS counter, so every LDS wait waits for them).
+template <class T>
+__device__ __forceinline__ T* uni_global(T* p) {
+  const uint64_t v = (uint64_t)uni((int64_t)reinterpret_cast<uintptr_t>(p));
+  return (T*)(__attribute__((address_space(1))) T*)v;
+}
 __device__ __forceinline__ float uni(float v) { return __int_as_float(uni((int32_t)__float_as_int(v))); }
 
 static_assert(sizeof(PlArray) == 160, "load_uniform copies every field of PlArray");
 __device__ __forceinline__ PlArray load_uniform(const PlArray* Ap) {
   const PlArray* p = uni(Ap);
   PlArray A;
-  A.x = uni(p->x);
-  A.vis = uni(p->vis);
-  A.part = uni(p->part);
-  A.chan = uni(p->chan);
-  A.taps = uni(p->taps);
-  A.tw = uni(p->tw);
+  A.x = uni_global(p->x);
+  A.vis = uni_global(p->vis);
+  A.part = uni_global(p->part);
+  A.chan = uni_global(p->chan);
+  A.taps = uni_global(p->taps);
+  A.tw = uni_global(p->tw);
   A.n_samp = uni(p->n_samp);
   A.spd = uni(p->spd);
   A.n_dump = uni(p->n_dump);
