@@ -423,7 +423,8 @@ qc_status channelize_any_impl(const void* x, int32_t sample, int64_t ld_x, int32
   Resolved r;
   qc_status st = resolve(nullptr, ld_x, n_ant, n_samp, p, nullptr, &r);
   if (st != QC_OK) return st;
-  const qc::ChanxArgs a{x, ld_x, n_ant, n_samp, p->n_fft, p->n_taps, r.args.taps, r.args.tw, hist};
+  const qc::ChanxArgs a{x, ld_x, n_ant, n_samp, p->n_fft, p->n_taps, r.args.taps, r.args.tw, hist,
+                       r.args.taps_symmetric, r.args.twp};
   if (out_prec != QC_F32) {
     double s2 = r.sum_h2;
     if (p->taps != nullptr) {

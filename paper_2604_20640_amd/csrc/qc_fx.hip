@@ -1024,18 +1024,66 @@ struct ChanRingCfg {
 // spectra, by all threads of a block, on an LDS region of
 // ChanRingCfg<N, NA, V, P, PP>::LDS_BYTES.  twp: the per-pass twiddle
 // table (read with PP only).
-template <int N, int NA, int V, int P, int PREC, bool PP = false>
+// Ring words: four consecutive samples of one input row as loaded (Sec. 3.3
+// quantisation modes).  Real words (int8, int16) fill two antennas per
+// packed transform; complex words (I, Q interleaved int8 or int16) fill
+// one antenna per transform, I as the real and Q as the imaginary part.
+template <int ST> struct RingWord;
+template <> struct RingWord<0> { using T = uint32_t; static constexpr int BYTES = 1; static constexpr bool CPLX = false; };
+template <> struct RingWord<1> { using T = uint2; static constexpr int BYTES = 2; static constexpr bool CPLX = false; };
+template <> struct RingWord<2> { using T = uint2; static constexpr int BYTES = 2; static constexpr bool CPLX = true; };
+template <> struct RingWord<3> { using T = uint4; static constexpr int BYTES = 4; static constexpr bool CPLX = true; };
+
+__device__ __forceinline__ float s16(uint32_t w, int hi) {
+  return (float)(int16_t)(hi ? (w >> 16) : (w & 0xffffu));
+}
+// Sample i of a ring word: the real value (real words) or I (complex).
+template <int ST, class T>
+__device__ __forceinline__ float word_re(const T& w, int i) {
+  if constexpr (ST == 0) return sbyte(w, i);
+  else if constexpr (ST == 1) return s16(i < 2 ? w.x : w.y, i & 1);
+  else if constexpr (ST == 2) return sbyte(i < 2 ? w.x : w.y, 2 * (i & 1));
+  else return s16(i == 0 ? w.x : i == 1 ? w.y : i == 2 ? w.z : w.w, 0);
+}
+// Q of sample i of a complex ring word.
+template <int ST, class T>
+__device__ __forceinline__ float word_im(const T& w, int i) {
+  if constexpr (ST == 2) return sbyte(i < 2 ? w.x : w.y, 2 * (i & 1) + 1);
+  else return s16(i == 0 ? w.x : i == 1 ? w.y : i == 2 ? w.z : w.w, 1);
+}
+// An empty asm reading and writing a ring word (keeps its update in place).
+__device__ __forceinline__ void pin_word(uint32_t& w) { asm volatile("" : "+v"(w)); }
+__device__ __forceinline__ void pin_word(uint2& w) { asm volatile("" : "+v"(w.x), "+v"(w.y)); }
+__device__ __forceinline__ void pin_word(uint4& w) {
+  asm volatile("" : "+v"(w.x), "+v"(w.y), "+v"(w.z), "+v"(w.w));
+}
+
+// Body of the ring F-engine for antenna group grp and run chk of spb
+// spectra, by all threads of a block, on an LDS region of
+// ChanRingCfg<N, NAF, V, P, PP>::LDS_BYTES (NAF = NA for real words, 2 NA
+// for complex ones: the same number of transforms).  x and hist are byte
+// pointers to rows of ST words (ld_x in samples).  twp: the per-pass
+// twiddle table (read with PP only).  Output [antenna][spectrum][channel]:
+// N/2 channels for real words (separated, times 1/2), N for complex words.
+template <int N, int NA, int V, int P, int PREC, bool PP = false, int ST = 0>
 __device__ __forceinline__ void chan_ring_body(const int8_t* __restrict__ x, int64_t ld_x, int n_ant,
                                                const int8_t* __restrict__ hist, const float* __restrict__ taps,
                                                const float2* __restrict__ tw, int64_t n_spec, int64_t spb,
                                                int grp, int64_t chk, const float* __restrict__ scale,
                                                void* __restrict__ out, float2* buf,
                                                const float2* __restrict__ twp = nullptr) {
-  using C = FusedCfg<N, NA, 1, V, false, 0>;
+  using W = RingWord<ST>;
+  using T = typename W::T;
+  constexpr bool CPLX = W::CPLX;
+  constexpr int SL = CPLX ? 1 : 2;               // ring slots per chunk
+  constexpr int NAF = CPLX ? 2 * NA : NA;
+  using C = FusedCfg<N, NAF, 1, V, false, 0>;
   using F = Fft<N, C::NT, V, false, false, true>;
   constexpr int G = C::CHUNKS;
   constexpr int L = P * N;
-  constexpr int NCH = N / 2;
+  constexpr int NCH = CPLX ? N : N / 2;          // channels out per transform
+  constexpr int CPT = NCH / C::NT;               // per thread per transform
+  static_assert(NCH % C::NT == 0, "every thread has CPT channels");
   static_assert(!PP || fft_pass_count(N, V) % 2 == 1, "odd pass count: the output lands in the second buffer");
   float2* b0 = buf;
   float2* b1 = PP ? buf + C::BUF : buf;      // where the transform's output lands
@@ -1058,35 +1106,38 @@ __device__ __forceinline__ void chan_ring_body(const int8_t* __restrict__ x, int
   int cn0[G];
 #pragma unroll
   for (int g = 0; g < G; ++g) cn0[g] = 4 * (tid + (g % GP) * C::NT);
-  auto load_blk = [&](int g, int which, int64_t blk) -> uint32_t {
-    const int a = a_base + 2 * (g / GP) + which;
-    if (a >= n_ant) return 0u;
-    if (blk >= 0) return *reinterpret_cast<const uint32_t*>(x + (int64_t)a * ld_x + (int)blk * N + cn0[g]);
-    if (!hist) return 0u;
-    return *reinterpret_cast<const uint32_t*>(hist + (int64_t)a * (P - 1) * N + (int)(blk + P - 1) * N + cn0[g]);
+  // antenna of chunk g, slot `which`
+  auto ant = [&](int g, int which) -> int { return a_base + (CPLX ? g / GP : 2 * (g / GP) + which); };
+  auto load_blk = [&](int g, int which, int64_t blk) -> T {
+    const int a = ant(g, which);
+    if (a >= n_ant) return T{};
+    if (blk >= 0)
+      return *reinterpret_cast<const T*>(x + ((int64_t)a * ld_x + (int)blk * N + cn0[g]) * W::BYTES);
+    if (!hist) return T{};
+    return *reinterpret_cast<const T*>(hist + ((int64_t)a * (P - 1) * N + (int)(blk + P - 1) * N + cn0[g]) *
+                                                  W::BYTES);
   };
   // Prefetch of stream block nb >= 0 (see the fused ring tile): one
   // unconditional load per chunk, from the last antenna for a slot past it
   // (zeroed when it enters the ring).
-  auto load_next = [&](int g, int which, int nb) -> uint32_t {
-    int a = a_base + 2 * (g / GP) + which;
+  auto load_next = [&](int g, int which, int nb) -> T {
+    int a = ant(g, which);
     a = a < n_ant ? a : n_ant - 1;
-    return *reinterpret_cast<const uint32_t*>(x + (int64_t)a * ld_x + nb * N + cn0[g]);
+    return *reinterpret_cast<const T*>(x + ((int64_t)a * ld_x + nb * N + cn0[g]) * W::BYTES);
   };
-  uint32_t ring[P][G][2];
+  T ring[P][G][SL];
 #pragma unroll
   for (int q = 0; q < P; ++q)
 #pragma unroll
-    for (int g = 0; g < G; ++g) {
-      const int64_t blk = m_lo - P + 1 + q;
-      ring[q][g][0] = load_blk(g, 0, blk);
-      ring[q][g][1] = load_blk(g, 1, blk);
-    }
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+      for (int w = 0; w < SL; ++w) ring[q][g][w] = load_blk(g, w, m_lo - P + 1 + q);
+  // output scale per antenna: with the 1/2 of the separation for real words
   float hs[NA];
 #pragma unroll
   for (int i = 0; i < NA; ++i) {
     const int a = a_base + i;
-    hs[i] = 0.5f * ((PREC != 0 && a < n_ant) ? scale[a] : 1.f);
+    hs[i] = (CPLX ? 1.f : 0.5f) * ((PREC != 0 && a < n_ant) ? scale[a] : 1.f);
   }
   __syncthreads();  // taps and twiddles in LDS
   float4 hr[GP][P];   // taps of the thread's distinct chunk positions
@@ -1103,30 +1154,31 @@ __device__ __forceinline__ void chan_ring_body(const int8_t* __restrict__ x, int
     }
   __syncthreads();  // the transform buffer is free for the FIR output
 
-  settle_words<P * G * 2>(&ring[0][0][0]);
+  settle_words<P * G * SL * (int)(sizeof(T) / 4)>(reinterpret_cast<uint32_t*>(&ring[0][0][0]));
   for (int64_t m = m_lo; m < m_hi; ++m) {
-    uint32_t nxt[G][2];
+    T nxt[G][SL];
     const int nb = (int)(m + 1 < m_hi ? m + 1 : m);
 #pragma unroll
-    for (int g = 0; g < G; ++g) {
-      nxt[g][0] = load_next(g, 0, nb);
-      nxt[g][1] = load_next(g, 1, nb);
-    }
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+      for (int w = 0; w < SL; ++w) nxt[g][w] = load_next(g, w, nb);
 #pragma unroll
     for (int g = 0; g < G; ++g) {
       float y0[4] = {0.f, 0.f, 0.f, 0.f}, y1[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int q = 0; q < P; ++q) {
         const float4 h = hr[g % GP][q];
-        const uint32_t w0 = ring[q][g][0], w1 = ring[q][g][1];
-        y0[0] += h.x * sbyte(w0, 0);
-        y0[1] += h.y * sbyte(w0, 1);
-        y0[2] += h.z * sbyte(w0, 2);
-        y0[3] += h.w * sbyte(w0, 3);
-        y1[0] += h.x * sbyte(w1, 0);
-        y1[1] += h.y * sbyte(w1, 1);
-        y1[2] += h.z * sbyte(w1, 2);
-        y1[3] += h.w * sbyte(w1, 3);
+        const float hv[4] = {h.x, h.y, h.z, h.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          if constexpr (CPLX) {
+            y0[i] += hv[i] * word_re<ST>(ring[q][g][0], i);
+            y1[i] += hv[i] * word_im<ST>(ring[q][g][0], i);
+          } else {
+            y0[i] += hv[i] * word_re<ST>(ring[q][g][0], i);
+            y1[i] += hv[i] * word_re<ST>(ring[q][g][SL - 1], i);
+          }
+        }
       }
 #pragma unroll
       for (int i = 0; i < 4; ++i) b0[lds_pad((g / GP) * N + cn0[g] + i)] = make_float2(y0[i], y1[i]);
@@ -1139,90 +1191,98 @@ __device__ __forceinline__ void chan_ring_body(const int8_t* __restrict__ x, int
 #pragma unroll
     for (int q = 0; q + 1 < P; ++q)
 #pragma unroll
-      for (int g = 0; g < G; ++g) {
-        ring[q][g][0] = ring[q + 1][g][0];
-        ring[q][g][1] = ring[q + 1][g][1];
+      for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int w = 0; w < SL; ++w) ring[q][g][w] = ring[q + 1][g][w];
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+      for (int w = 0; w < SL; ++w) {
+        ring[P - 1][g][w] = ant(g, w) < n_ant ? nxt[g][w] : T{};
+        // pin the update here (it would otherwise sink past the stores)
+        pin_word(ring[P - 1][g][w]);
       }
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-      const int a = a_base + 2 * (g / GP);
-      ring[P - 1][g][0] = a < n_ant ? nxt[g][0] : 0u;
-      ring[P - 1][g][1] = a + 1 < n_ant ? nxt[g][1] : 0u;
-      // pin the update here (it would otherwise sink past the stores)
-      asm volatile("" : "+v"(ring[P - 1][g][0]), "+v"(ring[P - 1][g][1]));
-    }
-    static_assert(NCH % C::NT == 0, "every thread has CPT channels");
     // the thread's transform outputs, all read before any is used
-    float2 zk[C::CPT][C::NP], zn[C::CPT][C::NP];
+    float2 zk[CPT][C::NP], zn[CPT][C::NP];
 #pragma unroll
-    for (int cc = 0; cc < C::CPT; ++cc) {
+    for (int cc = 0; cc < CPT; ++cc) {
       const int k = tid + cc * C::NT;
       const int kn = (N - k) & (N - 1);
 #pragma unroll
       for (int p = 0; p < C::NP; ++p) {
         zk[cc][p] = b1[lds_pad(p * N + k)];
-        zn[cc][p] = b1[lds_pad(p * N + kn)];
+        if constexpr (!CPLX) zn[cc][p] = b1[lds_pad(p * N + kn)];
       }
     }
+    auto put = [&](int a, int k, float2 y, float hh) {
+      const int64_t idx = ((int64_t)a * n_spec + m) * NCH + k;
+      if constexpr (PREC == 0) {
+        reinterpret_cast<float2*>(out)[idx] = make_float2(y.x * hh, y.y * hh);
+      } else if constexpr (PREC == 1) {
+        reinterpret_cast<uint32_t*>(out)[idx] = enc_f16(y.x * hh) | (enc_f16(y.y * hh) << 16);
+      } else if constexpr (PREC == 2) {
+        reinterpret_cast<uint32_t*>(out)[idx] = enc_bf16(y.x * hh) | (enc_bf16(y.y * hh) << 16);
+      } else {
+        reinterpret_cast<uint16_t*>(out)[idx] = enc_e4m3x2(y.x * hh, y.y * hh);
+      }
+    };
 #pragma unroll
-    for (int cc = 0; cc < C::CPT; ++cc) {
+    for (int cc = 0; cc < CPT; ++cc) {
       const int k = tid + cc * C::NT;
-      {
 #pragma unroll
-        for (int p = 0; p < C::NP; ++p) {
+      for (int p = 0; p < C::NP; ++p) {
+        if constexpr (CPLX) {
+          const int a = a_base + p;
+          if (a < n_ant) put(a, k, zk[cc][p], hs[p]);
+        } else {
           float2 ya, yb;
           separate(zk[cc][p], zn[cc][p], ya, yb);
 #pragma unroll
           for (int u = 0; u < 2; ++u) {
             const int a = a_base + 2 * p + u;
-            if (a < n_ant) {
-              const float2 y = u ? yb : ya;
-              const float hh = hs[2 * p + u];
-              const int64_t idx = ((int64_t)a * n_spec + m) * NCH + k;
-              if constexpr (PREC == 0) {
-                reinterpret_cast<float2*>(out)[idx] = make_float2(y.x * hh, y.y * hh);
-              } else if constexpr (PREC == 1) {
-                reinterpret_cast<uint32_t*>(out)[idx] = enc_f16(y.x * hh) | (enc_f16(y.y * hh) << 16);
-              } else if constexpr (PREC == 2) {
-                reinterpret_cast<uint32_t*>(out)[idx] = enc_bf16(y.x * hh) | (enc_bf16(y.y * hh) << 16);
-              } else {
-                reinterpret_cast<uint16_t*>(out)[idx] = enc_e4m3x2(y.x * hh, y.y * hh);
-              }
-            }
+            if (a < n_ant) put(a, k, u ? yb : ya, hs[2 * p + u]);
           }
         }
       }
     }
     // the next FIR overwrites b0: without PP every thread must be done
-    // reading it; with PP the separation read b1, which the next FIR's
-    // barrier protects
+    // reading it; with PP the transform output was read from b1, which the
+    // next FIR's barrier protects
     if constexpr (!PP) __syncthreads();
   }
 }
 
 
-template <int N, int NA, int V, int P, int PREC, bool PP>
-__global__ void __launch_bounds__((FusedCfg<N, NA, 1, V, false, 0>::NT))
+template <int N, int NA, int V, int P, int PREC, bool PP, int ST>
+__global__ void __launch_bounds__((FusedCfg<N, (ST >= 2 ? 2 * NA : NA), 1, V, false, 0>::NT))
 chan_ring_kernel(const int8_t* __restrict__ x, int64_t ld_x, int n_ant, const int8_t* __restrict__ hist,
                  const float* __restrict__ taps, const float2* __restrict__ tw, const float2* __restrict__ twp,
                  int64_t n_spec, int64_t spb, int64_t chunks, const float* __restrict__ scale,
                  void* __restrict__ out) {
   extern __shared__ float2 buf[];
-  chan_ring_body<N, NA, V, P, PREC, PP>(x, ld_x, n_ant, hist, taps, tw, n_spec, spb, (int)(blockIdx.x / chunks),
-                                        (int64_t)(blockIdx.x % chunks), scale, out, buf, twp);
+  chan_ring_body<N, NA, V, P, PREC, PP, ST>(x, ld_x, n_ant, hist, taps, tw, n_spec, spb,
+                                            (int)(blockIdx.x / chunks), (int64_t)(blockIdx.x % chunks), scale,
+                                            out, buf, twp);
 }
 
-// Ping-pong transform buffers at N = 4096 (four antennas, 154 KiB of LDS).
-template <int N, int NA, int PREC>
-static hipError_t launch_chan_ring_p(const FxArgs& a, void* out, const float* scale, hipStream_t s) {
+// The ring F-engine over n_ant rows of ST words.  Four real antennas (two
+// packed transforms) per workgroup up to N = 4096 and two at N = 8192;
+// complex words take half as many antennas, one transform each.  Ping-pong
+// transform buffers at N = 4096 (154 KiB of LDS).
+template <int N, int PREC, int ST>
+static hipError_t launch_chan_ring_w(const int8_t* x, int64_t ld_x, int n_ant, int64_t n_samp,
+                                     const int8_t* hist, const float* taps, const float2* tw,
+                                     const float2* twp, void* out, const float* scale, hipStream_t s) {
   constexpr int V = 16;
   constexpr bool PP = N == 4096;
-  using RC = ChanRingCfg<N, NA, V, 4, PP>;
-  if (PP && !a.twp) return hipErrorInvalidValue;
-  using C = FusedCfg<N, NA, 1, V, false, 0>;
+  constexpr int NAR = N >= 8192 ? 2 : 4;
+  constexpr int NA = ST >= 2 ? NAR / 2 : NAR;
+  using RC = ChanRingCfg<N, NAR, V, 4, PP>;
+  using C = FusedCfg<N, NAR, 1, V, false, 0>;
   static_assert(RC::LDS_BYTES <= 160 * 1024, "channelize ring: LDS");
-  const int64_t n_spec = a.n_samp / N;
-  const int groups = (a.n_ant + NA - 1) / NA;
+  if (PP && !twp) return hipErrorInvalidValue;
+  const int64_t n_spec = n_samp / N;
+  const int groups = (n_ant + NA - 1) / NA;
   // runs of at least 16 spectra (the ring reloads P-1 blocks per run and
   // each workgroup rebuilds its twiddle tables), about 512 workgroups in
   // total: two rounds of one resident workgroup per CU
@@ -1230,26 +1290,32 @@ static hipError_t launch_chan_ring_p(const FxArgs& a, void* out, const float* sc
   if (spb < 16) spb = 16;
   const int64_t chunks = (n_spec + spb - 1) / spb;
   if ((int64_t)groups * chunks > 0x7fffffffLL) return hipErrorInvalidValue;
-  const void* k = reinterpret_cast<const void*>(chan_ring_kernel<N, NA, V, 4, PREC, PP>);
+  const void* k = reinterpret_cast<const void*>(chan_ring_kernel<N, NA, V, 4, PREC, PP, ST>);
   hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)RC::LDS_BYTES);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((chan_ring_kernel<N, NA, V, 4, PREC, PP>), dim3((unsigned)(groups * chunks)), dim3(C::NT),
-                     RC::LDS_BYTES, s, a.x, a.ld_x, a.n_ant, a.hist, a.taps, a.tw, a.twp, n_spec, spb, chunks,
+  hipLaunchKernelGGL((chan_ring_kernel<N, NA, V, 4, PREC, PP, ST>), dim3((unsigned)(groups * chunks)),
+                     dim3(C::NT), RC::LDS_BYTES, s, x, ld_x, n_ant, hist, taps, tw, twp, n_spec, spb, chunks,
                      scale, out);
   return hipGetLastError();
 }
 
-// Four antennas (two packed transforms) per workgroup up to N = 4096; at
-// N = 8192 two antennas, so one transform and the twiddles fit in LDS.
+template <int N, int ST>
+static hipError_t launch_chan_ring_st(const int8_t* x, int64_t ld_x, int n_ant, int64_t n_samp,
+                                      const int8_t* hist, const float* taps, const float2* tw,
+                                      const float2* twp, int prec, void* out, const float* scale,
+                                      hipStream_t s) {
+  switch (prec) {
+    case 0: return launch_chan_ring_w<N, 0, ST>(x, ld_x, n_ant, n_samp, hist, taps, tw, twp, out, scale, s);
+    case 1: return launch_chan_ring_w<N, 1, ST>(x, ld_x, n_ant, n_samp, hist, taps, tw, twp, out, scale, s);
+    case 2: return launch_chan_ring_w<N, 2, ST>(x, ld_x, n_ant, n_samp, hist, taps, tw, twp, out, scale, s);
+    default: return launch_chan_ring_w<N, 3, ST>(x, ld_x, n_ant, n_samp, hist, taps, tw, twp, out, scale, s);
+  }
+}
+
 template <int N>
 static hipError_t launch_chan_ring(const FxArgs& a, int prec, void* out, const float* scale, hipStream_t s) {
-  constexpr int NA = N >= 8192 ? 2 : 4;
-  switch (prec) {
-    case 0: return launch_chan_ring_p<N, NA, 0>(a, out, scale, s);
-    case 1: return launch_chan_ring_p<N, NA, 1>(a, out, scale, s);
-    case 2: return launch_chan_ring_p<N, NA, 2>(a, out, scale, s);
-    default: return launch_chan_ring_p<N, NA, 3>(a, out, scale, s);
-  }
+  return launch_chan_ring_st<N, 0>(a.x, a.ld_x, a.n_ant, a.n_samp, a.hist, a.taps, a.tw, a.twp, prec, out,
+                                   scale, s);
 }
 
 template <int N>
@@ -1291,6 +1357,35 @@ static int g_chan_variant = 0;  // 0: ring variant where it applies, 1: always t
 
 void set_channelize_variant(int v) { g_chan_variant = v; }
 int get_channelize_variant() { return g_chan_variant; }
+
+template <int N>
+static hipError_t launch_chan_ring_any_n(const ChanxArgs& a, int sample, int prec, void* out,
+                                         const float* scale, hipStream_t s) {
+  const int8_t* x = static_cast<const int8_t*>(a.x);
+  const int8_t* h = static_cast<const int8_t*>(a.hist);
+  switch (sample) {
+    case 0: return launch_chan_ring_st<N, 0>(x, a.ld_x, a.n_ant, a.n_samp, h, a.taps, a.tw, a.twp, prec, out, scale, s);
+    case 1: return launch_chan_ring_st<N, 1>(x, a.ld_x, a.n_ant, a.n_samp, h, a.taps, a.tw, a.twp, prec, out, scale, s);
+    case 2: return launch_chan_ring_st<N, 2>(x, a.ld_x, a.n_ant, a.n_samp, h, a.taps, a.tw, a.twp, prec, out, scale, s);
+    case 3: return launch_chan_ring_st<N, 3>(x, a.ld_x, a.n_ant, a.n_samp, h, a.taps, a.tw, a.twp, prec, out, scale, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_channelize_ring_any(const ChanxArgs& a, int sample, int prec, void* out, const float* scale,
+                                      hipStream_t s) {
+  if (g_chan_variant != 0 || a.n_taps != 4 || !a.taps_symmetric) return hipErrorNotSupported;
+  // 16-bit words at N = 8192 (four distinct tap positions per thread and a
+  // ring twice as wide) would spill inside the loop: the plain kernel
+  if (a.n_fft == 8192 && (sample == 1 || sample == 3)) return hipErrorNotSupported;
+  switch (a.n_fft) {
+    case 1024: return launch_chan_ring_any_n<1024>(a, sample, prec, out, scale, s);
+    case 2048: return launch_chan_ring_any_n<2048>(a, sample, prec, out, scale, s);
+    case 4096: return launch_chan_ring_any_n<4096>(a, sample, prec, out, scale, s);
+    case 8192: return launch_chan_ring_any_n<8192>(a, sample, prec, out, scale, s);
+  }
+  return hipErrorNotSupported;
+}
 
 hipError_t launch_channelize(const FxArgs& a, int prec, void* out, const float* scale,
                              hipStream_t s) {

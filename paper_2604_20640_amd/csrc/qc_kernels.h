@@ -60,7 +60,13 @@ struct ChanxArgs {
   const float* taps;  // device [P*N]
   const float2* tw;   // device [N], exp(-2 pi i e/N)
   const void* hist;   // device [n_ant][(P-1)N] samples or null
+  bool taps_symmetric = false;  // h[q] == h[P*N-1-q] (the built-in prototype)
+  const float2* twp = nullptr;  // per-pass twiddles, as in FxArgs
 };
+// The ring F-engine for any word where it applies (P = 4, symmetric taps,
+// N = 1024..8192, ring variant selected); hipErrorNotSupported otherwise.
+hipError_t launch_channelize_ring_any(const ChanxArgs& a, int sample, int prec, void* out, const float* scale,
+                                      hipStream_t s);
 hipError_t launch_channelize_any(const ChanxArgs& a, int sample, int prec, void* out, const float* scale,
                                  hipStream_t s);
 // Scales as launch_scales, from |x|^2 of any input word.

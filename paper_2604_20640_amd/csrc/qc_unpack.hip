@@ -264,6 +264,8 @@ static hipError_t launch_chanx_st(const ChanxArgs& a, int prec, void* out, const
 
 hipError_t launch_channelize_any(const ChanxArgs& a, int sample, int prec, void* out, const float* scale,
                                  hipStream_t s) {
+  const hipError_t r = launch_channelize_ring_any(a, sample, prec, out, scale, s);
+  if (r != hipErrorNotSupported) return r;
   switch (sample) {
     case 0: return launch_chanx_st<0>(a, prec, out, scale, s);
     case 1: return launch_chanx_st<1>(a, prec, out, scale, s);

@@ -70,6 +70,43 @@ def test_channelize_any_word(qc, word, N, n_ant, P, n_spec):
         assert np.array_equal(hout.cpu().numpy(), full[:, full.shape[1] - keep:])
 
 
+# The ring F-engine (P = 4, built-in taps, N = 1024..8192) for every word:
+# several runs of spectra per antenna group (so runs start from in-stream
+# history), partial last groups, a carried history, and the plain kernel's
+# result beside it.  16-bit words at N = 8192 take the plain kernel.
+@pytest.mark.parametrize("word", WORDS)
+@pytest.mark.parametrize("N,n_ant,n_spec", [(4096, 5, 40), (2048, 3, 36), (1024, 7, 40), (8192, 3, 20)])
+def test_channelize_ring_any_word(qc, word, N, n_ant, n_spec):
+    import torch
+    P = 4
+    x = _stream(word, n_ant, N * n_spec, seed=5 * N + n_ant)
+    rng = np.random.default_rng(N + 1)
+    keep = (P - 1) * N
+    shape = (n_ant, keep, 2) if word.startswith("c") else (n_ant, keep)
+    lim = 8000 if word.endswith("16") else 120
+    hist = rng.integers(-lim, lim, shape).astype(x.dtype)
+    xd = torch.from_numpy(x).cuda()
+    hd = torch.from_numpy(hist).cuda()
+    assert qc.channelize_variant() == 0
+    out, _ = qc.pfb_channelize_ex(xd, N, P, hist=hd)
+    chans = np.unique(np.linspace(0, _n_chan(word, N) - 1, 40).astype(int))
+    X_ref = _oracle_X(word, x, N, P, hist=hist, chans=chans)
+    X = out.cpu().numpy()[:, :, chans]
+    rms = np.sqrt(np.mean(np.abs(X_ref) ** 2))
+    err = np.max(np.abs(X - X_ref)) / rms
+    print(f"ring {word} N={N} ants={n_ant}: {err:.2e}")
+    assert err <= TOL
+    try:
+        qc.channelize_variant(1)
+        plain, _ = qc.pfb_channelize_ex(xd, N, P, hist=hd)
+        torch.cuda.synchronize()
+    finally:
+        qc.channelize_variant(0)
+    # two float32 paths (different FFT twiddle forms and rounding orders),
+    # each about 1e-6 of the rms from the oracle
+    assert np.max(np.abs(plain.cpu().numpy() - out.cpu().numpy())) / rms <= 5e-6
+
+
 def test_i8_word_equals_plain_entry_point(qc):
     import torch
     x = _stream("i8", 4, 1024 * 20, seed=3)
