@@ -646,7 +646,28 @@ qc_status qc_xcorrelate_ex(const void* x, int32_t sample, int64_t ld_x, int32_t 
     return fail(QC_EUNSUPPORTED, "matrix-core X-engine needs n_ant <= 32 and n_chan %% 32 == 0");
   if (n_dumps_out) *n_dumps_out = n_dump;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  if (n_dump > 0) {
+  if (n_dump > 0 && x_prec == QC_F32 &&
+      qc::fused_words_supported(sample, N, n_ant, p->n_taps, p->taps == nullptr)) {
+    // real int16 words at a fused ring shape: F+X in one pass, as for int8
+    Resolved r;
+    st = resolve(static_cast<const int8_t*>(x), ld_x, n_ant, n_samp, p, static_cast<const int8_t*>(hist), &r);
+    if (st != QC_OK) return st;
+    r.args.n_samp = n_dump * spec_per_dump * N;
+    const int64_t nb = (int64_t)n_ant * (n_ant + 1) / 2;
+    const int64_t cpd = qc::fused_chunks_per_dump(N, n_ant, n_dump, spec_per_dump);
+    AsyncBuf part;
+    st = alloc_async(part, (size_t)(n_dump * cpd) * nb * n_chan * sizeof(float2), s);
+    if (st != QC_OK) return st;
+    {
+      KTimer t(QC_KERNEL_FX_FUSED, s);
+      QC_HIP(qc::launch_fused_words(r.args, sample, n_dump, spec_per_dump, cpd, (float2*)part.p, s),
+             "fused F+X kernel");
+    }
+    KTimer t(QC_KERNEL_REDUCE, s);
+    QC_HIP(qc::launch_reduce((const float2*)part.p, n_dump, cpd, nb * n_chan, 0.25f, accumulate,
+                             reinterpret_cast<float2*>(vis), s),
+           "reduce kernel");
+  } else if (n_dump > 0) {
     // two passes: the F-engine of the full dumps' spectra to HBM, then the X-engine
     const int64_t ns = n_dump * spec_per_dump;
     AsyncBuf v, scale;

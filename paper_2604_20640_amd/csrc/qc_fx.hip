@@ -58,6 +58,40 @@ __device__ __forceinline__ void settle_words(T* w) {
   for (int i = 0; i < K; ++i) asm volatile("" : "+v"(w[i]));
 }
 
+// Ring words: four consecutive samples of one input row as loaded (Sec. 3.3
+// quantisation modes).  Real words (int8, int16) fill two antennas per
+// packed transform; complex words (I, Q interleaved int8 or int16) fill
+// one antenna per transform, I as the real and Q as the imaginary part.
+template <int ST> struct RingWord;
+template <> struct RingWord<0> { using T = uint32_t; static constexpr int BYTES = 1; static constexpr bool CPLX = false; };
+template <> struct RingWord<1> { using T = uint2; static constexpr int BYTES = 2; static constexpr bool CPLX = false; };
+template <> struct RingWord<2> { using T = uint2; static constexpr int BYTES = 2; static constexpr bool CPLX = true; };
+template <> struct RingWord<3> { using T = uint4; static constexpr int BYTES = 4; static constexpr bool CPLX = true; };
+
+__device__ __forceinline__ float s16(uint32_t w, int hi) {
+  return (float)(int16_t)(hi ? (w >> 16) : (w & 0xffffu));
+}
+// Sample i of a ring word: the real value (real words) or I (complex).
+template <int ST, class T>
+__device__ __forceinline__ float word_re(const T& w, int i) {
+  if constexpr (ST == 0) return sbyte(w, i);
+  else if constexpr (ST == 1) return s16(i < 2 ? w.x : w.y, i & 1);
+  else if constexpr (ST == 2) return sbyte(i < 2 ? w.x : w.y, 2 * (i & 1));
+  else return s16(i == 0 ? w.x : i == 1 ? w.y : i == 2 ? w.z : w.w, 0);
+}
+// Q of sample i of a complex ring word.
+template <int ST, class T>
+__device__ __forceinline__ float word_im(const T& w, int i) {
+  if constexpr (ST == 2) return sbyte(i < 2 ? w.x : w.y, 2 * (i & 1) + 1);
+  else return s16(i == 0 ? w.x : i == 1 ? w.y : i == 2 ? w.z : w.w, 1);
+}
+// An empty asm reading and writing a ring word (keeps its update in place).
+__device__ __forceinline__ void pin_word(uint32_t& w) { asm volatile("" : "+v"(w)); }
+__device__ __forceinline__ void pin_word(uint2& w) { asm volatile("" : "+v"(w.x), "+v"(w.y)); }
+__device__ __forceinline__ void pin_word(uint4& w) {
+  asm volatile("" : "+v"(w.x), "+v"(w.y), "+v"(w.z), "+v"(w.w));
+}
+
 // FIR for 4 consecutive samples n0..n0+3 of spectrum m, antennas a0 (real
 // part) and a1 (imaginary part; a1 < 0 means none).
 __device__ __forceinline__ void fir4(const int8_t* __restrict__ x, int64_t ld_x,
@@ -278,13 +312,20 @@ struct RingCfg {
       sizeof(float2) * (C::LDS + N) + sizeof(float) * TAPS;  // FFT, twiddles, taps
 };
 
-template <int N, int NA, int V, int P>
+// ST selects the input word (real int8 or real int16, Sec. 3.3).  With
+// int16 words the ring is twice as wide, so the taps are read from LDS at
+// each use instead of being held in registers.
+template <int N, int NA, int V, int P, int ST = 0>
 __global__ void __launch_bounds__((FusedCfg<N, NA, 1, V, false, 0>::NT))
 fx_fused_ring_kernel(const int8_t* __restrict__ x, int64_t ld_x, const int8_t* __restrict__ hist,
                      const float* __restrict__ taps, const float2* __restrict__ tw,
                      int64_t spec_per_dump, int64_t cpd, float2* __restrict__ part) {
   using C = FusedCfg<N, NA, 1, V, false, 0>;
   using F = Fft<N, C::NT, V, false, false, true>;
+  using W = RingWord<ST>;
+  using T = typename W::T;
+  static_assert(!W::CPLX, "real words: two antennas per packed transform");
+  constexpr bool TAPS_IN_REGS = ST == 0;
   constexpr int G = C::CHUNKS;
   constexpr int L = P * N;
   extern __shared__ float2 buf[];
@@ -309,27 +350,27 @@ fx_fused_ring_kernel(const int8_t* __restrict__ x, int64_t ld_x, const int8_t* _
   int cn0[G];
 #pragma unroll
   for (int g = 0; g < G; ++g) cn0[g] = 4 * (tid + (g % GP) * C::NT);
-  auto row = [&](int a) -> const int8_t* { return x + (int64_t)a * ld_x; };
+  auto row = [&](int a) -> const int8_t* { return x + (int64_t)a * ld_x * W::BYTES; };
   auto hrow = [&](int a) -> const int8_t* {
-    return hist ? hist + (int64_t)a * (P - 1) * N : nullptr;
+    return hist ? hist + (int64_t)a * (P - 1) * N * W::BYTES : nullptr;
   };
-  auto load_blk = [&](int g, int which, int64_t blk) -> uint32_t {
+  auto load_blk = [&](int g, int which, int64_t blk) -> T {
     const int a = 2 * (g / GP) + which;
-    if (a >= NA) return 0u;
-    if (blk >= 0) return *reinterpret_cast<const uint32_t*>(row(a) + (int)blk * N + cn0[g]);
+    if (a >= NA) return T{};
+    if (blk >= 0) return *reinterpret_cast<const T*>(row(a) + ((int)blk * N + cn0[g]) * W::BYTES);
     const int8_t* h = hrow(a);
-    if (!h) return 0u;
-    return *reinterpret_cast<const uint32_t*>(h + (int)(blk + P - 1) * N + cn0[g]);
+    if (!h) return T{};
+    return *reinterpret_cast<const T*>(h + ((int)(blk + P - 1) * N + cn0[g]) * W::BYTES);
   };
   // Prefetch of stream block nb >= 0 for the next spectrum (block m again
   // on the last one, its value then unused).  The load is unconditional so
   // the loop body stays one basic block and the wait for it falls at the
   // end of the iteration, not inside the FIR.
-  auto load_next = [&](int g, int which, int nb) -> uint32_t {
+  auto load_next = [&](int g, int which, int nb) -> T {
     const int a = 2 * (g / GP) + which;
-    return a < NA ? *reinterpret_cast<const uint32_t*>(row(a) + nb * N + cn0[g]) : 0u;
+    return a < NA ? *reinterpret_cast<const T*>(row(a) + (nb * N + cn0[g]) * W::BYTES) : T{};
   };
-  uint32_t ring[P][G][2];
+  T ring[P][G][2];
 #pragma unroll
   for (int q = 0; q < P; ++q)
 #pragma unroll
@@ -345,76 +386,86 @@ fx_fused_ring_kernel(const int8_t* __restrict__ x, int64_t ld_x, const int8_t* _
 #pragma unroll
     for (int b = 0; b < C::NB; ++b) acc[cc][b] = make_float2(0.f, 0.f);
   __syncthreads();  // taps in LDS
-  // the taps of this thread's GP distinct chunk positions stay in registers
-  // for the whole run (chunks g and g + GP share a position)
-  float4 hr[GP][P];
+  // tap q at the thread's chunk position gp (chunks g and g + GP share one)
+  auto tap = [&](int gp, int q) -> float4 {
+    if (2 * q < P) return tl[(q * N + cn0[gp]) / 4];
+    const float4 r = tl[(L - q * N - cn0[gp] - 4) / 4];
+    return make_float4(r.w, r.z, r.y, r.x);
+  };
+  // with int8 words the taps stay in registers for the whole run
+  float4 hr[TAPS_IN_REGS ? GP : 1][P];
+  if constexpr (TAPS_IN_REGS) {
 #pragma unroll
-  for (int g = 0; g < GP; ++g)
+    for (int g = 0; g < GP; ++g)
 #pragma unroll
-    for (int q = 0; q < P; ++q) {
-      if (2 * q < P) {
-        hr[g][q] = tl[(q * N + cn0[g]) / 4];
-      } else {
-        const float4 r = tl[(L - q * N - cn0[g] - 4) / 4];
-        hr[g][q] = make_float4(r.w, r.z, r.y, r.x);
-      }
-    }
+      for (int q = 0; q < P; ++q) hr[g][q] = tap(g, q);
+  }
 
-  settle_words<P * G * 2>(&ring[0][0][0]);
+  settle_words<P * G * 2 * (int)(sizeof(T) / 4)>(reinterpret_cast<uint32_t*>(&ring[0][0][0]));
   for (int64_t m = m_lo; m < m_hi; ++m) {
-    // prefetch block m+1 (consumed at the end of this iteration)
-    uint32_t nxt[G][2];
+    // prefetch block m+1 (consumed at the end of this iteration); int16
+    // words issue it after the FIR, whose registers it would otherwise
+    // share with the wider ring
+    T nxt[G][2];
     const int nb = (int)(m + 1 < m_hi ? m + 1 : m);
+    auto prefetch = [&]() {
 #pragma unroll
-    for (int g = 0; g < G; ++g) {
-      nxt[g][0] = load_next(g, 0, nb);
-      nxt[g][1] = load_next(g, 1, nb);
-    }
+      for (int g = 0; g < G; ++g) {
+        nxt[g][0] = load_next(g, 0, nb);
+        nxt[g][1] = load_next(g, 1, nb);
+      }
+    };
+    if constexpr (ST == 0) prefetch();
     // polyphase FIR from the ring
 #pragma unroll
     for (int g = 0; g < G; ++g) {
       float y0[4] = {0.f, 0.f, 0.f, 0.f}, y1[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int q = 0; q < P; ++q) {
-        const float4 h = hr[g % GP][q];
-        const uint32_t w0 = ring[q][g][0], w1 = ring[q][g][1];
-        y0[0] += h.x * sbyte(w0, 0);
-        y0[1] += h.y * sbyte(w0, 1);
-        y0[2] += h.z * sbyte(w0, 2);
-        y0[3] += h.w * sbyte(w0, 3);
-        y1[0] += h.x * sbyte(w1, 0);
-        y1[1] += h.y * sbyte(w1, 1);
-        y1[2] += h.z * sbyte(w1, 2);
-        y1[3] += h.w * sbyte(w1, 3);
+        float4 h;
+        if constexpr (TAPS_IN_REGS) h = hr[g % GP][q];
+        else h = tap(g % GP, q);
+        const float hv[4] = {h.x, h.y, h.z, h.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          y0[i] += hv[i] * word_re<ST>(ring[q][g][0], i);
+          y1[i] += hv[i] * word_re<ST>(ring[q][g][1], i);
+        }
       }
 #pragma unroll
       for (int i = 0; i < 4; ++i) b0[lds_pad((g / GP) * N + cn0[g] + i)] = make_float2(y0[i], y1[i]);
     }
+    if constexpr (ST != 0) prefetch();
     __syncthreads();
     F::run(b0, b0, twl, tid);
+    static_assert(C::NCH % C::NT == 0, "every thread has CPT channels");
+    // all of the thread's transform outputs are read before any is used
+    float2 zk[C::CPT][C::NP], zn[C::CPT][C::NP];
 #pragma unroll
     for (int cc = 0; cc < C::CPT; ++cc) {
       const int k = tid + cc * C::NT;
-      if (C::NCH % C::NT == 0 || k < C::NCH) {
-        const int kn = (N - k) & (N - 1);
-        float2 X[2 * C::NP];
+      const int kn = (N - k) & (N - 1);
 #pragma unroll
-        for (int p = 0; p < C::NP; ++p) {
-          const float2 zk = b0[lds_pad(p * N + k)];
-          const float2 zn = b0[lds_pad(p * N + kn)];
-          separate(zk, zn, X[2 * p], X[2 * p + 1]);
-        }
-        int b = 0;
+      for (int p = 0; p < C::NP; ++p) {
+        zk[cc][p] = b0[lds_pad(p * N + k)];
+        zn[cc][p] = b0[lds_pad(p * N + kn)];
+      }
+    }
 #pragma unroll
-        for (int i = 0; i < NA; ++i) {
-          acc[cc][b].x += X[i].x * X[i].x + X[i].y * X[i].y;
+    for (int cc = 0; cc < C::CPT; ++cc) {
+      float2 X[2 * C::NP];
+#pragma unroll
+      for (int p = 0; p < C::NP; ++p) separate(zk[cc][p], zn[cc][p], X[2 * p], X[2 * p + 1]);
+      int b = 0;
+#pragma unroll
+      for (int i = 0; i < NA; ++i) {
+        acc[cc][b].x += X[i].x * X[i].x + X[i].y * X[i].y;
+        ++b;
+#pragma unroll
+        for (int j = i + 1; j < NA; ++j) {
+          acc[cc][b].x += X[i].x * X[j].x + X[i].y * X[j].y;
+          acc[cc][b].y += X[i].y * X[j].x - X[i].x * X[j].y;
           ++b;
-#pragma unroll
-          for (int j = i + 1; j < NA; ++j) {
-            acc[cc][b].x += X[i].x * X[j].x + X[i].y * X[j].y;
-            acc[cc][b].y += X[i].y * X[j].x - X[i].x * X[j].y;
-            ++b;
-          }
         }
       }
     }
@@ -436,10 +487,8 @@ fx_fused_ring_kernel(const int8_t* __restrict__ x, int64_t ld_x, const int8_t* _
 #pragma unroll
   for (int cc = 0; cc < C::CPT; ++cc) {
     const int k = tid + cc * C::NT;
-    if (C::NCH % C::NT == 0 || k < C::NCH) {
 #pragma unroll
-      for (int b = 0; b < C::NB; ++b) out[(int64_t)b * C::NCH + k] = acc[cc][b];
-    }
+    for (int b = 0; b < C::NB; ++b) out[(int64_t)b * C::NCH + k] = acc[cc][b];
   }
 }
 
@@ -692,13 +741,13 @@ static hipError_t launch_fused_ring_pp(const FxArgs& a, int64_t n_dump, int64_t 
   return hipGetLastError();
 }
 
-template <int N, int NA, int V>
+template <int N, int NA, int V, int ST = 0>
 static hipError_t launch_fused_ring(const FxArgs& a, int64_t n_dump, int64_t spd, int64_t cpd,
                                     float2* part, hipStream_t s) {
   using RC = RingCfg<N, NA, V, 4>;
   static_assert(RC::LDS_BYTES <= 160 * 1024, "ring tile: LDS");
   if (a.n_taps != 4) return hipErrorInvalidValue;
-  auto kern = fx_fused_ring_kernel<N, NA, V, 4>;
+  auto kern = fx_fused_ring_kernel<N, NA, V, 4, ST>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)RC::LDS_BYTES);
   if (e != hipSuccess) return e;
@@ -812,6 +861,24 @@ int64_t fused_chunks_per_dump(int n_fft, int n_ant, int64_t n_dump, int64_t spd)
   int64_t maxc = spd / 8 > 0 ? spd / 8 : 1;
   int64_t c = want < maxc ? want : maxc;
   return c < 1 ? 1 : c;
+}
+
+// Fused F+X of real int16 words (the 16-bit padded mode): the in-place ring
+// tile, for the shapes that have one, with P = 4 and the built-in prototype.
+bool fused_words_supported(int sample, int n_fft, int n_ant, int n_taps, bool taps_symmetric) {
+  if (sample != 1 || n_taps != 4 || !taps_symmetric) return false;
+  return (n_ant == 4 && (n_fft == 1024 || n_fft == 2048 || n_fft == 4096)) || (n_ant == 2 && n_fft == 4096);
+}
+
+hipError_t launch_fused_words(const FxArgs& a, int sample, int64_t n_dump, int64_t spd, int64_t cpd,
+                              float2* part, hipStream_t s) {
+  if (!fused_words_supported(sample, a.n_fft, a.n_ant, a.n_taps, a.taps_symmetric)) return hipErrorNotSupported;
+  if (a.n_ant == 2) return launch_fused_ring<4096, 2, 16, 1>(a, n_dump, spd, cpd, part, s);
+  switch (a.n_fft) {
+    case 1024: return launch_fused_ring<1024, 4, 16, 1>(a, n_dump, spd, cpd, part, s);
+    case 2048: return launch_fused_ring<2048, 4, 16, 1>(a, n_dump, spd, cpd, part, s);
+    default: return launch_fused_ring<4096, 4, 16, 1>(a, n_dump, spd, cpd, part, s);
+  }
 }
 
 hipError_t launch_fused(const FxArgs& a, int64_t n_dump, int64_t spd, int64_t cpd, float2* part,
@@ -1019,44 +1086,6 @@ struct ChanRingCfg {
   }
   static constexpr size_t LDS_BYTES = lds_bytes();
 };
-
-// Body of the ring F-engine for antenna group grp and run chk of spb
-// spectra, by all threads of a block, on an LDS region of
-// ChanRingCfg<N, NA, V, P, PP>::LDS_BYTES.  twp: the per-pass twiddle
-// table (read with PP only).
-// Ring words: four consecutive samples of one input row as loaded (Sec. 3.3
-// quantisation modes).  Real words (int8, int16) fill two antennas per
-// packed transform; complex words (I, Q interleaved int8 or int16) fill
-// one antenna per transform, I as the real and Q as the imaginary part.
-template <int ST> struct RingWord;
-template <> struct RingWord<0> { using T = uint32_t; static constexpr int BYTES = 1; static constexpr bool CPLX = false; };
-template <> struct RingWord<1> { using T = uint2; static constexpr int BYTES = 2; static constexpr bool CPLX = false; };
-template <> struct RingWord<2> { using T = uint2; static constexpr int BYTES = 2; static constexpr bool CPLX = true; };
-template <> struct RingWord<3> { using T = uint4; static constexpr int BYTES = 4; static constexpr bool CPLX = true; };
-
-__device__ __forceinline__ float s16(uint32_t w, int hi) {
-  return (float)(int16_t)(hi ? (w >> 16) : (w & 0xffffu));
-}
-// Sample i of a ring word: the real value (real words) or I (complex).
-template <int ST, class T>
-__device__ __forceinline__ float word_re(const T& w, int i) {
-  if constexpr (ST == 0) return sbyte(w, i);
-  else if constexpr (ST == 1) return s16(i < 2 ? w.x : w.y, i & 1);
-  else if constexpr (ST == 2) return sbyte(i < 2 ? w.x : w.y, 2 * (i & 1));
-  else return s16(i == 0 ? w.x : i == 1 ? w.y : i == 2 ? w.z : w.w, 0);
-}
-// Q of sample i of a complex ring word.
-template <int ST, class T>
-__device__ __forceinline__ float word_im(const T& w, int i) {
-  if constexpr (ST == 2) return sbyte(i < 2 ? w.x : w.y, 2 * (i & 1) + 1);
-  else return s16(i == 0 ? w.x : i == 1 ? w.y : i == 2 ? w.z : w.w, 1);
-}
-// An empty asm reading and writing a ring word (keeps its update in place).
-__device__ __forceinline__ void pin_word(uint32_t& w) { asm volatile("" : "+v"(w)); }
-__device__ __forceinline__ void pin_word(uint2& w) { asm volatile("" : "+v"(w.x), "+v"(w.y)); }
-__device__ __forceinline__ void pin_word(uint4& w) {
-  asm volatile("" : "+v"(w.x), "+v"(w.y), "+v"(w.z), "+v"(w.w));
-}
 
 // Body of the ring F-engine for antenna group grp and run chk of spb
 // spectra, by all threads of a block, on an LDS region of

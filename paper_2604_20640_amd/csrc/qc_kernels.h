@@ -63,6 +63,12 @@ struct ChanxArgs {
   bool taps_symmetric = false;  // h[q] == h[P*N-1-q] (the built-in prototype)
   const float2* twp = nullptr;  // per-pass twiddles, as in FxArgs
 };
+// Fused F+X of real int16 words where a ring tile applies (n_ant 4 at
+// N = 1024, 2048, 4096, or 2 at 4096; P = 4, the built-in prototype); the
+// partials as launch_fused's.
+bool fused_words_supported(int sample, int n_fft, int n_ant, int n_taps, bool taps_symmetric);
+hipError_t launch_fused_words(const FxArgs& a, int sample, int64_t n_dump, int64_t spd, int64_t cpd,
+                              float2* part, hipStream_t s);
 // The ring F-engine for any word where it applies (P = 4, symmetric taps,
 // N = 1024..8192, ring variant selected); hipErrorNotSupported otherwise.
 hipError_t launch_channelize_ring_any(const ChanxArgs& a, int sample, int prec, void* out, const float* scale,

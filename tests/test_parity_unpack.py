@@ -138,6 +138,31 @@ def test_xcorrelate_any_word(qc, word, N, n_ant, n_spec, spd):
         assert np.all(V[:, b].imag == 0) and np.all(V[:, b].real >= 0)
 
 
+# Real int16 words at a ring-tile shape take the fused F+X kernel (P = 4,
+# built-in taps): several chunks per dump, a carried history, accumulation.
+@pytest.mark.parametrize("N,n_ant,n_spec,spd", [(4096, 4, 24, 8), (4096, 2, 20, 10), (2048, 4, 30, 10),
+                                                (1024, 4, 36, 12)])
+def test_xcorrelate_i16_fused(qc, N, n_ant, n_spec, spd):
+    import torch
+    P = 4
+    x = _stream("i16", n_ant, N * n_spec, seed=3 * N + n_ant)
+    rng = np.random.default_rng(N + n_ant)
+    hist = rng.integers(-8000, 8000, (n_ant, (P - 1) * N)).astype(np.int16)
+    xd, hd = torch.from_numpy(x).cuda(), torch.from_numpy(hist).cuda()
+    hout = torch.empty_like(hd)
+    V = qc.xcorrelate_ex(xd, N, P, spd, hist=hd, hist_out=hout)
+    V_ref = xengine.correlate_fast(pfb.channelize(x, N, P, hist=hist), spd)
+    err = vis_err(V.cpu().numpy(), V_ref, n_ant)
+    print(f"i16 fused {n_ant} ant N={N}: {err:.2e}")
+    assert err <= TOL
+    full = np.concatenate([hist, x], axis=1)
+    assert np.array_equal(hout.cpu().numpy(), full[:, full.shape[1] - (P - 1) * N:])
+    # accumulate adds onto what vis holds
+    W = qc.xcorrelate_ex(xd, N, P, spd, hist=hd, vis=V.clone(), accumulate=True)
+    torch.cuda.synchronize()
+    assert np.max(np.abs(W.cpu().numpy() - 2 * V.cpu().numpy())) <= 1e-6 * np.abs(V_ref).max()
+
+
 @pytest.mark.parametrize("word", ["i16", "ci8", "ci16"])
 @pytest.mark.parametrize("prec", ["f16", "bf16", "fp8"])
 def test_requantised_any_word(qc, word, prec):
