@@ -371,7 +371,30 @@ __device__ __forceinline__ bool window_select(int64_t n, int64_t k, bool want2, 
     return q >= (K)(NBINS - 2) ? (unsigned)(NBINS - 1) : (unsigned)q + 1u;
   };
   __syncthreads();  // lo and sh read before sh[] is reused
-  for_keys<NT, K>(n, key, [&](int64_t, K kv) { atomicAdd(&sc.hist[bin(kv)], 1u); });
+  // keys outside the window all land in the two end bins: counted in
+  // registers and added once per wave instead of by same-address atomics
+  // (32-bit keys; with 64-bit keys the extra tests cost more VALU time
+  // than the atomics they save)
+  if constexpr (sizeof(K) == 4) {
+    unsigned under = 0u, over = 0u;
+    for_keys<NT, K>(n, key, [&](int64_t, K kv) {
+      const unsigned q = bin(kv);
+      if (q == 0u) ++under;
+      else if (q == (unsigned)(NBINS - 1)) ++over;
+      else atomicAdd(&sc.hist[q], 1u);
+    });
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+      under += __shfl_xor(under, d);
+      over += __shfl_xor(over, d);
+    }
+    if (lane == 0) {
+      if (under) atomicAdd(&sc.hist[0], under);
+      if (over) atomicAdd(&sc.hist[NBINS - 1], over);
+    }
+  } else {
+    for_keys<NT, K>(n, key, [&](int64_t, K kv) { atomicAdd(&sc.hist[bin(kv)], 1u); });
+  }
   __syncthreads();
   find_digit<NT, NBINS>(sc.hist, k, sc.wsum, sc.sh);
   const unsigned b = (unsigned)__builtin_amdgcn_readfirstlane((int)sc.sh[0]);
@@ -555,7 +578,7 @@ mad_kernel(const float2* __restrict__ vis, int64_t n_time, int64_t n_base, int n
   __shared__ unsigned long long red[2 * (NT / 64)];
   __shared__ unsigned long long cand[SEL_CAND];
   __shared__ unsigned ncand;
-  extern __shared__ float acache[];  // [cap] amplitude cache, then [comp_cap] compaction buffer
+  extern __shared__ __align__(16) float acache[];  // [cap] amplitude cache, then [comp_cap] compaction buffer
   const int64_t id = blockIdx.x;
   const Pop pop = make_pop(id, n_time, n_base, n_chan, population);
   const int64_t n = pop.count;
@@ -565,7 +588,36 @@ mad_kernel(const float2* __restrict__ vis, int64_t n_time, int64_t n_base, int n
   // one pass: the amplitudes into the LDS cache (when they fit) and the
   // range of their keys
   uint32_t amin = ~0u, amax = 0u;
-  {
+  const bool vec4 = gamp && cached && n % 4 == 0 && (reinterpret_cast<uintptr_t>(gamp + id * n) & 15u) == 0;
+  if (vec4) {
+    // four amplitudes per 16-byte load, eight loads in flight per thread
+    constexpr int U = 8;
+    const float4* g4 = reinterpret_cast<const float4*>(gamp + id * n);
+    float4* c4 = reinterpret_cast<float4*>(acache);
+    const int64_t n4 = n / 4;
+    for (int64_t j0 = threadIdx.x; j0 < n4; j0 += (int64_t)U * NT) {
+      float4 a[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t j = j0 + (int64_t)u * NT;
+        a[u] = j < n4 ? g4[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t j = j0 + (int64_t)u * NT;
+        if (j < n4) {
+          c4[j] = a[u];
+          const uint32_t k4[4] = {__float_as_uint(a[u].x), __float_as_uint(a[u].y), __float_as_uint(a[u].z),
+                                  __float_as_uint(a[u].w)};
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            amin = k4[v] < amin ? k4[v] : amin;
+            amax = k4[v] > amax ? k4[v] : amax;
+          }
+        }
+      }
+    }
+  } else {
     // eight loads in flight per thread before their amplitudes are formed
     constexpr int U = 8;
     for (int64_t i0 = threadIdx.x; i0 < n; i0 += (int64_t)U * NT) {
@@ -656,7 +708,29 @@ mad_kernel(const float2* __restrict__ vis, int64_t n_time, int64_t n_base, int n
   const double c = (double)sigma * 1.4826;
   const double T = med + c * madv;
   if (mask) {
-    if (cached && pop.inner_n >= NT) {
+    if (cached && pop.s_inner == 1 && pop.inner_n % 4 == 0 && pop.base % 4 == 0 && pop.s_outer % 4 == 0 &&
+        (reinterpret_cast<uintptr_t>(mask) & 3u) == 0 && n % 4 == 0) {
+      // four consecutive elements (one row, contiguous flags) per thread:
+      // one 16-byte LDS read and one 4-byte store; element 4j = q * inner_n + r
+      const float4* c4 = reinterpret_cast<const float4*>(acache);
+      const int64_t n4 = n / 4;
+      int64_t q = 0, r = 4 * (int64_t)threadIdx.x;
+      while (r >= pop.inner_n) {
+        r -= pop.inner_n;
+        ++q;
+      }
+      for (int64_t j = threadIdx.x; j < n4; j += NT) {
+        const float4 a = c4[j];
+        const uint32_t f = ((double)a.x > T ? 1u : 0u) | ((double)a.y > T ? 1u << 8 : 0u) |
+                           ((double)a.z > T ? 1u << 16 : 0u) | ((double)a.w > T ? 1u << 24 : 0u);
+        *reinterpret_cast<uint32_t*>(mask + pop.base + q * pop.s_outer + r) = f;
+        r += 4 * NT;
+        while (r >= pop.inner_n) {
+          r -= pop.inner_n;
+          ++q;
+        }
+      }
+    } else if (cached && pop.inner_n >= NT) {
       // element i = q * inner_n + r; a step of NT carries into q at most once
       int64_t q = 0, r = threadIdx.x;
       for (int64_t i = threadIdx.x; i < n; i += NT) {
