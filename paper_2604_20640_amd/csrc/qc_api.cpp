@@ -1019,7 +1019,6 @@ qc_status persist_build(qc_plan* P) {
     A.taps = te.dev;
     A.tw = tw;
     const int64_t elems = NB * NCH;
-    A.n_red_blocks = (int32_t)((elems + qc::PL_RED_BLOCK - 1) / qc::PL_RED_BLOCK);
     void* part = nullptr;
     if (qc::plan_fused_supported(N, NA)) {
       A.mode = 0;
@@ -1036,11 +1035,12 @@ qc_status persist_build(qc_plan* P) {
     } else {
       A.mode = 1;
       const int64_t ns = A.n_dump * A.spd;
-      // F-engine items: the ring body (groups of 4 antennas at N = 4096, 2
-      // at 8192, the built-in P = 4 prototype) or the plain body
-      const bool ring = (N == 4096 || N == 8192) && D.n_taps == 4;
+      // F-engine items: the ring body (groups of 8 antennas at N = 2048, 4
+      // at 4096, 2 at 8192: 512 threads each; the built-in P = 4 prototype)
+      // or the plain body
+      const bool ring = (N == 2048 || N == 4096 || N == 8192) && D.n_taps == 4;
       if (ring) {
-        const int na_g = N == 8192 ? 2 : 4;
+        const int na_g = N == 8192 ? 2 : N == 4096 ? 4 : 8;
         const int64_t groups = (NA + na_g - 1) / na_g;
         int64_t spb = (ns * groups + 511) / 512;  // about 512 items, runs of >= 16 spectra
         spb = std::max<int64_t>(16, spb);
@@ -1084,14 +1084,47 @@ qc_status persist_build(qc_plan* P) {
     if (e != hipSuccess) return fail(QC_ENOMEM, "plan partial buffer: %s", hipGetErrorString(e));
     P->bufs.push_back(part);
     A.part = (float2*)part;
+    // reduction items of about PL_RED_LOADS partial loads each: many
+    // visibilities where there are few partials, few where there are many
+    int64_t rb = qc::PL_RED_LOADS / std::max<int64_t>(1, A.n_split);
+    rb = std::max<int64_t>(qc::PL_NT, std::min<int64_t>(rb, 64 * qc::PL_NT));
+    rb = (rb / qc::PL_NT) * qc::PL_NT;
+    A.red_block = (int32_t)rb;
+    A.n_red_blocks = (int32_t)((elems + rb - 1) / rb);
     for (int64_t q = 0; q < A.n_dump * A.n_red_blocks; ++q) red.push_back({qc::PL_REDUCE, (uint16_t)i, (uint32_t)q});
   }
-  // spectra items of the two-pass arrays first (they feed the longest chains)
+  // spectra items of the two-pass arrays first (they feed the longest
+  // chains), then the X-engine items array by array; an array's reduction
+  // items follow the next array's X items (by then its partials are
+  // normally done, so they neither wait nor pile up at the end)
   std::stable_sort(first.begin(), first.end(),
                    [](const qc::PlItem& a, const qc::PlItem& b) { return a.kind > b.kind; });
   P->items = first;
-  P->items.insert(P->items.end(), xeng.begin(), xeng.end());
-  P->items.insert(P->items.end(), red.begin(), red.end());
+  std::vector<int> x_order;  // arrays with X items, in queue order
+  for (const qc::PlItem& it : xeng)
+    if (x_order.empty() || x_order.back() != it.array) x_order.push_back(it.array);
+  auto put_red = [&](int arr) {
+    for (const qc::PlItem& it : red)
+      if (it.array == arr) P->items.push_back(it);
+  };
+  std::vector<bool> red_done(P->n, false);
+  for (size_t j = 0; j < x_order.size(); ++j) {
+    for (const qc::PlItem& it : xeng)
+      if (it.array == x_order[j]) P->items.push_back(it);
+    if (j == 0) {
+      // the fused arrays' partials come from the first items of the queue
+      for (int i = 0; i < P->n; ++i)
+        if (P->arr[i].mode == 0) {
+          put_red(i);
+          red_done[i] = true;
+        }
+    } else {
+      put_red(x_order[j - 1]);
+      red_done[x_order[j - 1]] = true;
+    }
+  }
+  for (int i = 0; i < P->n; ++i)
+    if (!red_done[i]) put_red(i);
   if (P->items.size() >= 0x7fffffffu) return fail(QC_EUNSUPPORTED, "too many plan items");
   // the persistent kernel relies on these: per array, the counted items
   // match the wait targets, and every item precedes the items that wait on it

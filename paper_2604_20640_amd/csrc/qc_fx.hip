@@ -1729,7 +1729,8 @@ __device__ __forceinline__ PlArray load_uniform(const PlArray* Ap) {
   A.x_kind = uni(p->x_kind);
   A.n_cb = uni(p->n_cb);
   A.tile = uni(p->tile);
-  A.pad0 = A.pad1 = 0;
+  A.red_block = uni(p->red_block);
+  A.pad1 = 0;
   return A;
 }
 
@@ -1739,10 +1740,12 @@ __device__ __noinline__ void reduce_item(const PlArray* __restrict__ Ap, int64_t
   const int64_t nb = (int64_t)A.n_ant * (A.n_ant + 1) / 2;
   const int64_t elems = nb * (A.n_fft / 2);
   const int64_t d = index / A.n_red_blocks, eb = index % A.n_red_blocks;
-  const int64_t e_end = min(elems, (eb + 1) * (int64_t)PL_RED_BLOCK);
-  for (int64_t e = eb * PL_RED_BLOCK + threadIdx.x; e < e_end; e += PL_NT) {
+  const int64_t e_end = min(elems, (eb + 1) * (int64_t)A.red_block);
+  for (int64_t e = eb * A.red_block + threadIdx.x; e < e_end; e += PL_NT) {
     float2 acc = make_float2(0.f, 0.f);
     const float2* p = A.part + d * A.n_split * elems + e;
+    // partials added in order; unrolled so that several loads are in flight
+#pragma unroll 8
     for (int64_t c = 0; c < A.n_split; ++c) {
       const float2 v = p[c * elems];
       acc.x += v.x;
@@ -1922,7 +1925,8 @@ __global__ void __launch_bounds__(PL_NT) plan_kernel(PlArgs a) {
           case 8192: plan_chan<8192>(Ap, item.index, buf); break;
         }
       } else if (item.kind == PL_CHAN_RING) {
-        if (N == 4096) plan_chan_ring<4096, 4>(Ap, item.index, buf);
+        if (N == 2048) plan_chan_ring<2048, 8>(Ap, item.index, buf);
+        else if (N == 4096) plan_chan_ring<4096, 4>(Ap, item.index, buf);
         else plan_chan_ring<8192, 2>(Ap, item.index, buf);
       } else if (item.kind == PL_XENG) {
         xeng_item(Ap, item.index);

@@ -144,7 +144,7 @@ hipError_t launch_solve(const float2* vis, const uint8_t* mask, int64_t n_time, 
 // ---- batched plans: one persistent launch over heterogeneous work items ----
 constexpr int PL_NT = 512;          // threads per block of the persistent kernel
 constexpr int PL_MAX_ARRAYS = 8;
-constexpr int PL_RED_BLOCK = 2048;  // visibilities per reduction item
+constexpr int PL_RED_LOADS = 1 << 16;  // partial loads per reduction item (sizing target)
 
 // Work-item kinds: fused F+X; F-engine (plain body, or the ring body at
 // N = 4096 / 8192); X-engine (vector ALU, or matrix cores for 5..32
@@ -168,7 +168,8 @@ struct PlArray {
   int32_t x_kind;                        // 0 vector ALU, 1 matrix cores 32 x 32, 2 matrix cores 16 x 16
   int32_t n_cb;                          // matrix-core X items: channel blocks of 16
   int32_t tile;                          // partials: 0 [baseline][chan], else tile-major of this width
-  int32_t pad0, pad1;
+  int32_t red_block;                     // reduction items: visibilities per item (a multiple of PL_NT)
+  int32_t pad1;
 };
 
 struct PlItem {
