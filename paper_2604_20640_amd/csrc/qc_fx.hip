@@ -188,7 +188,7 @@ __device__ __forceinline__ void fir4_t(const int8_t* __restrict__ xa0, const int
 
 // Body of the fused kernel for work unit w (chunk w % cpd of dump w / cpd),
 // run by all C::NT threads of a block on the LDS region buf.
-template <int N, int NA, int S, int V, bool PP, int OCC, int PT>
+template <int N, int NA, int S, int V, bool PP, int OCC, int PT, bool WT = false>
 __device__ __forceinline__ void fused_body(const int8_t* __restrict__ x, int64_t ld_x,
                                            const int8_t* __restrict__ hist,
                                            const float* __restrict__ taps, int P_rt,
@@ -283,7 +283,7 @@ __device__ __forceinline__ void fused_body(const int8_t* __restrict__ x, int64_t
     const int k = (int)threadIdx.x + cc * C::NT;
     if (C::NCH % C::NT == 0 || k < C::NCH) {
 #pragma unroll
-      for (int b = 0; b < C::NB; ++b) out[(int64_t)b * C::NCH + k] = acc[cc][b];
+      for (int b = 0; b < C::NB; ++b) st_f2<WT>(&out[(int64_t)b * C::NCH + k], acc[cc][b]);
     }
   }
 }
@@ -981,7 +981,7 @@ struct ChanCfg {
 
 // Body of the F-engine for antenna pair p and spectra block bx (spec_per_blk
 // spectra), run by all NT threads of a block on the LDS region buf.
-template <int N, int SS, int PREC>
+template <int N, int SS, int PREC, bool WT = false>
 __device__ __forceinline__ void chan_body(const int8_t* __restrict__ x, int64_t ld_x, int n_ant,
                                           int64_t n_spec, const int8_t* __restrict__ hist,
                                           const float* __restrict__ taps, int P,
@@ -1032,8 +1032,8 @@ __device__ __forceinline__ void chan_body(const int8_t* __restrict__ x, int64_t 
         const int64_t ib = ((int64_t)a1 * n_spec + m) * C::NCH + k;
         if constexpr (PREC == 0) {
           float2* o = reinterpret_cast<float2*>(out);
-          o[ia] = make_float2(ya.x * 0.5f, ya.y * 0.5f);
-          if (a1 >= 0) o[ib] = make_float2(yb.x * 0.5f, yb.y * 0.5f);
+          st_f2<WT>(&o[ia], make_float2(ya.x * 0.5f, ya.y * 0.5f));
+          if (a1 >= 0) st_f2<WT>(&o[ib], make_float2(yb.x * 0.5f, yb.y * 0.5f));
         } else if constexpr (PREC == 1 || PREC == 2) {
           uint32_t* o = reinterpret_cast<uint32_t*>(out);
           auto enc = [](float v) -> uint32_t {
@@ -1094,7 +1094,7 @@ struct ChanRingCfg {
 // pointers to rows of ST words (ld_x in samples).  twp: the per-pass
 // twiddle table (read with PP only).  Output [antenna][spectrum][channel]:
 // N/2 channels for real words (separated, times 1/2), N for complex words.
-template <int N, int NA, int V, int P, int PREC, bool PP = false, int ST = 0>
+template <int N, int NA, int V, int P, int PREC, bool PP = false, int ST = 0, bool WT = false>
 __device__ __forceinline__ void chan_ring_body(const int8_t* __restrict__ x, int64_t ld_x, int n_ant,
                                                const int8_t* __restrict__ hist, const float* __restrict__ taps,
                                                const float2* __restrict__ tw, int64_t n_spec, int64_t spb,
@@ -1246,7 +1246,7 @@ __device__ __forceinline__ void chan_ring_body(const int8_t* __restrict__ x, int
     auto put = [&](int a, int k, float2 y, float hh) {
       const int64_t idx = ((int64_t)a * n_spec + m) * NCH + k;
       if constexpr (PREC == 0) {
-        reinterpret_cast<float2*>(out)[idx] = make_float2(y.x * hh, y.y * hh);
+        st_f2<WT>(&reinterpret_cast<float2*>(out)[idx], make_float2(y.x * hh, y.y * hh));
       } else if constexpr (PREC == 1) {
         reinterpret_cast<uint32_t*>(out)[idx] = enc_f16(y.x * hh) | (enc_f16(y.y * hh) << 16);
       } else if constexpr (PREC == 2) {
@@ -1535,7 +1535,7 @@ hipError_t launch_hist_copy(const int8_t* x, int64_t ld_x, int n_ant, int64_t n_
 // ---------------------------------------------------------------------------
 // Body of the X-engine for channel group cg (NTX channels), antenna block
 // pair bp and run dz (= dump * ksplit + split).
-template <int NTX>
+template <int NTX, bool WT = false>
 __device__ __forceinline__ void xeng_f32_body(const float2* __restrict__ v, int n_ant, int64_t n_spec,
                                               int n_chan, int64_t spec_per_dump, int64_t ksplit,
                                               int cg, int bp_in, int64_t dz, float2* __restrict__ part) {
@@ -1586,7 +1586,7 @@ __device__ __forceinline__ void xeng_f32_body(const float2* __restrict__ v, int 
         const int b = gi * n_ant - gi * (gi - 1) / 2 + (gj - gi);
         float2 r = acc[i][j];
         if (gi == gj) r.y = 0.f;
-        out[(int64_t)b * n_chan + k] = r;
+        st_f2<WT>(&out[(int64_t)b * n_chan + k], r);
       }
     }
 }
@@ -1769,10 +1769,10 @@ __device__ __noinline__ void plan_fused(const PlArray* __restrict__ Ap, int64_t 
   constexpr int S = 8192 / (((NA + 1) / 2) * N);
   static_assert(FusedCfg<N, NA, S, 16, false, 0>::NT == PL_NT, "plan fused tile");
   if (A.n_taps == 4)
-    fused_body<N, NA, S, 16, false, 0, 4>(A.x, A.n_samp, nullptr, A.taps, 4, A.tw, A.spd, A.n_split,
+    fused_body<N, NA, S, 16, false, 0, 4, true>(A.x, A.n_samp, nullptr, A.taps, 4, A.tw, A.spd, A.n_split,
                                           A.part, w, buf);
   else
-    fused_body<N, NA, S, 16, false, 0, 0>(A.x, A.n_samp, nullptr, A.taps, A.n_taps, A.tw, A.spd,
+    fused_body<N, NA, S, 16, false, 0, 0, true>(A.x, A.n_samp, nullptr, A.taps, A.n_taps, A.tw, A.spd,
                                           A.n_split, A.part, w, buf);
 }
 
@@ -1787,7 +1787,7 @@ __device__ __noinline__ void plan_chan(const PlArray* __restrict__ Ap, int64_t i
   const int p = (int)(index % n_pair);
   const int64_t bx = index / n_pair;
   const int64_t n_spec = A.n_dump * A.spd;
-  chan_body<N, S, 0>(A.x, A.n_samp, A.n_ant, n_spec, nullptr, A.taps, A.n_taps, A.tw,
+  chan_body<N, S, 0, true>(A.x, A.n_samp, A.n_ant, n_spec, nullptr, A.taps, A.n_taps, A.tw,
                      A.spec_per_item, nullptr, A.chan, bx, p, buf);
 }
 
@@ -1798,7 +1798,7 @@ __device__ __noinline__ void xeng_item(const PlArray* __restrict__ Ap, int64_t i
   const int64_t per_dz = (int64_t)A.n_bp * A.n_cgrp;
   const int64_t dz = index / per_dz;
   const int rem = (int)(index % per_dz);
-  xeng_f32_body<PL_NT>(A.chan, A.n_ant, A.n_dump * A.spd, A.n_fft / 2, A.spd, A.n_split,
+  xeng_f32_body<PL_NT, true>(A.chan, A.n_ant, A.n_dump * A.spd, A.n_fft / 2, A.spd, A.n_split,
                        rem % A.n_cgrp, rem / A.n_cgrp, dz, A.part);
 }
 
@@ -1809,7 +1809,7 @@ __device__ __noinline__ void plan_chan_ring(const PlArray* __restrict__ Ap, int6
   float2* buf = uni(buf_in);
   static_assert(FusedCfg<N, NA, 1, 16, false, 0>::NT == PL_NT, "plan ring F-engine tile");
   static_assert(ChanRingCfg<N, NA, 16, 4>::LDS_BYTES <= PLAN_LDS, "plan ring F-engine LDS");
-  chan_ring_body<N, NA, 16, 4, 0>(A.x, A.n_samp, A.n_ant, nullptr, A.taps, A.tw, A.n_dump * A.spd, A.spb,
+  chan_ring_body<N, NA, 16, 4, 0, false, 0, true>(A.x, A.n_samp, A.n_ant, nullptr, A.taps, A.tw, A.n_dump * A.spd, A.spb,
                                   (int)(index / A.n_chunks), index % A.n_chunks, nullptr, A.chan, buf);
 }
 
@@ -1823,9 +1823,9 @@ __device__ __noinline__ void plan_xmfma(const PlArray* __restrict__ Ap, int64_t 
   const int64_t dz = index / A.n_cb;
   const int64_t n_spec = A.n_dump * A.spd;
   if (A.x_kind == 1)
-    xeng_mfma_body<0>(A.chan, nullptr, A.n_ant, n_spec, A.n_fft / 2, A.spd, A.n_split, cb, dz, A.part, st0, st1);
+    xeng_mfma_body<0, true>(A.chan, nullptr, A.n_ant, n_spec, A.n_fft / 2, A.spd, A.n_split, cb, dz, A.part, st0, st1);
   else
-    xeng_mfma_body<4>(A.chan, nullptr, A.n_ant, n_spec, A.n_fft / 2, A.spd, A.n_split, cb, dz, A.part, st0, st1);
+    xeng_mfma_body<4, true>(A.chan, nullptr, A.n_ant, n_spec, A.n_fft / 2, A.spd, A.n_split, cb, dz, A.part, st0, st1);
 }
 
 // Every branch of the persistent loop below is wave-uniform.  The claim, the
@@ -1937,13 +1937,18 @@ __global__ void __launch_bounds__(PL_NT) plan_kernel(PlArgs a) {
       }
     }
     if (item.kind != PL_REDUCE) {
-      // publish: every wave writes its stores back at agent scope, then one
-      // release increment counts the item done (skipped items count too)
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      // publish.  What an item hands on (spectra, partials) was written
+      // with agent-scope stores (st_f2<true>), which write through the L2;
+      // every wave waits until its stores are complete, the barrier joins
+      // the waves, and one increment counts the item done (skipped items
+      // count too).  The consumers' acquire (plan_wait) invalidates their
+      // L2.  An agent-scope release here would also write back the whole
+      // L2 of this XCD, about 20 us per item.
+      __builtin_amdgcn_s_waitcnt(0x0f70);  // vmcnt(0)
       __syncthreads();
       if (wave == 0)
         __hip_atomic_fetch_add((item.kind == PL_CHAN || item.kind == PL_CHAN_RING) ? done_chan : done_part,
-                               (threadIdx.x & 63u) == 0u ? 1u : 0u, __ATOMIC_RELEASE,
+                               (threadIdx.x & 63u) == 0u ? 1u : 0u, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
     } else {
       __syncthreads();  // LDS and s_item reuse

@@ -172,6 +172,21 @@ struct PlArray {
   int32_t pad1;
 };
 
+// A float2 store for data that workgroups of the persistent plan kernel
+// hand to one another.  WT = true: an agent-scope relaxed atomic store,
+// which writes through the XCD's L2 to the device's coherence point, so
+// that publishing needs no writeback of the L2 (see plan_kernel).  The
+// separate kernels use plain stores (WT = false).
+template <bool WT>
+__device__ __forceinline__ void st_f2(float2* p, float2 v) {
+  if constexpr (WT) {
+    const uint64_t b = ((uint64_t)__float_as_uint(v.y) << 32) | __float_as_uint(v.x);
+    __hip_atomic_store(reinterpret_cast<uint64_t*>(p), b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  } else {
+    *p = v;
+  }
+}
+
 struct PlItem {
   uint16_t kind, array;
   uint32_t index;

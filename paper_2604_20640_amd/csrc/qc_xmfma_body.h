@@ -165,7 +165,7 @@ __device__ __forceinline__ void split_range(int64_t spd, int64_t ksplit, int64_t
 // Body of the matrix-core X-engine for channel block cb (CB channels) and
 // run dz = dump * ksplit + split, by all XM_NT threads of a block, with two
 // LDS stage buffers of XM_STAGE bytes each (16-byte aligned).
-template <int PREC>
+template <int PREC, bool WT = false>
 __device__ __forceinline__ void xeng_mfma_body(const void* __restrict__ vin, const float* __restrict__ scale,
                                                int n_ant, int64_t n_spec, int n_chan, int64_t spec_per_dump,
                                                int64_t ksplit, int cb, int64_t dz, float2* __restrict__ part,
@@ -352,7 +352,7 @@ __device__ __forceinline__ void xeng_mfma_body(const void* __restrict__ vin, con
     }
   }
   __syncthreads();
-  for (int q = tid; q < nb * C::CB; q += XM_NT) out[q] = trow(q / C::CB)[q % C::CB];
+  for (int q = tid; q < nb * C::CB; q += XM_NT) st_f2<WT>(&out[q], trow(q / C::CB)[q % C::CB]);
 }
 
 }  // namespace

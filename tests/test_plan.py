@@ -181,6 +181,32 @@ def test_plan_is_deterministic_and_overwrites(qc, mode):
 
 
 @pytest.mark.gpu
+def test_plan_persistent_new_inputs_each_execution(qc):
+    """Executions on alternating inputs: each result equals the graph mode's
+    for the same input.  The persistent kernel hands spectra and partials
+    between workgroups through buffers that every execution reuses, so data
+    left over from the previous execution (or not yet visible from this
+    one) would show here, where a repeated input could not reveal it."""
+    arrays = [_desc(*s) for s in SMALL[:5]]
+    _, xa = _inputs(arrays, seed=21)
+    _, xb = _inputs(arrays, seed=57)
+    g = qc.Plan(arrays, "graph")
+    ref = {}
+    for name, xs in (("a", xa), ("b", xb)):
+        ref[name] = g.empty_vis()
+        g.execute(xs, ref[name])
+    g.check()
+    p = qc.Plan(arrays, "persistent")
+    for name, xs in (("a", xa), ("b", xb), ("a", xa), ("b", xb)):
+        vis = p.empty_vis()
+        p.execute(xs, vis)
+        p.check()
+        for i, a in enumerate(arrays):
+            err = vis_err(vis[i].cpu().numpy(), ref[name][i].cpu().numpy(), a["n_ant"])
+            assert err <= _cross_bar("persistent"), (name, i, err)
+
+
+@pytest.mark.gpu
 @pytest.mark.parametrize("mode", MODES)
 def test_plan_graph_replays(qc, mode):
     """Replays of the captured graph, with eager work on the same device
