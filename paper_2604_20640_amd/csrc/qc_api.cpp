@@ -1094,11 +1094,19 @@ qc_status persist_build(qc_plan* P) {
     for (int64_t q = 0; q < A.n_dump * A.n_red_blocks; ++q) red.push_back({qc::PL_REDUCE, (uint16_t)i, (uint32_t)q});
   }
   // spectra items of the two-pass arrays first (they feed the longest
-  // chains), then the X-engine items array by array; an array's reduction
-  // items follow the next array's X items (by then its partials are
-  // normally done, so they neither wait nor pile up at the end)
-  std::stable_sort(first.begin(), first.end(),
-                   [](const qc::PlItem& a, const qc::PlItem& b) { return a.kind > b.kind; });
+  // chains), the largest arrays' first, then the X-engine items array by
+  // array in the same order (the longest items first, the shortest at the
+  // end); an array's reduction items follow the next array's X items (by
+  // then its partials are normally done, so they neither wait nor pile up
+  // at the end)
+  auto size_of = [&](int i) { return (int64_t)P->desc[i].n_ant * P->desc[i].n_samp; };
+  std::stable_sort(first.begin(), first.end(), [&](const qc::PlItem& a, const qc::PlItem& b) {
+    if (a.kind != b.kind) return a.kind > b.kind;
+    return size_of(a.array) > size_of(b.array);
+  });
+  std::stable_sort(xeng.begin(), xeng.end(), [&](const qc::PlItem& a, const qc::PlItem& b) {
+    return size_of(a.array) > size_of(b.array);
+  });
   P->items = first;
   std::vector<int> x_order;  // arrays with X items, in queue order
   for (const qc::PlItem& it : xeng)

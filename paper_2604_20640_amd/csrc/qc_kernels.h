@@ -144,7 +144,7 @@ hipError_t launch_solve(const float2* vis, const uint8_t* mask, int64_t n_time, 
 // ---- batched plans: one persistent launch over heterogeneous work items ----
 constexpr int PL_NT = 512;          // threads per block of the persistent kernel
 constexpr int PL_MAX_ARRAYS = 8;
-constexpr int PL_RED_LOADS = 1 << 16;  // partial loads per reduction item (sizing target)
+constexpr int PL_RED_LOADS = 1 << 14;  // partial loads per reduction item (sizing target)
 
 // Work-item kinds: fused F+X; F-engine (plain body, or the ring body at
 // N = 4096 / 8192); X-engine (vector ALU, or matrix cores for 5..32
