@@ -172,6 +172,50 @@ def divergent_loops_with_barriers(ins):
     return problems
 
 
+def main_loop(ins):
+    """Instructions (address order) of the function's largest natural loop."""
+    if not ins:
+        return []
+    blocks, succ = cfg(ins)
+    idom, pred, pos = dominators(len(blocks), succ)
+    best = set()
+    for u in pos:
+        for h in succ[u]:
+            if not dominates(idom, h, u):
+                continue
+            b, stack = {h}, [u]
+            while stack:
+                x = stack.pop()
+                if x not in b:
+                    b.add(x)
+                    stack.extend(pred[x])
+            if sum(len(blocks[x]) for x in b) > sum(len(blocks[x]) for x in best):
+                best = b
+    return sorted((i for x in best for i in blocks[x]), key=lambda t: t[0])
+
+
+def waits_before_first_barrier(loop):
+    """vmcnt waits between the loop's first global load (its prefetch) and
+    the first barrier after that load, in address order, that wait for one
+    of those loads: vmcnt(k) with fewer than the loads issued since allowed
+    outstanding (an older load's wait, vmcnt(k) with k >= those, is not
+    listed)."""
+    first = next((k for k, (_, op, _, _) in enumerate(loop) if op.startswith("global_load")), None)
+    if first is None:
+        return None
+    out, issued = [], 0
+    for a, op, args, _ in loop[first:]:
+        if op == "s_barrier":
+            return out
+        if op.startswith("global_load"):
+            issued += 1
+        if op == "s_waitcnt" and "vmcnt" in args:
+            k = int(re.search(r"vmcnt\((\d+)\)", args).group(1))
+            if k < issued:
+                out.append((a, args))
+    return out
+
+
 def scan_object(obj, tmpdir):
     """{function name: messages} for every function of `obj` with a finding."""
     out = {}
