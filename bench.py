@@ -8,8 +8,8 @@ bursts.  One step = fused F+X (+ fixed-order partial reduction) -> MAD
 flagging (5 sigma, per baseline) -> per-antenna delay/phase application.
 
 Prints one JSON line: input GB/s (10^9 B/s) with a roofline record of the
-dominant kernel (fused F+X, timed by HIP events around its own launches on
-its own stream), and sections for the other steps: the same stream pushed
+dominant kernel (fused F+X, timed by HIP stop events bound to the step's
+launches on their stream, so timing adds no packet between them), and sections for the other steps: the same stream pushed
 from pinned host memory, the delay/phase solve (checked against the
 injected lags), the 32-antenna X-engine comparison (float32 vs
 FP16/BF16/E4M3 on the matrix cores), five uneven arrays as one plan, and
@@ -203,7 +203,7 @@ def precision_section(torch, qc, steps, checks):
         vis = torch.empty((1, n_ant * (n_ant + 1) // 2, N // 2), dtype=torch.complex64, device="cuda")
         fn = lambda: qc.xcorrelate(xd, N, P, spd, vis=vis, x_prec=prec)  # noqa: E731
         fn()
-        qc.timing_enable(True)
+        qc.timing_enable("chained")
         ms = timed(torch, fn, reps)
         qc.timing_enable(False)
         k_ch, n_ch = qc.timing_read("channelize")
@@ -751,11 +751,15 @@ def main():
         del a, b
     # the autotuner picks the fused kernel's tile shape on this very input
     best_tile, tile_ms = qc.fx_autotune(xd, N, P, spd, reps=3)
-    log(f"[bench] autotune: tile {best_tile}; ms per tile {[round(v, 3) for v in tile_ms]}")
+    width = qc.fx_get_width(N, n_ant)
+    log(f"[bench] autotune: tile {best_tile}, width {width or 'default'}; "
+        f"ms per tile {[round(v, 3) for v in tile_ms]}")
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    qc.timing_enable(True)
+    # per-kernel durations from stop events bound to the launches themselves
+    # (no timing packets between the step's kernels)
+    qc.timing_enable("chained")
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t_wall = time.perf_counter()
@@ -807,7 +811,8 @@ def main():
                      "algorithmic_flop_per_launch": flops,
                      "hbm_frac_of_input_read": round(x.nbytes / (fx_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)},
         "stages_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in kt.items()},
-        "fused_tile": {"chosen": best_tile, "ms_per_tile": [round(v, 4) for v in tile_ms]},
+        "fused_tile": {"chosen": best_tile, "ms_per_tile": [round(v, 4) for v in tile_ms],
+                       "launch_width": width or 512},
         "wall_s_timed_region": round(t_wall, 4),
     }
     if not args.no_achievable:

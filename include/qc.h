@@ -461,23 +461,46 @@ const char* qc_stream_last_error(void);
 int32_t qc_fx_tile_count(int32_t n_fft, int32_t n_ant);
 qc_status qc_fx_set_tile(int32_t n_fft, int32_t n_ant, int32_t tile);
 int32_t qc_fx_get_tile(int32_t n_fft, int32_t n_ant);
+/* Launch width of qc_xcorrelate's fused F+X kernel for one (n_fft, n_ant):
+ * the number of workgroups a launch aims at, by splitting each dump into
+ * chunks of spectra whose partial visibilities the fixed-order reduction
+ * sums (each chunk keeps at least 8 spectra).  0 restores the default of
+ * 512; otherwise 1..2^20 (QC_EINVAL beyond; QC_EUNSUPPORTED when no fused
+ * kernel exists for the pair).  Sums are equal up to float32 rounding order
+ * whatever the width.  Process-wide; set by the autotuner. */
+qc_status qc_fx_set_width(int32_t n_fft, int32_t n_ant, int64_t workgroups);
+int64_t qc_fx_get_width(int32_t n_fft, int32_t n_ant);
 /* Autotuner for the fused kernel: times every tile shape of (n_fft, n_ant) on
  * the caller's input (reps calls of qc_xcorrelate each, after one untimed
- * call) with HIP events on `stream`, keeps the fastest via qc_fx_set_tile and
- * returns its index in *best_out (host).  vis: device scratch sized for the
+ * call) with HIP events on `stream` at the default width, then the fastest
+ * tile at one and at four workgroups per compute unit of the current device;
+ * keeps the fastest pair via qc_fx_set_tile and qc_fx_set_width and returns
+ * the tile's index in *best_out (host).  vis: device scratch sized for the
  * output of qc_xcorrelate on this input.  ms_per_tile: host double[cap] for
- * the per-tile average times, or NULL.  Synchronises. */
+ * the per-tile average times at the default width, or NULL.  Synchronises. */
 qc_status qc_fx_autotune(const int8_t* x, int64_t ld_x, int32_t n_ant, int64_t n_samp,
                          const qc_pfb_params* p, int64_t spec_per_dump, int32_t reps, float* vis,
                          double* ms_per_tile, int32_t cap, int32_t* best_out, void* stream);
 
-/* Kernel timing for measurement harnesses.  While enabled, every launch of
- * the kernels below is bracketed by HIP events recorded on the stream the
- * kernel is launched on (so the figure is the kernel's own duration, on its
- * own stream).  qc_timing_enable(1) starts a fresh record and qc_timing_enable(0)
- * stops recording; qc_timing_read synchronises on the recorded events and
- * returns the summed duration in milliseconds and the launch count.
- * Not thread-safe with respect to concurrent enable/read. */
+/* Kernel timing for measurement harnesses.  qc_timing_enable(mode) starts a
+ * fresh record, qc_timing_enable(0) stops recording; qc_timing_read
+ * synchronises on the recorded events and returns the summed duration in
+ * milliseconds and the launch count of the calls timed under each id below.
+ * Mode 1: each timed call is bracketed by two HIP events recorded on the
+ *   stream it runs on (the figure is the call's own duration; each event is a
+ *   packet of its own, which adds a few microseconds between launches).
+ * Mode 2 (chained): every kernel the library launches carries a stop event
+ *   bound to the launch itself (no extra packet, so the launches run as they
+ *   would untimed).  A timed call runs from the end of the library's previous
+ *   kernel on the same stream (or from an event recorded just before it when
+ *   there is none since timing was enabled) to the end of its own last
+ *   kernel.  Work the caller enqueues on that stream between library calls,
+ *   and time the stream sits idle waiting for the host, are therefore counted
+ *   in the next call's figure: use it where the stream runs library calls
+ *   only and the host enqueues ahead of the GPU.  The events carry no
+ *   system-scope fence (they serve timing only).
+ * Any other mode is QC_EINVAL.  Not thread-safe with respect to concurrent
+ * enable/read. */
 enum {
   QC_KERNEL_FX_FUSED = 0,   /* fused F+X (int8 -> per-chunk partial visibilities) */
   QC_KERNEL_CHANNELIZE = 1, /* standalone F-engine */

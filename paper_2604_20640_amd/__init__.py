@@ -125,6 +125,10 @@ def lib() -> ctypes.CDLL:
         L.qc_fx_set_tile.restype = ctypes.c_int32
         L.qc_fx_get_tile.argtypes = [_I32, _I32]
         L.qc_fx_get_tile.restype = ctypes.c_int32
+        L.qc_fx_set_width.argtypes = [_I32, _I32, _I64]
+        L.qc_fx_set_width.restype = ctypes.c_int32
+        L.qc_fx_get_width.argtypes = [_I32, _I32]
+        L.qc_fx_get_width.restype = ctypes.c_int64
         L.qc_fx_autotune.argtypes = [_P, _I64, _I32, _I64, ctypes.POINTER(PfbParams), _I64, _I32, _P,
                                      ctypes.POINTER(ctypes.c_double), _I32, ctypes.POINTER(_I32), _P]
         L.qc_fx_autotune.restype = ctypes.c_int32
@@ -477,9 +481,14 @@ KERNELS = {"fx_fused": 0, "channelize": 1, "xeng_f32": 2, "xeng_mfma": 3, "reduc
            "mad": 5, "apply": 6}
 
 
-def timing_enable(on: bool = True):
-    """Start (clearing) or stop per-kernel event timing inside the library."""
-    _check(lib().qc_timing_enable(1 if on else 0), "qc_timing_enable")
+def timing_enable(on=True):
+    """Start (clearing) or stop per-kernel event timing inside the library.
+
+    True: event pairs around each timed call; "chained": stop events bound to
+    the launches themselves (no added packets; the stream must carry library
+    calls only); False: off."""
+    mode = 2 if on == "chained" else (1 if on else 0)
+    _check(lib().qc_timing_enable(mode), "qc_timing_enable")
 
 
 def timing_read(kernel: str):
@@ -517,8 +526,18 @@ def fx_get_tile(n_fft: int, n_ant: int) -> int:
     return lib().qc_fx_get_tile(n_fft, n_ant)
 
 
+def fx_set_width(n_fft: int, n_ant: int, workgroups: int):
+    """Workgroups per fused launch for (n_fft, n_ant); 0 restores the default."""
+    _check(lib().qc_fx_set_width(n_fft, n_ant, workgroups), "qc_fx_set_width")
+
+
+def fx_get_width(n_fft: int, n_ant: int) -> int:
+    return lib().qc_fx_get_width(n_fft, n_ant)
+
+
 def fx_autotune(x, n_fft, n_taps, spec_per_dump, reps=5):
-    """Time every fused tile shape on x, keep the fastest; returns (best, [ms per tile])."""
+    """Time every fused tile shape on x, then the fastest at other launch
+    widths; keep the fastest; returns (best tile, [ms per tile])."""
     _check_x(x)
     n_ant, n_samp = x.shape
     n = fx_tile_count(n_fft, n_ant)

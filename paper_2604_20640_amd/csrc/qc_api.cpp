@@ -323,50 +323,111 @@ qc_status alloc_async(AsyncBuf& b, size_t bytes, hipStream_t s) {
 }
 
 // ---- kernel timing ----------------------------------------------------------
+// Mode 1 brackets each timed call with two events recorded on its stream.
+// Mode 2 records no packet of its own: every kernel the library launches
+// carries a stop event (timing_stop_event), and a timed call runs from the
+// stop event of the library's previous launch on the same stream (an event
+// recorded just before it when there is none) to the stop event of its own
+// last launch.
 struct TimingRec {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[QC_KERNEL_COUNT];
+  std::vector<hipEvent_t> owned;             // every event created while timing
+  std::map<hipStream_t, hipEvent_t> tail;    // mode 2: last stop event per stream
 };
 std::mutex g_tmu;
-bool g_timing = false;
+int g_timing = 0;
 TimingRec g_trec;
 
 void timing_clear_locked() {
-  for (auto& v : g_trec.ev) {
-    for (auto& p : v) {
-      (void)hipEventDestroy(p.first);
-      (void)hipEventDestroy(p.second);
-    }
-    v.clear();
-  }
+  for (hipEvent_t e : g_trec.owned) (void)hipEventDestroy(e);
+  g_trec.owned.clear();
+  for (auto& v : g_trec.ev) v.clear();
+  g_trec.tail.clear();
 }
 
-// Brackets one launch with events on its stream when timing is enabled.
+// Timing-only events: no system-scope fence when they complete, so binding
+// one to a launch adds no cache writeback after it.
+hipEvent_t timing_new_event_locked() {
+  hipEvent_t e = nullptr;
+  if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
+  g_trec.owned.push_back(e);
+  return e;
+}
+
+struct KTimer;
+thread_local KTimer* t_ktimer = nullptr;
+
+// Brackets one timed call on its stream while timing is enabled.
 struct KTimer {
   int k;
   hipStream_t s;
   hipEvent_t a = nullptr, b = nullptr;
+  KTimer* outer = nullptr;
   KTimer(int kernel, hipStream_t st) : k(kernel), s(st) {
     std::lock_guard<std::mutex> lk(g_tmu);
-    if (!g_timing) return;
-    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) { a = b = nullptr; return; }
+    if (g_timing == 2) {
+      outer = t_ktimer;
+      t_ktimer = this;
+      return;
+    }
+    if (g_timing != 1) return;
+    a = timing_new_event_locked();
+    b = timing_new_event_locked();
+    if (!a || !b) { a = b = nullptr; return; }
     (void)hipEventRecord(a, s);
   }
   ~KTimer() {
-    if (!a) return;
-    (void)hipEventRecord(b, s);
     std::lock_guard<std::mutex> lk(g_tmu);
+    if (t_ktimer == this) t_ktimer = outer;
+    if (!a || !b) return;
+    if (g_timing == 1) (void)hipEventRecord(b, s);
     g_trec.ev[k].emplace_back(a, b);
   }
 };
 
+}  // namespace
+
+namespace qc {
+hipEvent_t timing_stop_event(hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_tmu);
+  if (g_timing != 2) return nullptr;
+  hipEvent_t e = timing_new_event_locked();
+  if (!e) return nullptr;
+  KTimer* t = t_ktimer;
+  if (t && t->s == s) {
+    if (!t->a) {
+      auto it = g_trec.tail.find(s);
+      if (it != g_trec.tail.end()) {
+        t->a = it->second;
+      } else if ((t->a = timing_new_event_locked()) != nullptr) {
+        (void)hipEventRecord(t->a, s);
+      }
+    }
+    t->b = e;
+  }
+  g_trec.tail[s] = e;
+  return e;
+}
+}  // namespace qc
+
+namespace {
+
 // ---- fused-kernel tile selection (default 0; set by the autotuner) ---------
 std::mutex g_tile_mu;
 std::map<std::pair<int, int>, int> g_tile;  // (n_fft, n_ant) -> tile index
+// (n_fft, n_ant) -> workgroups per fused launch (absent: the default policy)
+std::map<std::pair<int, int>, int64_t> g_width;
 
 int fused_tile_for(int n_fft, int n_ant) {
   std::lock_guard<std::mutex> lk(g_tile_mu);
   auto it = g_tile.find({n_fft, n_ant});
   return it == g_tile.end() ? 0 : it->second;
+}
+
+int64_t fused_width_for(int n_fft, int n_ant) {
+  std::lock_guard<std::mutex> lk(g_tile_mu);
+  auto it = g_width.find({n_fft, n_ant});
+  return it == g_width.end() ? 0 : it->second;
 }
 
 qc_status channelize_impl(const Resolved& r, qc_prec out_prec, void* out, float* scale_out,
@@ -552,7 +613,7 @@ qc_status qc_xcorrelate(const int8_t* x, int64_t ld_x, int32_t n_ant, int64_t n_
     // only the spectra of full dumps are transformed
     r.args.n_samp = n_dump * spec_per_dump * N;
     if (x_prec == QC_F32 && qc::fused_supported(N, n_ant)) {
-      const int64_t cpd = qc::fused_chunks_per_dump(N, n_ant, n_dump, spec_per_dump);
+      const int64_t cpd = qc::fused_chunks_per_dump(N, n_ant, n_dump, spec_per_dump, fused_width_for(N, n_ant));
       AsyncBuf part;
       st = alloc_async(part, (size_t)(n_dump * cpd) * nb * nch * sizeof(float2), s);
       if (st != QC_OK) return st;
@@ -837,6 +898,21 @@ qc_status qc_fx_set_tile(int32_t n_fft, int32_t n_ant, int32_t tile) {
 
 int32_t qc_fx_get_tile(int32_t n_fft, int32_t n_ant) { return fused_tile_for(n_fft, n_ant); }
 
+qc_status qc_fx_set_width(int32_t n_fft, int32_t n_ant, int64_t workgroups) {
+  g_err.clear();
+  if (qc::fused_tile_count(n_fft, n_ant) == 0)
+    return fail(QC_EUNSUPPORTED, "no fused kernel for n_fft=%d n_ant=%d", n_fft, n_ant);
+  if (workgroups < 0 || workgroups > (1 << 20)) return fail(QC_EINVAL, "workgroups must be in [0, 2^20]");
+  std::lock_guard<std::mutex> lk(g_tile_mu);
+  if (workgroups == 0)
+    g_width.erase({n_fft, n_ant});
+  else
+    g_width[{n_fft, n_ant}] = workgroups;
+  return QC_OK;
+}
+
+int64_t qc_fx_get_width(int32_t n_fft, int32_t n_ant) { return fused_width_for(n_fft, n_ant); }
+
 qc_status qc_fx_autotune(const int8_t* x, int64_t ld_x, int32_t n_ant, int64_t n_samp,
                          const qc_pfb_params* p, int64_t spec_per_dump, int32_t reps, float* vis,
                          double* ms_per_tile, int32_t cap, int32_t* best_out, void* stream) {
@@ -849,50 +925,86 @@ qc_status qc_fx_autotune(const int8_t* x, int64_t ld_x, int32_t n_ant, int64_t n
     return fail(QC_EINVAL, "need reps >= 1 and at least one full dump");
   if (!vis) return fail(QC_EINVAL, "vis is NULL");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  int dev = 0, n_cu = 0;
+  QC_HIP(hipGetDevice(&dev), "hipGetDevice");
+  QC_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev), "CU count");
+  if (n_cu < 1) n_cu = 256;
   hipEvent_t a = nullptr, b = nullptr;
   QC_HIP(hipEventCreate(&a), "hipEventCreate");
   QC_HIP(hipEventCreate(&b), "hipEventCreate");
-  double best = 1e300;
-  int best_t = 0;
+  const std::pair<int, int> key{p->n_fft, n_ant};
   const int prev = fused_tile_for(p->n_fft, n_ant);
-  for (int t = 0; t < n; ++t) {
-    {
-      std::lock_guard<std::mutex> lk(g_tile_mu);
-      g_tile[{p->n_fft, n_ant}] = t;
+  const int64_t prev_w = fused_width_for(p->n_fft, n_ant);
+  // one untimed call (first-use set-up), then reps timed calls
+  auto time_calls = [&](double* per) -> qc_status {
+    qc_status q = qc_xcorrelate(x, ld_x, n_ant, n_samp, p, nullptr, nullptr, spec_per_dump, QC_F32, vis, 0,
+                                nullptr, stream);
+    if (q != QC_OK) return q;
+    QC_HIP(hipEventRecord(a, s), "hipEventRecord");
+    for (int r = 0; r < reps; ++r) {
+      q = qc_xcorrelate(x, ld_x, n_ant, n_samp, p, nullptr, nullptr, spec_per_dump, QC_F32, vis, 0, nullptr,
+                        stream);
+      if (q != QC_OK) return q;
     }
-    // one untimed call (first-use set-up), then reps timed calls
-    st = qc_xcorrelate(x, ld_x, n_ant, n_samp, p, nullptr, nullptr, spec_per_dump, QC_F32, vis, 0,
-                       nullptr, stream);
-    if (st == QC_OK) QC_HIP(hipEventRecord(a, s), "hipEventRecord");
-    for (int r = 0; st == QC_OK && r < reps; ++r)
-      st = qc_xcorrelate(x, ld_x, n_ant, n_samp, p, nullptr, nullptr, spec_per_dump, QC_F32, vis, 0,
-                         nullptr, stream);
-    if (st != QC_OK) break;
     QC_HIP(hipEventRecord(b, s), "hipEventRecord");
     QC_HIP(hipEventSynchronize(b), "hipEventSynchronize");
     float ms = 0.f;
     QC_HIP(hipEventElapsedTime(&ms, a, b), "hipEventElapsedTime");
-    const double per = (double)ms / reps;
+    *per = (double)ms / reps;
+    return QC_OK;
+  };
+  auto set_choice = [&](int t, int64_t w) {
+    std::lock_guard<std::mutex> lk(g_tile_mu);
+    g_tile[key] = t;
+    if (w > 0)
+      g_width[key] = w;
+    else
+      g_width.erase(key);
+  };
+  // tiles at the default width (512 workgroups), then the best tile at one
+  // and at four workgroups per CU (a tile that holds one workgroup per CU
+  // fills the chip in a single round at the first)
+  double best = 1e300;
+  int best_t = 0;
+  int64_t best_w = 0;
+  for (int t = 0; t < n && st == QC_OK; ++t) {
+    set_choice(t, 0);
+    double per = 0.0;
+    st = time_calls(&per);
+    if (st != QC_OK) break;
     if (ms_per_tile && t < cap) ms_per_tile[t] = per;
     if (per < best) {
       best = per;
       best_t = t;
     }
   }
+  for (int64_t w : {(int64_t)n_cu, 4 * (int64_t)n_cu}) {
+    if (st != QC_OK) break;
+    set_choice(best_t, w);
+    double per = 0.0;
+    st = time_calls(&per);
+    if (st == QC_OK && per < best) {
+      best = per;
+      best_w = w;
+    }
+  }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
-  std::lock_guard<std::mutex> lk(g_tile_mu);
-  g_tile[{p->n_fft, n_ant}] = (st == QC_OK) ? best_t : prev;
-  if (st != QC_OK) return st;
+  if (st != QC_OK) {
+    set_choice(prev, prev_w);
+    return st;
+  }
+  set_choice(best_t, best_w);
   if (best_out) *best_out = best_t;
   return QC_OK;
 }
 
 qc_status qc_timing_enable(int32_t on) {
   g_err.clear();
+  if (on < 0 || on > 2) return fail(QC_EINVAL, "timing mode %d (0 off, 1 event pairs, 2 chained)", on);
   std::lock_guard<std::mutex> lk(g_tmu);
   if (on) timing_clear_locked();
-  g_timing = on != 0;
+  g_timing = on;
   return QC_OK;
 }
 

@@ -775,9 +775,8 @@ hipError_t launch_mad(const float2* vis, int64_t n_time, int64_t n_base, int n_c
   if (npop <= 0) return hipSuccess;
   if (count <= MAD_CAP_SMALL) {
     const size_t lds = (size_t)count * sizeof(float);
-    hipLaunchKernelGGL((mad_kernel<64, 8>), dim3((unsigned)npop), dim3(64), lds, s, vis, n_time,
-                       n_base, n_chan, sigma, population, MAD_CAP_SMALL, (int64_t)0, nullptr, mask, thresh,
-                       stats);
+    return launch(mad_kernel<64, 8>, dim3((unsigned)npop), dim3(64), lds, s, vis, n_time, n_base, n_chan, sigma,
+                  population, MAD_CAP_SMALL, (int64_t)0, nullptr, mask, thresh, stats);
   } else {
     const int64_t cap = count <= MAD_CAP_BIG ? count : 0;
     const float* gamp = nullptr;
@@ -787,17 +786,17 @@ hipError_t launch_mad(const float2* vis, int64_t n_time, int64_t n_base, int n_c
       // element instead of forming a float64 square root each, and
       // populations beyond the LDS cache read 4 bytes per pass
       const int64_t total = npop * count;
+      hipError_t e;
       if (population == 0 && n_chan % 4 == 0 && (reinterpret_cast<uintptr_t>(vis) & 31u) == 0 &&
           (reinterpret_cast<uintptr_t>(amp_scratch) & 15u) == 0) {
         const int64_t total4 = total / 4;
-        hipLaunchKernelGGL(mad_amp4_kernel, dim3((unsigned)((total4 + 255) / 256)), dim3(256), 0, s,
-                           reinterpret_cast<const float4*>(vis), n_base, n_chan, count, total4,
-                           reinterpret_cast<float4*>(amp_scratch));
+        e = launch(mad_amp4_kernel, dim3((unsigned)((total4 + 255) / 256)), dim3(256), 0, s,
+                   reinterpret_cast<const float4*>(vis), n_base, n_chan, count, total4,
+                   reinterpret_cast<float4*>(amp_scratch));
       } else {
-        hipLaunchKernelGGL(mad_amp_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, vis, n_time,
-                           n_base, n_chan, population, count, total, amp_scratch);
+        e = launch(mad_amp_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, vis, n_time, n_base,
+                   n_chan, population, count, total, amp_scratch);
       }
-      hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
       gamp = amp_scratch;
     }
@@ -809,10 +808,9 @@ hipError_t launch_mad(const float2* vis, int64_t n_time, int64_t n_base, int n_c
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(mad_kernel<1024, 11>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((mad_kernel<1024, 11>), dim3((unsigned)npop), dim3(1024), lds, s, vis, n_time,
-                       n_base, n_chan, sigma, population, cap, comp_cap, gamp, mask, thresh, stats);
+    return launch(mad_kernel<1024, 11>, dim3((unsigned)npop), dim3(1024), lds, s, vis, n_time, n_base, n_chan,
+                  sigma, population, cap, comp_cap, gamp, mask, thresh, stats);
   }
-  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -857,8 +855,7 @@ hipError_t launch_apply(float2* vis, int64_t n_time, int n_ant, int n_chan, doub
   const int nb = n_ant * (n_ant + 1) / 2;
   if (n_time <= 0 || nb <= 0 || n_chan <= 0) return hipSuccess;
   dim3 grid((unsigned)((n_chan + 255) / 256), (unsigned)nb, (unsigned)n_time);
-  hipLaunchKernelGGL(apply_kernel, grid, dim3(256), 0, s, vis, n_ant, n_chan, f0, df, t);
-  return hipGetLastError();
+  return launch(apply_kernel, grid, dim3(256), 0, s, vis, n_ant, n_chan, f0, df, t);
 }
 
 }  // namespace qc

@@ -738,9 +738,8 @@ static hipError_t launch_fused_ring_pp(const FxArgs& a, int64_t n_dump, int64_t 
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)RC::LDS_BYTES);
   if (e != hipSuccess) return e;
   if (!a.twp) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(kern, dim3((unsigned)(n_dump * cpd)), dim3(RC::C::NT), RC::LDS_BYTES, s, a.x,
-                     a.ld_x, a.hist, a.taps, a.twp, spd, cpd, part);
-  return hipGetLastError();
+  return launch(kern, dim3((unsigned)(n_dump * cpd)), dim3(RC::C::NT), RC::LDS_BYTES, s, a.x, a.ld_x, a.hist,
+                a.taps, a.twp, spd, cpd, part);
 }
 
 template <int N, int NA, int V, int ST = 0>
@@ -753,9 +752,8 @@ static hipError_t launch_fused_ring(const FxArgs& a, int64_t n_dump, int64_t spd
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)RC::LDS_BYTES);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, dim3((unsigned)(n_dump * cpd)), dim3(RC::C::NT), RC::LDS_BYTES, s, a.x,
-                     a.ld_x, a.hist, a.taps, a.tw, spd, cpd, part);
-  return hipGetLastError();
+  return launch(kern, dim3((unsigned)(n_dump * cpd)), dim3(RC::C::NT), RC::LDS_BYTES, s, a.x, a.ld_x, a.hist,
+                a.taps, a.tw, spd, cpd, part);
 }
 
 template <int N, int NA, int S, int V, bool PP, int OCC, int PT>
@@ -767,9 +765,8 @@ static hipError_t launch_fused_t(const FxArgs& a, int64_t n_dump, int64_t spd, i
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, dim3((unsigned)(n_dump * cpd)), dim3(C::NT), lds, s, a.x, a.ld_x,
-                     a.hist, a.taps, a.n_taps, a.tw, spd, cpd, part);
-  return hipGetLastError();
+  return launch(kern, dim3((unsigned)(n_dump * cpd)), dim3(C::NT), lds, s, a.x, a.ld_x, a.hist, a.taps,
+                a.n_taps, a.tw, spd, cpd, part);
 }
 
 template <int N, int NA, int S, int V, bool PP, int OCC>
@@ -857,9 +854,10 @@ int fused_tile_count(int n_fft, int n_ant) {
 
 bool fused_supported(int n_fft, int n_ant) { return fused_tile_count(n_fft, n_ant) > 0; }
 
-int64_t fused_chunks_per_dump(int n_fft, int n_ant, int64_t n_dump, int64_t spd) {
-  // aim for ~2 waves of workgroups over 256 CUs, at least 8 spectra each
-  int64_t want = (512 + n_dump - 1) / n_dump;
+int64_t fused_chunks_per_dump(int n_fft, int n_ant, int64_t n_dump, int64_t spd, int64_t workgroups) {
+  // the default of 512 is two rounds of workgroups over 256 CUs
+  if (workgroups < 1) workgroups = 512;
+  int64_t want = (workgroups + n_dump - 1) / n_dump;
   int64_t maxc = spd / 8 > 0 ? spd / 8 : 1;
   int64_t c = want < maxc ? want : maxc;
   return c < 1 ? 1 : c;
@@ -941,9 +939,8 @@ hipError_t launch_reduce(const float2* part, int64_t n_dump, int64_t cpd, int64_
   int64_t bx = (elems + 255) / 256;
   if (bx > 4096) bx = 4096;
   const int64_t n_chan = tile > 0 ? elems / nb : 0;
-  hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)(bx * n_dump)), dim3(256), 0, s, part, cpd,
-                     elems, bx, scale, accumulate, tile, nb, n_chan, vis);
-  return hipGetLastError();
+  return launch(reduce_partials_kernel, dim3((unsigned)(bx * n_dump)), dim3(256), 0, s, part, cpd, elems, bx,
+                scale, accumulate, tile, nb, n_chan, vis);
 }
 
 // ---------------------------------------------------------------------------
@@ -1368,10 +1365,8 @@ static hipError_t launch_chan_ring_w(const int8_t* x, int64_t ld_x, int n_ant, i
   const void* k = reinterpret_cast<const void*>(chan_ring_kernel<N, NA, V, 4, PREC, PP, ST>);
   hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)RC::LDS_BYTES);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((chan_ring_kernel<N, NA, V, 4, PREC, PP, ST>), dim3((unsigned)(groups * chunks)),
-                     dim3(C::NT), RC::LDS_BYTES, s, x, ld_x, n_ant, hist, taps, tw, twp, n_spec, spb, chunks,
-                     scale, out);
-  return hipGetLastError();
+  return launch(chan_ring_kernel<N, NA, V, 4, PREC, PP, ST>, dim3((unsigned)(groups * chunks)), dim3(C::NT),
+                RC::LDS_BYTES, s, x, ld_x, n_ant, hist, taps, tw, twp, n_spec, spb, chunks, scale, out);
 }
 
 template <int N, int ST>
@@ -1415,17 +1410,16 @@ static hipError_t launch_chan_t(const FxArgs& a, int prec, void* out, const floa
   hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   dim3 grid((unsigned)nbx, (unsigned)n_pair);
-#define QC_CHAN_LAUNCH(PR)                                                                       \
-  hipLaunchKernelGGL((channelize_kernel<N, PR>), grid, dim3(C::NT), lds, s, a.x, a.ld_x,         \
-                     a.n_ant, n_spec, a.hist, a.taps, a.n_taps, a.tw, per, scale, out)
+#define QC_CHAN_LAUNCH(PR)                                                                              \
+  return launch(channelize_kernel<N, PR>, grid, dim3(C::NT), lds, s, a.x, a.ld_x, a.n_ant, n_spec, a.hist, \
+                a.taps, a.n_taps, a.tw, per, scale, out)
   switch (prec) {
-    case 0: QC_CHAN_LAUNCH(0); break;
-    case 1: QC_CHAN_LAUNCH(1); break;
-    case 2: QC_CHAN_LAUNCH(2); break;
-    default: QC_CHAN_LAUNCH(3); break;
+    case 0: QC_CHAN_LAUNCH(0);
+    case 1: QC_CHAN_LAUNCH(1);
+    case 2: QC_CHAN_LAUNCH(2);
+    default: QC_CHAN_LAUNCH(3);
   }
 #undef QC_CHAN_LAUNCH
-  return hipGetLastError();
 }
 
 static int g_chan_variant = 0;  // 0: ring variant where it applies, 1: always the plain kernel
@@ -1541,10 +1535,10 @@ __global__ void scales_finish_kernel(const unsigned long long* __restrict__ part
 
 hipError_t launch_scales(const int8_t* x, int64_t ld_x, int n_ant, int64_t n_use, double sum_h2,
                          double target, unsigned long long* part, float* scale_out, hipStream_t s) {
-  hipLaunchKernelGGL(scales_partial_kernel, dim3(SC_BLOCKS, n_ant), dim3(256), 0, s, x, ld_x, n_use, part);
-  hipLaunchKernelGGL(scales_finish_kernel, dim3((n_ant + 255) / 256), dim3(256), 0, s, part, n_ant, n_use,
-                     sum_h2, target, scale_out);
-  return hipGetLastError();
+  hipError_t e = launch(scales_partial_kernel, dim3(SC_BLOCKS, n_ant), dim3(256), 0, s, x, ld_x, n_use, part);
+  if (e != hipSuccess) return e;
+  return launch(scales_finish_kernel, dim3((n_ant + 255) / 256), dim3(256), 0, s, part, n_ant, n_use, sum_h2,
+                target, scale_out);
 }
 
 // ---------------------------------------------------------------------------
@@ -1570,9 +1564,8 @@ hipError_t launch_hist_copy(const int8_t* x, int64_t ld_x, int n_ant, int64_t n_
   if (keep <= 0) return hipSuccess;
   int64_t bx = (keep + 255) / 256;
   if (bx > 1024) bx = 1024;
-  hipLaunchKernelGGL(hist_copy_kernel, dim3((unsigned)bx, n_ant), dim3(256), 0, s, x, ld_x, n_samp,
-                     hist, keep, hist_out);
-  return hipGetLastError();
+  return launch(hist_copy_kernel, dim3((unsigned)bx, n_ant), dim3(256), 0, s, x, ld_x, n_samp, hist, keep,
+                hist_out);
 }
 
 // ---------------------------------------------------------------------------
@@ -1681,9 +1674,7 @@ hipError_t launch_xeng_f32(const float2* v, int n_ant, int64_t n_spec, int n_cha
   const int nblk = (n_ant + 3) / 4;
   const int n_cgrp = (n_chan + 255) / 256;
   dim3 grid((unsigned)(n_cgrp * n_dump * ksplit), (unsigned)(nblk * (nblk + 1) / 2));
-  hipLaunchKernelGGL(xeng_f32_kernel, grid, dim3(256), 0, s, v, n_ant, n_spec, n_chan, spd,
-                     ksplit, n_cgrp, part);
-  return hipGetLastError();
+  return launch(xeng_f32_kernel, grid, dim3(256), 0, s, v, n_ant, n_spec, n_chan, spd, ksplit, n_cgrp, part);
 }
 
 // ---------------------------------------------------------------------------
@@ -2010,11 +2001,9 @@ hipError_t prepare_plan() {
 
 hipError_t launch_plan(const PlArgs& a, int grid, hipStream_t s) {
   const int nctr = 2 + 2 * PL_MAX_ARRAYS;
-  hipLaunchKernelGGL(plan_reset_kernel, dim3(1), dim3(64), 0, s, a.ctr, nctr);
-  hipError_t e = hipGetLastError();
+  hipError_t e = launch(plan_reset_kernel, dim3(1), dim3(64), 0, s, a.ctr, nctr);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(plan_kernel, dim3(grid), dim3(PL_NT), PLAN_LDS, s, a);
-  return hipGetLastError();
+  return launch(plan_kernel, dim3(grid), dim3(PL_NT), PLAN_LDS, s, a);
 }
 
 }  // namespace qc

@@ -1,7 +1,12 @@
 // Launchers shared between the C-ABI layer and the kernel translation units.
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <tuple>
+#include <type_traits>
+#include <utility>
 
 namespace qc {
 
@@ -25,7 +30,10 @@ struct FxArgs {
 // (n_fft, n_ant); part must hold fused_part_elems() float2.
 bool fused_supported(int n_fft, int n_ant);
 int fused_tile_count(int n_fft, int n_ant);
-int64_t fused_chunks_per_dump(int n_fft, int n_ant, int64_t n_dump, int64_t spec_per_dump);
+// Chunks per dump of a fused launch: about `workgroups` workgroups in all
+// (at least 8 spectra per chunk).
+int64_t fused_chunks_per_dump(int n_fft, int n_ant, int64_t n_dump, int64_t spec_per_dump,
+                              int64_t workgroups = 512);
 // tile: index into the (n_fft, n_ant) tile list; 0 is the default shape.
 hipError_t launch_fused(const FxArgs& a, int64_t n_dump, int64_t spec_per_dump,
                         int64_t chunks_per_dump, float2* part, hipStream_t s, int tile);
@@ -253,5 +261,35 @@ hipError_t cnn_forward_f16(const float* params, const _Float16* w2p, const _Floa
 
 // Rate one measurement kernel of the given kind sustains (see qc_measure_peak).
 hipError_t measure_peak(int kind, void* scratch, int64_t bytes, int reps, double* rate, hipStream_t s);
+
+// Stop event to bind to a kernel launch on stream s, or null.  Non-null only
+// while chained kernel timing is enabled (qc_timing_enable(2)): the event
+// then records the end of that launch itself, with no packet of its own.
+hipEvent_t timing_stop_event(hipStream_t s);
+
+template <typename T>
+using launch_arg_t = std::remove_cv_t<std::remove_reference_t<T>>;
+
+template <typename Tup, size_t... I>
+inline void launch_arg_ptrs(Tup& t, void** p, std::index_sequence<I...>) {
+  ((p[I] = static_cast<void*>(&std::get<I>(t))), ...);
+}
+
+// Launches kernel k with its arguments converted to the kernel's own
+// parameter types.  With chained timing on, the launch carries the stop
+// event timing_stop_event() hands out.  Returns the launch's status.
+template <typename... P, typename... A>
+inline hipError_t launch(void (*k)(P...), dim3 grid, dim3 block, size_t lds, hipStream_t s, A&&... a) {
+  static_assert(sizeof...(P) == sizeof...(A), "kernel argument count");
+  std::tuple<launch_arg_t<P>...> t{static_cast<launch_arg_t<P>>(std::forward<A>(a))...};
+  void* ptrs[sizeof...(P) + 1];
+  launch_arg_ptrs(t, ptrs, std::index_sequence_for<P...>{});
+  hipEvent_t stop = timing_stop_event(s);
+  hipError_t e = stop ? hipExtLaunchKernel(reinterpret_cast<const void*>(k), grid, block, ptrs, lds, s,
+                                           nullptr, stop, 0)
+                      : hipLaunchKernel(reinterpret_cast<const void*>(k), grid, block, ptrs, lds, s);
+  hipError_t last = hipGetLastError();
+  return e != hipSuccess ? e : last;
+}
 
 }  // namespace qc

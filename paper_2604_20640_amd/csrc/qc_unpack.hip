@@ -229,17 +229,16 @@ static hipError_t launch_chanx_n(const ChanxArgs& a, int prec, void* out, const 
   const int64_t ldb = a.ld_x * Word<ST>::BYTES;
   const unsigned char* xb = static_cast<const unsigned char*>(a.x);
   const unsigned char* hb = static_cast<const unsigned char*>(a.hist);
-#define QC_CHANX(PR)                                                                                     \
-  hipLaunchKernelGGL((chanx_kernel<N, ST, PR>), grid, dim3(C::NT), lds, s, xb, ldb, a.n_ant, n_spec, hb, \
-                     a.taps, a.n_taps, a.tw, per, scale, out)
+#define QC_CHANX(PR)                                                                                   \
+  return launch(chanx_kernel<N, ST, PR>, grid, dim3(C::NT), lds, s, xb, ldb, a.n_ant, n_spec, hb, a.taps, \
+                a.n_taps, a.tw, per, scale, out)
   switch (prec) {
-    case 0: QC_CHANX(0); break;
-    case 1: QC_CHANX(1); break;
-    case 2: QC_CHANX(2); break;
-    default: QC_CHANX(3); break;
+    case 0: QC_CHANX(0);
+    case 1: QC_CHANX(1);
+    case 2: QC_CHANX(2);
+    default: QC_CHANX(3);
   }
 #undef QC_CHANX
-  return hipGetLastError();
 }
 
 template <int ST>
@@ -327,16 +326,17 @@ hipError_t launch_scales_any(const void* x, int sample, int64_t ld_x, int n_ant,
   const unsigned char* xb = static_cast<const unsigned char*>(x);
   const int bytes = sample == 0 ? 1 : sample == 3 ? 4 : 2;
   const dim3 grid(SC_BLOCKS, n_ant);
+  hipError_t e;
   switch (sample) {
-    case 0: hipLaunchKernelGGL(scalesx_partial_kernel<0>, grid, dim3(256), 0, s, xb, ld_x * bytes, n_use, part); break;
-    case 1: hipLaunchKernelGGL(scalesx_partial_kernel<1>, grid, dim3(256), 0, s, xb, ld_x * bytes, n_use, part); break;
-    case 2: hipLaunchKernelGGL(scalesx_partial_kernel<2>, grid, dim3(256), 0, s, xb, ld_x * bytes, n_use, part); break;
-    case 3: hipLaunchKernelGGL(scalesx_partial_kernel<3>, grid, dim3(256), 0, s, xb, ld_x * bytes, n_use, part); break;
+    case 0: e = launch(scalesx_partial_kernel<0>, grid, dim3(256), 0, s, xb, ld_x * bytes, n_use, part); break;
+    case 1: e = launch(scalesx_partial_kernel<1>, grid, dim3(256), 0, s, xb, ld_x * bytes, n_use, part); break;
+    case 2: e = launch(scalesx_partial_kernel<2>, grid, dim3(256), 0, s, xb, ld_x * bytes, n_use, part); break;
+    case 3: e = launch(scalesx_partial_kernel<3>, grid, dim3(256), 0, s, xb, ld_x * bytes, n_use, part); break;
     default: return hipErrorInvalidValue;
   }
-  hipLaunchKernelGGL(scalesx_finish_kernel, dim3((n_ant + 255) / 256), dim3(256), 0, s, part, n_ant, n_use,
-                     sum_h2, target, scale_out);
-  return hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch(scalesx_finish_kernel, dim3((n_ant + 255) / 256), dim3(256), 0, s, part, n_ant, n_use, sum_h2,
+                target, scale_out);
 }
 
 }  // namespace qc

@@ -77,9 +77,8 @@ hipError_t launch_xm_t(const void* v, const float* scale, int n_ant, int64_t n_s
   const int n_cb = n_chan / XmCfg<PREC>::CB;
   const int64_t blocks = (int64_t)n_cb * n_dump * ksplit;
   if (blocks <= 0 || blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(xeng_mfma_kernel<PREC>, dim3((unsigned)blocks), dim3(XM_NT), 0, s, v, scale, n_ant,
-                     n_spec, n_chan, spd, ksplit, n_cb, part);
-  return hipGetLastError();
+  return launch(xeng_mfma_kernel<PREC>, dim3((unsigned)blocks), dim3(XM_NT), 0, s, v, scale, n_ant, n_spec,
+                n_chan, spd, ksplit, n_cb, part);
 }
 
 }  // namespace

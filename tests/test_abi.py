@@ -146,6 +146,21 @@ def test_kernel_variant_switches():
     assert qc.cnn_variant() == 0
 
 
+def test_fused_width_setting():
+    # host-side state only: range checks and round trips, default restored
+    L = qc.lib()
+    assert L.qc_fx_get_width(4096, 4) == 0
+    assert L.qc_fx_set_width(4096, 4, -1) == QC_EINVAL
+    assert L.qc_fx_set_width(4096, 4, (1 << 20) + 1) == QC_EINVAL
+    assert L.qc_fx_set_width(4096, 3, 256) == QC_EUNSUPPORTED    # no fused kernel
+    try:
+        assert L.qc_fx_set_width(4096, 4, 256) == 0 and qc.fx_get_width(4096, 4) == 256
+        assert qc.fx_get_width(1024, 4) == 0                       # per (n_fft, n_ant)
+    finally:
+        assert L.qc_fx_set_width(4096, 4, 0) == 0
+    assert qc.fx_get_width(4096, 4) == 0
+
+
 def test_measure_peak_rejects_bad_arguments():
     # host-side validation only: no GPU work is started
     L = qc.lib()

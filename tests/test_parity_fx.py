@@ -191,9 +191,36 @@ def test_autotune_picks_a_tile(qc):
     best, ms = qc.fx_autotune(x, 1024, 4, 32, reps=2)
     assert 0 <= best < qc.fx_tile_count(1024, 4) and len(ms) == qc.fx_tile_count(1024, 4)
     assert qc.fx_get_tile(1024, 4) == best and min(ms) == ms[best] and all(m > 0 for m in ms)
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    assert qc.fx_get_width(1024, 4) in (0, n_cu, 4 * n_cu)
     qc.fx_set_tile(1024, 4, 0)
+    qc.fx_set_width(1024, 4, 0)
     with pytest.raises(qc.QCError):
         qc.fx_set_tile(1024, 4, 99)
+
+
+@pytest.mark.parametrize("N,n_ant", [(4096, 4), (1024, 8)])
+def test_fused_launch_widths_match_oracle(qc, N, n_ant):
+    """Any launch width (chunks per dump from 1 to the cap of 8 spectra per
+    chunk) gives the oracle's sums, for the default tile and the last one."""
+    import torch
+    P, spd, n_spec = 4, 80, 170
+    x = _stream(n_ant, N * n_spec, seed=7 + N + n_ant)
+    chans = _chans(N, n=24)
+    V_ref = _oracle_vis(x, N, P, spd, chans=chans)
+    xd = torch.from_numpy(x).cuda()
+    last = qc.fx_tile_count(N, n_ant) - 1
+    try:
+        for t in sorted({0, last}):
+            qc.fx_set_tile(N, n_ant, t)
+            for w in (1, 7, 256, 1024, 0):
+                qc.fx_set_width(N, n_ant, w)
+                assert qc.fx_get_width(N, n_ant) == w
+                V = qc.xcorrelate(xd, N, P, spd).cpu().numpy()[:, :, chans]
+                assert vis_err(V, V_ref, n_ant) <= TOL, (t, w, vis_err(V, V_ref, n_ant))
+    finally:
+        qc.fx_set_tile(N, n_ant, 0)
+        qc.fx_set_width(N, n_ant, 0)
 
 
 # N = 8192 runs two antennas (one packed transform) per workgroup; odd

@@ -1,0 +1,57 @@
+"""Kernel timing modes of the measurement interface: argument checks on the
+host, and on the GPU that both modes record every timed call and leave the
+results unchanged, and that chained figures tile the stream's time."""
+
+import numpy as np
+import pytest
+
+import paper_2604_20640_amd as qc_mod
+
+QC_EINVAL = -1
+
+
+def test_timing_modes_host():
+    L = qc_mod.lib()
+    for bad in (-1, 3):
+        assert L.qc_timing_enable(bad) == QC_EINVAL
+    for mode in (2, 1, 0):
+        assert L.qc_timing_enable(mode) == 0
+    # nothing recorded: zero launches, no device work
+    assert qc_mod.timing_read("fx_fused") == (0.0, 0)
+
+
+@pytest.mark.gpu
+def test_timing_modes_count_tile_and_leave_results_unchanged(qc):
+    import torch
+    from synth import array_spec, generate
+
+    N, P, spd, reps = 1024, 4, 64, 6
+    x = torch.from_numpy(generate(array_spec(4, 8 * spd * N, 41))).cuda()
+    ref = qc.xcorrelate(x, N, P, spd)
+    m_ref, _ = qc.mad_flag(ref, 5.0, 0)
+    names = ("fx_fused", "reduce", "mad")
+
+    def run(mode):
+        vis = torch.empty_like(ref)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        qc.timing_enable(mode)
+        e0.record()
+        for _ in range(reps):
+            qc.xcorrelate(x, N, P, spd, vis=vis)
+            m, _ = qc.mad_flag(vis, 5.0, 0)
+        e1.record()
+        torch.cuda.synchronize()
+        got = {k: qc.timing_read(k) for k in names}
+        qc.timing_enable(False)
+        assert torch.equal(vis, ref) and torch.equal(m, m_ref)
+        return got, e0.elapsed_time(e1)
+
+    (pairs, _), (chained, elapsed) = run(True), run("chained")
+    for k in names:
+        assert pairs[k][1] == chained[k][1] == reps, (k, pairs[k], chained[k])
+        assert pairs[k][0] > 0 and chained[k][0] > 0
+    # chained figures tile the stream: they sum to the region's elapsed time
+    # less what lies outside the first call's start and the last call's end
+    total = sum(chained[k][0] for k in names)
+    assert elapsed - 0.1 <= total <= elapsed + 1e-3, (total, elapsed)
