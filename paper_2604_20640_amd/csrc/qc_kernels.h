@@ -30,6 +30,10 @@ struct FxArgs {
 // (n_fft, n_ant); part must hold fused_part_elems() float2.
 bool fused_supported(int n_fft, int n_ant);
 int fused_tile_count(int n_fft, int n_ant);
+// Compute units of the current device (cached per device; 256 if the query
+// fails).
+int device_cu_count();
+
 // Chunks per dump of a fused launch: about `workgroups` workgroups in all
 // (at least 8 spectra per chunk).
 int64_t fused_chunks_per_dump(int n_fft, int n_ant, int64_t n_dump, int64_t spec_per_dump,
