@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <fstream>
@@ -335,7 +336,7 @@ struct TimingRec {
   std::map<hipStream_t, hipEvent_t> tail;    // mode 2: last stop event per stream
 };
 std::mutex g_tmu;
-int g_timing = 0;
+std::atomic<int> g_timing{0};  // written under g_tmu; read without it on the launch path
 TimingRec g_trec;
 
 void timing_clear_locked() {
@@ -389,8 +390,9 @@ struct KTimer {
 
 namespace qc {
 hipEvent_t timing_stop_event(hipStream_t s) {
+  if (g_timing.load(std::memory_order_relaxed) != 2) return nullptr;
   std::lock_guard<std::mutex> lk(g_tmu);
-  if (g_timing != 2) return nullptr;
+  if (g_timing.load(std::memory_order_relaxed) != 2) return nullptr;
   hipEvent_t e = timing_new_event_locked();
   if (!e) return nullptr;
   KTimer* t = t_ktimer;
