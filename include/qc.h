@@ -498,7 +498,8 @@ qc_status qc_fx_autotune(const int8_t* x, int64_t ld_x, int32_t n_ant, int64_t n
  *   and time the stream sits idle waiting for the host, are therefore counted
  *   in the next call's figure: use it where the stream runs library calls
  *   only and the host enqueues ahead of the GPU.  The events carry no
- *   system-scope fence (they serve timing only).
+ *   system-scope fence (they serve timing only).  Launches made while the
+ *   stream is being captured into a graph are not timed.
  * Any other mode is QC_EINVAL.  Not thread-safe with respect to concurrent
  * enable/read. */
 enum {

@@ -391,6 +391,9 @@ struct KTimer {
 namespace qc {
 hipEvent_t timing_stop_event(hipStream_t s) {
   if (g_timing.load(std::memory_order_relaxed) != 2) return nullptr;
+  // launches being captured into a graph carry no events
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return nullptr;
   std::lock_guard<std::mutex> lk(g_tmu);
   if (g_timing.load(std::memory_order_relaxed) != 2) return nullptr;
   hipEvent_t e = timing_new_event_locked();

@@ -55,3 +55,36 @@ def test_timing_modes_count_tile_and_leave_results_unchanged(qc):
     # less what lies outside the first call's start and the last call's end
     total = sum(chained[k][0] for k in names)
     assert elapsed - 0.1 <= total <= elapsed + 1e-3, (total, elapsed)
+
+
+@pytest.mark.gpu
+def test_chained_timing_leaves_graph_capture_alone(qc):
+    """With chained timing on, a plan captured into a graph carries no timing
+    events: the capture succeeds and each replay equals the eager result."""
+    import torch
+    from synth import array_spec, generate
+
+    arrays = [dict(n_ant=4, n_samp=1024 * 64, n_fft=1024, spec_per_dump=32)]
+    xs = [torch.from_numpy(generate(array_spec(4, 1024 * 64, 43))).cuda()]
+    plan = qc.Plan(arrays)
+    eager = plan.empty_vis()
+    plan.execute(xs, eager)
+    torch.cuda.synchronize()
+    vis = plan.empty_vis()
+    s = torch.cuda.Stream()
+    qc.timing_enable("chained")
+    try:
+        with torch.cuda.stream(s):
+            plan.capture_graph(xs, vis)
+        torch.cuda.synchronize()
+        for r in range(3):
+            for v in vis:
+                v.zero_()
+            torch.cuda.synchronize()
+            with torch.cuda.stream(s):
+                plan.replay()
+            s.synchronize()
+            for a, b in zip(vis, eager):
+                assert torch.equal(a, b), r
+    finally:
+        qc.timing_enable(False)
