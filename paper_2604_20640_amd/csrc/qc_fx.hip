@@ -1517,15 +1517,36 @@ scales_partial_kernel(const int8_t* __restrict__ x, int64_t ld_x, int64_t n_use,
   const uint32_t* xw = reinterpret_cast<const uint32_t*>(xa);
   const int64_t nw = n_use / 4;
   const int64_t w0 = nw * blockIdx.x / SC_BLOCKS, w1 = nw * (blockIdx.x + 1) / SC_BLOCKS;
-  unsigned long long acc = 0;
-  for (int64_t w = w0 + threadIdx.x; w < w1; w += 256) {
-    const uint32_t v = xw[w];
+  // squares of the four samples of a word: at most 4 * 128^2, exact in 32 bits
+  auto sq4 = [](uint32_t v) -> unsigned {
+    unsigned t = 0u;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int b = (int)(int8_t)((v >> (8 * i)) & 0xffu);
-      acc += (unsigned long long)(b * b);
+      t += (unsigned)(b * b);
     }
+    return t;
+  };
+  unsigned long long acc = 0;
+  int64_t wt = w0;
+  if ((reinterpret_cast<uintptr_t>(xw + w0) & 15u) == 0) {
+    // 16-byte loads, four in flight per thread before any is used
+    constexpr int U = 4;
+    const uint4* x4 = reinterpret_cast<const uint4*>(xw + w0);
+    const int64_t n4 = (w1 - w0) / 4;
+    for (int64_t j0 = threadIdx.x; j0 < n4; j0 += (int64_t)U * 256) {
+      uint4 v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t j = j0 + (int64_t)u * 256;
+        v[u] = j < n4 ? x4[j] : make_uint4(0u, 0u, 0u, 0u);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) acc += (unsigned long long)(sq4(v[u].x) + sq4(v[u].y) + sq4(v[u].z) + sq4(v[u].w));
+    }
+    wt = w0 + 4 * n4;
   }
+  for (int64_t w = wt + threadIdx.x; w < w1; w += 256) acc += (unsigned long long)sq4(xw[w]);
   if (blockIdx.x == SC_BLOCKS - 1 && threadIdx.x == 0)
     for (int64_t n = nw * 4; n < n_use; ++n) acc += (unsigned long long)((int)xa[n] * (int)xa[n]);
 #pragma unroll
