@@ -500,8 +500,8 @@ qc_status qc_fx_autotune(const int8_t* x, int64_t ld_x, int32_t n_ant, int64_t n
  *   only and the host enqueues ahead of the GPU.  The events carry no
  *   system-scope fence (they serve timing only).  Launches made while the
  *   stream is being captured into a graph are not timed.
- * Every recorded event is kept (and read by qc_timing_read) until the next
- * qc_timing_enable call: enable timing for bounded measurement windows.
+ * Every recorded event is kept (for qc_timing_read) until timing is next
+ * enabled: enable it for bounded measurement windows.
  * Any other mode is QC_EINVAL.  Not thread-safe with respect to concurrent
  * enable/read. */
 enum {
