@@ -558,7 +558,7 @@ __device__ __forceinline__ void fft_pp_passes(float2* b0, float2* b1, const floa
     if constexpr (NS * R == N)
       stockham_last_pass_half<N, NS, NT>(src, dst, twl, tid);
     else
-      stockham_pass<N, R, NS, NT, V, false, false, true>(src, dst, twl, tid);
+      stockham_pass<N, R, NS, NT, V, false, false, true, true>(src, dst, twl, tid);
     fft_pp_passes<N, NS * R, NT, V, PASS + 1>(b0, b1, twl, tid);
   }
 }
