@@ -146,10 +146,10 @@ __device__ __forceinline__ void build_pass_twiddles(float2* dst, const float2* _
   }
 }
 
-// TWG (with TWL): the table twiddles are read in groups of four, each group
-// issued together so it waits once instead of once per read (for kernels
-// with the registers to hold a group).
-template <int N, int R, int NS, int NT, int V, bool INPLACE, bool LN, bool TWL = false, bool TWG = false>
+// TWG > 0 (with TWL): the table twiddles are read in groups of TWG, each
+// group issued together so it waits once instead of once per read (for
+// kernels with the registers to hold a group).
+template <int N, int R, int NS, int NT, int V, bool INPLACE, bool LN, bool TWL = false, int TWG = 0>
 __device__ __forceinline__ void stockham_pass(const float2* src, float2* dst,
                                               const float2* __restrict__ tw, int tid) {
   // Twiddles and LDS addresses depend only on the thread index, so the
@@ -178,15 +178,15 @@ __device__ __forceinline__ void stockham_pass(const float2* src, float2* dst,
     const int q = tid + i * NT;
     const int f = q / NB, j = q % NB;
     const int jm = j % NS;
-    if constexpr (NS > 1 && TWL && TWG) {
+    if constexpr (NS > 1 && TWL && TWG > 0) {
 #pragma unroll
-      for (int r0 = 1; r0 < R; r0 += 4) {
-        float2 wt[4];
+      for (int r0 = 1; r0 < R; r0 += TWG) {
+        float2 wt[TWG];
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < TWG; ++u)
           if (r0 + u < R) wt[u] = tw[(NS - 1) + (r0 + u - 1) * NS + jm];
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < TWG; ++u)
           if (r0 + u < R) v[i][r0 + u] = cmul(v[i][r0 + u], wt[u]);
       }
     } else if constexpr (NS > 1) {

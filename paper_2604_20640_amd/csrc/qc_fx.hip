@@ -548,8 +548,9 @@ __device__ __forceinline__ void stockham_last_pass_half(const float2* src, float
   __syncthreads();
 }
 
-// TWG: table twiddles read in groups of four (see stockham_pass).
-template <int N, int NS, int NT, int V, int PASS, bool TWG = true>
+// TWG: table twiddles read in groups of TWG, 0 for one wait per read (see
+// stockham_pass).
+template <int N, int NS, int NT, int V, int PASS, int TWG = 4>
 __device__ __forceinline__ void fft_pp_passes(float2* b0, float2* b1, const float2* twl, int tid) {
   constexpr int REM = N / NS;
   if constexpr (REM > 1) {
@@ -1272,7 +1273,7 @@ __device__ __forceinline__ void chan_ring_body(const int8_t* __restrict__ x, int
       for (int i = 0; i < 4; ++i) b0[lds_pad((g / GP) * N + cn0[g] + i)] = make_float2(y0[i], y1[i]);
     }
     __syncthreads();
-    if constexpr (PP) fft_pp_passes<N, 1, C::NT, V, 0, false>(b0, b1, twl, tid);
+    if constexpr (PP) fft_pp_passes<N, 1, C::NT, V, 0, 0>(b0, b1, twl, tid);
     else F::run(b0, b0, twl, tid);
     // The FIR of spectrum m is done: shift the ring here, before the
     // stores, so the wait for the prefetch does not also wait for them.
